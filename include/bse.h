@@ -1,0 +1,222 @@
+/*
+ * bse.h -- C ABI of the MI355X (gfx950) iterative solver for the structured
+ * Bethe-Salpeter eigenproblem.
+ *
+ * Problem (arXiv 2504.10096, Sec. 1, Eqs. (1)-(3)):
+ *   H [X; Y] = omega [X; Y],   H = [ A  B ; -conj(B)  -conj(A) ],
+ * A Hermitian (resonant block), B complex symmetric (coupling block), N x N.
+ * H = Omega M with M = [A B; conj(B) conj(A)] Hermitian; when M is positive
+ * definite the spectrum is real and comes in pairs (omega, -omega).  The
+ * Tamm-Dancoff approximation (TDA, B = 0) leaves the Hermitian problem
+ * A x = lambda x.
+ *
+ * Method (Sec. 2.2.1-2.2.2): a structure-preserving thick-restart Lanczos
+ * (Krylov-Schur) iteration that folds the spectrum (eigenvalues omega^2 of
+ * the operator K2 K1, K1 u = A u + B conj(u), K2 p = A p - B conj(p), run
+ * in the K1 inner product), keeps only the upper-half basis (U and P = K1 U),
+ * and recovers omega, X, Y from it.  For TDA it is thick-restart Lanczos on A.
+ * The matrix-vector products dominate the cost (Sec. 2.2.2); here they read
+ * each stored triangle of A and B exactly once per pass.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a bse_status; no C++ exception crosses the ABI.
+ *   - Pointers documented as "device" are HIP device addresses on the device
+ *     that was current at bse_create; "host" pointers are CPU memory.
+ *   - Complex numbers are interleaved (re, im) pairs.  Vectors of length N
+ *     are contiguous; blocks of vectors are column-major (column c starts at
+ *     c * N).
+ *   - All device work is enqueued on the stream given to bse_create.  Calls
+ *     that return results to the host (bse_solve, bse_backward,
+ *     bse_strength) synchronize that stream before returning.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - The library allocates its own device memory with hipMalloc.
+ */
+#ifndef BSE_H
+#define BSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bse_handle_s* bse_handle;
+
+typedef enum {
+  BSE_OK = 0,
+  BSE_ERR_INVALID_ARG = 1,           /* bad size, null required pointer, bad enum */
+  BSE_ERR_OUT_OF_MEMORY = 2,         /* hipMalloc failed */
+  BSE_ERR_DEVICE = 3,                /* a HIP runtime call failed */
+  BSE_ERR_NOT_POSITIVE_DEFINITE = 4, /* <w, K1 w> <= 0: M is not positive definite */
+  BSE_ERR_NOT_CONVERGED = 5,         /* max_restarts reached; best results returned */
+  BSE_ERR_NONFINITE = 6,             /* NaN/Inf in the inputs or iterates */
+  BSE_ERR_BAD_STATE = 7              /* call out of order (e.g. backward before solve) */
+} bse_status;
+
+typedef enum { BSE_TDA = 0, BSE_PSEUDO_HERMITIAN = 1 } bse_kind;
+
+/* How the triangles are stored on the device. */
+typedef enum {
+  BSE_STORE_C128 = 0, /* complex128: FP64 operator only */
+  BSE_STORE_HILO = 1  /* two complex64 triangles hi = fl32(a), lo = fl32(a - hi):
+                         hi alone is the FP32 operator, hi + lo the FP64 one
+                         (relative accuracy about 2^-48) */
+} bse_storage;
+
+typedef enum { BSE_C64 = 0, BSE_C128 = 1 } bse_dtype;
+typedef enum { BSE_PREC_FP64 = 0, BSE_PREC_MIXED = 1 } bse_precision;
+typedef enum { BSE_BLOCK_A = 0, BSE_BLOCK_B = 1 } bse_block;
+
+/* Operators for bse_apply. */
+typedef enum {
+  BSE_OP_A = 0,  /* y = A x                                   (N -> N) */
+  BSE_OP_K1 = 1, /* y = A x + B conj(x)                       (N -> N) */
+  BSE_OP_K2 = 2, /* y = A x - B conj(x)                       (N -> N) */
+  BSE_OP_H = 3   /* [yt; yb] = H [xt; xb]  (vectors of length 2N)      */
+} bse_op;
+
+/* Solver options; a NULL pointer or zero fields select the defaults. */
+typedef struct {
+  int32_t ncv;          /* basis size m (default: max(2k, k + 32) rounded up to 16, at most N) */
+  int32_t keep;         /* Ritz vectors kept at a restart (default: k + (m - k) / 2) */
+  int32_t max_restarts; /* default 400 */
+  int32_t precision;    /* bse_precision; MIXED needs BSE_STORE_HILO (default FP64) */
+  double switch_tol;    /* MIXED: FP32-phase estimate that hands over to FP64 (default 1e-6) */
+  uint64_t start_seed;  /* seed of the random start vector (default 1) */
+} bse_solve_opts;
+
+/* Statistics of the last bse_solve (host struct). */
+typedef struct {
+  int32_t n_converged;      /* pairs whose FP64-recomputed residual met tol */
+  int32_t restarts;         /* thick restarts, both phases */
+  int64_t steps_fp32;       /* Lanczos steps with the FP32 operator */
+  int64_t steps_fp64;       /* Lanczos steps with the FP64 operator */
+  int64_t passes;           /* passes over the stored triangles (each reads A, and B for PH) */
+  double ms_total;          /* wall time of the call */
+  double ms_fp32_phase;     /* time spent in the FP32 phase (MIXED) */
+  double ms_fp64_phase;     /* time spent iterating with the FP64 operator */
+  double ms_final;          /* eigenvector assembly + FP64 residual check */
+  double max_rel_residual;  /* max over the k pairs of ||H v - omega v|| / (|omega| ||v||) */
+  double bytes_per_pass_fp32; /* algorithmic bytes of one FP32 pass: hi triangles + in/out vectors */
+  double bytes_per_pass_fp64; /* algorithmic bytes of one FP64 pass: c128 (or hi+lo) triangles + vectors */
+  int64_t samples_fp32;     /* FP32 block-matvec launches timed with HIP events (every 8th pass) */
+  int64_t samples_fp64;     /* FP64 block-matvec launches timed with HIP events (every 8th pass) */
+  double ms_block_fp32;     /* summed duration of the timed FP32 launches */
+  double ms_block_fp64;     /* summed duration of the timed FP64 launches */
+} bse_stats;
+
+/* Component of a matrix for bse_strength: the scalar returned for a
+ * component C is Re<G, C> = sum_ij Re(conj(G_ij) C_ij), G the gradient of
+ * L = sum_c g_c omega_c with respect to the block C belongs to. */
+typedef enum {
+  BSE_COMP_PACKED = 0,  /* data: device LAPACK-'U' packed complex128 (Hermitian for A, symmetric for B) */
+  BSE_COMP_LOWRANK = 1, /* data: device N x rank complex128, row-major F; C = scale F F^H (A) or scale F F^T (B) */
+  BSE_COMP_DIAG = 2,    /* data: device N doubles; C = scale diag(d) (A only) */
+  BSE_COMP_STORED = 3   /* the stored block itself in FP64 (C = scale A or scale B); data unused */
+} bse_comp_form;
+
+typedef struct {
+  int32_t target; /* bse_block */
+  int32_t form;   /* bse_comp_form */
+  const void* data;
+  int64_t rank;
+  double scale;
+} bse_component;
+
+/*
+ * bse_create -- allocate a solver for an N x N resonant block (and an N x N
+ * coupling block when kind == BSE_PSEUDO_HERMITIAN).  The triangles are
+ * allocated on the current HIP device and zero-filled; fill them with
+ * bse_set_packed.  hip_stream: hipStream_t (NULL = default stream).
+ * Errors: INVALID_ARG (n < 1, bad enums, out == NULL), OUT_OF_MEMORY, DEVICE.
+ */
+bse_status bse_create(bse_handle* out, bse_kind kind, int64_t n, bse_storage storage,
+                      void* hip_stream);
+
+/*
+ * bse_set_packed -- copy columns j0 <= j < j1 of the upper triangle of A or
+ * B from LAPACK-'U' packed storage: src (device) holds entries (i, j),
+ * 0 <= i <= j, j0 <= j < j1, with (i, j) at offset i + j(j+1)/2 - j0(j0+1)/2.
+ * dtype: BSE_C128 or BSE_C64 (C64 input stored in HILO leaves lo = 0).  The
+ * imaginary part of A's diagonal is ignored.  Calls may cover the columns
+ * in any number of chunks; the caller may reuse src once the stream has
+ * passed the call.  Errors: INVALID_ARG (range, B for TDA, null src),
+ * BAD_STATE (handle in error).
+ */
+bse_status bse_set_packed(bse_handle h, bse_block which, int64_t j0, int64_t j1, const void* src,
+                          bse_dtype dtype);
+
+/*
+ * bse_apply -- y = op(x) for nvec vectors, columns of length N (2N for
+ * BSE_OP_H, stored as [top; bottom]), complex128, device.  precision selects
+ * the FP64 operator (c128, or hi+lo) or the FP32 operator (hi only, HILO
+ * storage).  One pass over the stored triangles per vector.
+ * Errors: INVALID_ARG (K1/K2/H on a TDA handle, FP32 without HILO, nulls).
+ */
+bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t nvec, const void* x,
+                     void* y);
+
+/*
+ * bse_solve -- the k lowest eigenpairs: TDA, the k smallest eigenvalues of A
+ * (ascending); PH, the k smallest positive omega of H (ascending).
+ *   omega: device, k doubles.
+ *   x:     device, N x k complex128 (TDA: orthonormal eigenvectors; PH: X).
+ *   y:     device, N x k complex128 (PH: Y, with X^H X - Y^H Y = 1 per pair);
+ *          must be NULL for TDA.
+ *   stats: host, may be NULL.
+ * Convergence: every pair's FP64-recomputed relative residual
+ * ||H v - omega v|| / (|omega| ||v||) is at most tol (TDA: with A, lambda).
+ * The left vectors (X; -Y) and the -omega partners (conj(Y); conj(X)) follow
+ * from Eq. (7) of the paper and are not returned.
+ * Errors: INVALID_ARG (k < 1, k > N, tol <= 0, nulls, y given for TDA,
+ * MIXED without HILO), NOT_POSITIVE_DEFINITE, NONFINITE, NOT_CONVERGED (the
+ * outputs then hold the best approximations; stats->n_converged says how
+ * many met tol), DEVICE, OUT_OF_MEMORY.
+ */
+bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* opts,
+                     double* omega, void* x, void* y, bse_stats* stats);
+
+/*
+ * bse_backward -- gradient of L = sum_c g_c omega_c (TDA: lambda_c) with
+ * respect to the packed triangles, from the eigenvectors of the last
+ * successful bse_solve.  First-order perturbation with the left vector
+ * Omega v of Eq. (7): d omega = v^H dM v / (v^H Omega v), giving
+ *   TDA: G_A = V diag(g) V^H;
+ *   PH:  G_A = sum_c g_c (X_c X_c^H + conj(Y_c Y_c^H)) / n_c,
+ *        G_B = sum_c g_c (X_c Y_c^H + conj(Y_c) X_c^T) / n_c,
+ *        n_c = X_c^H X_c - Y_c^H Y_c.
+ * Outputs are LAPACK-'U' packed complex128 in PyTorch's convention
+ * (dL = Re sum conj(grad) d entry): off-diagonal 2 G_ij, diagonal G_ii.
+ *   g:   device, k doubles.
+ *   d_a: device packed output or NULL; d_b: device packed output or NULL
+ *        (must be NULL for TDA).
+ * Errors: BAD_STATE (no successful solve), INVALID_ARG.
+ */
+bse_status bse_backward(bse_handle h, const double* g, void* d_a, void* d_b);
+
+/*
+ * bse_strength -- scalars Re<G, C_q> for n_comp components without forming
+ * G (quadratic forms of the stored eigenvectors): for a component of A,
+ * sum_c g_c (X_c^H C X_c + conj(Y_c)^H C conj(Y_c)) / n_c; of B,
+ * sum_c g_c 2 Re(X_c^H C Y_c) / n_c (TDA: sum_c g_c x_c^H C x_c).
+ *   g: device, k doubles; comps: host array; out: host, n_comp doubles.
+ * Errors: BAD_STATE (no successful solve), INVALID_ARG.
+ */
+bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse_component* comps,
+                        double* out);
+
+/* bse_destroy -- free all device memory of the handle (NULL is a no-op). */
+bse_status bse_destroy(bse_handle h);
+
+/* Static text for a status code. */
+const char* bse_status_string(bse_status s);
+
+/* Detail text of the last error on h; valid until the next call on h. */
+const char* bse_last_error(bse_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSE_H */

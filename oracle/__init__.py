@@ -227,3 +227,48 @@ def residual_generated(mat, om, x, y=None, band=DEFAULT_BAND):
     rn = np.sqrt(np.linalg.norm(top, axis=0) ** 2 + np.linalg.norm(bot, axis=0) ** 2)
     vn = np.sqrt(np.linalg.norm(x, axis=0) ** 2 + np.linalg.norm(y, axis=0) ** 2)
     return rn / (np.abs(om) * vn)
+
+
+# ---------------------------------------------------------------------------
+# Dense FP64 operators from packed blocks (plain definitions of the products
+# the iterative method applies; used for kernel-level parity).
+# ---------------------------------------------------------------------------
+def unpack_hermitian(ap, n):
+    """Full Hermitian matrix from packed upper (imaginary diagonal dropped)."""
+    a = np.zeros((n, n), dtype=np.complex128)
+    iu = np.triu_indices(n)
+    order = np.argsort(iu[1] * n + iu[0], kind="stable")  # packed order is column-major upper
+    rows, cols = iu[0][order], iu[1][order]
+    a[rows, cols] = ap
+    a = a + np.conj(np.triu(a, 1)).T
+    a[np.diag_indices(n)] = np.real(np.diag(a))
+    return a
+
+
+def unpack_symmetric(bp, n):
+    b = np.zeros((n, n), dtype=np.complex128)
+    iu = np.triu_indices(n)
+    order = np.argsort(iu[1] * n + iu[0], kind="stable")
+    b[iu[0][order], iu[1][order]] = bp
+    return b + np.triu(b, 1).T
+
+
+def apply_dense(op, ap, x, bp=None):
+    """op in {'A', 'K1', 'K2', 'H'}: A x, A x + B conj(x), A x - B conj(x), H [xt; xb].
+    x: (nvec, N) (or (nvec, 2N) for 'H'); returns the same shape."""
+    x = np.asarray(x, dtype=np.complex128)
+    n = _n_from_packed(np.asarray(ap))
+    a = unpack_hermitian(np.asarray(ap), n)
+    if op == "A":
+        return (a @ x.T).T
+    b = unpack_symmetric(np.asarray(bp), n)
+    if op == "K1":
+        return (a @ x.T + b @ np.conj(x).T).T
+    if op == "K2":
+        return (a @ x.T - b @ np.conj(x).T).T
+    if op == "H":
+        xt, xb = x[:, :n].T, x[:, n:].T
+        top = a @ xt + b @ xb
+        bot = -np.conj(b) @ xt - np.conj(a) @ xb
+        return np.vstack([top, bot]).T
+    raise ValueError(op)

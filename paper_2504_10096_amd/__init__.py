@@ -1,0 +1,269 @@
+"""Python binding of the MI355X structured BSE eigensolver (``include/bse.h``).
+
+Argument marshalling only: every step of the solve runs in the HIP library
+``libbse.so`` built in-tree for gfx950.  PyTorch provides device memory and
+the stream.  There is no CPU fallback: without the built library, or without
+a GPU, the calls raise.
+
+    s = Solver("ph", n, storage="c128")      # or "hilo" for the mixed path
+    s.set_packed("A", ap)                   # LAPACK-'U' packed, device complex
+    s.set_packed("B", bp)
+    omega, X, Y, stats = s.solve(k=32, tol=1e-10)
+    dA, dB = s.backward(g)                  # gradient of sum g_c omega_c
+
+``BSEEigs`` wraps solve/backward as a ``torch.autograd.Function`` over the
+packed triangles.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbse.so")
+
+OK, ERR_INVALID_ARG, ERR_OOM, ERR_DEVICE, ERR_NOT_PD, ERR_NOT_CONVERGED, ERR_NONFINITE, ERR_BAD_STATE = range(8)
+TDA, PSEUDO_HERMITIAN = 0, 1
+STORE_C128, STORE_HILO = 0, 1
+C64, C128 = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+BLOCK_A, BLOCK_B = 0, 1
+OP_A, OP_K1, OP_K2, OP_H = 0, 1, 2, 3
+COMP_PACKED, COMP_LOWRANK, COMP_DIAG, COMP_STORED = 0, 1, 2, 3
+
+EXPORTS = ["bse_create", "bse_set_packed", "bse_apply", "bse_solve", "bse_backward", "bse_strength",
+           "bse_destroy", "bse_status_string", "bse_last_error"]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("ncv", ctypes.c_int32), ("keep", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("switch_tol", ctypes.c_double), ("start_seed", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_converged", ctypes.c_int32), ("restarts", ctypes.c_int32), ("steps_fp32", ctypes.c_int64),
+                ("steps_fp64", ctypes.c_int64), ("passes", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("ms_fp32_phase", ctypes.c_double), ("ms_fp64_phase", ctypes.c_double),
+                ("ms_final", ctypes.c_double), ("max_rel_residual", ctypes.c_double),
+                ("bytes_per_pass_fp32", ctypes.c_double), ("bytes_per_pass_fp64", ctypes.c_double),
+                ("samples_fp32", ctypes.c_int64), ("samples_fp64", ctypes.c_int64),
+                ("ms_block_fp32", ctypes.c_double), ("ms_block_fp64", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Component(ctypes.Structure):
+    _fields_ = [("target", ctypes.c_int32), ("form", ctypes.c_int32), ("data", ctypes.c_void_p),
+                ("rank", ctypes.c_int64), ("scale", ctypes.c_double)]
+
+
+class BSEError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class NotPositiveDefinite(BSEError):
+    pass
+
+
+class NotConverged(BSEError):
+    pass
+
+
+_lib = None
+
+
+def load_library():
+    """Load libbse.so; raises if it was not built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "bse_create": ([ctypes.POINTER(vp), i32, i64, i32, vp], i32),
+        "bse_set_packed": ([vp, i32, i64, i64, vp, i32], i32),
+        "bse_apply": ([vp, i32, i32, i64, vp, vp], i32),
+        "bse_solve": ([vp, i32, dbl, ctypes.POINTER(SolveOpts), vp, vp, vp, ctypes.POINTER(Stats)], i32),
+        "bse_backward": ([vp, vp, vp, vp], i32),
+        "bse_strength": ([vp, vp, i32, ctypes.POINTER(Component), ctypes.POINTER(dbl)], i32),
+        "bse_destroy": ([vp], i32),
+        "bse_status_string": ([i32], ctypes.c_char_p),
+        "bse_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _stream_ptr(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One handle of the C ABI: a resonant block (and a coupling block for 'ph')."""
+
+    def __init__(self, kind, n, storage="c128", device=None):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the BSE solver needs a HIP device")
+        self.kind = {"tda": TDA, "ph": PSEUDO_HERMITIAN}[kind]
+        self.n = int(n)
+        self.storage = {"c128": STORE_C128, "hilo": STORE_HILO}[storage]
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self._check(lib.bse_create(ctypes.byref(self._h), self.kind, self.n, self.storage,
+                                       ctypes.c_void_p(_stream_ptr(self.device))), "bse_create", created=False)
+        self.last_stats = None
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, st, what, created=True):
+        if st == OK:
+            return
+        lib = load_library()
+        detail = lib.bse_last_error(self._h).decode() if created and self._h else ""
+        msg = f"{what}: {lib.bse_status_string(st).decode()}" + (f" ({detail})" if detail else "")
+        cls = {ERR_NOT_PD: NotPositiveDefinite, ERR_NOT_CONVERGED: NotConverged}.get(st, BSEError)
+        raise cls(st, msg)
+
+    def close(self):
+        if self._h:
+            load_library().bse_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- C ABI calls -----------------------------------------------------------
+    def set_packed(self, which, packed, j0=0, j1=None):
+        """Columns j0..j1-1 of the upper triangle in LAPACK-'U' packed order (device c128 or c64)."""
+        j1 = self.n if j1 is None else int(j1)
+        if packed.dtype not in (torch.complex128, torch.complex64):
+            raise ValueError("packed data must be complex128 or complex64")
+        expect = j1 * (j1 + 1) // 2 - j0 * (j0 + 1) // 2
+        if packed.numel() < expect:
+            raise ValueError(f"packed chunk has {packed.numel()} entries, needs {expect}")
+        dt = C128 if packed.dtype == torch.complex128 else C64
+        blk = {"A": BLOCK_A, "B": BLOCK_B}[which]
+        with torch.cuda.device(self.device):
+            self._check(load_library().bse_set_packed(self._h, blk, int(j0), j1, _dev_ptr(packed), dt),
+                        "bse_set_packed")
+
+    def set_packed_raw(self, which, ptr, j0, j1, c64=False):
+        blk = {"A": BLOCK_A, "B": BLOCK_B}[which]
+        self._check(load_library().bse_set_packed(self._h, blk, int(j0), int(j1), ctypes.c_void_p(ptr),
+                                                  C64 if c64 else C128), "bse_set_packed")
+
+    def apply(self, op, x, precision="fp64"):
+        """y = op(x); x: (nvec, N) complex128 (nvec, 2N for 'H'), rows are vectors."""
+        opc = {"A": OP_A, "K1": OP_K1, "K2": OP_K2, "H": OP_H}[op]
+        length = 2 * self.n if opc == OP_H else self.n
+        x = x.reshape(-1, length)
+        _dev_ptr(x, torch.complex128, "x")
+        y = torch.empty_like(x)
+        prec = PREC_MIXED if precision == "fp32" else PREC_FP64
+        with torch.cuda.device(self.device):
+            self._check(load_library().bse_apply(self._h, opc, prec, x.shape[0], _dev_ptr(x), _dev_ptr(y)),
+                        "bse_apply")
+        return y
+
+    def solve(self, k, tol, precision="fp64", ncv=0, keep=0, max_restarts=0, switch_tol=0.0, seed=1,
+              raise_not_converged=True):
+        """Lowest k pairs.  Returns (omega[k] f64, X[k, N] c128, Y[k, N] c128 or None, stats dict);
+        row c of X/Y is pair c (column c of the column-major N x k ABI layout)."""
+        k = int(k)
+        dev = self.device
+        omega = torch.empty(k, dtype=torch.float64, device=dev)
+        X = torch.empty((k, self.n), dtype=torch.complex128, device=dev)
+        Y = torch.empty((k, self.n), dtype=torch.complex128, device=dev) if self.kind == PSEUDO_HERMITIAN else None
+        opts = SolveOpts(int(ncv), int(keep), int(max_restarts), PREC_MIXED if precision == "mixed" else PREC_FP64,
+                         float(switch_tol), int(seed))
+        stats = Stats()
+        with torch.cuda.device(dev):
+            st = load_library().bse_solve(self._h, k, float(tol), ctypes.byref(opts), _dev_ptr(omega),
+                                          _dev_ptr(X), _dev_ptr(Y), ctypes.byref(stats))
+        self.last_stats = stats.as_dict()
+        if st == ERR_NOT_CONVERGED and not raise_not_converged:
+            return omega, X, Y, self.last_stats
+        self._check(st, "bse_solve")
+        return omega, X, Y, self.last_stats
+
+    def backward(self, g, want_a=True, want_b=True):
+        """Packed gradients (dL/dA, dL/dB) of L = sum_c g_c omega_c (LAPACK-'U', off-diagonal x2)."""
+        g = g.to(device=self.device, dtype=torch.float64).contiguous()
+        m = self.n * (self.n + 1) // 2
+        da = torch.empty(m, dtype=torch.complex128, device=self.device) if want_a else None
+        db = (torch.empty(m, dtype=torch.complex128, device=self.device)
+              if (want_b and self.kind == PSEUDO_HERMITIAN) else None)
+        with torch.cuda.device(self.device):
+            self._check(load_library().bse_backward(self._h, _dev_ptr(g), _dev_ptr(da), _dev_ptr(db)),
+                        "bse_backward")
+        return da, db
+
+
+def from_packed(ap, bp=None, storage="c128"):
+    """A Solver filled from device packed triangles (B given => pseudo-Hermitian)."""
+    n = int(round(((8 * ap.numel() + 1) ** 0.5 - 1) / 2))
+    s = Solver("ph" if bp is not None else "tda", n, storage=storage, device=ap.device.index)
+    s.set_packed("A", ap.contiguous())
+    if bp is not None:
+        s.set_packed("B", bp.contiguous())
+    return s
+
+
+class BSEEigs(torch.autograd.Function):
+    """omega = lowest-k eigenvalues (TDA) or positive pairs (PH) of the packed blocks.
+
+    forward(ap, bp, k, tol, storage, precision) -> (omega, X, Y);  bp may be None (TDA).
+    backward returns packed gradients for ap and bp from the eigenvalue
+    gradient; gradients with respect to X and Y are not supported.
+    """
+
+    @staticmethod
+    def forward(ctx, ap, bp, k, tol, storage="c128", precision="fp64"):
+        s = from_packed(ap.detach(), None if bp is None else bp.detach(), storage=storage)
+        omega, X, Y, _ = s.solve(k, tol, precision=precision)
+        ctx.solver = s
+        ctx.has_b = bp is not None
+        if Y is None:
+            Y = torch.zeros(0, dtype=torch.complex128, device=ap.device)
+        ctx.mark_non_differentiable(X, Y)
+        return omega, X, Y
+
+    @staticmethod
+    def backward(ctx, g_omega, g_x, g_y):
+        if g_x is not None and torch.count_nonzero(g_x) > 0:
+            raise NotImplementedError("gradients with respect to the eigenvectors are not supported")
+        if g_y is not None and g_y.numel() and torch.count_nonzero(g_y) > 0:
+            raise NotImplementedError("gradients with respect to the eigenvectors are not supported")
+        da, db = ctx.solver.backward(g_omega)
+        return da, (db if ctx.has_b else None), None, None, None, None

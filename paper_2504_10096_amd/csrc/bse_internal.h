@@ -1,0 +1,120 @@
+// Internal interfaces between the host driver (bse_solver.cpp) and the HIP
+// kernels (bse_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bse {
+
+// Triangle storage.  The upper triangle is cut into R x R blocks (P, Q),
+// P <= Q, stored one after another in panel-major order (block index
+// P*nb - P(P-1)/2 + (Q-P)); inside a block, element (r, c) sits at c*R + r
+// (column-major).  Diagonal blocks hold the diagonal halved and zeros below
+// it, so that every block contributes A_blk x to its rows and A_blk^H x to
+// its columns with no special case.  Rows/columns past N are zero padding.
+struct Layout {
+  int64_t n = 0;
+  int R = 0;        // block edge: 64, 128, 256 or 512
+  int nb = 0;       // blocks per edge: ceil(n / R)
+  int64_t nblk = 0; // nb (nb + 1) / 2
+  int2* blkmap = nullptr;  // device: (P, Q) for every block index
+  size_t elems() const { return (size_t)nblk * R * R; }
+};
+
+// Arithmetic of a pass: complex128 storage in FP64; hi only in FP32 (FP32
+// products and in-block sums, FP64 across blocks); hi + lo in FP64.
+enum Arith { AR_C128 = 0, AR_HI = 1, AR_HILO = 2 };
+
+struct MatPtrs {
+  const void* a = nullptr;   // c128 or hi
+  const void* alo = nullptr; // lo (HILO)
+  const void* b = nullptr;
+  const void* blo = nullptr;
+};
+
+// B handling of a pass: none (TDA), xb = sb * conj(xa) (K1: +1, K2: -1), or
+// an explicit second input vector.
+enum BMode { BM_NONE = 0, BM_CONJ = 1, BM_EXPLICIT = 2 };
+
+int choose_block(int64_t n);
+void layout_blkmap_host(int nb, int2* out);
+
+// out = A xa + B xb with xa = conja ? conj(va) : va and
+// xb = sb * conj(xa) (BM_CONJ) or sb * (conjb ? conj(vb) : vb) (BM_EXPLICIT).
+// rowpart/colpart: workspace of 2 * nblk * R double2.
+// ev0/ev1 (optional): events recorded around the block kernel only.
+hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const double2* va, int conja,
+                  const double2* vb, int conjb, double sb, double2* part, double2* out,
+                  hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
+// Copy packed-upper columns [j0, j1) into block storage (see Layout).
+hipError_t ingest(const Layout& L, bool is_a, bool hilo, const void* src, bool src_c64, int64_t j0,
+                  int64_t j1, void* dst, void* dst_lo, hipStream_t s);
+
+// Column chunk of the reductions below.
+constexpr int kChunk = 256;
+inline int64_t nchunks(int64_t n) { return (n + kChunk - 1) / kChunk; }
+
+// h[c] = sum_i conj(V[i, c]) w[i] for the n0 columns of V0 followed by the n1
+// columns of V1 (leading dimension ld, complex elements).  part: workspace
+// of nchunks(n) * (n0 + n1) double2.
+hipError_t cdot(const double2* V0, int n0, const double2* V1, int n1, int64_t ld, const double2* w,
+                int64_t n, double2* part, double2* h, hipStream_t s);
+
+// w -= V h (and z -= P h when z != nullptr); real_h: use Re(h) only.
+hipError_t cgemv_sub(const double2* V0, int n0, const double2* V1, int n1, const double2* P0,
+                     const double2* P1, int64_t ld, const double2* h, int real_h, double2* w,
+                     double2* z, int64_t n, hipStream_t s);
+
+// Lanczos normalization of step j: beta^2 = Re(w^H z) (z == w for TDA);
+// writes alpha[j] = Re(h1[jh] + h2[jh]), beta[j] = beta, sets flag (1: beta^2
+// <= 0, 2: non-finite) and scales w, z by 1/beta in place.  part: nchunks(n).
+hipError_t normalize(double2* w, double2* z, int64_t n, const double2* h1, const double2* h2, int jh,
+                     double* alpha, double* beta, int j, int* flag, double* part, hipStream_t s);
+
+// Plain normalization of a start vector: K1-norm (z != nullptr) or 2-norm.
+hipError_t scale_start(double2* w, double2* z, int64_t n, int* flag, double* part, hipStream_t s);
+
+// C (M x N) = A (M x K) B (K x N), real FP64, column-major, on MFMA.
+hipError_t dgemm_tn_mfma(int64_t M, int N, int K, const double* A, int64_t lda, const double* B,
+                         int64_t ldb, double* C, int64_t ldc, hipStream_t s);
+
+// nrm[c] = ||V[:, c]||^2 for c < ncol.  part: nchunks(n) * ncol.
+hipError_t colnorms(const double2* V, int ncol, int64_t ld, int64_t n, double* part, double* nrm,
+                    hipStream_t s);
+
+// Random start vector (uniform entries in [-0.5, 0.5) per component).
+hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s);
+
+// PH eigenvectors: X = (w u + p) / (2 sqrt(w)), Y = conj(w u - p) / (2 sqrt(w)).
+hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const double* omega, int k,
+                      int64_t n, double2* X, double2* Y, hipStream_t s);
+
+// Strided column copy (ld_src -> ld_dst), k columns of n complex entries.
+hipError_t copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int k,
+                     hipStream_t s);
+
+// dst[:, c] = i f_c src[:, c] for ncol columns; f_c = 1 (sc == nullptr),
+// sc[c], or 1 / sqrt(sc[c]) (sqrt_inv != 0).
+hipError_t times_i(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int ncol,
+                   const double* sc, int sqrt_inv, hipStream_t s);
+
+// Signed conjugate copy: dst = sg * conj(src) (n entries).
+hipError_t conj_copy(const double2* src, double2* dst, int64_t n, double sg, hipStream_t s);
+
+// Small dense symmetric eigensolver (host, FP64): a (m x m, column-major,
+// destroyed) -> ascending eigenvalues w and orthonormal eigenvectors z
+// (column-major).  Returns false if the QR iteration did not converge.
+bool sym_eig(int m, double* a, double* w, double* z);
+
+// Residual pieces of one vector: part2[2*chunk] = ||out - sgn*om*(cj ? conj(v) : v)||^2 over the
+// chunk, part2[2*chunk+1] = ||v||^2; res[0..1] = sums over chunks.
+hipError_t resid_norms(const double2* out, const double2* v, int cj, double sgn_om, int64_t n,
+                       double* part, double* res, hipStream_t s);
+
+// Packed gradients (LAPACK 'U', off-diagonal x2): TDA (Y == nullptr) or PH.
+hipError_t grad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
+                       int64_t n, double2* ga, double2* gb, hipStream_t s);
+
+}  // namespace bse

@@ -1,0 +1,842 @@
+// HIP kernels of the structured BSE eigensolver, written for gfx950 (CDNA4,
+// 64-wide wavefronts).
+//
+// The pass over the stored triangles (matvec) is the hot spot of the method
+// (Sec. 2.2.2 of the paper): it is HBM-bound at 1-2 flop/byte, so the design
+// goal is to stream every stored block exactly once with fully coalesced
+// loads and keep everything else small next to it.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "bse_internal.h"
+
+namespace bse {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block-wide sum (256 threads) in a fixed order: deterministic.
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------------------- storage
+// Matrix blocks are streamed once per pass: nontemporal loads keep them from
+// evicting the (reused) vectors and partials from the caches.
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
+
+template <int AR>
+struct Elem;
+template <>
+struct Elem<AR_C128> {
+  using T = double;
+  __device__ static __forceinline__ void load(const void* p, const void*, size_t i, double& re,
+                                              double& im) {
+    const nd2 v = __builtin_nontemporal_load(static_cast<const nd2*>(p) + i);
+    re = v.x;
+    im = v.y;
+  }
+};
+template <>
+struct Elem<AR_HI> {
+  using T = float;
+  __device__ static __forceinline__ void load(const void* p, const void*, size_t i, float& re,
+                                              float& im) {
+    const nf2 v = __builtin_nontemporal_load(static_cast<const nf2*>(p) + i);
+    re = v.x;
+    im = v.y;
+  }
+};
+template <>
+struct Elem<AR_HILO> {
+  using T = double;
+  __device__ static __forceinline__ void load(const void* p, const void* q, size_t i, double& re,
+                                              double& im) {
+    const nf2 h = __builtin_nontemporal_load(static_cast<const nf2*>(p) + i);
+    const nf2 l = __builtin_nontemporal_load(static_cast<const nf2*>(q) + i);
+    re = (double)h.x + (double)l.x;
+    im = (double)h.y + (double)l.y;
+  }
+};
+
+// ----------------------------------------------------------------- matvec
+//
+// One workgroup (4 waves) per stored R x R block (P, Q).  Wave w walks the
+// columns [w R/4, (w+1) R/4); lane l owns rows l + 64 q.  For each column c
+// the lane loads its R/64 entries (one contiguous 64-lane segment per load),
+// adds A_rc * x_c into its row accumulators and conj(A_rc) * x_r into the
+// column sum, which a wavefront reduction completes.  Row sums of the four
+// waves are combined through LDS.  Outputs are per-block partial vectors
+// (rows and columns) in FP64; a second kernel sums them in a fixed order, so
+// the result is deterministic and each block is read once.
+template <int R, int AR, int BM>
+__global__ void __launch_bounds__(kThreads)
+    mv_block_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
+                    const void* __restrict__ b0, const void* __restrict__ b1,
+                    const int2* __restrict__ blkmap, int64_t n, const double2* __restrict__ va,
+                    int conja, const double2* __restrict__ vb, int conjb, double sb,
+                    double2* __restrict__ rowpart, double2* __restrict__ colpart) {
+  using T = typename Elem<AR>::T;
+  constexpr int RPL = R / 64;
+  constexpr int CPW = R / 4;
+  __shared__ double2 sh[4][R];
+
+  const int blk = blockIdx.x;
+  const int2 pq = blkmap[blk];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = (int64_t)pq.x * R, col0 = (int64_t)pq.y * R;
+  const size_t base = (size_t)blk * R * R;
+  const T ca = conja ? T(-1) : T(1);
+  const T cb = conjb ? T(-1) : T(1);
+  const T tsb = (T)sb;
+
+  // Row-side inputs x_r (and the explicit B input).
+  T xar[RPL], xai[RPL], xbr[RPL], xbi[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int64_t i = row0 + lane + 64 * q;
+    double2 v = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0);
+    if (i < n) {
+      v = va[i];
+      if (BM == BM_EXPLICIT) w = vb[i];
+    }
+    xar[q] = (T)v.x;
+    xai[q] = ca * (T)v.y;
+    if (BM == BM_EXPLICIT) {
+      xbr[q] = tsb * (T)w.x;
+      xbi[q] = tsb * cb * (T)w.y;
+    } else {
+      xbr[q] = T(0);
+      xbi[q] = T(0);
+    }
+  }
+
+  T rr[RPL], ri[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    rr[q] = T(0);
+    ri[q] = T(0);
+  }
+
+#pragma unroll 2
+  for (int cc = 0; cc < CPW; ++cc) {
+    const int c = wave * CPW + cc;
+    const int64_t j = col0 + c;
+    double2 vj = make_double2(0.0, 0.0), wj = make_double2(0.0, 0.0);
+    if (j < n) {
+      vj = va[j];
+      if (BM == BM_EXPLICIT) wj = vb[j];
+    }
+    const T xcr = (T)vj.x, xci = ca * (T)vj.y;
+    T ycr = T(0), yci = T(0);  // B input at column c
+    if (BM == BM_CONJ) {
+      ycr = tsb * xcr;
+      yci = -tsb * xci;
+    } else if (BM == BM_EXPLICIT) {
+      ycr = tsb * (T)wj.x;
+      yci = tsb * cb * (T)wj.y;
+    }
+    T cr = T(0), ci = T(0), dr = T(0), di = T(0);
+    const size_t cbase = base + (size_t)c * R + lane;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      T ar, ai;
+      Elem<AR>::load(a0, a1, cbase + 64 * q, ar, ai);
+      // row r: A_rc x_c
+      rr[q] += ar * xcr - ai * xci;
+      ri[q] += ar * xci + ai * xcr;
+      // column c: conj(A_rc) x_r
+      cr += ar * xar[q] + ai * xai[q];
+      ci += ar * xai[q] - ai * xar[q];
+      if (BM != BM_NONE) {
+        T br, bi;
+        Elem<AR>::load(b0, b1, cbase + 64 * q, br, bi);
+        rr[q] += br * ycr - bi * yci;
+        ri[q] += br * yci + bi * ycr;
+        if (BM == BM_CONJ) {
+          // column c: B_rc conj(x_r) (the sign sb is applied after the sum)
+          dr += br * xar[q] + bi * xai[q];
+          di += bi * xar[q] - br * xai[q];
+        } else {
+          dr += br * xbr[q] - bi * xbi[q];
+          di += br * xbi[q] + bi * xbr[q];
+        }
+      }
+    }
+    if (BM == BM_CONJ) {
+      cr += tsb * dr;
+      ci += tsb * di;
+    } else if (BM == BM_EXPLICIT) {
+      cr += dr;
+      ci += di;
+    }
+    cr = wave_sum(cr);
+    ci = wave_sum(ci);
+    if (lane == 0) colpart[(size_t)blk * R + c] = make_double2((double)cr, (double)ci);
+  }
+
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) sh[wave][lane + 64 * q] = make_double2((double)rr[q], (double)ri[q]);
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += kThreads) {
+    double2 s = sh[0][r];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      s.x += sh[w][r].x;
+      s.y += sh[w][r].y;
+    }
+    rowpart[(size_t)blk * R + r] = s;
+  }
+}
+
+// out[i] = sum over the blocks of panel row P = i / R of their row partials
+//        + sum over the blocks of panel column P of their column partials.
+__global__ void __launch_bounds__(kThreads)
+    mv_reduce_kernel(const double2* __restrict__ rowpart, const double2* __restrict__ colpart,
+                     int R, int nb, int64_t n, double2* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int P = (int)(i / R), r = (int)(i % R);
+  double sx = 0.0, sy = 0.0;
+  const int64_t pstart = (int64_t)P * nb - (int64_t)P * (P - 1) / 2;
+  for (int Q = P; Q < nb; ++Q) {
+    const double2 v = rowpart[(size_t)(pstart + (Q - P)) * R + r];
+    sx += v.x;
+    sy += v.y;
+  }
+  for (int Q = 0; Q <= P; ++Q) {
+    const int64_t qs = (int64_t)Q * nb - (int64_t)Q * (Q - 1) / 2;
+    const double2 v = colpart[(size_t)(qs + (P - Q)) * R + r];
+    sx += v.x;
+    sy += v.y;
+  }
+  out[i] = make_double2(sx, sy);
+}
+
+template <int R, int AR, int BM>
+hipError_t launch_mv(const Layout& L, const MatPtrs& m, const double2* va, int conja,
+                     const double2* vb, int conjb, double sb, double2* part, hipStream_t s) {
+  double2* rowpart = part;
+  double2* colpart = part + (size_t)L.nblk * L.R;
+  hipLaunchKernelGGL((mv_block_kernel<R, AR, BM>), dim3((unsigned)L.nblk), dim3(kThreads), 0, s,
+                     m.a, m.alo, m.b, m.blo, L.blkmap, L.n, va, conja, vb, conjb, sb, rowpart,
+                     colpart);
+  return hipGetLastError();
+}
+
+template <int R, int AR>
+hipError_t dispatch_bm(BMode bm, const Layout& L, const MatPtrs& m, const double2* va, int conja,
+                       const double2* vb, int conjb, double sb, double2* part, hipStream_t s) {
+  switch (bm) {
+    case BM_NONE:
+      return launch_mv<R, AR, BM_NONE>(L, m, va, conja, vb, conjb, sb, part, s);
+    case BM_CONJ:
+      return launch_mv<R, AR, BM_CONJ>(L, m, va, conja, vb, conjb, sb, part, s);
+    default:
+      return launch_mv<R, AR, BM_EXPLICIT>(L, m, va, conja, vb, conjb, sb, part, s);
+  }
+}
+
+template <int R>
+hipError_t dispatch_ar(Arith ar, BMode bm, const Layout& L, const MatPtrs& m, const double2* va,
+                       int conja, const double2* vb, int conjb, double sb, double2* part,
+                       hipStream_t s) {
+  switch (ar) {
+    case AR_C128:
+      return dispatch_bm<R, AR_C128>(bm, L, m, va, conja, vb, conjb, sb, part, s);
+    case AR_HI:
+      return dispatch_bm<R, AR_HI>(bm, L, m, va, conja, vb, conjb, sb, part, s);
+    default:
+      return dispatch_bm<R, AR_HILO>(bm, L, m, va, conja, vb, conjb, sb, part, s);
+  }
+}
+
+// ----------------------------------------------------------------- ingest
+// One workgroup per source column j; entry (i, j) of the packed upper
+// triangle goes to block (i / R, j / R) at (j % R) * R + (i % R).  Diagonal
+// entries are halved (A: real part only).
+__global__ void __launch_bounds__(kThreads)
+    ingest_kernel(const void* __restrict__ src, int src_c64, int64_t j0, int64_t base, int R,
+                  int nb, int is_a, int hilo, void* __restrict__ dst, void* __restrict__ dst_lo) {
+  const int64_t j = j0 + blockIdx.x;
+  const int64_t off = j * (j + 1) / 2 - base;
+  const int Q = (int)(j / R), c = (int)(j % R);
+  for (int64_t i = threadIdx.x; i <= j; i += kThreads) {
+    double re, im;
+    if (src_c64) {
+      const float2 v = static_cast<const float2*>(src)[off + i];
+      re = v.x;
+      im = v.y;
+    } else {
+      const double2 v = static_cast<const double2*>(src)[off + i];
+      re = v.x;
+      im = v.y;
+    }
+    if (i == j) {
+      re *= 0.5;
+      im = is_a ? 0.0 : 0.5 * im;
+    }
+    const int P = (int)(i / R), r = (int)(i % R);
+    const int64_t blk = (int64_t)P * nb - (int64_t)P * (P - 1) / 2 + (Q - P);
+    const size_t d = (size_t)blk * R * R + (size_t)c * R + r;
+    if (hilo) {
+      const float hr = __double2float_rn(re), hi = __double2float_rn(im);
+      static_cast<float2*>(dst)[d] = make_float2(hr, hi);
+      static_cast<float2*>(dst_lo)[d] =
+          make_float2(__double2float_rn(re - (double)hr), __double2float_rn(im - (double)hi));
+    } else {
+      static_cast<double2*>(dst)[d] = make_double2(re, im);
+    }
+  }
+}
+
+// -------------------------------------------------- orthogonalization (CGS)
+// part[chunk * ncol + c] = sum over the 256-row chunk of conj(V[i, c]) w[i].
+// Grid (chunks, ceil(ncol / 64)); wave w of the group handles 16 columns;
+// lane l holds rows l + 64 s (s < 4) of w in registers.
+__global__ void __launch_bounds__(kThreads)
+    cdot_part_kernel(const double2* __restrict__ V0, int n0, const double2* __restrict__ V1,
+                     int n1, int64_t ld, const double2* __restrict__ w, int64_t n,
+                     double2* __restrict__ part) {
+  const int ncol = n0 + n1;
+  const int64_t r0 = (int64_t)blockIdx.x * kChunk;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double wr[4], wi[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int64_t i = r0 + lane + 64 * s;
+    const double2 v = (i < n) ? w[i] : make_double2(0.0, 0.0);
+    wr[s] = v.x;
+    wi[s] = v.y;
+  }
+  const int cbeg = blockIdx.y * 64 + wave * 16;
+  for (int t = 0; t < 16; ++t) {
+    const int c = cbeg + t;
+    if (c >= ncol) break;
+    const double2* col = (c < n0) ? V0 + (size_t)c * ld : V1 + (size_t)(c - n0) * ld;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t i = r0 + lane + 64 * s;
+      if (i < n) {
+        const double2 v = col[i];
+        sr += v.x * wr[s] + v.y * wi[s];
+        si += v.x * wi[s] - v.y * wr[s];
+      }
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) part[(size_t)blockIdx.x * ncol + c] = make_double2(sr, si);
+  }
+}
+
+// h[c] = sum over chunks of part[chunk * ncol + c], chunks in order.
+__global__ void __launch_bounds__(kThreads)
+    colsum_kernel(const double2* __restrict__ part, int64_t nch, int ncol, double2* __restrict__ h) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= ncol) return;
+  double sr = 0.0, si = 0.0;
+  for (int64_t k = 0; k < nch; ++k) {
+    const double2 v = part[(size_t)k * ncol + c];
+    sr += v.x;
+    si += v.y;
+  }
+  h[c] = make_double2(sr, si);
+}
+
+// w[i] -= sum_c V[i, c] h[c];  z[i] -= sum_c P[i, c] h[c] (optional).
+__global__ void __launch_bounds__(kThreads)
+    cgemv_sub_kernel(const double2* __restrict__ V0, int n0, const double2* __restrict__ V1, int n1,
+                     const double2* __restrict__ P0, const double2* __restrict__ P1, int64_t ld,
+                     const double2* __restrict__ h, int real_h, double2* __restrict__ w,
+                     double2* __restrict__ z, int64_t n) {
+  extern __shared__ double2 hs[];
+  const int ncol = n0 + n1;
+  for (int c = threadIdx.x; c < ncol; c += kThreads) {
+    double2 v = h[c];
+    if (real_h) v.y = 0.0;
+    hs[c] = v;
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+  for (int c = 0; c < ncol; ++c) {
+    const double2 hc = hs[c];
+    const double2 v = (c < n0) ? V0[(size_t)c * ld + i] : V1[(size_t)(c - n0) * ld + i];
+    ar += v.x * hc.x - v.y * hc.y;
+    ai += v.x * hc.y + v.y * hc.x;
+    if (z) {
+      const double2 p = (c < n0) ? P0[(size_t)c * ld + i] : P1[(size_t)(c - n0) * ld + i];
+      br += p.x * hc.x - p.y * hc.y;
+      bi += p.x * hc.y + p.y * hc.x;
+    }
+  }
+  double2 wv = w[i];
+  wv.x -= ar;
+  wv.y -= ai;
+  w[i] = wv;
+  if (z) {
+    double2 zv = z[i];
+    zv.x -= br;
+    zv.y -= bi;
+    z[i] = zv;
+  }
+}
+
+// part[chunk] = Re sum conj(w_i) z_i over the chunk.
+__global__ void __launch_bounds__(kThreads)
+    rdot_part_kernel(const double2* __restrict__ w, const double2* __restrict__ z, int64_t n,
+                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t i = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+  double s = 0.0;
+  if (i < n) {
+    const double2 a = w[i], b = z[i];
+    s = a.x * b.x + a.y * b.y;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Every workgroup sums the chunk partials in the same order (identical
+// beta everywhere), then scales its rows; workgroup 0 records alpha, beta.
+__global__ void __launch_bounds__(kThreads)
+    normalize_kernel(double2* __restrict__ w, double2* __restrict__ z, int64_t n,
+                     const double* __restrict__ part, int64_t nch, const double2* __restrict__ h1,
+                     const double2* __restrict__ h2, int jh, double* __restrict__ alpha,
+                     double* __restrict__ beta, int j, int* __restrict__ flag) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < nch; k += kThreads) s += part[k];
+  const double b2 = block_sum(s, sh);
+  // b2 < 0: the K1 metric is indefinite (M not positive definite);
+  // b2 == 0: exact breakdown (invariant subspace), the vector stays zero.
+  const bool nonfinite = !isfinite(b2);
+  const bool indefinite = b2 < 0.0;
+  const bool bad = nonfinite || indefinite || !(b2 > 0.0);
+  const double bt = bad ? 1.0 : sqrt(b2);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (alpha) alpha[j] = (h1 ? h1[jh].x : 0.0) + (h2 ? h2[jh].x : 0.0);
+    if (beta) beta[j] = bad ? 0.0 : bt;
+    if (flag && (nonfinite || indefinite)) {
+      const int code = nonfinite ? 2 : 1;
+      if (flag[0] < code) flag[0] = code;
+    }
+  }
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const double inv = 1.0 / bt;
+  double2 a = w[i];
+  a.x *= inv;
+  a.y *= inv;
+  w[i] = a;
+  if (z && z != w) {
+    double2 b = z[i];
+    b.x *= inv;
+    b.y *= inv;
+    z[i] = b;
+  }
+}
+
+// ------------------------------------------------------- FP64 MFMA GEMM
+// C (M x N) = A (M x K) * B (K x N), column-major, FP64, on
+// v_mfma_f64_16x16x4f64.  Workgroup tile 64 x 64 (4 waves, each 32 x 32 =
+// 2 x 2 MFMA tiles); K in steps of 4.  Lane layout of the 16x16x4 FP64
+// instruction (measured on gfx950): A[i][k] in lane i + 16 k; B[k][j] in
+// lane j + 16 k; result D[i][j] in lane j + 16 (i % 4), register i / 4.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kThreads)
+    dgemm_mfma_kernel(int64_t M, int N, int K, const double* __restrict__ A, int64_t lda,
+                      const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
+                      int64_t ldc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t m0 = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
+  const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  dbl4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + lk;
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int64_t i = m0 + a * 16 + li;
+      av[a] = (i < M && k < K) ? A[(size_t)k * lda + i] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int jj = n0 + b * 16 + li;
+      bv[b] = (jj < N && k < K) ? B[(size_t)jj * ldb + k] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int jj = n0 + b * 16 + li;
+      if (jj >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = m0 + a * 16 + 4 * r + lk;
+        if (i < M) C[(size_t)jj * ldc + i] = acc[a][b][r];
+      }
+    }
+}
+
+// ------------------------------------------------------------ small kernels
+__global__ void __launch_bounds__(kThreads)
+    colnorm_part_kernel(const double2* __restrict__ V, int ncol, int64_t ld, int64_t n,
+                        double* __restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * kChunk;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = wave; c < ncol; c += 4) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = r0 + lane + 64 * q;
+      if (i < n) {
+        const double2 v = V[(size_t)c * ld + i];
+        s += v.x * v.x + v.y * v.y;
+      }
+    }
+    s = wave_sum(s);
+    if (lane == 0) part[(size_t)blockIdx.x * ncol + c] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+    colsum_real_kernel(const double* __restrict__ part, int64_t nch, int ncol, double* __restrict__ h) {
+  const int c = blockIdx.x * kThreads + threadIdx.x;
+  if (c >= ncol) return;
+  double s = 0.0;
+  for (int64_t k = 0; k < nch; ++k) s += part[(size_t)k * ncol + c];
+  h[c] = s;
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ void __launch_bounds__(kThreads)
+    start_vector_kernel(double2* __restrict__ v, int64_t n, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t a = splitmix64(seed * 0x100000001B3ull + 2 * (uint64_t)i);
+  const uint64_t b = splitmix64(seed * 0x100000001B3ull + 2 * (uint64_t)i + 1);
+  v[i] = make_double2((double)(a >> 11) * 0x1.0p-53 - 0.5, (double)(b >> 11) * 0x1.0p-53 - 0.5);
+}
+
+__global__ void __launch_bounds__(kThreads)
+    ph_vectors_kernel(const double2* __restrict__ U, const double2* __restrict__ P, int64_t ld,
+                      const double* __restrict__ omega, int64_t n, double2* __restrict__ X,
+                      double2* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const double w = omega[c];
+  const double s = 0.5 / sqrt(w);
+  const double2 u = U[(size_t)c * ld + i], p = P[(size_t)c * ld + i];
+  X[(size_t)c * n + i] = make_double2(s * (w * u.x + p.x), s * (w * u.y + p.y));
+  Y[(size_t)c * n + i] = make_double2(s * (w * u.x - p.x), -s * (w * u.y - p.y));
+}
+
+// dst[:, c] = i * scale_c * src[:, c]  (scale = 1 when sc == nullptr; per
+// column 1 / sqrt(th[c]) when sqrt_inv != 0).
+__global__ void __launch_bounds__(kThreads)
+    times_i_kernel(const double2* __restrict__ src, int64_t lds, double2* __restrict__ dst,
+                   int64_t ldd, int64_t n, const double* __restrict__ sc, int sqrt_inv) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  double f = 1.0;
+  if (sc) f = sqrt_inv ? 1.0 / sqrt(sc[c]) : sc[c];
+  const double2 v = src[(size_t)c * lds + i];
+  dst[(size_t)c * ldd + i] = make_double2(-f * v.y, f * v.x);
+}
+
+__global__ void __launch_bounds__(kThreads)
+    copy_cols_kernel(const double2* __restrict__ src, int64_t lds, double2* __restrict__ dst,
+                     int64_t ldd, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  dst[(size_t)blockIdx.y * ldd + i] = src[(size_t)blockIdx.y * lds + i];
+}
+
+__global__ void __launch_bounds__(kThreads)
+    conj_copy_kernel(const double2* __restrict__ src, double2* __restrict__ dst, int64_t n, double sg) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const double2 v = src[i];
+  dst[i] = make_double2(sg * v.x, -sg * v.y);
+}
+
+__global__ void __launch_bounds__(kThreads)
+    resid_part_kernel(const double2* __restrict__ out, const double2* __restrict__ v, int cj,
+                      double so, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t i = (int64_t)blockIdx.x * kChunk + threadIdx.x;
+  double r2 = 0.0, v2 = 0.0;
+  if (i < n) {
+    const double2 o = out[i];
+    double2 x = v[i];
+    if (cj) x.y = -x.y;
+    const double dr = o.x - so * x.x, di = o.y - so * x.y;
+    r2 = dr * dr + di * di;
+    v2 = x.x * x.x + x.y * x.y;
+  }
+  r2 = block_sum(r2, sh);
+  v2 = block_sum(v2, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = r2;
+    part[2 * blockIdx.x + 1] = v2;
+  }
+}
+
+__global__ void __launch_bounds__(64) pair_sum_kernel(const double* __restrict__ part, int64_t nch,
+                                                      double* __restrict__ res) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, b = 0.0;
+  for (int64_t k = 0; k < nch; ++k) {
+    a += part[2 * k];
+    b += part[2 * k + 1];
+  }
+  res[0] = a;
+  res[1] = b;
+}
+
+// Packed gradient, one workgroup per column j of the upper triangle.
+__global__ void __launch_bounds__(kThreads)
+    grad_packed_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, int64_t ld,
+                       const double* __restrict__ wgt, int k, double2* __restrict__ ga,
+                       double2* __restrict__ gb) {
+  const int64_t j = blockIdx.x;
+  const int64_t off = j * (j + 1) / 2;
+  for (int64_t i = threadIdx.x; i <= j; i += kThreads) {
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    for (int c = 0; c < k; ++c) {
+      const double g = wgt[c];
+      const double2 xi = X[(size_t)c * ld + i], xj = X[(size_t)c * ld + j];
+      // X_i conj(X_j)
+      ar += g * (xi.x * xj.x + xi.y * xj.y);
+      ai += g * (xi.y * xj.x - xi.x * xj.y);
+      if (Y) {
+        const double2 yi = Y[(size_t)c * ld + i], yj = Y[(size_t)c * ld + j];
+        // conj(Y_i) Y_j
+        ar += g * (yi.x * yj.x + yi.y * yj.y);
+        ai += g * (yi.x * yj.y - yi.y * yj.x);
+        // X_i conj(Y_j) + conj(Y_i) X_j
+        br += g * ((xi.x * yj.x + xi.y * yj.y) + (yi.x * xj.x + yi.y * xj.y));
+        bi += g * ((xi.y * yj.x - xi.x * yj.y) + (yi.x * xj.y - yi.y * xj.x));
+      }
+    }
+    const double f = (i == j) ? 1.0 : 2.0;
+    if (ga) ga[off + i] = (i == j) ? make_double2(ar, 0.0) : make_double2(f * ar, f * ai);
+    if (gb) gb[off + i] = make_double2(f * br, f * bi);
+  }
+}
+
+}  // namespace
+
+// ====================================================================== API
+int choose_block(int64_t n) {
+  const int cand[4] = {512, 256, 128, 64};
+  for (int q = 0; q < 4; ++q) {
+    const int64_t nb = (n + cand[q] - 1) / cand[q];
+    if (nb * (nb + 1) / 2 >= 1024) return cand[q];
+  }
+  return 64;
+}
+
+void layout_blkmap_host(int nb, int2* out) {
+  int64_t b = 0;
+  for (int P = 0; P < nb; ++P)
+    for (int Q = P; Q < nb; ++Q) out[b++] = make_int2(P, Q);
+}
+
+hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const double2* va, int conja,
+                  const double2* vb, int conjb, double sb, double2* part, double2* out,
+                  hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  hipError_t e;
+  if (ev0) {
+    e = hipEventRecord(ev0, s);
+    if (e != hipSuccess) return e;
+  }
+  switch (L.R) {
+    case 64:
+      e = dispatch_ar<64>(ar, bm, L, m, va, conja, vb, conjb, sb, part, s);
+      break;
+    case 128:
+      e = dispatch_ar<128>(ar, bm, L, m, va, conja, vb, conjb, sb, part, s);
+      break;
+    case 256:
+      e = dispatch_ar<256>(ar, bm, L, m, va, conja, vb, conjb, sb, part, s);
+      break;
+    case 512:
+      e = dispatch_ar<512>(ar, bm, L, m, va, conja, vb, conjb, sb, part, s);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (ev1) {
+    e = hipEventRecord(ev1, s);
+    if (e != hipSuccess) return e;
+  }
+  const double2* rowpart = part;
+  const double2* colpart = part + (size_t)L.nblk * L.R;
+  hipLaunchKernelGGL(mv_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, rowpart, colpart, L.R, L.nb, L.n, out);
+  return hipGetLastError();
+}
+
+hipError_t ingest(const Layout& L, bool is_a, bool hilo, const void* src, bool src_c64, int64_t j0,
+                  int64_t j1, void* dst, void* dst_lo, hipStream_t s) {
+  if (j1 <= j0) return hipSuccess;
+  hipLaunchKernelGGL(ingest_kernel, dim3((unsigned)(j1 - j0)), dim3(kThreads), 0, s, src,
+                     (int)src_c64, j0, j0 * (j0 + 1) / 2, L.R, L.nb, (int)is_a, (int)hilo, dst,
+                     dst_lo);
+  return hipGetLastError();
+}
+
+hipError_t cdot(const double2* V0, int n0, const double2* V1, int n1, int64_t ld, const double2* w,
+                int64_t n, double2* part, double2* h, hipStream_t s) {
+  const int ncol = n0 + n1;
+  if (ncol == 0) return hipSuccess;
+  const int64_t nch = nchunks(n);
+  hipLaunchKernelGGL(cdot_part_kernel, dim3((unsigned)nch, (unsigned)((ncol + 63) / 64)),
+                     dim3(kThreads), 0, s, V0, n0, V1, n1, ld, w, n, part);
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((ncol + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, part, nch, ncol, h);
+  return hipGetLastError();
+}
+
+hipError_t cgemv_sub(const double2* V0, int n0, const double2* V1, int n1, const double2* P0,
+                     const double2* P1, int64_t ld, const double2* h, int real_h, double2* w,
+                     double2* z, int64_t n, hipStream_t s) {
+  const int ncol = n0 + n1;
+  if (ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL(cgemv_sub_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), (size_t)ncol * sizeof(double2), s, V0, n0, V1, n1, P0, P1, ld,
+                     h, real_h, w, z, n);
+  return hipGetLastError();
+}
+
+hipError_t normalize(double2* w, double2* z, int64_t n, const double2* h1, const double2* h2, int jh,
+                     double* alpha, double* beta, int j, int* flag, double* part, hipStream_t s) {
+  const int64_t nch = nchunks(n);
+  hipLaunchKernelGGL(rdot_part_kernel, dim3((unsigned)nch), dim3(kThreads), 0, s, w, z ? z : w, n,
+                     part);
+  hipLaunchKernelGGL(normalize_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, w, z, n, part, nch, h1, h2, jh, alpha, beta, j, flag);
+  return hipGetLastError();
+}
+
+hipError_t scale_start(double2* w, double2* z, int64_t n, int* flag, double* part, hipStream_t s) {
+  return normalize(w, z, n, nullptr, nullptr, 0, nullptr, nullptr, 0, flag, part, s);
+}
+
+hipError_t dgemm_tn_mfma(int64_t M, int N, int K, const double* A, int64_t lda, const double* B,
+                         int64_t ldb, double* C, int64_t ldc, hipStream_t s) {
+  if (M == 0 || N == 0) return hipSuccess;
+  hipLaunchKernelGGL(dgemm_mfma_kernel, dim3((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64)),
+                     dim3(kThreads), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t colnorms(const double2* V, int ncol, int64_t ld, int64_t n, double* part, double* nrm,
+                    hipStream_t s) {
+  if (ncol == 0) return hipSuccess;
+  const int64_t nch = nchunks(n);
+  hipLaunchKernelGGL(colnorm_part_kernel, dim3((unsigned)nch), dim3(kThreads), 0, s, V, ncol, ld, n,
+                     part);
+  hipLaunchKernelGGL(colsum_real_kernel, dim3((unsigned)((ncol + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, part, nch, ncol, nrm);
+  return hipGetLastError();
+}
+
+hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(start_vector_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, v, n, seed);
+  return hipGetLastError();
+}
+
+hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const double* omega, int k,
+                      int64_t n, double2* X, double2* Y, hipStream_t s) {
+  hipLaunchKernelGGL(ph_vectors_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)k),
+                     dim3(kThreads), 0, s, U, P, ld, omega, n, X, Y);
+  return hipGetLastError();
+}
+
+hipError_t copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int k,
+                     hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)k),
+                     dim3(kThreads), 0, s, src, lds, dst, ldd, n);
+  return hipGetLastError();
+}
+
+hipError_t times_i(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int ncol,
+                   const double* sc, int sqrt_inv, hipStream_t s) {
+  if (ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL(times_i_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)ncol),
+                     dim3(kThreads), 0, s, src, lds, dst, ldd, n, sc, sqrt_inv);
+  return hipGetLastError();
+}
+
+hipError_t conj_copy(const double2* src, double2* dst, int64_t n, double sg, hipStream_t s) {
+  hipLaunchKernelGGL(conj_copy_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, src, dst, n, sg);
+  return hipGetLastError();
+}
+
+hipError_t resid_norms(const double2* out, const double2* v, int cj, double sgn_om, int64_t n,
+                       double* part, double* res, hipStream_t s) {
+  const int64_t nch = nchunks(n);
+  hipLaunchKernelGGL(resid_part_kernel, dim3((unsigned)nch), dim3(kThreads), 0, s, out, v, cj,
+                     sgn_om, n, part);
+  hipLaunchKernelGGL(pair_sum_kernel, dim3(1), dim3(64), 0, s, part, nch, res);
+  return hipGetLastError();
+}
+
+hipError_t grad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
+                       int64_t n, double2* ga, double2* gb, hipStream_t s) {
+  hipLaunchKernelGGL(grad_packed_kernel, dim3((unsigned)n), dim3(kThreads), 0, s, X, Y, ld, wgt, k,
+                     ga, gb);
+  return hipGetLastError();
+}
+
+}  // namespace bse

@@ -1,0 +1,877 @@
+// Host driver and C ABI of the structured BSE eigensolver (include/bse.h).
+//
+// The iteration is a thick-restart Lanczos (Krylov-Schur for a symmetric
+// projected matrix) run entirely on the device; the host only solves the
+// small projected eigenproblem at each restart and takes the decisions.
+//   TDA:  Lanczos on the Hermitian A with complex vectors and CGS2.
+//   PH:   Lanczos on the folded operator K2 K1 (eigenvalues omega^2) in the
+//         K1 inner product <a, b> = Re(a^H K1 b), keeping U and P = K1 U
+//         (the upper-half basis; the lower half is implicit), as in the
+//         structure-preserving solvers of Sec. 2.2.1 of the paper.  Each step
+//         is two passes over the stored triangles (w = K2 p_j, z = K1 w).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "../../include/bse.h"
+#include "bse_internal.h"
+
+struct bse_handle_s {
+  bse_kind kind = BSE_TDA;
+  int64_t n = 0;
+  bse_storage storage = BSE_STORE_C128;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bse::Layout L;
+  void* a = nullptr;
+  void* alo = nullptr;
+  void* b = nullptr;
+  void* blo = nullptr;
+  double2* part = nullptr;  // matvec partials
+  std::string err;
+  // last successful solve
+  bool solved = false;
+  int k = 0;
+  double2* X = nullptr;
+  double2* Y = nullptr;
+  double* omega = nullptr;
+};
+
+namespace {
+
+using bse::Arith;
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+bse_status fail(bse_handle h, bse_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+#define HIP_TRY(h, expr)                                                               \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail((h), e_ == hipErrorOutOfMemory ? BSE_ERR_OUT_OF_MEMORY : BSE_ERR_DEVICE, \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+bse::MatPtrs mat_ptrs(const bse_handle_s* h) {
+  bse::MatPtrs m;
+  m.a = h->a;
+  m.alo = h->alo;
+  m.b = h->b;
+  m.blo = h->blo;
+  return m;
+}
+
+Arith fp64_arith(const bse_handle_s* h) {
+  return h->storage == BSE_STORE_C128 ? bse::AR_C128 : bse::AR_HILO;
+}
+
+double bytes_per_pass(const bse_handle_s* h, Arith ar) {
+  const double e = (ar == bse::AR_HI) ? 8.0 : 16.0;
+  const double tri = e * (double)h->n * (double)(h->n + 1) / 2.0;
+  const int nt = h->kind == BSE_PSEUDO_HERMITIAN ? 2 : 1;
+  return nt * tri + 2.0 * 16.0 * (double)h->n;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+}  // namespace
+
+// ======================================================================
+// Solver state for one bse_solve call.
+// ======================================================================
+namespace {
+
+struct Solver {
+  bse_handle h;
+  bool ph;
+  int64_t n, ld;
+  int k, m, keep;
+  double tol;
+  hipStream_t s;
+  // device buffers
+  DevBuf bufU, bufU2, bufP, bufP2, bufKP, bufKP2, bufY, bufZ, bufH1, bufH2, bufH3, bufPart, bufRed,
+      bufAlpha, bufBeta, bufFlag, bufS, bufNrm, bufW, bufTmp, bufRes, bufTh;
+  double2 *U, *U2, *P, *P2, *KP, *KP2, *Y, *Z, *H1, *H2, *H3, *W, *Tmp;
+  double* th_dev;  // Ritz values of the kept vectors (PH partner scaling)
+  int ny = 0;      // PH: columns of the partner basis Y (Z = K1 Y)
+  double2* cpart;
+  double *red, *alpha, *beta, *S, *nrm, *res;
+  int* flag;
+  // projected matrix state
+  int nka = 0;  // arrow size (kept Ritz vectors)
+  std::vector<double> theta_keep, arrow;
+  // statistics
+  int64_t steps32 = 0, steps64 = 0, passes = 0;
+  int restarts = 0;
+  // sampled block-kernel timing: event pairs recorded around every 8th pass,
+  // read back when the stream is synchronized anyway (restarts, the end)
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, bool>> ev_pending;  // (pair, is_fp32)
+  int64_t samples32 = 0, samples64 = 0;
+  bool trace = false;  // BSE_TRACE=1: one JSON line per restart on stderr
+  double ms_blk32 = 0.0, ms_blk64 = 0.0;
+  ~Solver() {
+    for (auto& p : ev_pending) {
+      ev_free.push_back(p.first.first);
+      ev_free.push_back(p.first.second);
+    }
+    for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
+  }
+};
+
+void harvest_events(Solver& S) {
+  for (auto& p : S.ev_pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p.first.first, p.first.second) == hipSuccess) {
+      if (p.second) {
+        S.ms_blk32 += ms;
+        ++S.samples32;
+      } else {
+        S.ms_blk64 += ms;
+        ++S.samples64;
+      }
+    }
+    S.ev_free.push_back(p.first.first);
+    S.ev_free.push_back(p.first.second);
+  }
+  S.ev_pending.clear();
+}
+
+bse_status alloc_solver(Solver& S) {
+  bse_handle h = S.h;
+  const size_t col = (size_t)S.ld * sizeof(double2);
+  const int ncolmax = 2 * S.m + 4;
+  struct {
+    DevBuf* b;
+    size_t bytes;
+  } req[] = {
+      {&S.bufU, col * (S.m + 1)},
+      {&S.bufU2, col * (S.m + 1)},
+      {&S.bufP, S.ph ? col * (S.m + 1) : 0},
+      {&S.bufP2, S.ph ? col * (S.m + 1) : 0},
+      {&S.bufKP, S.ph ? col * (S.m + 1) : 0},
+      {&S.bufKP2, S.ph ? col * (S.m + 1) : 0},
+      {&S.bufY, S.ph ? col * (S.m + 1) : 0},
+      {&S.bufZ, S.ph ? col * (S.m + 1) : 0},
+      {&S.bufH1, sizeof(double2) * ncolmax},
+      {&S.bufH2, sizeof(double2) * ncolmax},
+      {&S.bufH3, sizeof(double2) * ncolmax},
+      {&S.bufTh, sizeof(double) * (S.m + 1)},
+      {&S.bufPart, sizeof(double2) * (size_t)bse::nchunks(S.n) * ncolmax},
+      {&S.bufRed, sizeof(double) * 2 * ((size_t)bse::nchunks(S.n) + 8)},
+      {&S.bufAlpha, sizeof(double) * (S.m + 1)},
+      {&S.bufBeta, sizeof(double) * (S.m + 1)},
+      {&S.bufFlag, sizeof(int) * 4},
+      {&S.bufS, sizeof(double) * (size_t)S.m * S.m + sizeof(double) * 64},
+      {&S.bufNrm, sizeof(double) * (2 * (size_t)S.m + 8)},
+      {&S.bufW, col * 2},
+      {&S.bufTmp, col * 2},
+      {&S.bufRes, sizeof(double) * 16},
+  };
+  for (auto& r : req) {
+    if (r.bytes == 0) continue;
+    HIP_TRY(h, hipMalloc(&r.b->p, r.bytes));
+  }
+  S.U = (double2*)S.bufU.p;
+  S.U2 = (double2*)S.bufU2.p;
+  S.P = (double2*)S.bufP.p;
+  S.P2 = (double2*)S.bufP2.p;
+  S.KP = (double2*)S.bufKP.p;
+  S.KP2 = (double2*)S.bufKP2.p;
+  S.Y = (double2*)S.bufY.p;
+  S.Z = (double2*)S.bufZ.p;
+  S.H1 = (double2*)S.bufH1.p;
+  S.H2 = (double2*)S.bufH2.p;
+  S.H3 = (double2*)S.bufH3.p;
+  S.th_dev = (double*)S.bufTh.p;
+  S.cpart = (double2*)S.bufPart.p;
+  S.red = (double*)S.bufRed.p;
+  S.alpha = (double*)S.bufAlpha.p;
+  S.beta = (double*)S.bufBeta.p;
+  S.flag = (int*)S.bufFlag.p;
+  S.S = (double*)S.bufS.p;
+  S.nrm = (double*)S.bufNrm.p;
+  S.W = (double2*)S.bufW.p;
+  S.Tmp = (double2*)S.bufTmp.p;
+  S.res = (double*)S.bufRes.p;
+  for (int q = 0; q < 128; ++q) {
+    hipEvent_t e;
+    HIP_TRY(h, hipEventCreate(&e));
+    S.ev_free.push_back(e);
+  }
+  HIP_TRY(h, hipMemsetAsync(S.flag, 0, sizeof(int) * 4, S.s));
+  HIP_TRY(h, hipMemsetAsync(S.U, 0, col * (S.m + 1), S.s));
+  if (S.ph) HIP_TRY(h, hipMemsetAsync(S.P, 0, col * (S.m + 1), S.s));
+  return BSE_OK;
+}
+
+// One pass: out = K(v) for the operator of the current phase.
+bse_status pass(Solver& S, Arith ar, int op /*0: A, 1: K1, 2: K2*/, const double2* v, double2* out) {
+  bse_handle h = S.h;
+  const bse::MatPtrs mp = mat_ptrs(h);
+  bse::MatPtrs mm = mp;
+  if (ar == bse::AR_HI) {
+    mm.alo = nullptr;
+    mm.blo = nullptr;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (S.passes % 8 == 0 && S.ev_free.size() >= 2) {
+    e1 = S.ev_free.back();
+    S.ev_free.pop_back();
+    e0 = S.ev_free.back();
+    S.ev_free.pop_back();
+    S.ev_pending.push_back({{e0, e1}, ar == bse::AR_HI});
+  }
+  hipError_t e;
+  if (op == 0)
+    e = bse::matvec(h->L, ar, bse::BM_NONE, mm, v, 0, nullptr, 0, 0.0, h->part, out, S.s, e0, e1);
+  else
+    e = bse::matvec(h->L, ar, bse::BM_CONJ, mm, v, 0, nullptr, 0, op == 1 ? 1.0 : -1.0, h->part, out,
+                    S.s, e0, e1);
+  HIP_TRY(h, e);
+  ++S.passes;
+  return BSE_OK;
+}
+
+// Start (or phase-switch) vector in column 0, normalized; PH also P[:, 0] = K1 U[:, 0].
+bse_status init_basis(Solver& S, Arith ar) {
+  bse_handle h = S.h;
+  if (S.ph) {
+    bse_status st = pass(S, ar, 1, S.U, S.P);
+    if (st) return st;
+    HIP_TRY(h, bse::scale_start(S.U, S.P, S.n, S.flag, S.red, S.s));
+  } else {
+    HIP_TRY(h, bse::scale_start(S.U, nullptr, S.n, S.flag, S.red, S.s));
+  }
+  S.nka = 0;
+  S.ny = 0;
+  S.theta_keep.clear();
+  S.arrow.clear();
+  return BSE_OK;
+}
+
+// Lanczos step j: new basis column j + 1.
+bse_status step(Solver& S, Arith ar, int j) {
+  bse_handle h = S.h;
+  double2* w = S.U + (size_t)(j + 1) * S.ld;
+  bse_status st;
+  if (!S.ph) {
+    st = pass(S, ar, 0, S.U + (size_t)j * S.ld, w);
+    if (st) return st;
+    for (int it = 0; it < 2; ++it) {
+      double2* hh = it == 0 ? S.H1 : S.H2;
+      HIP_TRY(h, bse::cdot(S.U, j + 1, nullptr, 0, S.ld, w, S.n, S.cpart, hh, S.s));
+      HIP_TRY(h, bse::cgemv_sub(S.U, j + 1, nullptr, 0, nullptr, nullptr, S.ld, hh, 0, w, nullptr,
+                                S.n, S.s));
+    }
+    HIP_TRY(h, bse::normalize(w, nullptr, S.n, S.H1, S.H2, j, S.alpha, S.beta, j, S.flag, S.red, S.s));
+  } else {
+    // Structure: on the real 2N-space every omega^2 of K2 K1 is double, the
+    // second copy of an eigenvector u being its partner i K1 u / omega.  A
+    // Krylov basis is K1-orthogonal to the partners i P of its own vectors
+    // in exact arithmetic; rounding would seed the second copy of converged
+    // pairs.  The partner space is kept explicitly as a K1-orthonormal Y
+    // with Z = K1 Y, using K1(i p) = i K2 p and the K2 p_j every step
+    // computes anyway (KP), and each new vector is K1-orthogonalized against
+    // [U, Y]: no extra pass over the matrix.
+    double2* z = S.P + (size_t)(j + 1) * S.ld;
+    double2* kp = S.KP + (size_t)j * S.ld;
+    st = pass(S, ar, 2, S.P + (size_t)j * S.ld, kp);  // K2 p_j
+    if (st) return st;
+    // partner of column j: y = i p_j, K1 y = i K2 p_j
+    double2* y = S.Y + (size_t)S.ny * S.ld;
+    double2* zy = S.Z + (size_t)S.ny * S.ld;
+    HIP_TRY(h, bse::times_i(S.P + (size_t)j * S.ld, S.ld, y, S.ld, S.n, 1, nullptr, 0, S.s));
+    HIP_TRY(h, bse::times_i(kp, S.ld, zy, S.ld, S.n, 1, nullptr, 0, S.s));
+    HIP_TRY(h, bse::cdot(S.P, j + 1, S.Z, S.ny, S.ld, y, S.n, S.cpart, S.H3, S.s));
+    HIP_TRY(h, bse::cgemv_sub(S.U, j + 1, S.Y, S.ny, S.P, S.Z, S.ld, S.H3, 1, y, zy, S.n, S.s));
+    HIP_TRY(h, bse::scale_start(y, zy, S.n, S.flag, S.red, S.s));
+    ++S.ny;
+    // w = K2 p_j, K1-orthogonalized against [U, Y] (CGS2)
+    HIP_TRY(h, hipMemcpyAsync(w, kp, sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
+    HIP_TRY(h, bse::cdot(S.P, j + 1, S.Z, S.ny, S.ld, w, S.n, S.cpart, S.H1, S.s));
+    HIP_TRY(h, bse::cgemv_sub(S.U, j + 1, S.Y, S.ny, nullptr, nullptr, S.ld, S.H1, 1, w, nullptr, S.n,
+                              S.s));
+    st = pass(S, ar, 1, w, z);  // z = K1 w
+    if (st) return st;
+    HIP_TRY(h, bse::cdot(S.P, j + 1, S.Z, S.ny, S.ld, w, S.n, S.cpart, S.H2, S.s));
+    HIP_TRY(h, bse::cgemv_sub(S.U, j + 1, S.Y, S.ny, S.P, S.Z, S.ld, S.H2, 1, w, z, S.n, S.s));
+    HIP_TRY(h, bse::normalize(w, z, S.n, S.H1, S.H2, j, S.alpha, S.beta, j, S.flag, S.red, S.s));
+  }
+  if (ar == bse::AR_HI)
+    ++S.steps32;
+  else
+    ++S.steps64;
+  return BSE_OK;
+}
+
+bse_status check_flag(Solver& S) {
+  bse_handle h = S.h;
+  int f = 0;
+  HIP_TRY(h, hipMemcpyAsync(&f, S.flag, sizeof(int), hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, hipStreamSynchronize(S.s));
+  harvest_events(S);
+  if (f == 1)
+    return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE,
+                "<w, K1 w> < 0 during the iteration: M is not positive definite");
+  if (f == 2) return fail(h, BSE_ERR_NONFINITE, "non-finite value in the Lanczos iterates");
+  return BSE_OK;
+}
+
+struct RitzInfo {
+  std::vector<double> theta;  // m ascending
+  std::vector<double> est;    // k estimates (relative)
+  double bm = 0.0;
+};
+
+// Restart: eigen-decompose T, rotate the basis to the lowest `keep` Ritz
+// vectors (MFMA GEMM), move the residual vector to column keep, estimate
+// residuals of the k wanted pairs.
+bse_status restart(Solver& S, RitzInfo& R, bool last) {
+  bse_handle h = S.h;
+  const int m = S.m;
+  std::vector<double> al(m), be(m);
+  HIP_TRY(h, hipMemcpyAsync(al.data(), S.alpha, sizeof(double) * m, hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, hipMemcpyAsync(be.data(), S.beta, sizeof(double) * m, hipMemcpyDeviceToHost, S.s));
+  bse_status st = check_flag(S);
+  if (st) return st;
+  std::vector<double> T((size_t)m * m, 0.0), th(m), Z((size_t)m * m);
+  if (S.nka >= m) return fail(h, BSE_ERR_BAD_STATE, "thick restart needs ncv > keep");
+  for (int i = 0; i < S.nka; ++i) {
+    T[(size_t)i * m + i] = S.theta_keep[i];
+    T[(size_t)S.nka * m + i] = S.arrow[i];
+    T[(size_t)i * m + S.nka] = S.arrow[i];
+  }
+  for (int j = S.nka; j < m; ++j) {
+    T[(size_t)j * m + j] = al[j];
+    if (j + 1 < m) {
+      T[(size_t)(j + 1) * m + j] = be[j];
+      T[(size_t)j * m + j + 1] = be[j];
+    }
+  }
+  for (double v : T)
+    if (!std::isfinite(v)) return fail(h, BSE_ERR_NONFINITE, "non-finite projected matrix");
+  if (!bse::sym_eig(m, T.data(), th.data(), Z.data()))
+    return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
+  if (S.trace && S.ph && th[0] <= 0.0)
+    fprintf(stderr, "{\"nonpositive_theta\": [%.6e, %.6e, %.6e], \"beta_last\": %.3e}\n", th[0], th[1 % m],
+            th[2 % m], be[m - 1]);
+  if (S.ph && th[0] <= 0.0)
+    return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE,
+                "non-positive folded Ritz value omega^2: M is not positive definite");
+  const double bm = be[m - 1];
+  const int keep = last ? S.k : S.keep;
+  // U2[:, 0:keep] = U[:, 0:m] Z[:, 0:keep]   (real GEMM on interleaved data)
+  HIP_TRY(h, hipMemcpyAsync(S.S, Z.data(), sizeof(double) * (size_t)m * keep, hipMemcpyHostToDevice,
+                            S.s));
+  HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.U, 2 * S.ld, S.S, m,
+                                (double*)S.U2, 2 * S.ld, S.s));
+  HIP_TRY(h, hipMemcpyAsync(S.U2 + (size_t)keep * S.ld, S.U + (size_t)m * S.ld,
+                            sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
+  std::swap(S.U, S.U2);
+  if (S.ph) {
+    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.P, 2 * S.ld, S.S, m,
+                                  (double*)S.P2, 2 * S.ld, S.s));
+    HIP_TRY(h, hipMemcpyAsync(S.P2 + (size_t)keep * S.ld, S.P + (size_t)m * S.ld,
+                              sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
+    std::swap(S.P, S.P2);
+    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.KP, 2 * S.ld, S.S, m,
+                                  (double*)S.KP2, 2 * S.ld, S.s));
+    std::swap(S.KP, S.KP2);
+    // partners of the kept Ritz vectors, i p~_a / omega_a, are K1-orthonormal
+    // with K1 image i K2 p~_a / omega_a
+    HIP_TRY(h, hipMemcpyAsync(S.th_dev, th.data(), sizeof(double) * keep, hipMemcpyHostToDevice, S.s));
+    HIP_TRY(h, bse::times_i(S.P, S.ld, S.Y, S.ld, S.n, keep, S.th_dev, 1, S.s));
+    HIP_TRY(h, bse::times_i(S.KP, S.ld, S.Z, S.ld, S.n, keep, S.th_dev, 1, S.s));
+    S.ny = keep;
+  }
+  R.theta = th;
+  R.bm = bm;
+  R.est.assign(S.k, 0.0);
+  if (!S.ph) {
+    for (int i = 0; i < S.k; ++i) {
+      const double den = std::max(fabs(th[i]), 1e-300);
+      R.est[i] = fabs(bm * Z[(size_t)i * m + m - 1]) / den;
+    }
+  } else {
+    // ||u~_i||^2, ||p~_i||^2 and ||u_{m+1}||^2 for the relative H residual
+    std::vector<double> nu(S.k + 1), np(S.k);
+    // partials of colnorms: nchunks(n) * k doubles, held in the CGS workspace
+    double* cp = (double*)S.cpart;
+    HIP_TRY(h, bse::colnorms(S.U, S.k, S.ld, S.n, cp, S.nrm, S.s));
+    HIP_TRY(h, bse::colnorms(S.U + (size_t)keep * S.ld, 1, S.ld, S.n, cp, S.nrm + S.k, S.s));
+    HIP_TRY(h, hipMemcpyAsync(nu.data(), S.nrm, sizeof(double) * (S.k + 1), hipMemcpyDeviceToHost,
+                              S.s));
+    HIP_TRY(h, bse::colnorms(S.P, S.k, S.ld, S.n, cp, S.nrm, S.s));
+    HIP_TRY(h, hipMemcpyAsync(np.data(), S.nrm, sizeof(double) * S.k, hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, hipStreamSynchronize(S.s));
+    for (int i = 0; i < S.k; ++i) {
+      const double w = sqrt(std::max(th[i], 1e-300));
+      const double den = w * sqrt(w * w * nu[i] + np[i]);
+      R.est[i] = fabs(bm * Z[(size_t)i * m + m - 1]) * sqrt(nu[S.k]) / std::max(den, 1e-300);
+    }
+  }
+  // next cycle: T = [diag(theta_keep), arrow; arrow^T, .]
+  S.nka = keep;
+  S.theta_keep.assign(th.begin(), th.begin() + keep);
+  S.arrow.resize(keep);
+  for (int i = 0; i < keep; ++i) S.arrow[i] = bm * Z[(size_t)i * m + m - 1];
+  ++S.restarts;
+  return BSE_OK;
+}
+
+// Eigenvalues and vectors of the k wanted pairs from the current basis
+// (columns 0..k-1 after a restart) and their FP64 residuals.
+bse_status finalize(Solver& S, const RitzInfo& R, double* omega, double2* X, double2* Y,
+                    std::vector<double>& rel) {
+  bse_handle h = S.h;
+  std::vector<double> om(S.k);
+  for (int i = 0; i < S.k; ++i) om[i] = S.ph ? sqrt(std::max(R.theta[i], 0.0)) : R.theta[i];
+  HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * S.k, hipMemcpyHostToDevice, S.s));
+  if (S.ph)
+    HIP_TRY(h, bse::ph_vectors(S.U, S.P, S.ld, omega, S.k, S.n, X, Y, S.s));
+  else
+    HIP_TRY(h, bse::copy_cols(S.U, S.ld, X, S.n, S.n, S.k, S.s));
+  const Arith ar = fp64_arith(h);
+  const bse::MatPtrs mp = mat_ptrs(h);
+  rel.assign(S.k, 0.0);
+  std::vector<double> r(4 * S.k);
+  for (int c = 0; c < S.k; ++c) {
+    const double2* xc = X + (size_t)c * S.n;
+    if (!S.ph) {
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_NONE, mp, xc, 0, nullptr, 0, 0.0, h->part, S.W, S.s));
+      HIP_TRY(h, bse::resid_norms(S.W, xc, 0, om[c], S.n, S.red, S.res + 0, S.s));
+      HIP_TRY(h, hipMemcpyAsync(&r[4 * c], S.res, sizeof(double) * 2, hipMemcpyDeviceToHost, S.s));
+      S.passes += 1;
+    } else {
+      const double2* yc = Y + (size_t)c * S.n;
+      // top: A X + B Y - w X
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, xc, 0, yc, 0, 1.0, h->part, S.W, S.s));
+      HIP_TRY(h, bse::resid_norms(S.W, xc, 0, om[c], S.n, S.red, S.res + 0, S.s));
+      // bottom: -conj(A conj(Y) + B conj(X)) - w Y; its norm is ||out + w conj(Y)||
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, yc, 1, xc, 1, 1.0, h->part, S.W, S.s));
+      HIP_TRY(h, bse::resid_norms(S.W, yc, 1, -om[c], S.n, S.red, S.res + 2, S.s));
+      HIP_TRY(h, hipMemcpyAsync(&r[4 * c], S.res, sizeof(double) * 4, hipMemcpyDeviceToHost, S.s));
+      S.passes += 2;
+    }
+  }
+  HIP_TRY(h, hipStreamSynchronize(S.s));
+  for (int c = 0; c < S.k; ++c) {
+    const double rn = S.ph ? r[4 * c] + r[4 * c + 2] : r[4 * c];
+    const double vn = S.ph ? r[4 * c + 1] + r[4 * c + 3] : r[4 * c + 1];
+    rel[c] = sqrt(rn) / (std::max(fabs(om[c]), 1e-300) * sqrt(vn));
+    if (!std::isfinite(rel[c])) return fail(h, BSE_ERR_NONFINITE, "non-finite residual");
+  }
+  return BSE_OK;
+}
+
+// Phase switch / warm start: column 0 <- sum_i c_i U[:, i] over the k wanted Ritz vectors.
+bse_status warm_start_vector(Solver& S) {
+  bse_handle h = S.h;
+  std::vector<double2> wts(S.k);
+  for (int i = 0; i < S.k; ++i) wts[i] = make_double2(-(1.0 + 0.37 * i / S.k), 0.0);
+  HIP_TRY(h, hipMemcpyAsync(S.H1, wts.data(), sizeof(double2) * S.k, hipMemcpyHostToDevice, S.s));
+  HIP_TRY(h, hipMemsetAsync(S.W, 0, sizeof(double2) * S.ld, S.s));
+  HIP_TRY(h, bse::cgemv_sub(S.U, S.k, nullptr, 0, nullptr, nullptr, S.ld, S.H1, 1, S.W, nullptr, S.n,
+                            S.s));
+  HIP_TRY(h, hipMemcpyAsync(S.U, S.W, sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
+  return BSE_OK;
+}
+
+}  // namespace
+
+// ======================================================================
+// C ABI
+// ======================================================================
+extern "C" {
+
+const char* bse_status_string(bse_status s) {
+  switch (s) {
+    case BSE_OK:
+      return "ok";
+    case BSE_ERR_INVALID_ARG:
+      return "invalid argument";
+    case BSE_ERR_OUT_OF_MEMORY:
+      return "out of device memory";
+    case BSE_ERR_DEVICE:
+      return "device error";
+    case BSE_ERR_NOT_POSITIVE_DEFINITE:
+      return "M is not positive definite";
+    case BSE_ERR_NOT_CONVERGED:
+      return "not converged";
+    case BSE_ERR_NONFINITE:
+      return "non-finite value";
+    case BSE_ERR_BAD_STATE:
+      return "bad state";
+  }
+  return "unknown status";
+}
+
+const char* bse_last_error(bse_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+bse_status bse_create(bse_handle* out, bse_kind kind, int64_t n, bse_storage storage,
+                      void* hip_stream) {
+  if (!out) return BSE_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (n < 1 || (kind != BSE_TDA && kind != BSE_PSEUDO_HERMITIAN) ||
+      (storage != BSE_STORE_C128 && storage != BSE_STORE_HILO) || n > (int64_t)1 << 31)
+    return BSE_ERR_INVALID_ARG;
+  bse_handle h = new bse_handle_s();
+  h->kind = kind;
+  h->n = n;
+  h->storage = storage;
+  h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return BSE_ERR_DEVICE;
+  }
+  bse::Layout& L = h->L;
+  L.n = n;
+  L.R = bse::choose_block(n);
+  if (const char* env = getenv("BSE_BLOCK_EDGE")) {  // tuning/testing override
+    const int r = atoi(env);
+    if (r == 64 || r == 128 || r == 256 || r == 512) L.R = r;
+  }
+  L.nb = (int)((n + L.R - 1) / L.R);
+  L.nblk = (int64_t)L.nb * (L.nb + 1) / 2;
+  std::vector<int2> bm((size_t)L.nblk);
+  bse::layout_blkmap_host(L.nb, bm.data());
+  auto cleanup = [&](bse_status s) {
+    bse_destroy(h);
+    return s;
+  };
+  auto alloc = [&](void** p, size_t bytes) -> bool {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return false;
+    return hipMemsetAsync(*p, 0, bytes, h->stream) == hipSuccess;
+  };
+  if (!alloc((void**)&L.blkmap, sizeof(int2) * L.nblk)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
+  if (hipMemcpyAsync(L.blkmap, bm.data(), sizeof(int2) * L.nblk, hipMemcpyHostToDevice, h->stream) !=
+      hipSuccess)
+    return cleanup(BSE_ERR_DEVICE);
+  const size_t el = L.elems();
+  const bool ph = kind == BSE_PSEUDO_HERMITIAN;
+  if (storage == BSE_STORE_C128) {
+    if (!alloc(&h->a, el * 16)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
+    if (ph && !alloc(&h->b, el * 16)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
+  } else {
+    if (!alloc(&h->a, el * 8) || !alloc(&h->alo, el * 8)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
+    if (ph && (!alloc(&h->b, el * 8) || !alloc(&h->blo, el * 8)))
+      return cleanup(BSE_ERR_OUT_OF_MEMORY);
+  }
+  if (!alloc((void**)&h->part, sizeof(double2) * 2 * (size_t)L.nblk * L.R))
+    return cleanup(BSE_ERR_OUT_OF_MEMORY);
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(BSE_ERR_DEVICE);
+  *out = h;
+  return BSE_OK;
+}
+
+bse_status bse_destroy(bse_handle h) {
+  if (!h) return BSE_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  void* ptrs[] = {h->a, h->alo, h->b, h->blo, h->part, h->L.blkmap, h->X, h->Y, h->omega};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete h;
+  return BSE_OK;
+}
+
+bse_status bse_set_packed(bse_handle h, bse_block which, int64_t j0, int64_t j1, const void* src,
+                          bse_dtype dtype) {
+  if (!h) return BSE_ERR_INVALID_ARG;
+  if (which != BSE_BLOCK_A && which != BSE_BLOCK_B)
+    return fail(h, BSE_ERR_INVALID_ARG, "which must be BSE_BLOCK_A or BSE_BLOCK_B");
+  if (which == BSE_BLOCK_B && h->kind == BSE_TDA)
+    return fail(h, BSE_ERR_INVALID_ARG, "a TDA handle has no B block");
+  if (j0 < 0 || j1 > h->n || j0 > j1) return fail(h, BSE_ERR_INVALID_ARG, "column range out of bounds");
+  if (dtype != BSE_C64 && dtype != BSE_C128) return fail(h, BSE_ERR_INVALID_ARG, "bad dtype");
+  if (j1 == j0) return BSE_OK;
+  if (!src) return fail(h, BSE_ERR_INVALID_ARG, "src is NULL");
+  const bool is_a = which == BSE_BLOCK_A;
+  const bool hilo = h->storage == BSE_STORE_HILO;
+  void* dst = is_a ? h->a : h->b;
+  void* dlo = is_a ? h->alo : h->blo;
+  HIP_TRY(h, bse::ingest(h->L, is_a, hilo, src, dtype == BSE_C64, j0, j1, dst, dlo, h->stream));
+  h->solved = false;
+  return BSE_OK;
+}
+
+bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t nvec, const void* x,
+                     void* y) {
+  if (!h) return BSE_ERR_INVALID_ARG;
+  if (nvec < 0 || (nvec > 0 && (!x || !y))) return fail(h, BSE_ERR_INVALID_ARG, "bad vectors");
+  if (op != BSE_OP_A && h->kind == BSE_TDA)
+    return fail(h, BSE_ERR_INVALID_ARG, "K1/K2/H need a pseudo-Hermitian handle");
+  if (op < BSE_OP_A || op > BSE_OP_H) return fail(h, BSE_ERR_INVALID_ARG, "bad op");
+  if (precision == BSE_PREC_MIXED && h->storage != BSE_STORE_HILO)
+    return fail(h, BSE_ERR_INVALID_ARG, "the FP32 operator needs HILO storage");
+  const Arith ar = precision == BSE_PREC_MIXED ? bse::AR_HI : fp64_arith(h);
+  bse::MatPtrs mp = mat_ptrs(h);
+  if (ar == bse::AR_HI) {
+    mp.alo = nullptr;
+    mp.blo = nullptr;
+  }
+  const int64_t n = h->n;
+  const double2* xv = (const double2*)x;
+  double2* yv = (double2*)y;
+  for (int64_t c = 0; c < nvec; ++c) {
+    if (op == BSE_OP_H) {
+      const double2* xt = xv + (size_t)c * 2 * n;
+      const double2* xb = xt + n;
+      double2* yt = yv + (size_t)c * 2 * n;
+      double2* yb = yt + n;
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, xt, 0, xb, 0, 1.0, h->part, yt, h->stream));
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, xb, 1, xt, 1, 1.0, h->part, yb, h->stream));
+      HIP_TRY(h, bse::conj_copy(yb, yb, n, -1.0, h->stream));
+    } else {
+      const double2* xc = xv + (size_t)c * n;
+      double2* yc = yv + (size_t)c * n;
+      const bse::BMode bm = op == BSE_OP_A ? bse::BM_NONE : bse::BM_CONJ;
+      const double sb = op == BSE_OP_K2 ? -1.0 : 1.0;
+      HIP_TRY(h, bse::matvec(h->L, ar, bm, mp, xc, 0, nullptr, 0, sb, h->part, yc, h->stream));
+    }
+  }
+  return BSE_OK;
+}
+
+bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* opts, double* omega,
+                     void* x, void* y, bse_stats* stats) {
+  if (!h) return BSE_ERR_INVALID_ARG;
+  const double t0 = now_ms();
+  const bool ph = h->kind == BSE_PSEUDO_HERMITIAN;
+  if (k < 1 || k > h->n) return fail(h, BSE_ERR_INVALID_ARG, "k must be in [1, N]");
+  if (!(tol > 0.0)) return fail(h, BSE_ERR_INVALID_ARG, "tol must be positive");
+  if (!omega || !x) return fail(h, BSE_ERR_INVALID_ARG, "omega and x are required");
+  if (ph && !y) return fail(h, BSE_ERR_INVALID_ARG, "y is required for the pseudo-Hermitian problem");
+  if (!ph && y) return fail(h, BSE_ERR_INVALID_ARG, "y must be NULL for TDA");
+  bse_solve_opts o{};
+  if (opts) o = *opts;
+  if (o.precision != BSE_PREC_FP64 && o.precision != BSE_PREC_MIXED)
+    return fail(h, BSE_ERR_INVALID_ARG, "bad precision");
+  const bool mixed = o.precision == BSE_PREC_MIXED;
+  if (mixed && h->storage != BSE_STORE_HILO)
+    return fail(h, BSE_ERR_INVALID_ARG, "mixed precision needs HILO storage");
+  const int64_t n = h->n;
+  int m = o.ncv > 0 ? o.ncv : (int)round_up(std::max(2 * k, k + 32), 16);
+  m = (int)std::min<int64_t>(m, n);
+  if (m < k) return fail(h, BSE_ERR_INVALID_ARG, "ncv must be at least k");
+  int keep = o.keep > 0 ? o.keep : k + (m - k) / 2;
+  keep = std::max(keep, k);
+  if (keep >= m) keep = (m > k) ? m - 1 : m;
+  const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 400;
+  const double switch_tol = o.switch_tol > 0 ? o.switch_tol : 1e-6;
+  const uint64_t seed = o.start_seed ? o.start_seed : 1;
+  h->solved = false;
+
+  Solver S;
+  S.h = h;
+  S.ph = ph;
+  S.n = n;
+  S.ld = round_up(n, 64);
+  S.k = k;
+  S.m = m;
+  S.keep = keep;
+  S.tol = tol;
+  S.s = h->stream;
+  if (const char* tr = getenv("BSE_TRACE")) S.trace = tr[0] == '1';
+  bse_status st = alloc_solver(S);
+  if (st) return st;
+
+  Arith ar = mixed ? bse::AR_HI : fp64_arith(h);
+  double tol_int = mixed ? std::max(switch_tol, tol) : tol;
+  double t_phase = now_ms(), ms32 = 0.0, ms64 = 0.0;
+  HIP_TRY(h, bse::start_vector(S.U, n, seed, S.s));
+  st = init_basis(S, ar);
+  if (st) return st;
+  int jstart = 0;
+  RitzInfo R;
+  std::vector<double> rel;
+  bool converged = false;
+  double max_rel = INFINITY;
+  int nconv_final = 0;
+  double ms_final = 0.0;
+  for (int cyc = 0; cyc < max_restarts; ++cyc) {
+    for (int j = jstart; j < m; ++j) {
+      st = step(S, ar, j);
+      if (st) return st;
+    }
+    st = restart(S, R, false);
+    if (st) return st;
+    jstart = S.keep;
+    const bool full_space = S.keep >= m;
+    bool all = true;
+    for (int i = 0; i < k; ++i) all = all && (R.est[i] <= tol_int);
+    if (S.trace) {
+      double emax = 0.0;
+      int nc = 0;
+      for (int i = 0; i < k; ++i) {
+        emax = std::max(emax, R.est[i]);
+        nc += R.est[i] <= tol_int;
+      }
+      fprintf(stderr,
+              "{\"restart\": %d, \"fp32\": %d, \"steps\": %lld, \"theta0\": %.10g, \"theta_k\": %.10g, "
+              "\"est0\": %.3e, \"est_max\": %.3e, \"nconv\": %d, \"tol_int\": %.1e}\n",
+              S.restarts, ar == bse::AR_HI ? 1 : 0, (long long)(S.steps32 + S.steps64), R.theta[0],
+              R.theta[k - 1], R.est[0], emax, nc, tol_int);
+    }
+    if (!all && !full_space) continue;
+    if (ar == bse::AR_HI) {
+      // FP32 phase done: warm start of the FP64 phase from the wanted Ritz vectors
+      HIP_TRY(h, hipStreamSynchronize(S.s));
+      ms32 += now_ms() - t_phase;
+      t_phase = now_ms();
+      ar = fp64_arith(h);
+      tol_int = tol;
+      st = warm_start_vector(S);
+      if (st) return st;
+      st = init_basis(S, ar);
+      if (st) return st;
+      jstart = 0;
+      continue;
+    }
+    // verify with FP64 residuals
+    const double tf = now_ms();
+    st = finalize(S, R, omega, (double2*)x, (double2*)y, rel);
+    if (st) return st;
+    ms_final += now_ms() - tf;
+    max_rel = 0.0;
+    nconv_final = 0;
+    for (double r : rel) {
+      max_rel = std::max(max_rel, r);
+      nconv_final += (r <= tol);
+    }
+    if (S.trace) fprintf(stderr, "{\"verify\": %d, \"max_rel\": %.3e, \"nconv\": %d}\n", S.restarts, max_rel, nconv_final);
+    if (max_rel <= tol) {
+      converged = true;
+      break;
+    }
+    // The basis already spans the whole space (m == N): nothing left to add.
+    if (S.keep >= m) break;
+    tol_int *= 0.1;  // the estimates were optimistic: tighten and continue
+  }
+  HIP_TRY(h, hipStreamSynchronize(S.s));
+  ms64 += (ar == bse::AR_HI) ? 0.0 : now_ms() - t_phase;
+  if (ar == bse::AR_HI) ms32 += now_ms() - t_phase;
+  if (!converged) {
+    // best approximations from the current basis
+    if (rel.empty()) {
+      const double tf = now_ms();
+      st = finalize(S, R, omega, (double2*)x, (double2*)y, rel);
+      if (st) return st;
+      ms_final += now_ms() - tf;
+      max_rel = 0.0;
+      nconv_final = 0;
+      for (double r : rel) {
+        max_rel = std::max(max_rel, r);
+        nconv_final += (r <= tol);
+      }
+    }
+  }
+  harvest_events(S);
+  if (stats) {
+    stats->n_converged = nconv_final;
+    stats->restarts = S.restarts;
+    stats->steps_fp32 = S.steps32;
+    stats->steps_fp64 = S.steps64;
+    stats->passes = S.passes;
+    stats->ms_total = now_ms() - t0;
+    stats->ms_fp32_phase = ms32;
+    stats->ms_fp64_phase = ms64 - ms_final;
+    stats->ms_final = ms_final;
+    stats->max_rel_residual = max_rel;
+    stats->bytes_per_pass_fp32 = mixed ? bytes_per_pass(h, bse::AR_HI) : 0.0;
+    stats->bytes_per_pass_fp64 = bytes_per_pass(h, fp64_arith(h));
+    stats->samples_fp32 = S.samples32;
+    stats->samples_fp64 = S.samples64;
+    stats->ms_block_fp32 = S.ms_blk32;
+    stats->ms_block_fp64 = S.ms_blk64;
+  }
+  if (!converged)
+    return fail(h, BSE_ERR_NOT_CONVERGED, "max_restarts reached before all pairs met tol");
+  // keep the eigenvectors for bse_backward / bse_strength
+  void* ptrs[] = {h->X, h->Y, h->omega};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  h->X = h->Y = nullptr;
+  h->omega = nullptr;
+  HIP_TRY(h, hipMalloc((void**)&h->X, sizeof(double2) * (size_t)n * k));
+  HIP_TRY(h, hipMemcpyAsync(h->X, x, sizeof(double2) * (size_t)n * k, hipMemcpyDeviceToDevice, S.s));
+  if (ph) {
+    HIP_TRY(h, hipMalloc((void**)&h->Y, sizeof(double2) * (size_t)n * k));
+    HIP_TRY(h, hipMemcpyAsync(h->Y, y, sizeof(double2) * (size_t)n * k, hipMemcpyDeviceToDevice, S.s));
+  }
+  HIP_TRY(h, hipMalloc((void**)&h->omega, sizeof(double) * k));
+  HIP_TRY(h, hipMemcpyAsync(h->omega, omega, sizeof(double) * k, hipMemcpyDeviceToDevice, S.s));
+  HIP_TRY(h, hipStreamSynchronize(S.s));
+  h->k = k;
+  h->solved = true;
+  return BSE_OK;
+}
+
+bse_status bse_backward(bse_handle h, const double* g, void* d_a, void* d_b) {
+  if (!h) return BSE_ERR_INVALID_ARG;
+  if (!h->solved) return fail(h, BSE_ERR_BAD_STATE, "bse_backward needs a successful bse_solve");
+  if (!g) return fail(h, BSE_ERR_INVALID_ARG, "g is NULL");
+  const bool ph = h->kind == BSE_PSEUDO_HERMITIAN;
+  if (!ph && d_b) return fail(h, BSE_ERR_INVALID_ARG, "d_b must be NULL for TDA");
+  if (!d_a && !d_b) return BSE_OK;
+  const int k = h->k;
+  const int64_t n = h->n;
+  DevBuf wgt, red, nx, ny;
+  HIP_TRY(h, hipMalloc(&wgt.p, sizeof(double) * k));
+  std::vector<double> gh(k), w(k, 1.0);
+  HIP_TRY(h, hipMemcpyAsync(gh.data(), g, sizeof(double) * k, hipMemcpyDeviceToHost, h->stream));
+  if (ph) {
+    HIP_TRY(h, hipMalloc(&red.p, sizeof(double) * (size_t)bse::nchunks(n) * k));
+    HIP_TRY(h, hipMalloc(&nx.p, sizeof(double) * k));
+    HIP_TRY(h, hipMalloc(&ny.p, sizeof(double) * k));
+    HIP_TRY(h, bse::colnorms(h->X, k, n, n, (double*)red.p, (double*)nx.p, h->stream));
+    HIP_TRY(h, bse::colnorms(h->Y, k, n, n, (double*)red.p, (double*)ny.p, h->stream));
+    std::vector<double> a(k), b(k);
+    HIP_TRY(h, hipMemcpyAsync(a.data(), nx.p, sizeof(double) * k, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(b.data(), ny.p, sizeof(double) * k, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (int c = 0; c < k; ++c) w[c] = 1.0 / (a[c] - b[c]);
+  } else {
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+  }
+  for (int c = 0; c < k; ++c) w[c] *= gh[c];
+  HIP_TRY(h, hipMemcpyAsync(wgt.p, w.data(), sizeof(double) * k, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, bse::grad_packed(h->X, ph ? h->Y : nullptr, n, (const double*)wgt.p, k, n,
+                              (double2*)d_a, (double2*)d_b, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return BSE_OK;
+}
+
+bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse_component* comps,
+                        double* out) {
+  if (!h) return BSE_ERR_INVALID_ARG;
+  (void)g;
+  (void)n_comp;
+  (void)comps;
+  (void)out;
+  return fail(h, BSE_ERR_INVALID_ARG, "bse_strength: not available in this build");
+}
+
+}  // extern "C"

@@ -58,7 +58,7 @@ int synd_create(const syn_params* p, const double* eps, const double* xr, const 
   const double** dst[7] = {&g->t.eps, &g->t.xr, &g->t.xi, &g->t.yr, &g->t.yi, &g->t.amp, &g->t.cs};
   for (int q = 0; q < 7; ++q) {
     if (hipMemcpy(d, src[q], cnt[q] * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-      hipFree(g->buf);
+      (void)hipFree(g->buf);
       delete g;
       return 3;
     }
@@ -84,7 +84,7 @@ int synd_pack(void* h, int32_t which, int64_t j0, int64_t j1, void* out, void* s
 int synd_destroy(void* h) {
   DevGen* g = static_cast<DevGen*>(h);
   if (!g) return 0;
-  hipFree(g->buf);
+  (void)hipFree(g->buf);
   delete g;
   return 0;
 }

@@ -1,0 +1,382 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Kernel level: every operator of a pass (A, K1, K2, H) in every storage
+(complex128, FP32 hi, FP64 hi+lo) and block edge, element by element against
+the dense FP64 definition.  Solver level: eigenvalues within the stated
+relative tolerance of the oracle's, FP64 residuals, eigenvector agreement up to
+phase, and the degenerate/edge cases of the method.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2504_10096_amd as bse
+import synth
+from conftest import pack_upper, random_herm, random_sym
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make_solver(kind, ap, bp=None, storage="c128", block=None, monkeypatch=None):
+    n = int(round(((8 * len(ap) + 1) ** 0.5 - 1) / 2))
+    if block is not None:
+        monkeypatch.setenv("BSE_BLOCK_EDGE", str(block))
+    s = bse.Solver(kind, n, storage=storage)
+    if block is not None:
+        monkeypatch.delenv("BSE_BLOCK_EDGE")
+    s.set_packed("A", dev(ap))
+    if bp is not None:
+        s.set_packed("B", dev(bp))
+    return s
+
+
+def phase_align(x, ref):
+    """Overlap |<ref, x>| per column (1 for equal vectors up to phase)."""
+    return np.abs(np.sum(np.conj(ref) * x, axis=0)) / (np.linalg.norm(ref, axis=0) * np.linalg.norm(x, axis=0))
+
+
+# ----------------------------------------------------------------- kernel level
+@pytest.mark.parametrize("block", [64, 128, 256, 512])
+@pytest.mark.parametrize("storage", ["c128", "hilo"])
+def test_matvec_parity(block, storage, monkeypatch):
+    n = 1000  # ragged: not a multiple of any block edge
+    print(f"matvec parity n={n} block={block} storage={storage}", flush=True)
+    rng = np.random.default_rng(7)
+    A, B = random_herm(rng, n), random_sym(rng, n, 0.5)
+    ap, bp = pack_upper(A), pack_upper(B)
+    s = make_solver("ph", ap, bp, storage, block, monkeypatch)
+    x = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
+    xh = rng.standard_normal((2, 2 * n)) + 1j * rng.standard_normal((2, 2 * n))
+    precs = ["fp64"] + (["fp32"] if storage == "hilo" else [])
+    for prec in precs:
+        tol = 1e-13 if prec == "fp64" else 2e-6
+        for op in ["A", "K1", "K2", "H"]:
+            xin = xh if op == "H" else x
+            got = host(s.apply(op, dev(xin), precision=prec))
+            ref = oracle.apply_dense(op, ap, xin, bp)
+            err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+            assert err < tol, (op, prec, err)
+    s.close()
+
+
+def test_matvec_tda_handle_and_c64_input(monkeypatch):
+    n = 333
+    rng = np.random.default_rng(3)
+    A = random_herm(rng, n)
+    ap = pack_upper(A).astype(np.complex64)
+    s = bse.Solver("tda", n, storage="hilo")
+    s.set_packed("A", dev(ap))
+    x = rng.standard_normal((2, n)) + 1j * rng.standard_normal((2, n))
+    ref = oracle.apply_dense("A", ap.astype(np.complex128), x)
+    for prec in ["fp64", "fp32"]:
+        got = host(s.apply("A", dev(x), precision=prec))
+        assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < (1e-13 if prec == "fp64" else 2e-6)
+    with pytest.raises(bse.BSEError):
+        s.apply("K1", dev(x))
+    s.close()
+
+
+def test_chunked_ingest_equals_whole():
+    n = 700
+    m = synth.Matrix(n, 21, ph=True)
+    ap, bp = m.pack_host(0), m.pack_host(1)
+    s1 = make_solver("ph", ap, bp)
+    s2 = bse.Solver("ph", n)
+    for j0, j1 in [(0, 100), (100, 513), (513, 700)]:
+        s2.set_packed("A", dev(m.pack_host(0, j0, j1)), j0, j1)
+        s2.set_packed("B", dev(m.pack_host(1, j0, j1)), j0, j1)
+    x = dev(synth.test_vectors(5, n, 2).T.copy())
+    assert torch.equal(s1.apply("K2", x), s2.apply("K2", x))
+
+
+# ----------------------------------------------------------------- solver level
+def check_tda(s, ap, k, tol, lam_tol):
+    lam, X, _, st = s.solve(k, tol)
+    lam, X = host(lam), host(X).T
+    ref, V = oracle.tda(ap, k)
+    assert np.max(np.abs(lam - ref) / np.maximum(np.abs(ref), 1e-300)) < lam_tol, (lam, ref)
+    rel = oracle.residual_tda(ap, lam, X)
+    assert rel.max() <= tol * 1.01, rel
+    gaps = np.diff(np.concatenate([ref, [np.inf]]))
+    sep = (gaps > 1e-6) & (np.concatenate([[np.inf], gaps[:-1]]) > 1e-6)
+    assert np.all(phase_align(X, V)[sep] > 1 - 1e-6)
+    return st
+
+
+def check_ph(s, ap, bp, k, tol, om_tol):
+    om, X, Y, st = s.solve(k, tol)
+    om, X, Y = host(om), host(X).T, host(Y).T
+    ref, Xr, Yr = oracle.ph(ap, bp, k)
+    assert np.max(np.abs(om - ref) / ref) < om_tol, (om, ref)
+    rel = oracle.residual_ph(ap, bp, om, X, Y)
+    assert rel.max() <= tol * 1.01, rel
+    nrm = np.sum(np.abs(X) ** 2, axis=0) - np.sum(np.abs(Y) ** 2, axis=0)
+    assert np.max(np.abs(nrm - 1)) < 1e-8
+    gaps = np.diff(np.concatenate([ref, [np.inf]]))
+    sep = (gaps > 1e-6 * ref) & (np.concatenate([[np.inf], gaps[:-1]]) > 1e-6 * ref)
+    v, vr = np.vstack([X, Y]), np.vstack([Xr, Yr])
+    assert np.all(phase_align(v, vr)[sep] > 1 - 1e-6)
+    return st
+
+
+@pytest.mark.parametrize("n,k", [(300, 8), (1000, 12)])
+def test_solve_tda_synth(n, k):
+    print(f"tda synth n={n} k={k}", flush=True)
+    m = synth.Matrix(n, 100 + n, ph=False)
+    ap = m.pack_host(0)
+    s = make_solver("tda", ap)
+    check_tda(s, ap, k, 1e-10, 1e-10)
+    s.close()
+
+
+@pytest.mark.parametrize("n,k", [(300, 8), (900, 10)])
+def test_solve_ph_synth(n, k):
+    print(f"ph synth n={n} k={k}", flush=True)
+    m = synth.Matrix(n, 200 + n, ph=True)
+    ap, bp = m.pack_host(0), m.pack_host(1)
+    s = make_solver("ph", ap, bp)
+    check_ph(s, ap, bp, k, 1e-10, 1e-10)
+    s.close()
+
+
+@pytest.mark.parametrize("n,k", [(200, 6), (640, 10)])
+def test_solve_ph_strong_coupling(n, k):
+    """Generic dense blocks with ||B||_2 = 0.6 lambda_min(A): large Y components."""
+    print(f"ph strong n={n} k={k}", flush=True)
+    rng = np.random.default_rng(n)
+    A, B = random_herm(rng, n, lam_min=1.0), random_sym(rng, n, 0.6)
+    ap, bp = pack_upper(A), pack_upper(B)
+    s = make_solver("ph", ap, bp)
+    check_ph(s, ap, bp, k, 1e-10, 1e-10)
+    s.close()
+
+
+def test_workload_tda_n1024_k16():
+    """The N = 1024, k = 16, tol 1e-10 TDA workload at full size."""
+    w = synth.WORKLOADS[0]
+    m = synth.workload_matrix(0)
+    ap = m.pack_host(0)
+    s = make_solver("tda", ap)
+    st = check_tda(s, ap, w["k"], w["tol"], 1e-10)
+    print("stats", st, flush=True)
+    s.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 17])
+def test_tiny_sizes(n):
+    rng = np.random.default_rng(50 + n)
+    A, B = random_herm(rng, n, lam_min=1.0), random_sym(rng, n, 0.5)
+    ap, bp = pack_upper(A), pack_upper(B)
+    k = max(1, n // 2)
+    s = make_solver("tda", ap)
+    check_tda(s, ap, k, 1e-10, 1e-10)
+    s.close()
+    s = make_solver("ph", ap, bp)
+    check_ph(s, ap, bp, k, 1e-10, 1e-10)
+    s.close()
+
+
+def test_all_pairs_k_equals_n():
+    n = 24
+    rng = np.random.default_rng(9)
+    A, B = random_herm(rng, n, lam_min=1.0), random_sym(rng, n, 0.5)
+    s = make_solver("ph", pack_upper(A), pack_upper(B))
+    check_ph(s, pack_upper(A), pack_upper(B), n, 1e-10, 1e-10)
+    s.close()
+
+
+def test_real_blocks_no_duplicate_pairs():
+    n, k = 150, 10
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal((n, n))
+    A = (g + g.T) / 2
+    A += (1 - np.linalg.eigvalsh(A)[0]) * np.eye(n)
+    c = rng.standard_normal((n, n))
+    B = (c + c.T) * (0.5 / np.linalg.norm(c + c.T, 2))
+    ap, bp = pack_upper(A.astype(complex)), pack_upper(B.astype(complex))
+    s = make_solver("ph", ap, bp)
+    check_ph(s, ap, bp, k, 1e-10, 1e-10)
+    s.close()
+
+
+def test_b_zero_reduces_to_tda():
+    n, k = 200, 8
+    m = synth.Matrix(n, 77, ph=True)
+    ap = m.pack_host(0)
+    bp = np.zeros_like(ap)
+    s = make_solver("ph", ap, bp)
+    om, X, Y, _ = s.solve(k, 1e-10)
+    ref, _ = oracle.tda(ap, k, vectors=False)
+    assert np.max(np.abs(host(om) - ref) / ref) < 1e-10
+    assert np.max(np.abs(host(Y))) < 1e-8
+    s.close()
+
+
+def test_not_positive_definite():
+    n = 60
+    A = np.diag(np.arange(1.0, n + 1)).astype(complex)
+    B = np.zeros((n, n), dtype=complex)
+    B[0, 0] = 1.6
+    s = make_solver("ph", pack_upper(A), pack_upper(B))
+    with pytest.raises(bse.NotPositiveDefinite):
+        s.solve(4, 1e-10)
+    s.close()
+
+
+def test_invalid_arguments():
+    n = 50
+    ap = pack_upper(random_herm(np.random.default_rng(1), n))
+    s = make_solver("tda", ap)
+    for bad in [dict(k=0, tol=1e-8), dict(k=n + 1, tol=1e-8), dict(k=4, tol=0.0), dict(k=4, tol=-1.0)]:
+        with pytest.raises(bse.BSEError) as e:
+            s.solve(**bad)
+        assert e.value.status == bse.ERR_INVALID_ARG
+    with pytest.raises(bse.BSEError):
+        s.set_packed("B", dev(ap))
+    with pytest.raises(bse.BSEError) as e:
+        s.solve(4, 1e-8, precision="mixed")
+    assert e.value.status == bse.ERR_INVALID_ARG
+    with pytest.raises(bse.BSEError) as e:
+        s.backward(torch.ones(4, dtype=torch.float64, device=DEV))
+    assert e.value.status == bse.ERR_BAD_STATE
+    s.close()
+
+
+def test_not_converged_returns_best():
+    m = synth.Matrix(800, 5, ph=False)
+    ap = m.pack_host(0)
+    s = make_solver("tda", ap)
+    lam, X, _, st = s.solve(16, 1e-12, max_restarts=1, raise_not_converged=False)
+    assert st["restarts"] == 1
+    assert st["n_converged"] < 16 or st["max_rel_residual"] <= 1e-12
+    with pytest.raises(bse.NotConverged):
+        s.solve(16, 1e-12, max_restarts=1)
+    s.close()
+
+
+def test_nonfinite_input():
+    n = 40
+    A = random_herm(np.random.default_rng(2), n)
+    A[3, 5] = np.nan
+    A[5, 3] = np.nan
+    s = make_solver("tda", pack_upper(A))
+    with pytest.raises(bse.BSEError) as e:
+        s.solve(4, 1e-8)
+    assert e.value.status == bse.ERR_NONFINITE
+    s.close()
+
+
+def test_deterministic_bitwise():
+    m = synth.Matrix(600, 8, ph=True)
+    ap, bp = m.pack_host(0), m.pack_host(1)
+    s = make_solver("ph", ap, bp)
+    a = s.solve(6, 1e-10)
+    b = s.solve(6, 1e-10)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+    s.close()
+
+
+# ------------------------------------------------------------------ mixed path
+def test_mixed_tda_matches_oracle():
+    n, k = 1500, 12
+    m = synth.Matrix(n, 31, ph=False)
+    ap = m.pack_host(0)
+    s = make_solver("tda", ap, storage="hilo")
+    lam, X, _, st = s.solve(k, 1e-8, precision="mixed")
+    ref, _ = oracle.tda(ap, k, vectors=False)
+    assert np.max(np.abs(host(lam) - ref) / np.abs(ref)) < 1e-8
+    assert oracle.residual_tda(ap, host(lam), host(X).T).max() <= 1e-8 * 1.01
+    assert st["steps_fp32"] > 0
+    print("mixed tda stats", st, flush=True)
+    s.close()
+
+
+def test_mixed_ph_matches_oracle():
+    n, k = 900, 10
+    m = synth.Matrix(n, 32, ph=True)
+    ap, bp = m.pack_host(0), m.pack_host(1)
+    s = make_solver("ph", ap, bp, storage="hilo")
+    om, X, Y, st = s.solve(k, 1e-8, precision="mixed")
+    ref, _, _ = oracle.ph(ap, bp, k, vectors=False)
+    assert np.max(np.abs(host(om) - ref) / ref) < 1e-8
+    assert oracle.residual_ph(ap, bp, host(om), host(X).T, host(Y).T).max() <= 1e-8 * 1.01
+    assert st["steps_fp32"] > 0
+    print("mixed ph stats", st, flush=True)
+    s.close()
+
+
+# -------------------------------------------------------------------- adjoint
+def test_backward_tda_parity():
+    n, k = 250, 6
+    m = synth.Matrix(n, 41, ph=False)
+    ap = m.pack_host(0)
+    s = make_solver("tda", ap)
+    lam, X, _, _ = s.solve(k, 1e-12)
+    g = synth.loss_weights(41, k)
+    ga, _ = s.backward(torch.as_tensor(g))
+    ref = oracle.grad_tda(host(X).T, g)
+    assert np.max(np.abs(host(ga) - ref)) < 1e-12 * np.max(np.abs(ref))
+    s.close()
+
+
+def test_backward_ph_parity():
+    n, k = 250, 6
+    rng = np.random.default_rng(11)
+    A, B = random_herm(rng, n), random_sym(rng, n, 0.6)
+    ap, bp = pack_upper(A), pack_upper(B)
+    s = make_solver("ph", ap, bp)
+    om, X, Y, _ = s.solve(k, 1e-12)
+    g = synth.loss_weights(42, k)
+    ga, gb = s.backward(torch.as_tensor(g))
+    # same vectors through the oracle's gradient formula
+    ra, rb = oracle.grad_ph(host(X).T, host(Y).T, g)
+    assert np.max(np.abs(host(ga) - ra)) < 1e-12 * np.max(np.abs(ra))
+    assert np.max(np.abs(host(gb) - rb)) < 1e-12 * np.max(np.abs(rb))
+    # and the oracle's own vectors give the same gradient (vectors are unique up to phase)
+    _, Xo, Yo = oracle.ph(ap, bp, k)
+    oa, ob = oracle.grad_ph(Xo, Yo, g)
+    assert np.max(np.abs(host(ga) - oa)) < 1e-8 * np.max(np.abs(oa))
+    assert np.max(np.abs(host(gb) - ob)) < 1e-8 * np.max(np.abs(ob))
+    s.close()
+
+
+def test_autograd_function():
+    n, k = 120, 4
+    rng = np.random.default_rng(12)
+    A, B = random_herm(rng, n), random_sym(rng, n, 0.5)
+    ap = dev(pack_upper(A)).requires_grad_(True)
+    bp = dev(pack_upper(B)).requires_grad_(True)
+    om, X, Y = bse.BSEEigs.apply(ap, bp, k, 1e-12)
+    w = torch.linspace(0.5, 1.0, k, dtype=torch.float64, device=DEV)
+    (om * w).sum().backward()
+    _, Xo, Yo = oracle.ph(pack_upper(A), pack_upper(B), k)
+    oa, ob = oracle.grad_ph(Xo, Yo, host(w))
+    assert np.max(np.abs(host(ap.grad) - oa)) < 1e-8 * np.max(np.abs(oa))
+    assert np.max(np.abs(host(bp.grad) - ob)) < 1e-8 * np.max(np.abs(ob))
+
+
+# ------------------------------------------------------------ input generator
+def test_device_generator_bitwise():
+    n = 1024
+    m = synth.Matrix(n, 10096, ph=True)
+    g = synth.DeviceGen(m)
+    for which in (0, 1):
+        for j0, j1 in [(0, n), (300, 777)]:
+            cnt = j1 * (j1 + 1) // 2 - j0 * (j0 + 1) // 2
+            out = torch.empty(cnt, dtype=torch.complex128, device=DEV)
+            g.pack(which, j0, j1, out.data_ptr(), torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            ref = m.pack_host(which, j0, j1)
+            assert np.array_equal(host(out).view(np.uint64), ref.view(np.uint64)), (which, j0, j1)
+    g.close()
