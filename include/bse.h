@@ -111,7 +111,8 @@ typedef struct {
  * L = sum_c g_c omega_c with respect to the block C belongs to. */
 typedef enum {
   BSE_COMP_PACKED = 0,  /* data: device LAPACK-'U' packed complex128 (Hermitian for A, symmetric for B) */
-  BSE_COMP_LOWRANK = 1, /* data: device N x rank complex128, row-major F; C = scale F F^H (A) or scale F F^T (B) */
+  BSE_COMP_LOWRANK = 1, /* data: device N x rank complex128 F, column-major (column t at t*N);
+                           C = scale F F^H (A) or scale F F^T (B) */
   BSE_COMP_DIAG = 2,    /* data: device N doubles; C = scale diag(d) (A only) */
   BSE_COMP_STORED = 3   /* the stored block itself in FP64 (C = scale A or scale B); data unused */
 } bse_comp_form;

@@ -230,6 +230,35 @@ class Solver:
         return da, db
 
 
+    def strength(self, g, comps):
+        """Scalars Re<G, C_q> of L = sum_c g_c omega_c for components given as
+        (target 'A'|'B', form 'packed'|'lowrank'|'diag'|'stored', data tensor or None, scale).
+        packed: LAPACK-'U' complex128; lowrank: N x r complex128 factor F (C = s F F^H for A,
+        s F F^T for B); diag: N float64 (A only); stored: the stored block itself."""
+        g = g.to(device=self.device, dtype=torch.float64).contiguous()
+        forms = {"packed": COMP_PACKED, "lowrank": COMP_LOWRANK, "diag": COMP_DIAG, "stored": COMP_STORED}
+        arr = (Component * len(comps))()
+        keep = []
+        for q, (target, form, data, scale) in enumerate(comps):
+            rank = 0
+            ptr = None
+            if data is not None:
+                if form == "lowrank":
+                    data = data.to(self.device, torch.complex128).t().contiguous()  # column-major N x r
+                    rank = data.shape[0]
+                elif form == "diag":
+                    data = data.to(self.device, torch.float64).contiguous()
+                else:
+                    data = data.to(self.device, torch.complex128).contiguous()
+                keep.append(data)
+                ptr = data.data_ptr()
+            arr[q] = Component({"A": BLOCK_A, "B": BLOCK_B}[target], forms[form], ptr, rank, float(scale))
+        out = (ctypes.c_double * len(comps))()
+        with torch.cuda.device(self.device):
+            self._check(load_library().bse_strength(self._h, _dev_ptr(g), len(comps), arr, out), "bse_strength")
+        return [float(v) for v in out]
+
+
 def from_packed(ap, bp=None, storage="c128"):
     """A Solver filled from device packed triangles (B given => pseudo-Hermitian)."""
     n = int(round(((8 * ap.numel() + 1) ** 0.5 - 1) / 2))

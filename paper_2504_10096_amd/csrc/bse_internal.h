@@ -95,6 +95,10 @@ hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const doub
 hipError_t copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int k,
                      hipStream_t s);
 
+// R[:, c] = W[:, c] - th[c] V[:, c] for ncol columns (leading dimension ld).
+hipError_t resid_cols(const double2* W, const double2* V, const double* th, int64_t ld, int64_t n,
+                      int ncol, double2* R, hipStream_t s);
+
 // dst[:, c] = i f_c src[:, c] for ncol columns; f_c = 1 (sc == nullptr),
 // sc[c], or 1 / sqrt(sc[c]) (sqrt_inv != 0).
 hipError_t times_i(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int ncol,
@@ -116,5 +120,14 @@ hipError_t resid_norms(const double2* out, const double2* v, int cj, double sgn_
 // Packed gradients (LAPACK 'U', off-diagonal x2): TDA (Y == nullptr) or PH.
 hipError_t grad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
                        int64_t n, double2* ga, double2* gb, hipStream_t s);
+
+// part[j] (j < n) = Re sum_{i<=j} conj(g_ij) C_ij for a packed component C of
+// block A (target_b 0) or B (1); g as in grad_packed, formed on the fly.
+hipError_t quad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k, int64_t n,
+                       const double2* C, int target_b, double* part, hipStream_t s);
+
+// part[b] = sum over rows of block b of d_i sum_c wgt_c (|X_ci|^2 + |Y_ci|^2).
+hipError_t quad_diag(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
+                     const double* d, int64_t n, double* part, hipStream_t s);
 
 }  // namespace bse

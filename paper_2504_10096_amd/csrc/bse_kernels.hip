@@ -440,10 +440,8 @@ __global__ void __launch_bounds__(kThreads)
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (alpha) alpha[j] = (h1 ? h1[jh].x : 0.0) + (h2 ? h2[jh].x : 0.0);
     if (beta) beta[j] = bad ? 0.0 : bt;
-    if (flag && (nonfinite || indefinite)) {
-      const int code = nonfinite ? 2 : 1;
-      if (flag[0] < code) flag[0] = code;
-    }
+    // the first failure is the one reported (later ones are its consequences)
+    if (flag && (nonfinite || indefinite) && flag[0] == 0) flag[0] = nonfinite ? 2 : 1;
   }
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
@@ -574,6 +572,18 @@ __global__ void __launch_bounds__(kThreads)
   Y[(size_t)c * n + i] = make_double2(s * (w * u.x - p.x), -s * (w * u.y - p.y));
 }
 
+// R[:, c] = W[:, c] - th[c] V[:, c]
+__global__ void __launch_bounds__(kThreads)
+    resid_cols_kernel(const double2* __restrict__ W, const double2* __restrict__ V,
+                      const double* __restrict__ th, int64_t ld, int64_t n, double2* __restrict__ R) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const double t = th[c];
+  const double2 w = W[(size_t)c * ld + i], v = V[(size_t)c * ld + i];
+  R[(size_t)c * ld + i] = make_double2(w.x - t * v.x, w.y - t * v.y);
+}
+
 // dst[:, c] = i * scale_c * src[:, c]  (scale = 1 when sc == nullptr; per
 // column 1 / sqrt(th[c]) when sqrt_inv != 0).
 __global__ void __launch_bounds__(kThreads)
@@ -667,6 +677,71 @@ __global__ void __launch_bounds__(kThreads)
     if (ga) ga[off + i] = (i == j) ? make_double2(ar, 0.0) : make_double2(f * ar, f * ai);
     if (gb) gb[off + i] = make_double2(f * br, f * bi);
   }
+}
+
+// part[j] = Re sum_{i <= j} conj(g_ij) C_ij over column j of a packed
+// component C, with g the packed gradient entry (off-diagonal 2 G_ij, diagonal
+// G_ii) of block A (target_b == 0) or B (target_b == 1), formed on the fly.
+__global__ void __launch_bounds__(kThreads)
+    quad_packed_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, int64_t ld,
+                       const double* __restrict__ wgt, int k, const double2* __restrict__ C, int target_b,
+                       double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t j = blockIdx.x;
+  const int64_t off = j * (j + 1) / 2;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i <= j; i += kThreads) {
+    double gr = 0.0, gi = 0.0;
+    for (int c = 0; c < k; ++c) {
+      const double g = wgt[c];
+      const double2 xi = X[(size_t)c * ld + i], xj = X[(size_t)c * ld + j];
+      if (!target_b) {
+        gr += g * (xi.x * xj.x + xi.y * xj.y);
+        gi += g * (xi.y * xj.x - xi.x * xj.y);
+        if (Y) {
+          const double2 yi = Y[(size_t)c * ld + i], yj = Y[(size_t)c * ld + j];
+          gr += g * (yi.x * yj.x + yi.y * yj.y);
+          gi += g * (yi.x * yj.y - yi.y * yj.x);
+        }
+      } else {
+        const double2 yi = Y[(size_t)c * ld + i], yj = Y[(size_t)c * ld + j];
+        gr += g * ((xi.x * yj.x + xi.y * yj.y) + (yi.x * xj.x + yi.y * xj.y));
+        gi += g * ((xi.y * yj.x - xi.x * yj.y) + (yi.x * xj.y - yi.y * xj.x));
+      }
+    }
+    const double f = (i == j) ? 1.0 : 2.0;
+    const double2 cv = C[off + i];
+    if (i == j && !target_b)
+      acc += gr * cv.x;
+    else
+      acc += f * (gr * cv.x + gi * cv.y);
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[j] = acc;
+}
+
+// part[block] = sum_i d_i sum_c wgt_c (|X_ci|^2 + |Y_ci|^2) over the block's rows.
+__global__ void __launch_bounds__(kThreads)
+    quad_diag_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, int64_t ld,
+                     const double* __restrict__ wgt, int k, const double* __restrict__ d, int64_t n,
+                     double* __restrict__ part) {
+  __shared__ double sh[4];
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  double acc = 0.0;
+  if (i < n) {
+    for (int c = 0; c < k; ++c) {
+      const double2 x = X[(size_t)c * ld + i];
+      double t = x.x * x.x + x.y * x.y;
+      if (Y) {
+        const double2 y = Y[(size_t)c * ld + i];
+        t += y.x * y.x + y.y * y.y;
+      }
+      acc += wgt[c] * t;
+    }
+    acc *= d[i];
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
 }  // namespace
@@ -809,6 +884,14 @@ hipError_t copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd,
   return hipGetLastError();
 }
 
+hipError_t resid_cols(const double2* W, const double2* V, const double* th, int64_t ld, int64_t n,
+                      int ncol, double2* R, hipStream_t s) {
+  if (ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL(resid_cols_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)ncol),
+                     dim3(kThreads), 0, s, W, V, th, ld, n, R);
+  return hipGetLastError();
+}
+
 hipError_t times_i(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int ncol,
                    const double* sc, int sqrt_inv, hipStream_t s) {
   if (ncol == 0) return hipSuccess;
@@ -829,6 +912,20 @@ hipError_t resid_norms(const double2* out, const double2* v, int cj, double sgn_
   hipLaunchKernelGGL(resid_part_kernel, dim3((unsigned)nch), dim3(kThreads), 0, s, out, v, cj,
                      sgn_om, n, part);
   hipLaunchKernelGGL(pair_sum_kernel, dim3(1), dim3(64), 0, s, part, nch, res);
+  return hipGetLastError();
+}
+
+hipError_t quad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k, int64_t n,
+                       const double2* C, int target_b, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(quad_packed_kernel, dim3((unsigned)n), dim3(kThreads), 0, s, X, Y, ld, wgt, k, C,
+                     target_b, part);
+  return hipGetLastError();
+}
+
+hipError_t quad_diag(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
+                     const double* d, int64_t n, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(quad_diag_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     s, X, Y, ld, wgt, k, d, n, part);
   return hipGetLastError();
 }
 

@@ -111,8 +111,8 @@ struct Solver {
   hipStream_t s;
   // device buffers
   DevBuf bufU, bufU2, bufP, bufP2, bufKP, bufKP2, bufY, bufZ, bufH1, bufH2, bufH3, bufPart, bufRed,
-      bufAlpha, bufBeta, bufFlag, bufS, bufNrm, bufW, bufTmp, bufRes, bufTh;
-  double2 *U, *U2, *P, *P2, *KP, *KP2, *Y, *Z, *H1, *H2, *H3, *W, *Tmp;
+      bufAlpha, bufBeta, bufFlag, bufS, bufNrm, bufW, bufTmp, bufRes, bufTh, bufR, bufGd, bufTd;
+  double2 *U, *U2, *P, *P2, *KP, *KP2, *Y, *Z, *H1, *H2, *H3, *W, *Tmp, *Rv, *Gd, *Td;
   double* th_dev;  // Ritz values of the kept vectors (PH partner scaling)
   int ny = 0;      // PH: columns of the partner basis Y (Z = K1 Y)
   double2* cpart;
@@ -177,13 +177,16 @@ bse_status alloc_solver(Solver& S) {
       {&S.bufH1, sizeof(double2) * ncolmax},
       {&S.bufH2, sizeof(double2) * ncolmax},
       {&S.bufH3, sizeof(double2) * ncolmax},
-      {&S.bufTh, sizeof(double) * (S.m + 1)},
+      {&S.bufTh, sizeof(double) * (S.m + 2)},
+      {&S.bufR, S.ph ? col * (S.k + 9) : 0},
+      {&S.bufGd, S.ph ? sizeof(double2) * (size_t)(S.m + 2) * (S.m + 2) : 0},
+      {&S.bufTd, S.ph ? sizeof(double2) * (size_t)(S.m + 2) * (S.m + 2) : 0},
       {&S.bufPart, sizeof(double2) * (size_t)bse::nchunks(S.n) * ncolmax},
       {&S.bufRed, sizeof(double) * 2 * ((size_t)bse::nchunks(S.n) + 8)},
       {&S.bufAlpha, sizeof(double) * (S.m + 1)},
       {&S.bufBeta, sizeof(double) * (S.m + 1)},
       {&S.bufFlag, sizeof(int) * 4},
-      {&S.bufS, sizeof(double) * (size_t)S.m * S.m + sizeof(double) * 64},
+      {&S.bufS, sizeof(double) * (size_t)(S.m + 2) * (S.m + 2)},
       {&S.bufNrm, sizeof(double) * (2 * (size_t)S.m + 8)},
       {&S.bufW, col * 2},
       {&S.bufTmp, col * 2},
@@ -205,6 +208,9 @@ bse_status alloc_solver(Solver& S) {
   S.H2 = (double2*)S.bufH2.p;
   S.H3 = (double2*)S.bufH3.p;
   S.th_dev = (double*)S.bufTh.p;
+  S.Rv = (double2*)S.bufR.p;
+  S.Gd = (double2*)S.bufGd.p;
+  S.Td = (double2*)S.bufTd.p;
   S.cpart = (double2*)S.bufPart.p;
   S.red = (double*)S.bufRed.p;
   S.alpha = (double*)S.bufAlpha.p;
@@ -486,6 +492,214 @@ bse_status finalize(Solver& S, const RitzInfo& R, double* omega, double2* X, dou
   return BSE_OK;
 }
 
+// ---------------------------------------------------------------------
+// Small dense helpers (host, column-major s x s with leading dimension ld).
+// ---------------------------------------------------------------------
+bool chol_lower(int s, double* a, int ld) {
+  for (int j = 0; j < s; ++j) {
+    double d = a[(size_t)j * ld + j];
+    for (int p = 0; p < j; ++p) d -= a[(size_t)p * ld + j] * a[(size_t)p * ld + j];
+    if (!(d > 0.0)) return false;
+    d = sqrt(d);
+    a[(size_t)j * ld + j] = d;
+    for (int i = j + 1; i < s; ++i) {
+      double t = a[(size_t)j * ld + i];
+      for (int p = 0; p < j; ++p) t -= a[(size_t)p * ld + i] * a[(size_t)p * ld + j];
+      a[(size_t)j * ld + i] = t / d;
+    }
+  }
+  return true;
+}
+
+// X <- L^{-1} X (lower L), X s x c.
+void lsolve(int s, const double* l, int ld, double* x, int ldx, int c) {
+  for (int q = 0; q < c; ++q)
+    for (int i = 0; i < s; ++i) {
+      double t = x[(size_t)q * ldx + i];
+      for (int p = 0; p < i; ++p) t -= l[(size_t)p * ld + i] * x[(size_t)q * ldx + p];
+      x[(size_t)q * ldx + i] = t / l[(size_t)i * ld + i];
+    }
+}
+
+// X <- L^{-T} X.
+void ltsolve(int s, const double* l, int ld, double* x, int ldx, int c) {
+  for (int q = 0; q < c; ++q)
+    for (int i = s - 1; i >= 0; --i) {
+      double t = x[(size_t)q * ldx + i];
+      for (int p = i + 1; p < s; ++p) t -= l[(size_t)i * ld + p] * x[(size_t)q * ldx + p];
+      x[(size_t)q * ldx + i] = t / l[(size_t)i * ld + i];
+    }
+}
+
+struct RefineOut {
+  std::vector<double> theta;  // Ritz values (omega^2), ascending
+  std::vector<double> rel;    // FP64 relative residuals of H for the k wanted
+  bool converged = false;
+};
+
+// FP64 block refinement of the pseudo-Hermitian pairs: Rayleigh-Ritz of
+// K2 K1 in the K1 inner product on span(V), with P = K1 V and W = K2 P
+// formed explicitly by FP64 passes (V = U[:, 0:s0] on entry, any K1-nearly-
+// orthonormal set), expanded by the residuals W s - theta V s of the
+// unconverged wanted pairs until every one meets tol.  Because p~ = K1 u~ is
+// exact here, ||H v - omega v|| = sqrt(2) ||K2 p~ - omega^2 u~|| and
+// ||v||^2 = 2 (omega^2 ||u~||^2 + ||p~||^2) with v = [omega u~ + p~;
+// conj(omega u~ - p~)]: the returned residuals are the FP64 residuals of H.
+bse_status refine_ph(Solver& S, int s0, double tol, int max_iter, RefineOut& out) {
+  bse_handle h = S.h;
+  const Arith ar = fp64_arith(h);
+  const int cap = S.m + 1;
+  const int ldg = S.m + 2;
+  const int k = S.k;
+  std::vector<double> G((size_t)ldg * ldg, 0.0), T((size_t)ldg * ldg, 0.0);
+  auto col = [&](double2* base, int c) { return base + (size_t)c * S.ld; };
+  // Gram columns c in [c0, c1): G[:, c] = Re(V^H P_c), T[:, c] = Re(P^H W_c)
+  auto gram_cols = [&](int c0, int c1) -> bse_status {
+    for (int c = c0; c < c1; ++c) {
+      HIP_TRY(h, bse::cdot(S.U, c + 1, nullptr, 0, S.ld, col(S.P, c), S.n, S.cpart, S.Gd + (size_t)c * ldg,
+                           S.s));
+      HIP_TRY(h, bse::cdot(S.P, c + 1, nullptr, 0, S.ld, col(S.KP, c), S.n, S.cpart, S.Td + (size_t)c * ldg,
+                           S.s));
+    }
+    std::vector<double2> gh((size_t)(c1 - c0) * ldg), th((size_t)(c1 - c0) * ldg);
+    HIP_TRY(h, hipMemcpyAsync(gh.data(), S.Gd + (size_t)c0 * ldg, sizeof(double2) * gh.size(),
+                              hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, hipMemcpyAsync(th.data(), S.Td + (size_t)c0 * ldg, sizeof(double2) * th.size(),
+                              hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, hipStreamSynchronize(S.s));
+    for (int c = c0; c < c1; ++c)
+      for (int a = 0; a <= c; ++a) {
+        const double g = gh[(size_t)(c - c0) * ldg + a].x, t = th[(size_t)(c - c0) * ldg + a].x;
+        G[(size_t)c * ldg + a] = G[(size_t)a * ldg + c] = g;
+        T[(size_t)c * ldg + a] = T[(size_t)a * ldg + c] = t;
+      }
+    return BSE_OK;
+  };
+  bse_status st;
+  int s = s0;
+  for (int c = 0; c < s; ++c) {
+    if ((st = pass(S, ar, 1, col(S.U, c), col(S.P, c)))) return st;
+    if ((st = pass(S, ar, 2, col(S.P, c), col(S.KP, c)))) return st;
+  }
+  if ((st = gram_cols(0, s))) return st;
+  if ((st = check_flag(S))) return st;
+  for (int iter = 0; iter < max_iter; ++iter) {
+    // generalized Rayleigh-Ritz: T x = theta G x on span(V)
+    std::vector<double> L((size_t)s * s), C((size_t)s * s), Q((size_t)s * s), th(s);
+    for (int j = 0; j < s; ++j)
+      for (int i = 0; i < s; ++i) {
+        L[(size_t)j * s + i] = G[(size_t)j * ldg + i];
+        C[(size_t)j * s + i] = T[(size_t)j * ldg + i];
+      }
+    if (!chol_lower(s, L.data(), s))
+      return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "K1 Gram of the refinement basis is not positive definite");
+    lsolve(s, L.data(), s, C.data(), s, s);  // L^{-1} T
+    for (int j = 0; j < s; ++j)               // transpose
+      for (int i = j + 1; i < s; ++i) std::swap(C[(size_t)j * s + i], C[(size_t)i * s + j]);
+    lsolve(s, L.data(), s, C.data(), s, s);  // L^{-1} T L^{-T}
+    for (int j = 0; j < s; ++j)
+      for (int i = j + 1; i < s; ++i) {
+        const double v = 0.5 * (C[(size_t)j * s + i] + C[(size_t)i * s + j]);
+        C[(size_t)j * s + i] = C[(size_t)i * s + j] = v;
+      }
+    if (!bse::sym_eig(s, C.data(), th.data(), Q.data()))
+      return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
+    if (th[0] <= 0.0)
+      return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "non-positive omega^2 in the FP64 refinement");
+    ltsolve(s, L.data(), s, Q.data(), s, s);  // G-orthonormal Ritz coefficients
+    const int sk = s;
+    HIP_TRY(h, hipMemcpyAsync(S.S, Q.data(), sizeof(double) * (size_t)s * sk, hipMemcpyHostToDevice, S.s));
+    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, sk, s, (const double*)S.U, 2 * S.ld, S.S, s, (double*)S.U2,
+                                  2 * S.ld, S.s));
+    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, sk, s, (const double*)S.P, 2 * S.ld, S.S, s, (double*)S.P2,
+                                  2 * S.ld, S.s));
+    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, sk, s, (const double*)S.KP, 2 * S.ld, S.S, s, (double*)S.KP2,
+                                  2 * S.ld, S.s));
+    std::swap(S.U, S.U2);
+    std::swap(S.P, S.P2);
+    std::swap(S.KP, S.KP2);
+    s = sk;
+    std::fill(G.begin(), G.end(), 0.0);
+    std::fill(T.begin(), T.end(), 0.0);
+    for (int i = 0; i < s; ++i) {
+      G[(size_t)i * ldg + i] = 1.0;
+      T[(size_t)i * ldg + i] = th[i];
+    }
+    // residuals of the wanted pairs and of up to kGuard pairs just above them
+    // (expanding along the latter keeps the last wanted pairs from stalling
+    // on a close neighbour that the basis does not resolve yet)
+    constexpr int kGuard = 0;
+    const int ng = std::min(kGuard, s - k);
+    HIP_TRY(h, hipMemcpyAsync(S.th_dev, th.data(), sizeof(double) * s, hipMemcpyHostToDevice, S.s));
+    HIP_TRY(h, bse::resid_cols(S.KP, S.U, S.th_dev, S.ld, S.n, k + ng, S.Rv, S.s));
+    double* cp = (double*)S.cpart;
+    std::vector<double> rr(k + ng), nu(k), np(k);
+    HIP_TRY(h, bse::colnorms(S.Rv, k + ng, S.ld, S.n, cp, S.nrm, S.s));
+    HIP_TRY(h, hipMemcpyAsync(rr.data(), S.nrm, sizeof(double) * (k + ng), hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, bse::colnorms(S.U, k, S.ld, S.n, cp, S.nrm, S.s));
+    HIP_TRY(h, hipMemcpyAsync(nu.data(), S.nrm, sizeof(double) * k, hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, bse::colnorms(S.P, k, S.ld, S.n, cp, S.nrm, S.s));
+    HIP_TRY(h, hipMemcpyAsync(np.data(), S.nrm, sizeof(double) * k, hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, hipStreamSynchronize(S.s));
+    out.theta.assign(th.begin(), th.begin() + s);
+    out.rel.assign(k, 0.0);
+    std::vector<int> bad;
+    for (int a = 0; a < k; ++a) {
+      const double w = sqrt(th[a]);
+      out.rel[a] = sqrt(rr[a]) / (w * sqrt(w * w * nu[a] + np[a]));
+      if (!std::isfinite(out.rel[a])) return fail(h, BSE_ERR_NONFINITE, "non-finite refinement residual");
+      if (out.rel[a] > tol) bad.push_back(a);
+    }
+    if (S.trace) {
+      double mx = 0.0;
+      for (double r : out.rel) mx = std::max(mx, r);
+      fprintf(stderr, "{\"refine\": %d, \"basis\": %d, \"max_rel\": %.3e, \"unconverged\": %d}\n", iter, s, mx,
+              (int)bad.size());
+    }
+    if (bad.empty()) {
+      out.converged = true;
+      return BSE_OK;
+    }
+    if (iter + 1 == max_iter) break;
+    for (int a = k; a < k + ng; ++a) bad.push_back(a);
+    // room for the expansion: drop the highest Ritz vectors if needed
+    if (s + (int)bad.size() > cap) s = std::max(k + ng, cap - (int)bad.size());
+    while (s + (int)bad.size() > cap) bad.pop_back();
+    // partner space of the rotated basis: i p_b / omega_b, K1 image i w_b / omega_b
+    HIP_TRY(h, bse::times_i(S.P, S.ld, S.Y, S.ld, S.n, s, S.th_dev, 1, S.s));
+    HIP_TRY(h, bse::times_i(S.KP, S.ld, S.Z, S.ld, S.n, s, S.th_dev, 1, S.s));
+    const int ny = s;
+    // expansion by the residuals of the unconverged pairs
+    for (int a : bad) {
+      if (s >= cap) break;
+      double2* x = col(S.U, s);
+      HIP_TRY(h, hipMemcpyAsync(x, col(S.Rv, a), sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
+      for (int it = 0; it < 2; ++it) {
+        HIP_TRY(h, bse::cdot(S.P, s, S.Z, ny, S.ld, x, S.n, S.cpart, S.H3, S.s));
+        HIP_TRY(h, bse::cgemv_sub(S.U, s, S.Y, ny, nullptr, nullptr, S.ld, S.H3, 1, x, nullptr, S.n, S.s));
+      }
+      // rank test: a direction (nearly) inside the span is dropped
+      double nx = 0.0;
+      HIP_TRY(h, bse::colnorms(x, 1, S.ld, S.n, cp, S.nrm, S.s));
+      HIP_TRY(h, hipMemcpyAsync(&nx, S.nrm, sizeof(double), hipMemcpyDeviceToHost, S.s));
+      HIP_TRY(h, hipStreamSynchronize(S.s));
+      if (!(nx > 1e-8 * rr[a])) continue;
+      if ((st = pass(S, ar, 1, x, col(S.P, s)))) return st;
+      HIP_TRY(h, bse::normalize(x, col(S.P, s), S.n, nullptr, nullptr, 0, nullptr, S.beta, 0, S.flag, S.red,
+                                S.s));
+      double bt = 0.0;
+      HIP_TRY(h, hipMemcpyAsync(&bt, S.beta, sizeof(double), hipMemcpyDeviceToHost, S.s));
+      if ((st = check_flag(S))) return st;
+      if (!(bt > 0.0)) continue;  // direction already in the span
+      if ((st = pass(S, ar, 2, col(S.P, s), col(S.KP, s)))) return st;
+      if ((st = gram_cols(s, s + 1))) return st;
+      ++s;
+    }
+  }
+  out.converged = false;
+  return BSE_OK;
+}
+
 // Phase switch / warm start: column 0 <- sum_i c_i U[:, i] over the k wanted Ritz vectors.
 bse_status warm_start_vector(Solver& S) {
   bse_handle h = S.h;
@@ -736,6 +950,37 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
               R.theta[k - 1], R.est[0], emax, nc, tol_int);
     }
     if (!all && !full_space) continue;
+    if (ph) {
+      // FP64 block refinement + exact FP64 residuals (after the FP32 phase,
+      // or as the final Rayleigh-Ritz of the FP64 iteration)
+      const bool from32 = ar == bse::AR_HI;
+      HIP_TRY(h, hipStreamSynchronize(S.s));
+      if (from32) {
+        ms32 += now_ms() - t_phase;
+        t_phase = now_ms();
+      }
+      const int s0 = from32 ? std::min(S.keep, k + std::max(4, k / 8)) : k;
+      RefineOut ro;
+      const double tf = now_ms();
+      st = refine_ph(S, s0, tol, 200, ro);
+      if (st) return st;
+      std::vector<double> om(k);
+      for (int i = 0; i < k; ++i) om[i] = sqrt(ro.theta[i]);
+      HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, S.s));
+      HIP_TRY(h, bse::ph_vectors(S.U, S.P, S.ld, omega, k, S.n, (double2*)x, (double2*)y, S.s));
+      HIP_TRY(h, hipStreamSynchronize(S.s));
+      ms_final += now_ms() - tf;
+      rel = ro.rel;
+      max_rel = 0.0;
+      nconv_final = 0;
+      for (double r : rel) {
+        max_rel = std::max(max_rel, r);
+        nconv_final += (r <= tol);
+      }
+      ar = fp64_arith(h);
+      converged = ro.converged;
+      break;
+    }
     if (ar == bse::AR_HI) {
       // FP32 phase done: warm start of the FP64 phase from the wanted Ritz vectors
       HIP_TRY(h, hipStreamSynchronize(S.s));
@@ -867,11 +1112,136 @@ bse_status bse_backward(bse_handle h, const double* g, void* d_a, void* d_b) {
 bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse_component* comps,
                         double* out) {
   if (!h) return BSE_ERR_INVALID_ARG;
-  (void)g;
-  (void)n_comp;
-  (void)comps;
-  (void)out;
-  return fail(h, BSE_ERR_INVALID_ARG, "bse_strength: not available in this build");
+  if (!h->solved) return fail(h, BSE_ERR_BAD_STATE, "bse_strength needs a successful bse_solve");
+  if (n_comp < 0 || (n_comp > 0 && (!comps || !out)) || !g)
+    return fail(h, BSE_ERR_INVALID_ARG, "bad component list");
+  const bool ph = h->kind == BSE_PSEUDO_HERMITIAN;
+  const int k = h->k;
+  const int64_t n = h->n;
+  for (int q = 0; q < n_comp; ++q) {
+    const bse_component& c = comps[q];
+    if ((c.target != BSE_BLOCK_A && c.target != BSE_BLOCK_B) || (c.target == BSE_BLOCK_B && !ph))
+      return fail(h, BSE_ERR_INVALID_ARG, "component target must be A, or B for the pseudo-Hermitian problem");
+    if (c.form < BSE_COMP_PACKED || c.form > BSE_COMP_STORED)
+      return fail(h, BSE_ERR_INVALID_ARG, "bad component form");
+    if (c.form != BSE_COMP_STORED && !c.data) return fail(h, BSE_ERR_INVALID_ARG, "component data is NULL");
+    if (c.form == BSE_COMP_DIAG && c.target != BSE_BLOCK_A)
+      return fail(h, BSE_ERR_INVALID_ARG, "a diagonal component belongs to A");
+    if (c.form == BSE_COMP_LOWRANK && c.rank < 1) return fail(h, BSE_ERR_INVALID_ARG, "rank must be >= 1");
+  }
+  hipStream_t st = h->stream;
+  // weights g_c / n_c, n_c = X^H X - Y^H Y (TDA: 1)
+  std::vector<double> gh(k), w(k, 1.0);
+  HIP_TRY(h, hipMemcpyAsync(gh.data(), g, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  const int64_t nch = bse::nchunks(n);
+  int64_t maxrank = 1;
+  for (int q = 0; q < n_comp; ++q)
+    if (comps[q].form == BSE_COMP_LOWRANK) maxrank = std::max<int64_t>(maxrank, comps[q].rank);
+  DevBuf wgt, part, tmp, tmp2, zero, hv, cpart;
+  HIP_TRY(h, hipMalloc(&wgt.p, sizeof(double) * k));
+  HIP_TRY(h, hipMalloc(&part.p, sizeof(double) * std::max<int64_t>(n, nch * k)));
+  HIP_TRY(h, hipMalloc(&tmp.p, sizeof(double2) * n));
+  HIP_TRY(h, hipMalloc(&tmp2.p, sizeof(double2) * n));
+  HIP_TRY(h, hipMalloc(&zero.p, sizeof(double2) * n));
+  HIP_TRY(h, hipMalloc(&hv.p, sizeof(double2) * (maxrank + 2)));
+  HIP_TRY(h, hipMalloc(&cpart.p, sizeof(double2) * nch * (maxrank + 2)));
+  HIP_TRY(h, hipMemsetAsync(zero.p, 0, sizeof(double2) * n, st));
+  if (ph) {
+    std::vector<double> a(k), b(k);
+    HIP_TRY(h, bse::colnorms(h->X, k, n, n, (double*)part.p, (double*)wgt.p, st));
+    HIP_TRY(h, hipMemcpyAsync(a.data(), wgt.p, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(h, bse::colnorms(h->Y, k, n, n, (double*)part.p, (double*)wgt.p, st));
+    HIP_TRY(h, hipMemcpyAsync(b.data(), wgt.p, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(h, hipStreamSynchronize(st));
+    for (int c = 0; c < k; ++c) w[c] = 1.0 / (a[c] - b[c]);
+  } else {
+    HIP_TRY(h, hipStreamSynchronize(st));
+  }
+  for (int c = 0; c < k; ++c) w[c] *= gh[c];
+  HIP_TRY(h, hipMemcpyAsync(wgt.p, w.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+  const bse::MatPtrs mp = mat_ptrs(h);
+  const Arith ar = fp64_arith(h);
+  double2* t1 = (double2*)tmp.p;
+  double2* t2 = (double2*)tmp2.p;
+  double2* hd = (double2*)hv.p;
+  // complex inner product u^H v (device vectors, n entries) -> host
+  auto dotc = [&](const double2* u, const double2* v, double2* res) -> bse_status {
+    HIP_TRY(h, bse::cdot(u, 1, nullptr, 0, n, v, n, (double2*)cpart.p, hd, st));
+    HIP_TRY(h, hipMemcpyAsync(res, hd, sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIP_TRY(h, hipStreamSynchronize(st));
+    return BSE_OK;
+  };
+  bse_status sst;
+  for (int q = 0; q < n_comp; ++q) {
+    const bse_component& c = comps[q];
+    const bool tb = c.target == BSE_BLOCK_B;
+    double sum = 0.0;
+    if (c.form == BSE_COMP_PACKED) {
+      HIP_TRY(h, bse::quad_packed(h->X, ph ? h->Y : nullptr, n, (const double*)wgt.p, k, n,
+                                  (const double2*)c.data, tb ? 1 : 0, (double*)part.p, st));
+      std::vector<double> ph_(n);
+      HIP_TRY(h, hipMemcpyAsync(ph_.data(), part.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+      HIP_TRY(h, hipStreamSynchronize(st));
+      for (double v : ph_) sum += v;
+    } else if (c.form == BSE_COMP_DIAG) {
+      HIP_TRY(h, bse::quad_diag(h->X, ph ? h->Y : nullptr, n, (const double*)wgt.p, k, (const double*)c.data,
+                                n, (double*)part.p, st));
+      std::vector<double> ph_(nch);
+      HIP_TRY(h, hipMemcpyAsync(ph_.data(), part.p, sizeof(double) * nch, hipMemcpyDeviceToHost, st));
+      HIP_TRY(h, hipStreamSynchronize(st));
+      for (double v : ph_) sum += v;
+    } else if (c.form == BSE_COMP_LOWRANK) {
+      const double2* F = (const double2*)c.data;
+      const int r = (int)c.rank;
+      std::vector<double2> a(r), b(r);
+      for (int p = 0; p < k; ++p) {
+        const double2* xc = h->X + (size_t)p * n;
+        HIP_TRY(h, bse::cdot(F, r, nullptr, 0, n, xc, n, (double2*)cpart.p, hd, st));  // F^H x
+        HIP_TRY(h, hipMemcpyAsync(a.data(), hd, sizeof(double2) * r, hipMemcpyDeviceToHost, st));
+        if (ph) {
+          HIP_TRY(h, bse::conj_copy(h->Y + (size_t)p * n, t1, n, 1.0, st));
+          HIP_TRY(h, bse::cdot(F, r, nullptr, 0, n, t1, n, (double2*)cpart.p, hd, st));  // F^H conj(y)
+          HIP_TRY(h, hipMemcpyAsync(b.data(), hd, sizeof(double2) * r, hipMemcpyDeviceToHost, st));
+        }
+        HIP_TRY(h, hipStreamSynchronize(st));
+        double v = 0.0;
+        if (!tb) {
+          for (int t = 0; t < r; ++t) v += a[t].x * a[t].x + a[t].y * a[t].y;
+          if (ph)
+            for (int t = 0; t < r; ++t) v += b[t].x * b[t].x + b[t].y * b[t].y;
+        } else {
+          // 2 Re(x^H F F^T y) = 2 Re(a^H conj(b)), a = F^H x, b = F^H conj(y)
+          for (int t = 0; t < r; ++t) v += 2.0 * (a[t].x * b[t].x - a[t].y * b[t].y);
+        }
+        sum += w[p] * v;
+      }
+    } else {  // STORED: quadratic forms with the stored FP64 block
+      for (int p = 0; p < k; ++p) {
+        const double2* xc = h->X + (size_t)p * n;
+        double2 d1;
+        if (!tb) {
+          HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_NONE, mp, xc, 0, nullptr, 0, 0.0, h->part, t2, st));
+          if ((sst = dotc(xc, t2, &d1))) return sst;
+          double v = d1.x;
+          if (ph) {
+            HIP_TRY(h, bse::conj_copy(h->Y + (size_t)p * n, t1, n, 1.0, st));
+            HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_NONE, mp, t1, 0, nullptr, 0, 0.0, h->part, t2, st));
+            if ((sst = dotc(t1, t2, &d1))) return sst;
+            v += d1.x;
+          }
+          sum += w[p] * v;
+        } else {
+          // B y alone: A * 0 + B y
+          HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, (const double2*)zero.p, 0,
+                                 h->Y + (size_t)p * n, 0, 1.0, h->part, t2, st));
+          if ((sst = dotc(xc, t2, &d1))) return sst;
+          sum += w[p] * 2.0 * d1.x;
+        }
+      }
+    }
+    out[q] = c.scale * sum;
+  }
+  return BSE_OK;
 }
 
 }  // extern "C"

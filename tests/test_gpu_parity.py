@@ -380,3 +380,85 @@ def test_device_generator_bitwise():
             ref = m.pack_host(which, j0, j1)
             assert np.array_equal(host(out).view(np.uint64), ref.view(np.uint64)), (which, j0, j1)
     g.close()
+
+
+# ------------------------------------------------------- full-size workloads
+def _golden(name):
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "make_golden", os.path.join(os.path.dirname(__file__), "golden", "make_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.load(name)
+
+
+def test_workload_ph_n4096_k32_golden():
+    """Pseudo-Hermitian workload N = 4096 (operator 8192), lowest 32 pairs at
+    tol 1e-10 against the oracle's stored values; residuals checked by the oracle."""
+    w = synth.WORKLOADS[1]
+    m = synth.workload_matrix(1)
+    ap, bp = m.pack_host(0), m.pack_host(1)
+    ref = _golden("ph_n4096_k32.txt")
+    s = make_solver("ph", ap, bp)
+    om, X, Y, st = s.solve(w["k"], w["tol"])
+    om = host(om)
+    print("stats", st, flush=True)
+    assert np.max(np.abs(om - ref) / ref) < 1e-10
+    idx = [0, w["k"] // 2, w["k"] - 1]
+    rel = oracle.residual_generated(m, om[idx], host(X)[idx].T, host(Y)[idx].T)
+    assert rel.max() <= 1e-10 * 1.01, rel
+    s.close()
+
+
+def test_workload_tda_n1024_k16_golden():
+    w = synth.WORKLOADS[0]
+    m = synth.workload_matrix(0)
+    s = make_solver("tda", m.pack_host(0))
+    lam, X, _, st = s.solve(w["k"], w["tol"])
+    ref = _golden("tda_n1024_k16.txt")
+    assert np.max(np.abs(host(lam) - ref) / np.abs(ref)) < 1e-10
+    s.close()
+
+
+# ----------------------------------------------------------- strength scalars
+@pytest.mark.parametrize("kind", ["tda", "ph"])
+def test_strength_components(kind):
+    """Re<G, C> for packed, low-rank, diagonal and stored components against the
+    oracle's packed gradient (same eigenvectors)."""
+    n, k = 260, 6
+    m = synth.Matrix(n, 61, ph=(kind == "ph"))
+    ap = m.pack_host(0)
+    bp = m.pack_host(1) if kind == "ph" else None
+    s = make_solver(kind, ap, bp)
+    om, X, Y, _ = s.solve(k, 1e-12)
+    g = synth.loss_weights(62, k)
+    Xh = host(X).T
+    if kind == "ph":
+        ga, gb = oracle.grad_ph(Xh, host(Y).T, g)
+    else:
+        ga, gb = oracle.grad_tda(Xh, g), None
+    t = m.tables
+    xf = t.x_factor()
+    kx = xf @ xf.conj().T / n
+    comps = [("A", "packed", dev(pack_upper(kx)), 1.0),
+             ("A", "lowrank", dev(xf), 1.0 / n),
+             ("A", "diag", dev(t.eps + m.shift), 1.0),
+             ("A", "stored", None, 1.0)]
+    ref = [oracle.packed_inner(ga, pack_upper(kx)), oracle.packed_inner(ga, pack_upper(kx)),
+           oracle.packed_inner(ga, pack_upper(np.diag(t.eps + m.shift).astype(complex))),
+           oracle.packed_inner(ga, ap)]
+    if kind == "ph":
+        yf = t.y_factor()
+        b0 = m.b0_scale * (yf @ yf.T)
+        comps += [("B", "packed", dev(pack_upper(b0)), 1.0), ("B", "lowrank", dev(yf), m.b0_scale),
+                  ("B", "stored", None, 1.0)]
+        ref += [oracle.packed_inner(gb, pack_upper(b0)), oracle.packed_inner(gb, pack_upper(b0)),
+                oracle.packed_inner(gb, bp)]
+    got = s.strength(torch.as_tensor(g), comps)
+    for a, b in zip(got, ref):
+        assert abs(a - b) <= 1e-10 * max(1.0, abs(b)), (got, ref)
+    # Euler homogeneity: sum g omega = Re<G_A, A> + Re<G_B, B>
+    tot = got[3] + (got[-1] if kind == "ph" else 0.0)
+    assert abs(tot - float(g @ host(om))) < 1e-9 * abs(tot)
+    s.close()
