@@ -95,6 +95,11 @@ def main():
     p.add_argument("--check", choices=["on", "off"], default="on",
                    help="oracle FP64 residuals of sampled pairs (streaming, CPU)")
     p.add_argument("--chunk-gb", type=float, default=2.0)
+    p.add_argument("--mode", choices=["solve", "passbench", "copy"], default="solve",
+                   help="solve: the benchmark; passbench: only passes over the stored triangles "
+                        "(for counter runs); copy: a plain device copy of known size (counter calibration)")
+    p.add_argument("--passes", type=int, default=5, help="passbench: timed passes per precision")
+    p.add_argument("--copy-gb", type=float, default=8.0)
     args = p.parse_args()
 
     if args.gpus != 1:
@@ -107,6 +112,21 @@ def main():
 
     import paper_2504_10096_amd as bse
     import synth
+
+    if args.mode == "copy":
+        nel = int(args.copy_gb * 2 ** 30 / 8)
+        a = torch.ones(nel, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        print(json.dumps({"mode": "copy", "bytes_read": nel * 8, "bytes_written": nel * 8, "ms": ms,
+                          "GBps": 2 * nel * 8 / (ms * 1e-3) / 1e9}), flush=True)
+        return
 
     w = dict(synth.WORKLOADS[args.workload])
     n = args.n or w["n"]
@@ -126,6 +146,28 @@ def main():
     fill_from_generator(solver, mat, int(args.chunk_gb * 2 ** 30 / 16), stream)
     t_setup = time.perf_counter() - t0
     log(f"  setup (tables + device generation + ingest) {t_setup:.1f} s")
+
+    if args.mode == "passbench":
+        x = torch.randn(n, dtype=torch.complex128, device="cuda").reshape(1, n)
+        out = {"mode": "passbench", "n": n, "kind": "ph" if ph else "tda"}
+        op = "K1" if ph else "A"
+        for prec in (["hi64", "fp32", "fp64"] if storage == "hilo" else ["fp64"]):
+            solver.apply(op, x, precision=prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.passes):
+                solver.apply(op, x, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.passes
+            e = 16 if prec == "fp64" else 8
+            nbytes = (2 if ph else 1) * e * n * (n + 1) / 2 + 32 * n
+            out[prec] = {"ms_per_pass": ms, "bytes_per_pass": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9}
+            log(f"  {prec}: {ms:.3f} ms per pass (block + reduce), {nbytes / (ms * 1e-3) / 1e9:.0f} GB/s")
+        solver.close()
+        print(json.dumps(out), flush=True)
+        return
 
     for i in range(args.warmup):
         solver.solve(k, tol, precision=precision)

@@ -65,7 +65,11 @@ typedef enum {
 } bse_storage;
 
 typedef enum { BSE_C64 = 0, BSE_C128 = 1 } bse_dtype;
-typedef enum { BSE_PREC_FP64 = 0, BSE_PREC_MIXED = 1 } bse_precision;
+/* FP64: the FP64 operator (complex128, or hi + lo).  MIXED: bse_solve's mixed
+ * path; for bse_apply, the complex FP32 operator on hi.  HI_FP64 (bse_apply
+ * only): FP64 arithmetic on the complex64 hi triangles, the operator of the
+ * mixed path's bulk passes. */
+typedef enum { BSE_PREC_FP64 = 0, BSE_PREC_MIXED = 1, BSE_PREC_HI_FP64 = 2 } bse_precision;
 typedef enum { BSE_BLOCK_A = 0, BSE_BLOCK_B = 1 } bse_block;
 
 /* Operators for bse_apply. */
@@ -84,25 +88,29 @@ typedef struct {
   int32_t precision;    /* bse_precision; MIXED needs BSE_STORE_HILO (default FP64) */
   double switch_tol;    /* MIXED: FP32-phase estimate that hands over to FP64 (default 1e-6) */
   uint64_t start_seed;  /* seed of the random start vector (default 1) */
+  int32_t fp32_arith;   /* MIXED bulk passes over the complex64 triangles: 0 (default) FP64
+                           products and sums; 1 complex FP32 products and in-block sums
+                           (FP64 across blocks).  Both read 8 bytes per entry. */
+  int32_t reserved_;
 } bse_solve_opts;
 
 /* Statistics of the last bse_solve (host struct). */
 typedef struct {
   int32_t n_converged;      /* pairs whose FP64-recomputed residual met tol */
   int32_t restarts;         /* thick restarts, both phases */
-  int64_t steps_fp32;       /* Lanczos steps with the FP32 operator */
+  int64_t steps_fp32;       /* Lanczos steps over the FP32-stored (hi) triangles (MIXED bulk) */
   int64_t steps_fp64;       /* Lanczos steps with the FP64 operator */
   int64_t passes;           /* passes over the stored triangles (each reads A, and B for PH) */
   double ms_total;          /* wall time of the call */
-  double ms_fp32_phase;     /* time spent in the FP32 phase (MIXED) */
+  double ms_fp32_phase;     /* time spent in the bulk phase over the hi triangles (MIXED) */
   double ms_fp64_phase;     /* time spent iterating with the FP64 operator */
   double ms_final;          /* eigenvector assembly + FP64 residual check */
   double max_rel_residual;  /* max over the k pairs of ||H v - omega v|| / (|omega| ||v||) */
-  double bytes_per_pass_fp32; /* algorithmic bytes of one FP32 pass: hi triangles + in/out vectors */
+  double bytes_per_pass_fp32; /* algorithmic bytes of one pass over hi: hi triangles + in/out vectors */
   double bytes_per_pass_fp64; /* algorithmic bytes of one FP64 pass: c128 (or hi+lo) triangles + vectors */
-  int64_t samples_fp32;     /* FP32 block-matvec launches timed with HIP events (every 8th pass) */
+  int64_t samples_fp32;     /* hi-only block-matvec launches timed with HIP events (every 8th pass) */
   int64_t samples_fp64;     /* FP64 block-matvec launches timed with HIP events (every 8th pass) */
-  double ms_block_fp32;     /* summed duration of the timed FP32 launches */
+  double ms_block_fp32;     /* summed duration of the timed hi-only launches */
   double ms_block_fp64;     /* summed duration of the timed FP64 launches */
 } bse_stats;
 
@@ -151,9 +159,10 @@ bse_status bse_set_packed(bse_handle h, bse_block which, int64_t j0, int64_t j1,
 /*
  * bse_apply -- y = op(x) for nvec vectors, columns of length N (2N for
  * BSE_OP_H, stored as [top; bottom]), complex128, device.  precision selects
- * the FP64 operator (c128, or hi+lo) or the FP32 operator (hi only, HILO
- * storage).  One pass over the stored triangles per vector.
- * Errors: INVALID_ARG (K1/K2/H on a TDA handle, FP32 without HILO, nulls).
+ * the FP64 operator (c128, or hi+lo), the FP32 operator (MIXED: hi only) or
+ * FP64 arithmetic on hi (HI_FP64); the last two need HILO storage.  One pass
+ * over the stored triangles per vector.
+ * Errors: INVALID_ARG (K1/K2/H on a TDA handle, hi-only without HILO, nulls).
  */
 bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t nvec, const void* x,
                      void* y);

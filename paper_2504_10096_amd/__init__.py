@@ -26,7 +26,7 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_DEVICE, ERR_NOT_PD, ERR_NOT_CONVERGED, ERR_NON
 TDA, PSEUDO_HERMITIAN = 0, 1
 STORE_C128, STORE_HILO = 0, 1
 C64, C128 = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_HI_FP64 = 0, 1, 2
 BLOCK_A, BLOCK_B = 0, 1
 OP_A, OP_K1, OP_K2, OP_H = 0, 1, 2, 3
 COMP_PACKED, COMP_LOWRANK, COMP_DIAG, COMP_STORED = 0, 1, 2, 3
@@ -37,7 +37,8 @@ EXPORTS = ["bse_create", "bse_set_packed", "bse_apply", "bse_solve", "bse_backwa
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("ncv", ctypes.c_int32), ("keep", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("switch_tol", ctypes.c_double), ("start_seed", ctypes.c_uint64)]
+                ("precision", ctypes.c_int32), ("switch_tol", ctypes.c_double), ("start_seed", ctypes.c_uint64),
+                ("fp32_arith", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -184,29 +185,32 @@ class Solver:
                                                   C64 if c64 else C128), "bse_set_packed")
 
     def apply(self, op, x, precision="fp64"):
-        """y = op(x); x: (nvec, N) complex128 (nvec, 2N for 'H'), rows are vectors."""
+        """y = op(x); x: (nvec, N) complex128 (nvec, 2N for 'H'), rows are vectors.  precision:
+        "fp64" (FP64 operator), "fp32" (complex FP32 on hi), "hi64" (FP64 arithmetic on hi)."""
         opc = {"A": OP_A, "K1": OP_K1, "K2": OP_K2, "H": OP_H}[op]
         length = 2 * self.n if opc == OP_H else self.n
         x = x.reshape(-1, length)
         _dev_ptr(x, torch.complex128, "x")
         y = torch.empty_like(x)
-        prec = PREC_MIXED if precision == "fp32" else PREC_FP64
+        prec = {"fp64": PREC_FP64, "fp32": PREC_MIXED, "hi64": PREC_HI_FP64}[precision]
         with torch.cuda.device(self.device):
             self._check(load_library().bse_apply(self._h, opc, prec, x.shape[0], _dev_ptr(x), _dev_ptr(y)),
                         "bse_apply")
         return y
 
     def solve(self, k, tol, precision="fp64", ncv=0, keep=0, max_restarts=0, switch_tol=0.0, seed=1,
-              raise_not_converged=True):
+              raise_not_converged=True, fp32_arith=False):
         """Lowest k pairs.  Returns (omega[k] f64, X[k, N] c128, Y[k, N] c128 or None, stats dict);
-        row c of X/Y is pair c (column c of the column-major N x k ABI layout)."""
+        row c of X/Y is pair c (column c of the column-major N x k ABI layout).  With
+        precision="mixed", fp32_arith selects complex FP32 arithmetic for the bulk passes
+        (default: FP64 arithmetic on the FP32-stored triangles)."""
         k = int(k)
         dev = self.device
         omega = torch.empty(k, dtype=torch.float64, device=dev)
         X = torch.empty((k, self.n), dtype=torch.complex128, device=dev)
         Y = torch.empty((k, self.n), dtype=torch.complex128, device=dev) if self.kind == PSEUDO_HERMITIAN else None
         opts = SolveOpts(int(ncv), int(keep), int(max_restarts), PREC_MIXED if precision == "mixed" else PREC_FP64,
-                         float(switch_tol), int(seed))
+                         float(switch_tol), int(seed), 1 if fp32_arith else 0, 0)
         stats = Stats()
         with torch.cuda.device(dev):
             st = load_library().bse_solve(self._h, k, float(tol), ctypes.byref(opts), _dev_ptr(omega),

@@ -23,8 +23,9 @@ struct Layout {
 };
 
 // Arithmetic of a pass: complex128 storage in FP64; hi only in FP32 (FP32
-// products and in-block sums, FP64 across blocks); hi + lo in FP64.
-enum Arith { AR_C128 = 0, AR_HI = 1, AR_HILO = 2 };
+// products and in-block sums, FP64 across blocks); hi + lo in FP64; hi only
+// with FP64 products and sums (FP32 storage, FP64 arithmetic).
+enum Arith { AR_C128 = 0, AR_HI = 1, AR_HILO = 2, AR_HI64 = 3 };
 
 struct MatPtrs {
   const void* a = nullptr;   // c128 or hi

@@ -68,6 +68,16 @@ struct Elem<AR_HI> {
   }
 };
 template <>
+struct Elem<AR_HI64> {
+  using T = double;
+  __device__ static __forceinline__ void load(const void* p, const void*, size_t i, double& re,
+                                              double& im) {
+    const nf2 v = __builtin_nontemporal_load(static_cast<const nf2*>(p) + i);
+    re = (double)v.x;
+    im = (double)v.y;
+  }
+};
+template <>
 struct Elem<AR_HILO> {
   using T = double;
   __device__ static __forceinline__ void load(const void* p, const void* q, size_t i, double& re,
@@ -267,6 +277,8 @@ hipError_t dispatch_ar(Arith ar, BMode bm, const Layout& L, const MatPtrs& m, co
       return dispatch_bm<R, AR_C128>(bm, L, m, va, conja, vb, conjb, sb, part, s);
     case AR_HI:
       return dispatch_bm<R, AR_HI>(bm, L, m, va, conja, vb, conjb, sb, part, s);
+    case AR_HI64:
+      return dispatch_bm<R, AR_HI64>(bm, L, m, va, conja, vb, conjb, sb, part, s);
     default:
       return dispatch_bm<R, AR_HILO>(bm, L, m, va, conja, vb, conjb, sb, part, s);
   }

@@ -82,7 +82,7 @@ Arith fp64_arith(const bse_handle_s* h) {
 }
 
 double bytes_per_pass(const bse_handle_s* h, Arith ar) {
-  const double e = (ar == bse::AR_HI) ? 8.0 : 16.0;
+  const double e = (ar == bse::AR_HI || ar == bse::AR_HI64) ? 8.0 : 16.0;
   const double tri = e * (double)h->n * (double)(h->n + 1) / 2.0;
   const int nt = h->kind == BSE_PSEUDO_HERMITIAN ? 2 : 1;
   return nt * tri + 2.0 * 16.0 * (double)h->n;
@@ -237,7 +237,7 @@ bse_status pass(Solver& S, Arith ar, int op /*0: A, 1: K1, 2: K2*/, const double
   bse_handle h = S.h;
   const bse::MatPtrs mp = mat_ptrs(h);
   bse::MatPtrs mm = mp;
-  if (ar == bse::AR_HI) {
+  if (ar == bse::AR_HI || ar == bse::AR_HI64) {
     mm.alo = nullptr;
     mm.blo = nullptr;
   }
@@ -247,7 +247,7 @@ bse_status pass(Solver& S, Arith ar, int op /*0: A, 1: K1, 2: K2*/, const double
     S.ev_free.pop_back();
     e0 = S.ev_free.back();
     S.ev_free.pop_back();
-    S.ev_pending.push_back({{e0, e1}, ar == bse::AR_HI});
+    S.ev_pending.push_back({{e0, e1}, ar == bse::AR_HI || ar == bse::AR_HI64});
   }
   hipError_t e;
   if (op == 0)
@@ -325,7 +325,7 @@ bse_status step(Solver& S, Arith ar, int j) {
     HIP_TRY(h, bse::cgemv_sub(S.U, j + 1, S.Y, S.ny, S.P, S.Z, S.ld, S.H2, 1, w, z, S.n, S.s));
     HIP_TRY(h, bse::normalize(w, z, S.n, S.H1, S.H2, j, S.alpha, S.beta, j, S.flag, S.red, S.s));
   }
-  if (ar == bse::AR_HI)
+  if (ar == bse::AR_HI || ar == bse::AR_HI64)
     ++S.steps32;
   else
     ++S.steps64;
@@ -838,11 +838,15 @@ bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t n
   if (op != BSE_OP_A && h->kind == BSE_TDA)
     return fail(h, BSE_ERR_INVALID_ARG, "K1/K2/H need a pseudo-Hermitian handle");
   if (op < BSE_OP_A || op > BSE_OP_H) return fail(h, BSE_ERR_INVALID_ARG, "bad op");
-  if (precision == BSE_PREC_MIXED && h->storage != BSE_STORE_HILO)
-    return fail(h, BSE_ERR_INVALID_ARG, "the FP32 operator needs HILO storage");
-  const Arith ar = precision == BSE_PREC_MIXED ? bse::AR_HI : fp64_arith(h);
+  if (precision < BSE_PREC_FP64 || precision > BSE_PREC_HI_FP64)
+    return fail(h, BSE_ERR_INVALID_ARG, "bad precision");
+  if (precision != BSE_PREC_FP64 && h->storage != BSE_STORE_HILO)
+    return fail(h, BSE_ERR_INVALID_ARG, "the hi-only operators need HILO storage");
+  const Arith ar = precision == BSE_PREC_MIXED    ? bse::AR_HI
+                   : precision == BSE_PREC_HI_FP64 ? bse::AR_HI64
+                                                   : fp64_arith(h);
   bse::MatPtrs mp = mat_ptrs(h);
-  if (ar == bse::AR_HI) {
+  if (ar == bse::AR_HI || ar == bse::AR_HI64) {
     mp.alo = nullptr;
     mp.blo = nullptr;
   }
@@ -912,7 +916,8 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   bse_status st = alloc_solver(S);
   if (st) return st;
 
-  Arith ar = mixed ? bse::AR_HI : fp64_arith(h);
+  const Arith bulk = o.fp32_arith ? bse::AR_HI : bse::AR_HI64;
+  Arith ar = mixed ? bulk : fp64_arith(h);
   double tol_int = mixed ? std::max(switch_tol, tol) : tol;
   double t_phase = now_ms(), ms32 = 0.0, ms64 = 0.0;
   HIP_TRY(h, bse::start_vector(S.U, n, seed, S.s));
@@ -946,14 +951,14 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
       fprintf(stderr,
               "{\"restart\": %d, \"fp32\": %d, \"steps\": %lld, \"theta0\": %.10g, \"theta_k\": %.10g, "
               "\"est0\": %.3e, \"est_max\": %.3e, \"nconv\": %d, \"tol_int\": %.1e}\n",
-              S.restarts, ar == bse::AR_HI ? 1 : 0, (long long)(S.steps32 + S.steps64), R.theta[0],
+              S.restarts, ar == bulk ? 1 : 0, (long long)(S.steps32 + S.steps64), R.theta[0],
               R.theta[k - 1], R.est[0], emax, nc, tol_int);
     }
     if (!all && !full_space) continue;
     if (ph) {
       // FP64 block refinement + exact FP64 residuals (after the FP32 phase,
       // or as the final Rayleigh-Ritz of the FP64 iteration)
-      const bool from32 = ar == bse::AR_HI;
+      const bool from32 = ar == bulk;
       HIP_TRY(h, hipStreamSynchronize(S.s));
       if (from32) {
         ms32 += now_ms() - t_phase;
@@ -981,7 +986,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
       converged = ro.converged;
       break;
     }
-    if (ar == bse::AR_HI) {
+    if (ar == bulk) {
       // FP32 phase done: warm start of the FP64 phase from the wanted Ritz vectors
       HIP_TRY(h, hipStreamSynchronize(S.s));
       ms32 += now_ms() - t_phase;
@@ -1016,8 +1021,8 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
     tol_int *= 0.1;  // the estimates were optimistic: tighten and continue
   }
   HIP_TRY(h, hipStreamSynchronize(S.s));
-  ms64 += (ar == bse::AR_HI) ? 0.0 : now_ms() - t_phase;
-  if (ar == bse::AR_HI) ms32 += now_ms() - t_phase;
+  ms64 += (ar == bulk) ? 0.0 : now_ms() - t_phase;
+  if (ar == bulk) ms32 += now_ms() - t_phase;
   if (!converged) {
     // best approximations from the current basis
     if (rel.empty()) {
