@@ -95,6 +95,8 @@ def main():
     p.add_argument("--check", choices=["on", "off"], default="on",
                    help="oracle FP64 residuals of sampled pairs (streaming, CPU)")
     p.add_argument("--chunk-gb", type=float, default=2.0)
+    p.add_argument("--precision", choices=["auto", "fp64"], default="auto",
+                   help="auto: the mixed path where the workload uses it; fp64: FP64 passes only")
     p.add_argument("--mode", choices=["solve", "passbench", "copy"], default="solve",
                    help="solve: the benchmark; passbench: only passes over the stored triangles "
                         "(for counter runs); copy: a plain device copy of known size (counter calibration)")
@@ -135,7 +137,7 @@ def main():
     ph = w["ph"]
     mixed_capable = args.workload in (2, 4)
     storage = "hilo" if mixed_capable else "c128"
-    precision = "mixed" if mixed_capable else "fp64"
+    precision = "mixed" if mixed_capable and args.precision != "fp64" else "fp64"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream().cuda_stream
 

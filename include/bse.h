@@ -112,6 +112,9 @@ typedef struct {
   int64_t samples_fp64;     /* FP64 block-matvec launches timed with HIP events (every 8th pass) */
   double ms_block_fp32;     /* summed duration of the timed hi-only launches */
   double ms_block_fp64;     /* summed duration of the timed FP64 launches */
+  int64_t samples_fused;    /* PH FP64 refinement: timed fused full-H launches (every 8th pass) */
+  double ms_block_fused;    /* summed duration of the timed fused launches */
+  int64_t fused_vectors;    /* vectors multiplied by H in the refinement (two per fused launch) */
 } bse_stats;
 
 /* Component of a matrix for bse_strength: the scalar returned for a

@@ -48,7 +48,9 @@ class Stats(ctypes.Structure):
                 ("ms_final", ctypes.c_double), ("max_rel_residual", ctypes.c_double),
                 ("bytes_per_pass_fp32", ctypes.c_double), ("bytes_per_pass_fp64", ctypes.c_double),
                 ("samples_fp32", ctypes.c_int64), ("samples_fp64", ctypes.c_int64),
-                ("ms_block_fp32", ctypes.c_double), ("ms_block_fp64", ctypes.c_double)]
+                ("ms_block_fp32", ctypes.c_double), ("ms_block_fp64", ctypes.c_double),
+                ("samples_fused", ctypes.c_int64), ("ms_block_fused", ctypes.c_double),
+                ("fused_vectors", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

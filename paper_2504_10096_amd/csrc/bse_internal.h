@@ -49,6 +49,17 @@ hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const d
                   const double2* vb, int conjb, double sb, double2* part, double2* out,
                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// Full-H products [A x_q + B y_q; bsign conj(A conj(y_q) + B conj(x_q))]
+// (bsign = 1: M v_q; bsign = -1: H v_q) for nh (1 or 2) vectors in one read
+// of the stored A and B, FP64 arithmetic (ar: AR_C128, AR_HILO or AR_HI64).
+// Column q of V (and MV): top at q ldv, bottom at q ldv + ldh, n entries
+// each.  part: mh_part_elems(L, nh) complex entries.  ev0 / ev1 (optional)
+// are recorded around the block kernel.
+size_t mh_part_elems(const Layout& L, int nh);
+hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const double2* V, int64_t ldv,
+                    int64_t ldh, double2* part, double2* MV, double bsign, hipStream_t s,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+
 // Copy packed-upper columns [j0, j1) into block storage (see Layout).
 hipError_t ingest(const Layout& L, bool is_a, bool hilo, const void* src, bool src_c64, int64_t j0,
                   int64_t j1, void* dst, void* dst_lo, hipStream_t s);
@@ -90,7 +101,25 @@ hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s);
 
 // PH eigenvectors: X = (w u + p) / (2 sqrt(w)), Y = conj(w u - p) / (2 sqrt(w)).
 hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const double* omega, int k,
-                      int64_t n, double2* X, double2* Y, hipStream_t s);
+                      int64_t n, double2* X, double2* Y, int64_t ldo, hipStream_t s);
+
+// Complex C (M x N) = A (M x K) B (K x N), column-major, FP64 MFMA.
+hipError_t zgemm_mfma(int64_t M, int N, int K, const double2* A, int64_t lda, const double2* B,
+                      int64_t ldb, double2* C, int64_t ldc, hipStream_t s);
+
+// FP64 refinement on the full H (columns [top; bottom], each half ld long,
+// column stride 2 ld, n entries used per half):
+//   resid_h: R[:, c] = diag(I, -I) MV[:, c] - om[c] V[:, c] for c < ncol;
+//   precond_h: t = (diag(d, -d) - om)^{-1} r, |denominators| >= floor;
+//   h_out: X[:, c] = sqrt(om_c) V_top, Y[:, c] = sqrt(om_c) V_bottom (ld n);
+//   diag_a: d = diag(A) in FP64 from the stored blocks.
+hipError_t resid_h(const double2* MV, const double2* V, const double* om, int64_t ld, int64_t n, int ncol,
+                   double2* R, hipStream_t s);
+hipError_t precond_h(const double2* r, const double* d, double om, double floor, int64_t ld, int64_t n,
+                     double2* t, hipStream_t s);
+hipError_t h_out(const double2* V, const double* om, int64_t ld, int64_t n, int k, double2* X, double2* Y,
+                 hipStream_t s);
+hipError_t diag_a(const Layout& L, Arith ar, const void* a, const void* alo, double* d, hipStream_t s);
 
 // Strided column copy (ld_src -> ld_dst), k columns of n complex entries.
 hipError_t copy_cols(const double2* src, int64_t lds, double2* dst, int64_t ldd, int64_t n, int k,
@@ -112,6 +141,12 @@ hipError_t conj_copy(const double2* src, double2* dst, int64_t n, double sg, hip
 // destroyed) -> ascending eigenvalues w and orthonormal eigenvectors z
 // (column-major).  Returns false if the QR iteration did not converge.
 bool sym_eig(int m, double* a, double* w, double* z);
+
+// Small dense Hermitian eigensolver (host, FP64): a (m x m complex,
+// column-major, read only) -> ascending eigenvalues w and orthonormal
+// eigenvectors z (column-major).  Returns false if the QR iteration did not
+// converge.
+bool herm_eig(int m, double2* a, double* w, double2* z);
 
 // Residual pieces of one vector: part2[2*chunk] = ||out - sgn*om*(cj ? conj(v) : v)||^2 over the
 // chunk, part2[2*chunk+1] = ||v||^2; res[0..1] = sums over chunks.

@@ -244,6 +244,193 @@ __global__ void __launch_bounds__(kThreads)
   out[i] = make_double2(sx, sy);
 }
 
+// ------------------------------------------------- full-H products (FP64)
+//
+// M v for NH vectors v_q = [x_q; y_q] in one read of A and B: output 2q is
+// A x_q + B y_q (top of M v_q), output 2q+1 is A conj(y_q) + B conj(x_q)
+// (the conjugate of the bottom).  Per stored entry pair (A_rc, B_rc) and
+// vector the row r gains A_rc a_c + B_rc b_c and the column c gains
+// conj(A_rc) a_r + B_rc b_r (A Hermitian, B symmetric), (a, b) = (x, y) or
+// (conj y, conj x).  A workgroup covers RS <= 256 rows of a block (grid.y
+// row slices) so that the per-lane row state of 2 NH outputs stays in
+// registers; wave w walks columns [w R/4, (w+1) R/4) as in the one-vector
+// kernel.  Row partials: rowpart[o][blk][R]; column partials:
+// colpart[o][blk][slice][R]; mh_reduce_kernel sums them in a fixed order.
+template <int R, int AR, int NH>
+__global__ void __launch_bounds__(kThreads)
+    mh_block_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
+                    const void* __restrict__ b0, const void* __restrict__ b1,
+                    const int2* __restrict__ blkmap, int64_t nblk, int64_t n,
+                    const double2* __restrict__ V, int64_t ldv, int64_t ldh,
+                    double2* __restrict__ rowpart, double2* __restrict__ colpart) {
+  constexpr int RS = R < 256 ? R : 256;
+  constexpr int NS = R / RS;
+  constexpr int RPL = RS / 64;
+  constexpr int CPW = R / 4;
+  constexpr int NO = 2 * NH;
+  __shared__ double2 sh[4][RS];
+
+  const int blk = blockIdx.x;
+  const int slice = blockIdx.y;
+  const int2 pq = blkmap[blk];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
+  const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
+
+  double xr[NH][RPL], xi[NH][RPL], yr[NH][RPL], yi[NH][RPL];
+#pragma unroll
+  for (int q = 0; q < NH; ++q)
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      const int64_t i = row0 + lane + 64 * p;
+      double2 x = make_double2(0.0, 0.0), y = make_double2(0.0, 0.0);
+      if (i < n) {
+        x = V[(size_t)q * ldv + i];
+        y = V[(size_t)q * ldv + ldh + i];
+      }
+      xr[q][p] = x.x;
+      xi[q][p] = x.y;
+      yr[q][p] = y.x;
+      yi[q][p] = y.y;
+    }
+  double rr[NO][RPL], ri[NO][RPL];
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      rr[o][p] = 0.0;
+      ri[o][p] = 0.0;
+    }
+
+  for (int cc = 0; cc < CPW; ++cc) {
+    const int c = wave * CPW + cc;
+    const int64_t j = col0 + c;
+    double cxr[NH], cxi[NH], cyr[NH], cyi[NH];
+#pragma unroll
+    for (int q = 0; q < NH; ++q) {
+      double2 x = make_double2(0.0, 0.0), y = make_double2(0.0, 0.0);
+      if (j < n) {
+        x = V[(size_t)q * ldv + j];
+        y = V[(size_t)q * ldv + ldh + j];
+      }
+      cxr[q] = x.x;
+      cxi[q] = x.y;
+      cyr[q] = y.x;
+      cyi[q] = y.y;
+    }
+    double sr[NO], si[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      sr[o] = 0.0;
+      si[o] = 0.0;
+    }
+    const size_t cbase = base + (size_t)c * R + lane;
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      double ar, ai, br, bi;
+      Elem<AR>::load(a0, a1, cbase + 64 * p, ar, ai);
+      Elem<AR>::load(b0, b1, cbase + 64 * p, br, bi);
+#pragma unroll
+      for (int q = 0; q < NH; ++q) {
+        // top, row r: A x_c + B y_c
+        rr[2 * q][p] += ar * cxr[q] - ai * cxi[q] + br * cyr[q] - bi * cyi[q];
+        ri[2 * q][p] += ar * cxi[q] + ai * cxr[q] + br * cyi[q] + bi * cyr[q];
+        // bottom (conjugated), row r: A conj(y_c) + B conj(x_c)
+        rr[2 * q + 1][p] += ar * cyr[q] + ai * cyi[q] + br * cxr[q] + bi * cxi[q];
+        ri[2 * q + 1][p] += ai * cyr[q] - ar * cyi[q] + bi * cxr[q] - br * cxi[q];
+        // top, column c: conj(A) x_r + B y_r
+        sr[2 * q] += ar * xr[q][p] + ai * xi[q][p] + br * yr[q][p] - bi * yi[q][p];
+        si[2 * q] += ar * xi[q][p] - ai * xr[q][p] + br * yi[q][p] + bi * yr[q][p];
+        // bottom (conjugated), column c: conj(A) conj(y_r) + B conj(x_r)
+        sr[2 * q + 1] += ar * yr[q][p] - ai * yi[q][p] + br * xr[q][p] + bi * xi[q][p];
+        si[2 * q + 1] += -ar * yi[q][p] - ai * yr[q][p] + bi * xr[q][p] - br * xi[q][p];
+      }
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+      const double tr = wave_sum(sr[o]), ti = wave_sum(si[o]);
+      if (lane == 0) colpart[(((size_t)o * nblk + blk) * NS + slice) * R + c] = make_double2(tr, ti);
+    }
+  }
+
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) sh[wave][lane + 64 * p] = make_double2(rr[o][p], ri[o][p]);
+    __syncthreads();
+    for (int r = threadIdx.x; r < RS; r += kThreads) {
+      double2 t = sh[0][r];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        t.x += sh[w][r].x;
+        t.y += sh[w][r].y;
+      }
+      rowpart[((size_t)o * nblk + blk) * R + slice * RS + r] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Sum of the full-H partials; output 2q goes to the top of column q of MV,
+// output 2q+1 conjugated and times bsign to its bottom (bsign = 1: M v;
+// -1: H v).  Grid (ceil(n / 256), 2 NH).
+__global__ void __launch_bounds__(kThreads)
+    mh_reduce_kernel(const double2* __restrict__ rowpart, const double2* __restrict__ colpart, int R, int NS,
+                     int nb, int64_t nblk, int64_t n, double2* __restrict__ MV, int64_t ldv, int64_t ldh,
+                     double bsign) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int o = blockIdx.y;
+  if (i >= n) return;
+  const int P = (int)(i / R), r = (int)(i % R);
+  const double2* rp = rowpart + (size_t)o * nblk * R;
+  const double2* cp = colpart + (size_t)o * nblk * NS * R;
+  double sx = 0.0, sy = 0.0;
+  const int64_t pstart = (int64_t)P * nb - (int64_t)P * (P - 1) / 2;
+  for (int Q = P; Q < nb; ++Q) {
+    const double2 v = rp[(size_t)(pstart + (Q - P)) * R + r];
+    sx += v.x;
+    sy += v.y;
+  }
+  for (int Q = 0; Q <= P; ++Q) {
+    const int64_t b = (int64_t)Q * nb - (int64_t)Q * (Q - 1) / 2 + (P - Q);
+    for (int sl = 0; sl < NS; ++sl) {
+      const double2 v = cp[((size_t)b * NS + sl) * R + r];
+      sx += v.x;
+      sy += v.y;
+    }
+  }
+  const int q = o >> 1;
+  if (o & 1)
+    MV[(size_t)q * ldv + ldh + i] = make_double2(bsign * sx, -bsign * sy);
+  else
+    MV[(size_t)q * ldv + i] = make_double2(sx, sy);
+}
+
+template <int R, int AR>
+hipError_t launch_mh(int nh, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv, int64_t ldh,
+                     double2* part, hipStream_t s) {
+  constexpr int NS = R < 256 ? 1 : R / 256;
+  double2* rowpart = part;
+  double2* colpart = part + (size_t)2 * nh * L.nblk * R;
+  const dim3 grid((unsigned)L.nblk, (unsigned)NS);
+  if (nh == 1)
+    hipLaunchKernelGGL((mh_block_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo, L.blkmap,
+                       L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+  else
+    hipLaunchKernelGGL((mh_block_kernel<R, AR, 2>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo, L.blkmap,
+                       L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t dispatch_mh(Arith ar, int nh, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv,
+                       int64_t ldh, double2* part, hipStream_t s) {
+  if (ar == AR_C128) return launch_mh<R, AR_C128>(nh, L, m, V, ldv, ldh, part, s);
+  if (ar == AR_HI64) return launch_mh<R, AR_HI64>(nh, L, m, V, ldv, ldh, part, s);
+  return launch_mh<R, AR_HILO>(nh, L, m, V, ldv, ldh, part, s);
+}
+
 template <int R, int AR, int BM>
 hipError_t launch_mv(const Layout& L, const MatPtrs& m, const double2* va, int conja,
                      const double2* vb, int conjb, double sb, double2* part, hipStream_t s) {
@@ -524,6 +711,61 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
+// Complex C (M x N) = A (M x K) * B (K x N), column-major complex128, on the
+// same FP64 MFMA tile: four real products per complex one, two accumulators.
+__global__ void __launch_bounds__(kThreads)
+    zgemm_mfma_kernel(int64_t M, int N, int K, const double2* __restrict__ A, int64_t lda,
+                      const double2* __restrict__ B, int64_t ldb, double2* __restrict__ C,
+                      int64_t ldc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t m0 = (int64_t)blockIdx.x * 64 + (wave & 1) * 32;
+  const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  dbl4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+      ci[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + lk;
+    double2 av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int64_t i = m0 + a * 16 + li;
+      av[a] = (i < M && k < K) ? A[(size_t)k * lda + i] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int jj = n0 + b * 16 + li;
+      bv[b] = (jj < N && k < K) ? B[(size_t)jj * ldb + k] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].x, cr[a][b], 0, 0, 0);
+        cr[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, -bv[b].y, cr[a][b], 0, 0, 0);
+        ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].x, bv[b].y, ci[a][b], 0, 0, 0);
+        ci[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a].y, bv[b].x, ci[a][b], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int jj = n0 + b * 16 + li;
+      if (jj >= N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = m0 + a * 16 + 4 * r + lk;
+        if (i < M) C[(size_t)jj * ldc + i] = make_double2(cr[a][b][r], ci[a][b][r]);
+      }
+    }
+}
+
 // ------------------------------------------------------------ small kernels
 __global__ void __launch_bounds__(kThreads)
     colnorm_part_kernel(const double2* __restrict__ V, int ncol, int64_t ld, int64_t n,
@@ -573,15 +815,80 @@ __global__ void __launch_bounds__(kThreads)
 __global__ void __launch_bounds__(kThreads)
     ph_vectors_kernel(const double2* __restrict__ U, const double2* __restrict__ P, int64_t ld,
                       const double* __restrict__ omega, int64_t n, double2* __restrict__ X,
-                      double2* __restrict__ Y) {
+                      double2* __restrict__ Y, int64_t ldo) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int c = blockIdx.y;
   if (i >= n) return;
   const double w = omega[c];
   const double s = 0.5 / sqrt(w);
   const double2 u = U[(size_t)c * ld + i], p = P[(size_t)c * ld + i];
-  X[(size_t)c * n + i] = make_double2(s * (w * u.x + p.x), s * (w * u.y + p.y));
-  Y[(size_t)c * n + i] = make_double2(s * (w * u.x - p.x), -s * (w * u.y - p.y));
+  X[(size_t)c * ldo + i] = make_double2(s * (w * u.x + p.x), s * (w * u.y + p.y));
+  Y[(size_t)c * ldo + i] = make_double2(s * (w * u.x - p.x), -s * (w * u.y - p.y));
+}
+
+// ---------------------------------------------- FP64 refinement (full H)
+// Columns of length 2N stored as [top (ld); bottom (ld)], column stride 2 ld.
+
+// R[:, c] = Omega MV[:, c] - om[c] V[:, c], Omega = diag(I, -I).
+__global__ void __launch_bounds__(kThreads)
+    resid_h_kernel(const double2* __restrict__ MV, const double2* __restrict__ V,
+                   const double* __restrict__ om, int64_t ld, int64_t n, double2* __restrict__ R) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const double w = om[c];
+  const size_t t = (size_t)c * 2 * ld + i, b = t + ld;
+  const double2 mt = MV[t], vt = V[t], mb = MV[b], vb = V[b];
+  R[t] = make_double2(mt.x - w * vt.x, mt.y - w * vt.y);
+  R[b] = make_double2(-mb.x - w * vb.x, -mb.y - w * vb.y);
+}
+
+// Diagonal correction t = (D - om)^{-1} r, D = diag(d, -d) the diagonal of H
+// (d = diag A); denominators are kept at least floor in magnitude.
+__global__ void __launch_bounds__(kThreads)
+    precond_h_kernel(const double2* __restrict__ r, const double* __restrict__ d, double om,
+                     double floor, int64_t ld, int64_t n, double2* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  double dt = d[i] - om, db = -d[i] - om;
+  if (fabs(dt) < floor) dt = dt < 0.0 ? -floor : floor;
+  if (fabs(db) < floor) db = db < 0.0 ? -floor : floor;
+  const double2 a = r[i], b = r[i + ld];
+  t[i] = make_double2(a.x / dt, a.y / dt);
+  t[i + ld] = make_double2(b.x / db, b.y / db);
+}
+
+// X[:, c] = sqrt(om_c) top of V[:, c], Y[:, c] = sqrt(om_c) bottom (leading dimension n).
+__global__ void __launch_bounds__(kThreads)
+    h_out_kernel(const double2* __restrict__ V, const double* __restrict__ om, int64_t ld, int64_t n,
+                 double2* __restrict__ X, double2* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const double f = sqrt(om[c]);
+  const double2 a = V[(size_t)c * 2 * ld + i], b = V[(size_t)c * 2 * ld + ld + i];
+  X[(size_t)c * n + i] = make_double2(f * a.x, f * a.y);
+  Y[(size_t)c * n + i] = make_double2(f * b.x, f * b.y);
+}
+
+// diag(A) in FP64 from the stored diagonal blocks (stored halved).
+template <Arith AR>
+__global__ void __launch_bounds__(kThreads)
+    diag_a_kernel(const void* __restrict__ a, const void* __restrict__ alo, int R, int nb, int64_t n,
+                  double* __restrict__ d) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const int64_t P = i / R, r = i % R;
+  const int64_t blk = P * nb - P * (P - 1) / 2;
+  const size_t idx = (size_t)blk * R * R + (size_t)r * R + r;
+  double v;
+  if (AR == AR_C128) {
+    v = static_cast<const double2*>(a)[idx].x;
+  } else {
+    v = (double)static_cast<const float2*>(a)[idx].x;
+    if (AR == AR_HILO) v += (double)static_cast<const float2*>(alo)[idx].x;
+  }
+  d[i] = 2.0 * v;
 }
 
 // R[:, c] = W[:, c] - th[c] V[:, c]
@@ -810,6 +1117,49 @@ hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const d
   return hipGetLastError();
 }
 
+size_t mh_part_elems(const Layout& L, int nh) {
+  const int ns = L.R < 256 ? 1 : L.R / 256;
+  return (size_t)2 * nh * L.nblk * L.R * (1 + ns);
+}
+
+hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const double2* V, int64_t ldv,
+                    int64_t ldh, double2* part, double2* MV, double bsign, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1) {
+  if (nh < 1 || nh > 2 || ar == AR_HI) return hipErrorInvalidValue;
+  hipError_t e;
+  if (ev0) {
+    e = hipEventRecord(ev0, s);
+    if (e != hipSuccess) return e;
+  }
+  switch (L.R) {
+    case 64:
+      e = dispatch_mh<64>(ar, nh, L, m, V, ldv, ldh, part, s);
+      break;
+    case 128:
+      e = dispatch_mh<128>(ar, nh, L, m, V, ldv, ldh, part, s);
+      break;
+    case 256:
+      e = dispatch_mh<256>(ar, nh, L, m, V, ldv, ldh, part, s);
+      break;
+    case 512:
+      e = dispatch_mh<512>(ar, nh, L, m, V, ldv, ldh, part, s);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (ev1) {
+    e = hipEventRecord(ev1, s);
+    if (e != hipSuccess) return e;
+  }
+  const int ns = L.R < 256 ? 1 : L.R / 256;
+  const double2* rowpart = part;
+  const double2* colpart = part + (size_t)2 * nh * L.nblk * L.R;
+  hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)(2 * nh)),
+                     dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, MV, ldv, ldh, bsign);
+  return hipGetLastError();
+}
+
 hipError_t ingest(const Layout& L, bool is_a, bool hilo, const void* src, bool src_c64, int64_t j0,
                   int64_t j1, void* dst, void* dst_lo, hipStream_t s) {
   if (j1 <= j0) return hipSuccess;
@@ -882,9 +1232,52 @@ hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s) {
 }
 
 hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const double* omega, int k,
-                      int64_t n, double2* X, double2* Y, hipStream_t s) {
+                      int64_t n, double2* X, double2* Y, int64_t ldo, hipStream_t s) {
+  if (k == 0) return hipSuccess;
   hipLaunchKernelGGL(ph_vectors_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)k),
-                     dim3(kThreads), 0, s, U, P, ld, omega, n, X, Y);
+                     dim3(kThreads), 0, s, U, P, ld, omega, n, X, Y, ldo);
+  return hipGetLastError();
+}
+
+hipError_t zgemm_mfma(int64_t M, int N, int K, const double2* A, int64_t lda, const double2* B,
+                      int64_t ldb, double2* C, int64_t ldc, hipStream_t s) {
+  if (M == 0 || N == 0) return hipSuccess;
+  hipLaunchKernelGGL(zgemm_mfma_kernel, dim3((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64)),
+                     dim3(kThreads), 0, s, M, N, K, A, lda, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t resid_h(const double2* MV, const double2* V, const double* om, int64_t ld, int64_t n, int ncol,
+                   double2* R, hipStream_t s) {
+  if (ncol == 0) return hipSuccess;
+  hipLaunchKernelGGL(resid_h_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)ncol),
+                     dim3(kThreads), 0, s, MV, V, om, ld, n, R);
+  return hipGetLastError();
+}
+
+hipError_t precond_h(const double2* r, const double* d, double om, double floor, int64_t ld, int64_t n,
+                     double2* t, hipStream_t s) {
+  hipLaunchKernelGGL(precond_h_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     s, r, d, om, floor, ld, n, t);
+  return hipGetLastError();
+}
+
+hipError_t h_out(const double2* V, const double* om, int64_t ld, int64_t n, int k, double2* X, double2* Y,
+                 hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  hipLaunchKernelGGL(h_out_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)k),
+                     dim3(kThreads), 0, s, V, om, ld, n, X, Y);
+  return hipGetLastError();
+}
+
+hipError_t diag_a(const Layout& L, Arith ar, const void* a, const void* alo, double* d, hipStream_t s) {
+  const dim3 g((unsigned)((L.n + kThreads - 1) / kThreads));
+  if (ar == AR_C128)
+    hipLaunchKernelGGL(diag_a_kernel<AR_C128>, g, dim3(kThreads), 0, s, a, alo, L.R, L.nb, L.n, d);
+  else if (ar == AR_HILO)
+    hipLaunchKernelGGL(diag_a_kernel<AR_HILO>, g, dim3(kThreads), 0, s, a, alo, L.R, L.nb, L.n, d);
+  else
+    hipLaunchKernelGGL(diag_a_kernel<AR_HI>, g, dim3(kThreads), 0, s, a, alo, L.R, L.nb, L.n, d);
   return hipGetLastError();
 }
 

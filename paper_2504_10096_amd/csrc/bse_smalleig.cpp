@@ -1,12 +1,15 @@
-// Projected eigenproblem of the thick-restart Lanczos iteration: a small
-// dense real symmetric matrix (arrowhead + tridiagonal after a restart,
-// m <= a few hundred).  Host FP64: Householder reduction to tridiagonal form
-// with explicit accumulation of the orthogonal factor, then implicit
-// symmetric QR steps with the Wilkinson shift and Givens bulge chasing
-// (Golub and Van Loan, Matrix Computations, Sec. 8.3).
+// Small dense eigenproblems on the host in FP64: the projected matrix of the
+// thick-restart Lanczos iteration (real symmetric, arrowhead + tridiagonal
+// after a restart) and the complex Hermitian projected pencil of the FP64
+// refinement (m <= a few hundred).  Householder reduction to tridiagonal form
+// with explicit accumulation of the unitary factor (complex reflectors for
+// the Hermitian case, whose tridiagonal is made real by a diagonal phase
+// similarity), then implicit symmetric QR steps with the Wilkinson shift and
+// Givens bulge chasing (Golub and Van Loan, Matrix Computations, Sec. 8.3).
 #include <math.h>
 
 #include <algorithm>
+#include <complex>
 #include <numeric>
 #include <vector>
 
@@ -102,17 +105,60 @@ void qr_step(int m, int lo, int hi, double* d, double* e, double* q) {
   }
 }
 
-}  // namespace
-
-bool sym_eig(int m, double* a, double* w, double* z) {
-  if (m <= 0) return true;
-  if (m == 1) {
-    w[0] = a[0];
-    z[0] = 1.0;
-    return true;
+// Complex Hermitian a (column-major, m x m) = Q T Q^H, T tridiagonal with
+// real diagonal d and complex subdiagonal e; q receives Q.
+using cplx = std::complex<double>;
+void herm_tridiagonalize(int m, cplx* a, double* d, cplx* e, cplx* q) {
+  auto A = [&](int i, int j) -> cplx& { return a[(size_t)j * m + i]; };
+  std::vector<cplx> v(m), p(m);
+  std::vector<cplx> vs((size_t)m * m, 0.0);
+  for (int k = 0; k + 2 < m; ++k) {
+    double xn = 0.0;
+    for (int i = k + 1; i < m; ++i) xn += std::norm(A(i, k));
+    xn = sqrt(xn);
+    if (xn == 0.0) continue;
+    const cplx x0 = A(k + 1, k);
+    const double ax0 = std::abs(x0);
+    const cplx ph = ax0 > 0.0 ? x0 / ax0 : cplx(1.0, 0.0);
+    const cplx alpha = -ph * xn;  // H x = alpha e1, no cancellation in x0 - alpha
+    for (int i = 0; i < m; ++i) v[i] = 0.0;
+    for (int i = k + 1; i < m; ++i) v[i] = A(i, k);
+    v[k + 1] -= alpha;
+    double vn = 0.0;
+    for (int i = k + 1; i < m; ++i) vn += std::norm(v[i]);
+    vn = sqrt(vn);
+    for (int i = k + 1; i < m; ++i) v[i] /= vn;
+    // A <- H A H, H = I - 2 v v^H: p = A v, g = v^H p (real), q = p - g v,
+    // A -= 2 (v q^H + q v^H)
+    for (int i = k; i < m; ++i) {
+      cplx t = 0.0;
+      for (int j = k + 1; j < m; ++j) t += A(i, j) * v[j];
+      p[i] = t;
+    }
+    cplx g = 0.0;
+    for (int i = k + 1; i < m; ++i) g += std::conj(v[i]) * p[i];
+    for (int i = k; i < m; ++i) p[i] -= g.real() * v[i];
+    for (int j = k; j < m; ++j)
+      for (int i = k; i < m; ++i) A(i, j) -= 2.0 * (v[i] * std::conj(p[j]) + p[i] * std::conj(v[j]));
+    for (int i = k + 1; i < m; ++i) vs[(size_t)k * m + i] = v[i];
   }
-  std::vector<double> d(m), e(m, 0.0), q((size_t)m * m);
-  tridiagonalize(m, a, d.data(), e.data(), q.data());
+  for (int i = 0; i < m; ++i) d[i] = A(i, i).real();
+  for (int i = 0; i + 1 < m; ++i) e[i] = A(i + 1, i);
+  for (size_t t = 0; t < (size_t)m * m; ++t) q[t] = 0.0;
+  for (int i = 0; i < m; ++i) q[(size_t)i * m + i] = 1.0;
+  for (int k = m - 3; k >= 0; --k) {
+    const cplx* vk = &vs[(size_t)k * m];
+    for (int c = 0; c < m; ++c) {
+      cplx t = 0.0;
+      for (int i = k + 1; i < m; ++i) t += std::conj(vk[i]) * q[(size_t)c * m + i];
+      if (t == 0.0) continue;
+      for (int i = k + 1; i < m; ++i) q[(size_t)c * m + i] -= 2.0 * t * vk[i];
+    }
+  }
+}
+
+// Tridiagonal QR iteration on (d, e) accumulating rotations into q (m x m).
+bool tridiag_qr(int m, double* d, double* e, double* q) {
   const double eps = 2.220446049250313e-16;
   int hi = m - 1;
   long iters = 0;
@@ -126,9 +172,61 @@ bool sym_eig(int m, double* a, double* w, double* z) {
     int lo = hi - 1;
     while (lo > 0 && fabs(e[lo - 1]) > eps * (fabs(d[lo - 1]) + fabs(d[lo]))) --lo;
     if (lo > 0) e[lo - 1] = 0.0;
-    qr_step(m, lo, hi, d.data(), e.data(), q.data());
+    qr_step(m, lo, hi, d, e, q);
     if (++iters > max_iters) return false;
   }
+  return true;
+}
+
+}  // namespace
+
+bool herm_eig(int m, double2* a, double* w, double2* z) {
+  if (m <= 0) return true;
+  std::vector<cplx> ac((size_t)m * m), qh((size_t)m * m);
+  for (size_t t = 0; t < (size_t)m * m; ++t) ac[t] = cplx(a[t].x, a[t].y);
+  std::vector<double> d(m), e(m, 0.0), qr((size_t)m * m, 0.0);
+  std::vector<cplx> ec(m, 0.0);
+  if (m == 1) {
+    d[0] = ac[0].real();
+    qh[0] = 1.0;
+  } else {
+    herm_tridiagonalize(m, ac.data(), d.data(), ec.data(), qh.data());
+  }
+  // T = D T_r D^H with T_r real: D = diag(delta), delta_{k+1} = delta_k e_k / |e_k|
+  std::vector<cplx> delta(m, 1.0);
+  for (int k = 0; k + 1 < m; ++k) {
+    const double ae = std::abs(ec[k]);
+    e[k] = ae;
+    delta[k + 1] = ae > 0.0 ? delta[k] * (ec[k] / ae) : delta[k];
+  }
+  for (int i = 0; i < m; ++i) qr[(size_t)i * m + i] = 1.0;
+  if (!tridiag_qr(m, d.data(), e.data(), qr.data())) return false;
+  std::vector<int> ord(m);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
+  // eigenvectors Z = Q_h D Q_r
+  for (int c = 0; c < m; ++c) {
+    const int oc = ord[c];
+    w[c] = d[oc];
+    for (int i = 0; i < m; ++i) {
+      cplx t = 0.0;
+      for (int j = 0; j < m; ++j) t += qh[(size_t)j * m + i] * delta[j] * qr[(size_t)oc * m + j];
+      z[(size_t)c * m + i] = make_double2(t.real(), t.imag());
+    }
+  }
+  return true;
+}
+
+bool sym_eig(int m, double* a, double* w, double* z) {
+  if (m <= 0) return true;
+  if (m == 1) {
+    w[0] = a[0];
+    z[0] = 1.0;
+    return true;
+  }
+  std::vector<double> d(m), e(m, 0.0), q((size_t)m * m);
+  tridiagonalize(m, a, d.data(), e.data(), q.data());
+  if (!tridiag_qr(m, d.data(), e.data(), q.data())) return false;
   std::vector<int> ord(m);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });

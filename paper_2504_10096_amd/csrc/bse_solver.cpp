@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <complex>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,7 @@ struct bse_handle_s {
   void* b = nullptr;
   void* blo = nullptr;
   double2* part = nullptr;  // matvec partials
+  double2* mhpart = nullptr;  // fused full-H partials (bse_apply, allocated on first use)
   std::string err;
   // last successful solve
   bool solved = false;
@@ -77,6 +79,16 @@ bse::MatPtrs mat_ptrs(const bse_handle_s* h) {
   return m;
 }
 
+// Workspace of the fused full-H products, kept with the handle.
+bse_status ensure_mhpart(bse_handle h) {
+  if (h->mhpart) return BSE_OK;
+  if (hipMalloc((void**)&h->mhpart, sizeof(double2) * bse::mh_part_elems(h->L, 2)) != hipSuccess) {
+    h->mhpart = nullptr;
+    return fail(h, BSE_ERR_OUT_OF_MEMORY, "full-H workspace");
+  }
+  return BSE_OK;
+}
+
 Arith fp64_arith(const bse_handle_s* h) {
   return h->storage == BSE_STORE_C128 ? bse::AR_C128 : bse::AR_HILO;
 }
@@ -111,8 +123,8 @@ struct Solver {
   hipStream_t s;
   // device buffers
   DevBuf bufU, bufU2, bufP, bufP2, bufKP, bufKP2, bufY, bufZ, bufH1, bufH2, bufH3, bufPart, bufRed,
-      bufAlpha, bufBeta, bufFlag, bufS, bufNrm, bufW, bufTmp, bufRes, bufTh, bufR, bufGd, bufTd;
-  double2 *U, *U2, *P, *P2, *KP, *KP2, *Y, *Z, *H1, *H2, *H3, *W, *Tmp, *Rv, *Gd, *Td;
+      bufAlpha, bufBeta, bufFlag, bufS, bufNrm, bufW, bufTmp, bufRes, bufTh;
+  double2 *U, *U2, *P, *P2, *KP, *KP2, *Y, *Z, *H1, *H2, *H3, *W, *Tmp;
   double* th_dev;  // Ritz values of the kept vectors (PH partner scaling)
   int ny = 0;      // PH: columns of the partner basis Y (Z = K1 Y)
   double2* cpart;
@@ -129,12 +141,20 @@ struct Solver {
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, bool>> ev_pending;  // (pair, is_fp32)
   int64_t samples32 = 0, samples64 = 0;
+  // fused full-H launches of the refinement, timed separately
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_mh;
+  int64_t samples_mh = 0, mh_vectors = 0;
+  double ms_mh = 0.0;
   bool trace = false;  // BSE_TRACE=1: one JSON line per restart on stderr
   double ms_blk32 = 0.0, ms_blk64 = 0.0;
   ~Solver() {
     for (auto& p : ev_pending) {
       ev_free.push_back(p.first.first);
       ev_free.push_back(p.first.second);
+    }
+    for (auto& p : ev_mh) {
+      ev_free.push_back(p.first);
+      ev_free.push_back(p.second);
     }
     for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
   }
@@ -156,6 +176,16 @@ void harvest_events(Solver& S) {
     S.ev_free.push_back(p.first.second);
   }
   S.ev_pending.clear();
+  for (auto& p : S.ev_mh) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) {
+      S.ms_mh += ms;
+      ++S.samples_mh;
+    }
+    S.ev_free.push_back(p.first);
+    S.ev_free.push_back(p.second);
+  }
+  S.ev_mh.clear();
 }
 
 bse_status alloc_solver(Solver& S) {
@@ -178,9 +208,6 @@ bse_status alloc_solver(Solver& S) {
       {&S.bufH2, sizeof(double2) * ncolmax},
       {&S.bufH3, sizeof(double2) * ncolmax},
       {&S.bufTh, sizeof(double) * (S.m + 2)},
-      {&S.bufR, S.ph ? col * (S.k + 9) : 0},
-      {&S.bufGd, S.ph ? sizeof(double2) * (size_t)(S.m + 2) * (S.m + 2) : 0},
-      {&S.bufTd, S.ph ? sizeof(double2) * (size_t)(S.m + 2) * (S.m + 2) : 0},
       {&S.bufPart, sizeof(double2) * (size_t)bse::nchunks(S.n) * ncolmax},
       {&S.bufRed, sizeof(double) * 2 * ((size_t)bse::nchunks(S.n) + 8)},
       {&S.bufAlpha, sizeof(double) * (S.m + 1)},
@@ -208,9 +235,6 @@ bse_status alloc_solver(Solver& S) {
   S.H2 = (double2*)S.bufH2.p;
   S.H3 = (double2*)S.bufH3.p;
   S.th_dev = (double*)S.bufTh.p;
-  S.Rv = (double2*)S.bufR.p;
-  S.Gd = (double2*)S.bufGd.p;
-  S.Td = (double2*)S.bufTd.p;
   S.cpart = (double2*)S.bufPart.p;
   S.red = (double*)S.bufRed.p;
   S.alpha = (double*)S.bufAlpha.p;
@@ -456,7 +480,7 @@ bse_status finalize(Solver& S, const RitzInfo& R, double* omega, double2* X, dou
   for (int i = 0; i < S.k; ++i) om[i] = S.ph ? sqrt(std::max(R.theta[i], 0.0)) : R.theta[i];
   HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * S.k, hipMemcpyHostToDevice, S.s));
   if (S.ph)
-    HIP_TRY(h, bse::ph_vectors(S.U, S.P, S.ld, omega, S.k, S.n, X, Y, S.s));
+    HIP_TRY(h, bse::ph_vectors(S.U, S.P, S.ld, omega, S.k, S.n, X, Y, S.n, S.s));
   else
     HIP_TRY(h, bse::copy_cols(S.U, S.ld, X, S.n, S.n, S.k, S.s));
   const Arith ar = fp64_arith(h);
@@ -493,162 +517,248 @@ bse_status finalize(Solver& S, const RitzInfo& R, double* omega, double2* X, dou
 }
 
 // ---------------------------------------------------------------------
-// Small dense helpers (host, column-major s x s with leading dimension ld).
+// Small dense complex helpers (host, column-major s x s, leading dimension s).
 // ---------------------------------------------------------------------
-bool chol_lower(int s, double* a, int ld) {
+using cplx = std::complex<double>;
+
+// a = L L^H; the lower triangle of a receives L.  False if a is not positive definite.
+bool zchol(int s, cplx* a) {
   for (int j = 0; j < s; ++j) {
-    double d = a[(size_t)j * ld + j];
-    for (int p = 0; p < j; ++p) d -= a[(size_t)p * ld + j] * a[(size_t)p * ld + j];
+    double d = a[(size_t)j * s + j].real();
+    for (int p = 0; p < j; ++p) d -= std::norm(a[(size_t)p * s + j]);
     if (!(d > 0.0)) return false;
     d = sqrt(d);
-    a[(size_t)j * ld + j] = d;
+    a[(size_t)j * s + j] = d;
     for (int i = j + 1; i < s; ++i) {
-      double t = a[(size_t)j * ld + i];
-      for (int p = 0; p < j; ++p) t -= a[(size_t)p * ld + i] * a[(size_t)p * ld + j];
-      a[(size_t)j * ld + i] = t / d;
+      cplx t = a[(size_t)j * s + i];
+      for (int p = 0; p < j; ++p) t -= a[(size_t)p * s + i] * std::conj(a[(size_t)p * s + j]);
+      a[(size_t)j * s + i] = t / d;
     }
   }
   return true;
 }
 
-// X <- L^{-1} X (lower L), X s x c.
-void lsolve(int s, const double* l, int ld, double* x, int ldx, int c) {
+// X <- L^{-1} X for c columns (X s x c, leading dimension s).
+void zlsolve(int s, const cplx* l, cplx* x, int c) {
   for (int q = 0; q < c; ++q)
     for (int i = 0; i < s; ++i) {
-      double t = x[(size_t)q * ldx + i];
-      for (int p = 0; p < i; ++p) t -= l[(size_t)p * ld + i] * x[(size_t)q * ldx + p];
-      x[(size_t)q * ldx + i] = t / l[(size_t)i * ld + i];
+      cplx t = x[(size_t)q * s + i];
+      for (int p = 0; p < i; ++p) t -= l[(size_t)p * s + i] * x[(size_t)q * s + p];
+      x[(size_t)q * s + i] = t / l[(size_t)i * s + i].real();
     }
 }
 
-// X <- L^{-T} X.
-void ltsolve(int s, const double* l, int ld, double* x, int ldx, int c) {
+// X <- L^{-H} X.
+void zlhsolve(int s, const cplx* l, cplx* x, int c) {
   for (int q = 0; q < c; ++q)
     for (int i = s - 1; i >= 0; --i) {
-      double t = x[(size_t)q * ldx + i];
-      for (int p = i + 1; p < s; ++p) t -= l[(size_t)i * ld + p] * x[(size_t)q * ldx + p];
-      x[(size_t)q * ldx + i] = t / l[(size_t)i * ld + i];
+      cplx t = x[(size_t)q * s + i];
+      for (int p = i + 1; p < s; ++p) t -= std::conj(l[(size_t)i * s + p]) * x[(size_t)q * s + p];
+      x[(size_t)q * s + i] = t / l[(size_t)i * s + i].real();
     }
 }
 
 struct RefineOut {
-  std::vector<double> theta;  // Ritz values (omega^2), ascending
-  std::vector<double> rel;    // FP64 relative residuals of H for the k wanted
+  std::vector<double> omega;  // the k wanted, ascending
+  std::vector<double> rel;    // their FP64 relative residuals ||H v - omega v|| / (omega ||v||)
   bool converged = false;
 };
 
-// FP64 block refinement of the pseudo-Hermitian pairs: Rayleigh-Ritz of
-// K2 K1 in the K1 inner product on span(V), with P = K1 V and W = K2 P
-// formed explicitly by FP64 passes (V = U[:, 0:s0] on entry, any K1-nearly-
-// orthonormal set), expanded by the residuals W s - theta V s of the
-// unconverged wanted pairs until every one meets tol.  Because p~ = K1 u~ is
-// exact here, ||H v - omega v|| = sqrt(2) ||K2 p~ - omega^2 u~|| and
-// ||v||^2 = 2 (omega^2 ||u~||^2 + ||p~||^2) with v = [omega u~ + p~;
-// conj(omega u~ - p~)]: the returned residuals are the FP64 residuals of H.
-bse_status refine_ph(Solver& S, int s0, double tol, int max_iter, RefineOut& out) {
+// FP64 refinement of the pseudo-Hermitian pairs on the full H = Omega M
+// (M = [A B; conj(B) conj(A)] positive definite, Omega = diag(I, -I)),
+// started from the folded Ritz pairs (u~, p~, omega^2) in columns 0..s0-1
+// of U, P.  The structure-preserving projection of H onto a complex
+// subspace span(V) is the Hermitian pencil (V^H Omega V, V^H M V) with a
+// positive definite second matrix: its eigenvalues mu are 1/omega, real,
+// and the largest positive ones give the lowest positive omega.  Because
+// the subspace is complex, v and i v are the same direction and no Ritz
+// value is doubled.  Each unconverged wanted pair expands the subspace by
+// its residual H v - omega v scaled by the inverse of diag(H) - omega
+// (diagonal correction; BSE matrices are diagonally dominant), orthogonal to
+// V.  M V is formed explicitly by FP64 passes, so the residuals are the
+// FP64 residuals of H.  On convergence X, Y hold sqrt(omega) times the top
+// and bottom of v, normalized so that X^H X - Y^H Y = 1 per pair.
+bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double tol, int max_iter,
+                    double* omega, double2* X, double2* Y, RefineOut& out) {
   bse_handle h = S.h;
   const Arith ar = fp64_arith(h);
-  const int cap = S.m + 1;
-  const int ldg = S.m + 2;
   const int k = S.k;
-  std::vector<double> G((size_t)ldg * ldg, 0.0), T((size_t)ldg * ldg, 0.0);
-  auto col = [&](double2* base, int c) { return base + (size_t)c * S.ld; };
-  // Gram columns c in [c0, c1): G[:, c] = Re(V^H P_c), T[:, c] = Re(P^H W_c)
-  auto gram_cols = [&](int c0, int c1) -> bse_status {
+  const int64_t n = S.n, ld = S.ld, ld2 = 2 * S.ld, n2 = S.ld + S.n;
+  const int cap = (int)std::min<int64_t>(2 * n, std::max(s0, k) + 2 * k + 16);
+  if (s0 < k || s0 > cap) return fail(h, BSE_ERR_BAD_STATE, "refinement start size");
+  DevBuf bV, bMV, bV2, bMV2, bR, bPart, bH, bD, bOm, bC, bG, bSt, bSb, bNrm;
+  if (bse_status e = ensure_mhpart(h)) return e;
+  const size_t colb = sizeof(double2) * (size_t)ld2;
+  struct {
+    DevBuf* b;
+    size_t bytes;
+  } req[] = {
+      {&bV, colb * cap},
+      {&bMV, colb * cap},
+      {&bV2, colb * cap},
+      {&bMV2, colb * cap},
+      {&bR, colb * k},
+      {&bPart, sizeof(double2) * (size_t)bse::nchunks(n2) * cap},
+      {&bH, sizeof(double2) * cap},
+      {&bD, sizeof(double) * n},
+      {&bOm, sizeof(double) * cap},
+      {&bC, sizeof(double2) * (size_t)cap * cap},
+      {&bG, sizeof(double2) * (size_t)cap * cap},
+      {&bSt, sizeof(double2) * (size_t)cap * cap},
+      {&bSb, sizeof(double2) * (size_t)cap * cap},
+      {&bNrm, sizeof(double) * 2 * cap},
+  };
+  for (auto& r : req) {
+    hipError_t e = hipMalloc(&r.b->p, r.bytes);
+    if (e != hipSuccess) return fail(h, BSE_ERR_OUT_OF_MEMORY, "refinement workspace");
+  }
+  double2 *V = (double2*)bV.p, *MV = (double2*)bMV.p, *V2 = (double2*)bV2.p, *MV2 = (double2*)bMV2.p;
+  double2* R = (double2*)bR.p;
+  double2* part = (double2*)bPart.p;
+  double* dpart = (double*)bPart.p;
+  double2* H = (double2*)bH.p;
+  double* D = (double*)bD.p;
+  double* Om = (double*)bOm.p;
+  double2 *Cd = (double2*)bC.p, *Gd = (double2*)bG.p, *Std = (double2*)bSt.p, *Sbd = (double2*)bSb.p;
+  double* nrm = (double*)bNrm.p;
+  double2* mhpart = h->mhpart;
+  // padding rows stay zero: every writer covers rows [0, n) of each half
+  for (DevBuf* b : {&bV, &bMV, &bV2, &bMV2}) HIP_TRY(h, hipMemsetAsync(b->p, 0, colb * cap, S.s));
+  HIP_TRY(h, hipMemsetAsync(R, 0, colb * k, S.s));
+  HIP_TRY(h, bse::diag_a(h->L, ar, h->a, h->alo, D, S.s));
+  auto col = [&](double2* base, int c) { return base + (size_t)c * ld2; };
+  // M v = [A x + B y; conj(A conj(y) + B conj(x))] for columns [c0, c1),
+  // two vectors per read of the stored A and B
+  auto mapply = [&](int c0, int c1) -> bse_status {
+    for (int c = c0; c < c1; c += 2) {
+      const int nh = std::min(2, c1 - c);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (S.passes % 8 == 0 && S.ev_free.size() >= 2) {
+        e1 = S.ev_free.back();
+        S.ev_free.pop_back();
+        e0 = S.ev_free.back();
+        S.ev_free.pop_back();
+        S.ev_mh.push_back({e0, e1});
+      }
+      HIP_TRY(h, bse::mh_apply(h->L, ar, mat_ptrs(h), nh, col(V, c), ld2, ld, mhpart, col(MV, c), 1.0, S.s, e0,
+                               e1));
+      ++S.passes;
+      S.mh_vectors += nh;
+    }
+    return BSE_OK;
+  };
+  std::vector<cplx> G((size_t)cap * cap, 0.0), Sm((size_t)cap * cap, 0.0);
+  // Gram columns [c0, c1): G[:, c] = V^H M v_c, Sm[:, c] = V^H Omega v_c
+  auto gram = [&](int c0, int c1) -> bse_status {
+    if (c1 <= c0) return BSE_OK;
     for (int c = c0; c < c1; ++c) {
-      HIP_TRY(h, bse::cdot(S.U, c + 1, nullptr, 0, S.ld, col(S.P, c), S.n, S.cpart, S.Gd + (size_t)c * ldg,
-                           S.s));
-      HIP_TRY(h, bse::cdot(S.P, c + 1, nullptr, 0, S.ld, col(S.KP, c), S.n, S.cpart, S.Td + (size_t)c * ldg,
+      HIP_TRY(h, bse::cdot(V, c + 1, nullptr, 0, ld2, col(MV, c), n2, part, Gd + (size_t)c * cap, S.s));
+      HIP_TRY(h, bse::cdot(V, c + 1, nullptr, 0, ld2, col(V, c), n, part, Std + (size_t)c * cap, S.s));
+      HIP_TRY(h, bse::cdot(V + ld, c + 1, nullptr, 0, ld2, col(V, c) + ld, n, part, Sbd + (size_t)c * cap,
                            S.s));
     }
-    std::vector<double2> gh((size_t)(c1 - c0) * ldg), th((size_t)(c1 - c0) * ldg);
-    HIP_TRY(h, hipMemcpyAsync(gh.data(), S.Gd + (size_t)c0 * ldg, sizeof(double2) * gh.size(),
-                              hipMemcpyDeviceToHost, S.s));
-    HIP_TRY(h, hipMemcpyAsync(th.data(), S.Td + (size_t)c0 * ldg, sizeof(double2) * th.size(),
-                              hipMemcpyDeviceToHost, S.s));
+    const size_t cnt = (size_t)(c1 - c0) * cap;
+    std::vector<double2> g(cnt), st(cnt), sb(cnt);
+    HIP_TRY(h, hipMemcpyAsync(g.data(), Gd + (size_t)c0 * cap, sizeof(double2) * cnt, hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, hipMemcpyAsync(st.data(), Std + (size_t)c0 * cap, sizeof(double2) * cnt, hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, hipMemcpyAsync(sb.data(), Sbd + (size_t)c0 * cap, sizeof(double2) * cnt, hipMemcpyDeviceToHost, S.s));
     HIP_TRY(h, hipStreamSynchronize(S.s));
     for (int c = c0; c < c1; ++c)
       for (int a = 0; a <= c; ++a) {
-        const double g = gh[(size_t)(c - c0) * ldg + a].x, t = th[(size_t)(c - c0) * ldg + a].x;
-        G[(size_t)c * ldg + a] = G[(size_t)a * ldg + c] = g;
-        T[(size_t)c * ldg + a] = T[(size_t)a * ldg + c] = t;
+        const size_t q = (size_t)(c - c0) * cap + a;
+        cplx gv(g[q].x, g[q].y), sv(st[q].x - sb[q].x, st[q].y - sb[q].y);
+        if (a == c) {
+          gv = gv.real();
+          sv = sv.real();
+        }
+        G[(size_t)c * cap + a] = gv;
+        G[(size_t)a * cap + c] = std::conj(gv);
+        Sm[(size_t)c * cap + a] = sv;
+        Sm[(size_t)a * cap + c] = std::conj(sv);
       }
     return BSE_OK;
   };
+  // starting vectors v = [omega u + p; conj(omega u - p)] / (2 sqrt(omega))
+  std::vector<double> om0(s0);
+  for (int c = 0; c < s0; ++c) om0[c] = sqrt(std::max(theta0[c], 1e-300));
+  HIP_TRY(h, hipMemcpyAsync(Om, om0.data(), sizeof(double) * s0, hipMemcpyHostToDevice, S.s));
+  HIP_TRY(h, bse::ph_vectors(S.U, S.P, ld, Om, s0, n, V, V + ld, ld2, S.s));
   bse_status st;
+  if ((st = mapply(0, s0))) return st;
+  if ((st = gram(0, s0))) return st;
   int s = s0;
-  for (int c = 0; c < s; ++c) {
-    if ((st = pass(S, ar, 1, col(S.U, c), col(S.P, c)))) return st;
-    if ((st = pass(S, ar, 2, col(S.P, c), col(S.KP, c)))) return st;
-  }
-  if ((st = gram_cols(0, s))) return st;
-  if ((st = check_flag(S))) return st;
+  std::vector<double> om(k), rr(k), vv(k);
   for (int iter = 0; iter < max_iter; ++iter) {
-    // generalized Rayleigh-Ritz: T x = theta G x on span(V)
-    std::vector<double> L((size_t)s * s), C((size_t)s * s), Q((size_t)s * s), th(s);
+    // projected pencil: Sm y = mu G y, via G = L L^H and L^{-1} Sm L^{-H}
+    std::vector<cplx> L((size_t)s * s), C((size_t)s * s), Z((size_t)s * s);
     for (int j = 0; j < s; ++j)
       for (int i = 0; i < s; ++i) {
-        L[(size_t)j * s + i] = G[(size_t)j * ldg + i];
-        C[(size_t)j * s + i] = T[(size_t)j * ldg + i];
+        L[(size_t)j * s + i] = G[(size_t)j * cap + i];
+        C[(size_t)j * s + i] = Sm[(size_t)j * cap + i];
       }
-    if (!chol_lower(s, L.data(), s))
-      return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "K1 Gram of the refinement basis is not positive definite");
-    lsolve(s, L.data(), s, C.data(), s, s);  // L^{-1} T
-    for (int j = 0; j < s; ++j)               // transpose
-      for (int i = j + 1; i < s; ++i) std::swap(C[(size_t)j * s + i], C[(size_t)i * s + j]);
-    lsolve(s, L.data(), s, C.data(), s, s);  // L^{-1} T L^{-T}
+    if (!zchol(s, L.data()))
+      return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "V^H M V is not positive definite: M is not positive definite");
+    zlsolve(s, L.data(), C.data(), s);  // L^{-1} Sm
+    for (int j = 0; j < s; ++j)         // conjugate transpose: Sm L^{-H}
+      for (int i = j; i < s; ++i) {
+        const cplx a = C[(size_t)j * s + i], b = C[(size_t)i * s + j];
+        C[(size_t)j * s + i] = std::conj(b);
+        C[(size_t)i * s + j] = std::conj(a);
+      }
+    zlsolve(s, L.data(), C.data(), s);  // L^{-1} Sm L^{-H}
     for (int j = 0; j < s; ++j)
-      for (int i = j + 1; i < s; ++i) {
-        const double v = 0.5 * (C[(size_t)j * s + i] + C[(size_t)i * s + j]);
-        C[(size_t)j * s + i] = C[(size_t)i * s + j] = v;
+      for (int i = j; i < s; ++i) {
+        const cplx v = 0.5 * (C[(size_t)j * s + i] + std::conj(C[(size_t)i * s + j]));
+        C[(size_t)j * s + i] = v;
+        C[(size_t)i * s + j] = std::conj(v);
       }
-    if (!bse::sym_eig(s, C.data(), th.data(), Q.data()))
+    for (cplx v : C)
+      if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+        return fail(h, BSE_ERR_NONFINITE, "non-finite projected pencil in the refinement");
+    std::vector<double> mu(s);
+    if (!bse::herm_eig(s, reinterpret_cast<double2*>(C.data()), mu.data(), reinterpret_cast<double2*>(Z.data())))
       return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
-    if (th[0] <= 0.0)
-      return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "non-positive omega^2 in the FP64 refinement");
-    ltsolve(s, L.data(), s, Q.data(), s, s);  // G-orthonormal Ritz coefficients
-    const int sk = s;
-    HIP_TRY(h, hipMemcpyAsync(S.S, Q.data(), sizeof(double) * (size_t)s * sk, hipMemcpyHostToDevice, S.s));
-    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, sk, s, (const double*)S.U, 2 * S.ld, S.S, s, (double*)S.U2,
-                                  2 * S.ld, S.s));
-    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, sk, s, (const double*)S.P, 2 * S.ld, S.S, s, (double*)S.P2,
-                                  2 * S.ld, S.s));
-    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, sk, s, (const double*)S.KP, 2 * S.ld, S.S, s, (double*)S.KP2,
-                                  2 * S.ld, S.s));
-    std::swap(S.U, S.U2);
-    std::swap(S.P, S.P2);
-    std::swap(S.KP, S.KP2);
-    s = sk;
-    std::fill(G.begin(), G.end(), 0.0);
-    std::fill(T.begin(), T.end(), 0.0);
-    for (int i = 0; i < s; ++i) {
-      G[(size_t)i * ldg + i] = 1.0;
-      T[(size_t)i * ldg + i] = th[i];
+    // descending mu = ascending positive omega; drop the negative branch
+    int npos = 0;
+    for (double m_ : mu) npos += m_ > 0.0;
+    if (npos < k)
+      return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "fewer than k positive Ritz values in the refinement");
+    const int sk = npos;
+    std::vector<cplx> Yc((size_t)s * sk);
+    std::vector<double> mud(sk);
+    for (int c = 0; c < sk; ++c) {
+      const int src = s - 1 - c;
+      mud[c] = mu[src];
+      for (int i = 0; i < s; ++i) Yc[(size_t)c * s + i] = Z[(size_t)src * s + i];
     }
-    // residuals of the wanted pairs and of up to kGuard pairs just above them
-    // (expanding along the latter keeps the last wanted pairs from stalling
-    // on a close neighbour that the basis does not resolve yet)
-    constexpr int kGuard = 0;
-    const int ng = std::min(kGuard, s - k);
-    HIP_TRY(h, hipMemcpyAsync(S.th_dev, th.data(), sizeof(double) * s, hipMemcpyHostToDevice, S.s));
-    HIP_TRY(h, bse::resid_cols(S.KP, S.U, S.th_dev, S.ld, S.n, k + ng, S.Rv, S.s));
-    double* cp = (double*)S.cpart;
-    std::vector<double> rr(k + ng), nu(k), np(k);
-    HIP_TRY(h, bse::colnorms(S.Rv, k + ng, S.ld, S.n, cp, S.nrm, S.s));
-    HIP_TRY(h, hipMemcpyAsync(rr.data(), S.nrm, sizeof(double) * (k + ng), hipMemcpyDeviceToHost, S.s));
-    HIP_TRY(h, bse::colnorms(S.U, k, S.ld, S.n, cp, S.nrm, S.s));
-    HIP_TRY(h, hipMemcpyAsync(nu.data(), S.nrm, sizeof(double) * k, hipMemcpyDeviceToHost, S.s));
-    HIP_TRY(h, bse::colnorms(S.P, k, S.ld, S.n, cp, S.nrm, S.s));
-    HIP_TRY(h, hipMemcpyAsync(np.data(), S.nrm, sizeof(double) * k, hipMemcpyDeviceToHost, S.s));
+    zlhsolve(s, L.data(), Yc.data(), sk);  // coefficients with Yc^H G Yc = I
+    HIP_TRY(h, hipMemcpyAsync(Cd, Yc.data(), sizeof(double2) * (size_t)s * sk, hipMemcpyHostToDevice, S.s));
+    HIP_TRY(h, bse::zgemm_mfma(ld2, sk, s, V, ld2, Cd, s, V2, ld2, S.s));
+    HIP_TRY(h, bse::zgemm_mfma(ld2, sk, s, MV, ld2, Cd, s, MV2, ld2, S.s));
+    std::swap(V, V2);
+    std::swap(MV, MV2);
+    s = sk;
+    std::fill(G.begin(), G.end(), cplx(0.0));
+    std::fill(Sm.begin(), Sm.end(), cplx(0.0));
+    for (int i = 0; i < s; ++i) {
+      G[(size_t)i * cap + i] = 1.0;
+      Sm[(size_t)i * cap + i] = mud[i];
+    }
+    for (int c = 0; c < k; ++c) om[c] = 1.0 / mud[c];
+    HIP_TRY(h, hipMemcpyAsync(Om, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, S.s));
+    HIP_TRY(h, bse::resid_h(MV, V, Om, ld, n, k, R, S.s));
+    HIP_TRY(h, bse::colnorms(R, k, ld2, n2, dpart, nrm, S.s));
+    HIP_TRY(h, bse::colnorms(V, k, ld2, n2, dpart, nrm + k, S.s));
+    HIP_TRY(h, hipMemcpyAsync(rr.data(), nrm, sizeof(double) * k, hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, hipMemcpyAsync(vv.data(), nrm + k, sizeof(double) * k, hipMemcpyDeviceToHost, S.s));
     HIP_TRY(h, hipStreamSynchronize(S.s));
-    out.theta.assign(th.begin(), th.begin() + s);
+    out.omega = om;
     out.rel.assign(k, 0.0);
     std::vector<int> bad;
-    for (int a = 0; a < k; ++a) {
-      const double w = sqrt(th[a]);
-      out.rel[a] = sqrt(rr[a]) / (w * sqrt(w * w * nu[a] + np[a]));
-      if (!std::isfinite(out.rel[a])) return fail(h, BSE_ERR_NONFINITE, "non-finite refinement residual");
-      if (out.rel[a] > tol) bad.push_back(a);
+    for (int c = 0; c < k; ++c) {
+      out.rel[c] = sqrt(rr[c]) / (om[c] * sqrt(vv[c]));
+      if (!std::isfinite(out.rel[c])) return fail(h, BSE_ERR_NONFINITE, "non-finite refinement residual");
+      if (out.rel[c] > tol) bad.push_back(c);
     }
     if (S.trace) {
       double mx = 0.0;
@@ -657,46 +767,42 @@ bse_status refine_ph(Solver& S, int s0, double tol, int max_iter, RefineOut& out
               (int)bad.size());
     }
     if (bad.empty()) {
+      HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, S.s));
+      HIP_TRY(h, bse::h_out(V, Om, ld, n, k, X, Y, S.s));
+      HIP_TRY(h, hipStreamSynchronize(S.s));
       out.converged = true;
       return BSE_OK;
     }
     if (iter + 1 == max_iter) break;
-    for (int a = k; a < k + ng; ++a) bad.push_back(a);
     // room for the expansion: drop the highest Ritz vectors if needed
-    if (s + (int)bad.size() > cap) s = std::max(k + ng, cap - (int)bad.size());
-    while (s + (int)bad.size() > cap) bad.pop_back();
-    // partner space of the rotated basis: i p_b / omega_b, K1 image i w_b / omega_b
-    HIP_TRY(h, bse::times_i(S.P, S.ld, S.Y, S.ld, S.n, s, S.th_dev, 1, S.s));
-    HIP_TRY(h, bse::times_i(S.KP, S.ld, S.Z, S.ld, S.n, s, S.th_dev, 1, S.s));
-    const int ny = s;
-    // expansion by the residuals of the unconverged pairs
+    if (s + (int)bad.size() > cap) s = std::max(k, cap - (int)bad.size());
+    const int s_old = s;
     for (int a : bad) {
       if (s >= cap) break;
-      double2* x = col(S.U, s);
-      HIP_TRY(h, hipMemcpyAsync(x, col(S.Rv, a), sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
+      double2* t = col(V, s);
+      HIP_TRY(h, bse::precond_h(R + (size_t)a * ld2, D, om[a], 1e-3 * om[a], ld, n, t, S.s));
+      HIP_TRY(h, bse::colnorms(t, 1, ld2, n2, dpart, nrm, S.s));
       for (int it = 0; it < 2; ++it) {
-        HIP_TRY(h, bse::cdot(S.P, s, S.Z, ny, S.ld, x, S.n, S.cpart, S.H3, S.s));
-        HIP_TRY(h, bse::cgemv_sub(S.U, s, S.Y, ny, nullptr, nullptr, S.ld, S.H3, 1, x, nullptr, S.n, S.s));
+        HIP_TRY(h, bse::cdot(V, s, nullptr, 0, ld2, t, n2, part, H, S.s));
+        HIP_TRY(h, bse::cgemv_sub(V, s, nullptr, 0, nullptr, nullptr, ld2, H, 0, t, nullptr, n2, S.s));
       }
-      // rank test: a direction (nearly) inside the span is dropped
-      double nx = 0.0;
-      HIP_TRY(h, bse::colnorms(x, 1, S.ld, S.n, cp, S.nrm, S.s));
-      HIP_TRY(h, hipMemcpyAsync(&nx, S.nrm, sizeof(double), hipMemcpyDeviceToHost, S.s));
+      HIP_TRY(h, bse::colnorms(t, 1, ld2, n2, dpart, nrm + 1, S.s));
+      double nb[2];
+      HIP_TRY(h, hipMemcpyAsync(nb, nrm, sizeof(double) * 2, hipMemcpyDeviceToHost, S.s));
       HIP_TRY(h, hipStreamSynchronize(S.s));
-      if (!(nx > 1e-8 * rr[a])) continue;
-      if ((st = pass(S, ar, 1, x, col(S.P, s)))) return st;
-      HIP_TRY(h, bse::normalize(x, col(S.P, s), S.n, nullptr, nullptr, 0, nullptr, S.beta, 0, S.flag, S.red,
-                                S.s));
-      double bt = 0.0;
-      HIP_TRY(h, hipMemcpyAsync(&bt, S.beta, sizeof(double), hipMemcpyDeviceToHost, S.s));
-      if ((st = check_flag(S))) return st;
-      if (!(bt > 0.0)) continue;  // direction already in the span
-      if ((st = pass(S, ar, 2, col(S.P, s), col(S.KP, s)))) return st;
-      if ((st = gram_cols(s, s + 1))) return st;
+      // a direction (nearly) inside the span is dropped
+      if (!(nb[1] > 1e-10 * nb[0])) continue;
+      HIP_TRY(h, bse::normalize(t, nullptr, n2, nullptr, nullptr, 0, nullptr, nullptr, 0, nullptr, dpart, S.s));
       ++s;
     }
+    if (s == s_old) break;  // no new direction: stagnation
+    if ((st = mapply(s_old, s))) return st;
+    if ((st = gram(s_old, s))) return st;
   }
   out.converged = false;
+  HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, S.s));
+  HIP_TRY(h, bse::h_out(V, Om, ld, n, k, X, Y, S.s));
+  HIP_TRY(h, hipStreamSynchronize(S.s));
   return BSE_OK;
 }
 
@@ -804,7 +910,7 @@ bse_status bse_create(bse_handle* out, bse_kind kind, int64_t n, bse_storage sto
 bse_status bse_destroy(bse_handle h) {
   if (!h) return BSE_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  void* ptrs[] = {h->a, h->alo, h->b, h->blo, h->part, h->L.blkmap, h->X, h->Y, h->omega};
+  void* ptrs[] = {h->a, h->alo, h->b, h->blo, h->part, h->mhpart, h->L.blkmap, h->X, h->Y, h->omega};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -853,6 +959,16 @@ bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t n
   const int64_t n = h->n;
   const double2* xv = (const double2*)x;
   double2* yv = (double2*)y;
+  if (op == BSE_OP_H && ar != bse::AR_HI) {
+    // fused: two vectors per read of A and B
+    if (bse_status st = ensure_mhpart(h)) return st;
+    for (int64_t c = 0; c < nvec; c += 2) {
+      const int nh = (int)std::min<int64_t>(2, nvec - c);
+      HIP_TRY(h, bse::mh_apply(h->L, ar, mp, nh, xv + (size_t)c * 2 * n, 2 * n, n, h->mhpart,
+                               yv + (size_t)c * 2 * n, -1.0, h->stream));
+    }
+    return BSE_OK;
+  }
   for (int64_t c = 0; c < nvec; ++c) {
     if (op == BSE_OP_H) {
       const double2* xt = xv + (size_t)c * 2 * n;
@@ -967,13 +1083,8 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
       const int s0 = from32 ? std::min(S.keep, k + std::max(4, k / 8)) : k;
       RefineOut ro;
       const double tf = now_ms();
-      st = refine_ph(S, s0, tol, 200, ro);
+      st = refine_h(S, s0, R.theta, tol, 200, omega, (double2*)x, (double2*)y, ro);
       if (st) return st;
-      std::vector<double> om(k);
-      for (int i = 0; i < k; ++i) om[i] = sqrt(ro.theta[i]);
-      HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, S.s));
-      HIP_TRY(h, bse::ph_vectors(S.U, S.P, S.ld, omega, k, S.n, (double2*)x, (double2*)y, S.s));
-      HIP_TRY(h, hipStreamSynchronize(S.s));
       ms_final += now_ms() - tf;
       rel = ro.rel;
       max_rel = 0.0;
@@ -1056,6 +1167,9 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
     stats->samples_fp64 = S.samples64;
     stats->ms_block_fp32 = S.ms_blk32;
     stats->ms_block_fp64 = S.ms_blk64;
+    stats->samples_fused = S.samples_mh;
+    stats->ms_block_fused = S.ms_mh;
+    stats->fused_vectors = S.mh_vectors;
   }
   if (!converged)
     return fail(h, BSE_ERR_NOT_CONVERGED, "max_restarts reached before all pairs met tol");

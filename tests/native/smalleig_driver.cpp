@@ -1,0 +1,33 @@
+// Test driver for the host eigensolvers of the library (sym_eig, herm_eig):
+// reads "kind m" and a column-major matrix (real, or re im pairs) from
+// stdin, prints the eigenvalues and eigenvectors.
+#include <hip/hip_runtime.h>
+#include <cstdio>
+#include <vector>
+
+#include "../../paper_2504_10096_amd/csrc/bse_internal.h"
+
+int main() {
+  char kind[8];
+  int m;
+  while (scanf("%7s %d", kind, &m) == 2) {
+    std::vector<double> w(m);
+    if (kind[0] == 's') {
+      std::vector<double> a((size_t)m * m), z((size_t)m * m);
+      for (auto& v : a) scanf("%lf", &v);
+      const bool ok = bse::sym_eig(m, a.data(), w.data(), z.data());
+      printf("%d\n", ok ? 1 : 0);
+      for (double v : w) printf("%.17g\n", v);
+      for (double v : z) printf("%.17g\n", v);
+    } else {
+      std::vector<double2> a((size_t)m * m), z((size_t)m * m);
+      for (auto& v : a) scanf("%lf %lf", &v.x, &v.y);
+      const bool ok = bse::herm_eig(m, a.data(), w.data(), z.data());
+      printf("%d\n", ok ? 1 : 0);
+      for (double v : w) printf("%.17g\n", v);
+      for (auto& v : z) printf("%.17g %.17g\n", v.x, v.y);
+    }
+    fflush(stdout);
+  }
+  return 0;
+}
