@@ -110,13 +110,14 @@ hipError_t zgemm_mfma(int64_t M, int N, int K, const double2* A, int64_t lda, co
 // FP64 refinement on the full H (columns [top; bottom], each half ld long,
 // column stride 2 ld, n entries used per half):
 //   resid_h: R[:, c] = diag(I, -I) MV[:, c] - om[c] V[:, c] for c < ncol;
-//   precond_h: t = (diag(d, -d) - om)^{-1} r, |denominators| >= floor;
+//   precond_h: t = (diag(d, -d) - om)^{-1} r (two != 0; else diag(d) on the
+//   top half only), |denominators| >= floor;
 //   h_out: X[:, c] = sqrt(om_c) V_top, Y[:, c] = sqrt(om_c) V_bottom (ld n);
 //   diag_a: d = diag(A) in FP64 from the stored blocks.
 hipError_t resid_h(const double2* MV, const double2* V, const double* om, int64_t ld, int64_t n, int ncol,
                    double2* R, hipStream_t s);
 hipError_t precond_h(const double2* r, const double* d, double om, double floor, int64_t ld, int64_t n,
-                     double2* t, hipStream_t s);
+                     int two, double2* t, hipStream_t s);
 hipError_t h_out(const double2* V, const double* om, int64_t ld, int64_t n, int k, double2* X, double2* Y,
                  hipStream_t s);
 hipError_t diag_a(const Layout& L, Arith ar, const void* a, const void* alo, double* d, hipStream_t s);

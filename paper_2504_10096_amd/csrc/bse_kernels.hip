@@ -844,18 +844,23 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // Diagonal correction t = (D - om)^{-1} r, D = diag(d, -d) the diagonal of H
-// (d = diag A); denominators are kept at least floor in magnitude.
+// (two != 0) or D = diag(d) (TDA), d = diag A; denominators are kept at
+// least floor in magnitude.
 __global__ void __launch_bounds__(kThreads)
     precond_h_kernel(const double2* __restrict__ r, const double* __restrict__ d, double om,
-                     double floor, int64_t ld, int64_t n, double2* __restrict__ t) {
+                     double floor, int64_t ld, int64_t n, int two, double2* __restrict__ t) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
-  double dt = d[i] - om, db = -d[i] - om;
+  double dt = d[i] - om;
   if (fabs(dt) < floor) dt = dt < 0.0 ? -floor : floor;
-  if (fabs(db) < floor) db = db < 0.0 ? -floor : floor;
-  const double2 a = r[i], b = r[i + ld];
+  const double2 a = r[i];
   t[i] = make_double2(a.x / dt, a.y / dt);
-  t[i + ld] = make_double2(b.x / db, b.y / db);
+  if (two) {
+    double db = -d[i] - om;
+    if (fabs(db) < floor) db = db < 0.0 ? -floor : floor;
+    const double2 b = r[i + ld];
+    t[i + ld] = make_double2(b.x / db, b.y / db);
+  }
 }
 
 // X[:, c] = sqrt(om_c) top of V[:, c], Y[:, c] = sqrt(om_c) bottom (leading dimension n).
@@ -1256,9 +1261,9 @@ hipError_t resid_h(const double2* MV, const double2* V, const double* om, int64_
 }
 
 hipError_t precond_h(const double2* r, const double* d, double om, double floor, int64_t ld, int64_t n,
-                     double2* t, hipStream_t s) {
+                     int two, double2* t, hipStream_t s) {
   hipLaunchKernelGGL(precond_h_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0,
-                     s, r, d, om, floor, ld, n, t);
+                     s, r, d, om, floor, ld, n, two, t);
   return hipGetLastError();
 }
 

@@ -564,30 +564,36 @@ struct RefineOut {
   bool converged = false;
 };
 
-// FP64 refinement of the pseudo-Hermitian pairs on the full H = Omega M
-// (M = [A B; conj(B) conj(A)] positive definite, Omega = diag(I, -I)),
-// started from the folded Ritz pairs (u~, p~, omega^2) in columns 0..s0-1
-// of U, P.  The structure-preserving projection of H onto a complex
+// FP64 refinement of the wanted pairs, started from the Ritz pairs in
+// columns 0..s0-1 of the Lanczos basis.  TDA: Rayleigh-Ritz of A on a
+// complex subspace (V^H A V y = lambda V^H V y), the k lowest kept.
+// PH: on the full H = Omega M (M = [A B; conj(B) conj(A)] positive
+// definite, Omega = diag(I, -I)), started from the folded Ritz pairs
+// (u~, p~, omega^2) of U, P.  The structure-preserving projection of H onto a complex
 // subspace span(V) is the Hermitian pencil (V^H Omega V, V^H M V) with a
 // positive definite second matrix: its eigenvalues mu are 1/omega, real,
 // and the largest positive ones give the lowest positive omega.  Because
 // the subspace is complex, v and i v are the same direction and no Ritz
 // value is doubled.  Each unconverged wanted pair expands the subspace by
-// its residual H v - omega v scaled by the inverse of diag(H) - omega
-// (diagonal correction; BSE matrices are diagonally dominant), orthogonal to
-// V.  M V is formed explicitly by FP64 passes, so the residuals are the
-// FP64 residuals of H.  On convergence X, Y hold sqrt(omega) times the top
-// and bottom of v, normalized so that X^H X - Y^H Y = 1 per pair.
+// its residual H v - omega v (TDA: A v - lambda v) scaled by the inverse of
+// diag(H) - omega (diagonal correction; BSE matrices are diagonally
+// dominant), orthogonal to V.  M V (A V) is formed explicitly by FP64 passes,
+// so the residuals are the FP64 residuals.  On convergence X (and Y) hold
+// the vectors: TDA orthonormal; PH sqrt(omega) times the top and bottom of
+// v, normalized so that X^H X - Y^H Y = 1 per pair.
 bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double tol, int max_iter,
                     double* omega, double2* X, double2* Y, RefineOut& out) {
   bse_handle h = S.h;
   const Arith ar = fp64_arith(h);
   const int k = S.k;
-  const int64_t n = S.n, ld = S.ld, ld2 = 2 * S.ld, n2 = S.ld + S.n;
-  const int cap = (int)std::min<int64_t>(2 * n, std::max(s0, k) + 2 * k + 16);
+  const bool ph = S.ph;
+  // PH columns hold [top (ld); bottom (ld)]; TDA columns are plain N-vectors
+  const int64_t n = S.n, ld = S.ld, ld2 = ph ? 2 * S.ld : S.ld, n2 = ph ? S.ld + S.n : S.n;
+  const int cap = (int)std::min<int64_t>(ph ? 2 * n : n, std::max(s0, k) + 2 * k + 16);
   if (s0 < k || s0 > cap) return fail(h, BSE_ERR_BAD_STATE, "refinement start size");
   DevBuf bV, bMV, bV2, bMV2, bR, bPart, bH, bD, bOm, bC, bG, bSt, bSb, bNrm;
-  if (bse_status e = ensure_mhpart(h)) return e;
+  if (ph)
+    if (bse_status e = ensure_mhpart(h)) return e;
   const size_t colb = sizeof(double2) * (size_t)ld2;
   struct {
     DevBuf* b;
@@ -628,8 +634,13 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   HIP_TRY(h, bse::diag_a(h->L, ar, h->a, h->alo, D, S.s));
   auto col = [&](double2* base, int c) { return base + (size_t)c * ld2; };
   // M v = [A x + B y; conj(A conj(y) + B conj(x))] for columns [c0, c1),
-  // two vectors per read of the stored A and B
+  // two vectors per read of the stored A and B (TDA: A v, one per pass)
   auto mapply = [&](int c0, int c1) -> bse_status {
+    if (!ph) {
+      for (int c = c0; c < c1; ++c)
+        if (bse_status e = pass(S, ar, 0, col(V, c), col(MV, c))) return e;
+      return BSE_OK;
+    }
     for (int c = c0; c < c1; c += 2) {
       const int nh = std::min(2, c1 - c);
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -648,14 +659,22 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     return BSE_OK;
   };
   std::vector<cplx> G((size_t)cap * cap, 0.0), Sm((size_t)cap * cap, 0.0);
-  // Gram columns [c0, c1): G[:, c] = V^H M v_c, Sm[:, c] = V^H Omega v_c
+  // Gram columns [c0, c1) of the pencil (Sm, G), G positive definite:
+  // PH G[:, c] = V^H M v_c, Sm[:, c] = V^H Omega v_c; TDA G[:, c] = V^H v_c,
+  // Sm[:, c] = V^H A v_c
   auto gram = [&](int c0, int c1) -> bse_status {
     if (c1 <= c0) return BSE_OK;
     for (int c = c0; c < c1; ++c) {
-      HIP_TRY(h, bse::cdot(V, c + 1, nullptr, 0, ld2, col(MV, c), n2, part, Gd + (size_t)c * cap, S.s));
-      HIP_TRY(h, bse::cdot(V, c + 1, nullptr, 0, ld2, col(V, c), n, part, Std + (size_t)c * cap, S.s));
-      HIP_TRY(h, bse::cdot(V + ld, c + 1, nullptr, 0, ld2, col(V, c) + ld, n, part, Sbd + (size_t)c * cap,
-                           S.s));
+      if (ph) {
+        HIP_TRY(h, bse::cdot(V, c + 1, nullptr, 0, ld2, col(MV, c), n2, part, Gd + (size_t)c * cap, S.s));
+        HIP_TRY(h, bse::cdot(V, c + 1, nullptr, 0, ld2, col(V, c), n, part, Std + (size_t)c * cap, S.s));
+        HIP_TRY(h, bse::cdot(V + ld, c + 1, nullptr, 0, ld2, col(V, c) + ld, n, part,
+                             Sbd + (size_t)c * cap, S.s));
+      } else {
+        HIP_TRY(h, bse::cdot(V, c + 1, nullptr, 0, ld2, col(V, c), n, part, Gd + (size_t)c * cap, S.s));
+        HIP_TRY(h, bse::cdot(V, c + 1, nullptr, 0, ld2, col(MV, c), n, part, Std + (size_t)c * cap, S.s));
+        HIP_TRY(h, hipMemsetAsync(Sbd + (size_t)c * cap, 0, sizeof(double2) * (c + 1), S.s));
+      }
     }
     const size_t cnt = (size_t)(c1 - c0) * cap;
     std::vector<double2> g(cnt), st(cnt), sb(cnt);
@@ -678,16 +697,29 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
       }
     return BSE_OK;
   };
-  // starting vectors v = [omega u + p; conj(omega u - p)] / (2 sqrt(omega))
-  std::vector<double> om0(s0);
-  for (int c = 0; c < s0; ++c) om0[c] = sqrt(std::max(theta0[c], 1e-300));
-  HIP_TRY(h, hipMemcpyAsync(Om, om0.data(), sizeof(double) * s0, hipMemcpyHostToDevice, S.s));
-  HIP_TRY(h, bse::ph_vectors(S.U, S.P, ld, Om, s0, n, V, V + ld, ld2, S.s));
+  // starting vectors: PH v = [omega u + p; conj(omega u - p)] / (2 sqrt(omega)); TDA the Ritz vectors
+  if (ph) {
+    std::vector<double> om0(s0);
+    for (int c = 0; c < s0; ++c) om0[c] = sqrt(std::max(theta0[c], 1e-300));
+    HIP_TRY(h, hipMemcpyAsync(Om, om0.data(), sizeof(double) * s0, hipMemcpyHostToDevice, S.s));
+    HIP_TRY(h, bse::ph_vectors(S.U, S.P, ld, Om, s0, n, V, V + ld, ld2, S.s));
+  } else {
+    HIP_TRY(h, bse::copy_cols(S.U, ld, V, ld2, n, s0, S.s));
+  }
   bse_status st;
   if ((st = mapply(0, s0))) return st;
   if ((st = gram(0, s0))) return st;
   int s = s0;
   std::vector<double> om(k), rr(k), vv(k);
+  auto write_out = [&]() -> bse_status {
+    HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, S.s));
+    if (ph)
+      HIP_TRY(h, bse::h_out(V, Om, ld, n, k, X, Y, S.s));
+    else
+      HIP_TRY(h, bse::copy_cols(V, ld2, X, n, n, k, S.s));
+    HIP_TRY(h, hipStreamSynchronize(S.s));
+    return BSE_OK;
+  };
   for (int iter = 0; iter < max_iter; ++iter) {
     // projected pencil: Sm y = mu G y, via G = L L^H and L^{-1} Sm L^{-H}
     std::vector<cplx> L((size_t)s * s), C((size_t)s * s), Z((size_t)s * s);
@@ -696,8 +728,11 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
         L[(size_t)j * s + i] = G[(size_t)j * cap + i];
         C[(size_t)j * s + i] = Sm[(size_t)j * cap + i];
       }
-    if (!zchol(s, L.data()))
-      return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "V^H M V is not positive definite: M is not positive definite");
+    if (!zchol(s, L.data())) {
+      if (ph)
+        return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "V^H M V is not positive definite: M is not positive definite");
+      return fail(h, BSE_ERR_DEVICE, "refinement basis lost rank");
+    }
     zlsolve(s, L.data(), C.data(), s);  // L^{-1} Sm
     for (int j = 0; j < s; ++j)         // conjugate transpose: Sm L^{-H}
       for (int i = j; i < s; ++i) {
@@ -718,16 +753,17 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     std::vector<double> mu(s);
     if (!bse::herm_eig(s, reinterpret_cast<double2*>(C.data()), mu.data(), reinterpret_cast<double2*>(Z.data())))
       return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
-    // descending mu = ascending positive omega; drop the negative branch
+    // PH: descending mu = ascending positive omega, the negative branch is
+    // dropped; TDA: ascending lambda
     int npos = 0;
     for (double m_ : mu) npos += m_ > 0.0;
-    if (npos < k)
+    if (ph && npos < k)
       return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "fewer than k positive Ritz values in the refinement");
-    const int sk = npos;
+    const int sk = ph ? npos : s;
     std::vector<cplx> Yc((size_t)s * sk);
     std::vector<double> mud(sk);
     for (int c = 0; c < sk; ++c) {
-      const int src = s - 1 - c;
+      const int src = ph ? s - 1 - c : c;
       mud[c] = mu[src];
       for (int i = 0; i < s; ++i) Yc[(size_t)c * s + i] = Z[(size_t)src * s + i];
     }
@@ -744,9 +780,12 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
       G[(size_t)i * cap + i] = 1.0;
       Sm[(size_t)i * cap + i] = mud[i];
     }
-    for (int c = 0; c < k; ++c) om[c] = 1.0 / mud[c];
+    for (int c = 0; c < k; ++c) om[c] = ph ? 1.0 / mud[c] : mud[c];
     HIP_TRY(h, hipMemcpyAsync(Om, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, S.s));
-    HIP_TRY(h, bse::resid_h(MV, V, Om, ld, n, k, R, S.s));
+    if (ph)
+      HIP_TRY(h, bse::resid_h(MV, V, Om, ld, n, k, R, S.s));
+    else
+      HIP_TRY(h, bse::resid_cols(MV, V, Om, ld2, n, k, R, S.s));
     HIP_TRY(h, bse::colnorms(R, k, ld2, n2, dpart, nrm, S.s));
     HIP_TRY(h, bse::colnorms(V, k, ld2, n2, dpart, nrm + k, S.s));
     HIP_TRY(h, hipMemcpyAsync(rr.data(), nrm, sizeof(double) * k, hipMemcpyDeviceToHost, S.s));
@@ -756,7 +795,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     out.rel.assign(k, 0.0);
     std::vector<int> bad;
     for (int c = 0; c < k; ++c) {
-      out.rel[c] = sqrt(rr[c]) / (om[c] * sqrt(vv[c]));
+      out.rel[c] = sqrt(rr[c]) / (std::max(fabs(om[c]), 1e-300) * sqrt(vv[c]));
       if (!std::isfinite(out.rel[c])) return fail(h, BSE_ERR_NONFINITE, "non-finite refinement residual");
       if (out.rel[c] > tol) bad.push_back(c);
     }
@@ -767,11 +806,8 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
               (int)bad.size());
     }
     if (bad.empty()) {
-      HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, S.s));
-      HIP_TRY(h, bse::h_out(V, Om, ld, n, k, X, Y, S.s));
-      HIP_TRY(h, hipStreamSynchronize(S.s));
       out.converged = true;
-      return BSE_OK;
+      return write_out();
     }
     if (iter + 1 == max_iter) break;
     // room for the expansion: drop the highest Ritz vectors if needed
@@ -780,7 +816,8 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     for (int a : bad) {
       if (s >= cap) break;
       double2* t = col(V, s);
-      HIP_TRY(h, bse::precond_h(R + (size_t)a * ld2, D, om[a], 1e-3 * om[a], ld, n, t, S.s));
+      HIP_TRY(h, bse::precond_h(R + (size_t)a * ld2, D, om[a], 1e-3 * std::max(fabs(om[a]), 1e-300), ld, n,
+                                ph ? 1 : 0, t, S.s));
       HIP_TRY(h, bse::colnorms(t, 1, ld2, n2, dpart, nrm, S.s));
       for (int it = 0; it < 2; ++it) {
         HIP_TRY(h, bse::cdot(V, s, nullptr, 0, ld2, t, n2, part, H, S.s));
@@ -800,23 +837,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     if ((st = gram(s_old, s))) return st;
   }
   out.converged = false;
-  HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * k, hipMemcpyHostToDevice, S.s));
-  HIP_TRY(h, bse::h_out(V, Om, ld, n, k, X, Y, S.s));
-  HIP_TRY(h, hipStreamSynchronize(S.s));
-  return BSE_OK;
-}
-
-// Phase switch / warm start: column 0 <- sum_i c_i U[:, i] over the k wanted Ritz vectors.
-bse_status warm_start_vector(Solver& S) {
-  bse_handle h = S.h;
-  std::vector<double2> wts(S.k);
-  for (int i = 0; i < S.k; ++i) wts[i] = make_double2(-(1.0 + 0.37 * i / S.k), 0.0);
-  HIP_TRY(h, hipMemcpyAsync(S.H1, wts.data(), sizeof(double2) * S.k, hipMemcpyHostToDevice, S.s));
-  HIP_TRY(h, hipMemsetAsync(S.W, 0, sizeof(double2) * S.ld, S.s));
-  HIP_TRY(h, bse::cgemv_sub(S.U, S.k, nullptr, 0, nullptr, nullptr, S.ld, S.H1, 1, S.W, nullptr, S.n,
-                            S.s));
-  HIP_TRY(h, hipMemcpyAsync(S.U, S.W, sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
-  return BSE_OK;
+  return write_out();
 }
 
 }  // namespace
@@ -1071,9 +1092,10 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
               R.theta[k - 1], R.est[0], emax, nc, tol_int);
     }
     if (!all && !full_space) continue;
-    if (ph) {
-      // FP64 block refinement + exact FP64 residuals (after the FP32 phase,
-      // or as the final Rayleigh-Ritz of the FP64 iteration)
+    if (ph || ar == bulk) {
+      // FP64 block refinement + exact FP64 residuals (after the bulk phase
+      // over the complex64 triangles, or, PH, as the final Rayleigh-Ritz of
+      // the FP64 iteration)
       const bool from32 = ar == bulk;
       HIP_TRY(h, hipStreamSynchronize(S.s));
       if (from32) {
@@ -1083,7 +1105,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
       const int s0 = from32 ? std::min(S.keep, k + std::max(4, k / 8)) : k;
       RefineOut ro;
       const double tf = now_ms();
-      st = refine_h(S, s0, R.theta, tol, 200, omega, (double2*)x, (double2*)y, ro);
+      st = refine_h(S, s0, R.theta, tol, 200, omega, (double2*)x, ph ? (double2*)y : nullptr, ro);
       if (st) return st;
       ms_final += now_ms() - tf;
       rel = ro.rel;
@@ -1096,20 +1118,6 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
       ar = fp64_arith(h);
       converged = ro.converged;
       break;
-    }
-    if (ar == bulk) {
-      // FP32 phase done: warm start of the FP64 phase from the wanted Ritz vectors
-      HIP_TRY(h, hipStreamSynchronize(S.s));
-      ms32 += now_ms() - t_phase;
-      t_phase = now_ms();
-      ar = fp64_arith(h);
-      tol_int = tol;
-      st = warm_start_vector(S);
-      if (st) return st;
-      st = init_basis(S, ar);
-      if (st) return st;
-      jstart = 0;
-      continue;
     }
     // verify with FP64 residuals
     const double tf = now_ms();
