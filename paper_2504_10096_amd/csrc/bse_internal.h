@@ -60,6 +60,13 @@ hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const d
                     int64_t ldh, double2* part, double2* MV, double bsign, hipStream_t s,
                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// A x_q for nv (1..4) vectors in one read of the stored A, FP64 arithmetic
+// (ar: AR_C128, AR_HILO or AR_HI64); column q of V and MV at q ldv.  part:
+// mh_part_elems(L, 2) complex entries suffice (nv <= 2 nh).
+hipError_t ma_apply(const Layout& L, Arith ar, const MatPtrs& m, int nv, const double2* V, int64_t ldv,
+                    double2* part, double2* MV, hipStream_t s, hipEvent_t ev0 = nullptr,
+                    hipEvent_t ev1 = nullptr);
+
 // Copy packed-upper columns [j0, j1) into block storage (see Layout).
 hipError_t ingest(const Layout& L, bool is_a, bool hilo, const void* src, bool src_c64, int64_t j0,
                   int64_t j1, void* dst, void* dst_lo, hipStream_t s);

@@ -372,13 +372,100 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// Sum of the full-H partials; output 2q goes to the top of column q of MV,
-// output 2q+1 conjugated and times bsign to its bottom (bsign = 1: M v;
-// -1: H v).  Grid (ceil(n / 256), 2 NH).
+// A x_q for NV vectors in one read of A (the TDA counterpart of
+// mh_block_kernel, same slicing and partial layout): row r gains A_rc x_c,
+// column c gains conj(A_rc) x_r.
+template <int R, int AR, int NV>
+__global__ void __launch_bounds__(kThreads)
+    ma_block_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
+                    const int2* __restrict__ blkmap, int64_t nblk, int64_t n,
+                    const double2* __restrict__ V, int64_t ldv,
+                    double2* __restrict__ rowpart, double2* __restrict__ colpart) {
+  constexpr int RS = R < 256 ? R : 256;
+  constexpr int NS = R / RS;
+  constexpr int RPL = RS / 64;
+  constexpr int CPW = R / 4;
+  __shared__ double2 sh[4][RS];
+
+  const int blk = blockIdx.x;
+  const int slice = blockIdx.y;
+  const int2 pq = blkmap[blk];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
+  const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
+
+  double xr[NV][RPL], xi[NV][RPL], rr[NV][RPL], ri[NV][RPL];
+#pragma unroll
+  for (int q = 0; q < NV; ++q)
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      const int64_t i = row0 + lane + 64 * p;
+      const double2 x = (i < n) ? V[(size_t)q * ldv + i] : make_double2(0.0, 0.0);
+      xr[q][p] = x.x;
+      xi[q][p] = x.y;
+      rr[q][p] = 0.0;
+      ri[q][p] = 0.0;
+    }
+
+  for (int cc = 0; cc < CPW; ++cc) {
+    const int c = wave * CPW + cc;
+    const int64_t j = col0 + c;
+    double cxr[NV], cxi[NV], sr[NV], si[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double2 x = (j < n) ? V[(size_t)q * ldv + j] : make_double2(0.0, 0.0);
+      cxr[q] = x.x;
+      cxi[q] = x.y;
+      sr[q] = 0.0;
+      si[q] = 0.0;
+    }
+    const size_t cbase = base + (size_t)c * R + lane;
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+      double ar, ai;
+      Elem<AR>::load(a0, a1, cbase + 64 * p, ar, ai);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        rr[q][p] += ar * cxr[q] - ai * cxi[q];
+        ri[q][p] += ar * cxi[q] + ai * cxr[q];
+        sr[q] += ar * xr[q][p] + ai * xi[q][p];
+        si[q] += ar * xi[q][p] - ai * xr[q][p];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
+      if (lane == 0) colpart[(((size_t)q * nblk + blk) * NS + slice) * R + c] = make_double2(tr, ti);
+    }
+  }
+
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) sh[wave][lane + 64 * p] = make_double2(rr[q][p], ri[q][p]);
+    __syncthreads();
+    for (int r = threadIdx.x; r < RS; r += kThreads) {
+      double2 t = sh[0][r];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        t.x += sh[w][r].x;
+        t.y += sh[w][r].y;
+      }
+      rowpart[((size_t)q * nblk + blk) * R + slice * RS + r] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Sum of the partials of mh_block_kernel (pairs != 0: output 2q goes to the
+// top of column q of MV, output 2q+1 conjugated and times bsign to its
+// bottom; bsign = 1: M v, -1: H v) or of ma_block_kernel (pairs == 0:
+// output q to column q).  Grid (ceil(n / 256), outputs).
 __global__ void __launch_bounds__(kThreads)
     mh_reduce_kernel(const double2* __restrict__ rowpart, const double2* __restrict__ colpart, int R, int NS,
                      int nb, int64_t nblk, int64_t n, double2* __restrict__ MV, int64_t ldv, int64_t ldh,
-                     double bsign) {
+                     double bsign, int pairs) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int o = blockIdx.y;
   if (i >= n) return;
@@ -399,6 +486,10 @@ __global__ void __launch_bounds__(kThreads)
       sx += v.x;
       sy += v.y;
     }
+  }
+  if (!pairs) {
+    MV[(size_t)o * ldv + i] = make_double2(sx, sy);
+    return;
   }
   const int q = o >> 1;
   if (o & 1)
@@ -1161,7 +1252,81 @@ hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const d
   const double2* rowpart = part;
   const double2* colpart = part + (size_t)2 * nh * L.nblk * L.R;
   hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)(2 * nh)),
-                     dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, MV, ldv, ldh, bsign);
+                     dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, MV, ldv, ldh, bsign, 1);
+  return hipGetLastError();
+}
+
+template <int R, int AR>
+hipError_t launch_ma(int nv, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv, double2* part,
+                     hipStream_t s) {
+  constexpr int NS = R < 256 ? 1 : R / 256;
+  double2* rowpart = part;
+  double2* colpart = part + (size_t)nv * L.nblk * R;
+  const dim3 grid((unsigned)L.nblk, (unsigned)NS);
+  switch (nv) {
+    case 1:
+      hipLaunchKernelGGL((ma_block_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, L.blkmap, L.nblk,
+                         L.n, V, ldv, rowpart, colpart);
+      break;
+    case 2:
+      hipLaunchKernelGGL((ma_block_kernel<R, AR, 2>), grid, dim3(kThreads), 0, s, m.a, m.alo, L.blkmap, L.nblk,
+                         L.n, V, ldv, rowpart, colpart);
+      break;
+    case 3:
+      hipLaunchKernelGGL((ma_block_kernel<R, AR, 3>), grid, dim3(kThreads), 0, s, m.a, m.alo, L.blkmap, L.nblk,
+                         L.n, V, ldv, rowpart, colpart);
+      break;
+    default:
+      hipLaunchKernelGGL((ma_block_kernel<R, AR, 4>), grid, dim3(kThreads), 0, s, m.a, m.alo, L.blkmap, L.nblk,
+                         L.n, V, ldv, rowpart, colpart);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t dispatch_ma(Arith ar, int nv, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv,
+                       double2* part, hipStream_t s) {
+  if (ar == AR_C128) return launch_ma<R, AR_C128>(nv, L, m, V, ldv, part, s);
+  if (ar == AR_HI64) return launch_ma<R, AR_HI64>(nv, L, m, V, ldv, part, s);
+  return launch_ma<R, AR_HILO>(nv, L, m, V, ldv, part, s);
+}
+
+hipError_t ma_apply(const Layout& L, Arith ar, const MatPtrs& m, int nv, const double2* V, int64_t ldv,
+                    double2* part, double2* MV, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  if (nv < 1 || nv > 4 || ar == AR_HI) return hipErrorInvalidValue;
+  hipError_t e;
+  if (ev0) {
+    e = hipEventRecord(ev0, s);
+    if (e != hipSuccess) return e;
+  }
+  switch (L.R) {
+    case 64:
+      e = dispatch_ma<64>(ar, nv, L, m, V, ldv, part, s);
+      break;
+    case 128:
+      e = dispatch_ma<128>(ar, nv, L, m, V, ldv, part, s);
+      break;
+    case 256:
+      e = dispatch_ma<256>(ar, nv, L, m, V, ldv, part, s);
+      break;
+    case 512:
+      e = dispatch_ma<512>(ar, nv, L, m, V, ldv, part, s);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (ev1) {
+    e = hipEventRecord(ev1, s);
+    if (e != hipSuccess) return e;
+  }
+  const int ns = L.R < 256 ? 1 : L.R / 256;
+  const double2* rowpart = part;
+  const double2* colpart = part + (size_t)nv * L.nblk * L.R;
+  hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)nv),
+                     dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, MV, ldv, (int64_t)0, 1.0,
+                     0);
   return hipGetLastError();
 }
 

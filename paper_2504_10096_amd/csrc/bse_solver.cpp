@@ -592,8 +592,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   const int cap = (int)std::min<int64_t>(ph ? 2 * n : n, std::max(s0, k) + 2 * k + 16);
   if (s0 < k || s0 > cap) return fail(h, BSE_ERR_BAD_STATE, "refinement start size");
   DevBuf bV, bMV, bV2, bMV2, bR, bPart, bH, bD, bOm, bC, bG, bSt, bSb, bNrm;
-  if (ph)
-    if (bse_status e = ensure_mhpart(h)) return e;
+  if (bse_status e = ensure_mhpart(h)) return e;
   const size_t colb = sizeof(double2) * (size_t)ld2;
   struct {
     DevBuf* b;
@@ -634,15 +633,10 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   HIP_TRY(h, bse::diag_a(h->L, ar, h->a, h->alo, D, S.s));
   auto col = [&](double2* base, int c) { return base + (size_t)c * ld2; };
   // M v = [A x + B y; conj(A conj(y) + B conj(x))] for columns [c0, c1),
-  // two vectors per read of the stored A and B (TDA: A v, one per pass)
+  // two vectors per read of the stored A and B (TDA: A v, four per read)
   auto mapply = [&](int c0, int c1) -> bse_status {
-    if (!ph) {
-      for (int c = c0; c < c1; ++c)
-        if (bse_status e = pass(S, ar, 0, col(V, c), col(MV, c))) return e;
-      return BSE_OK;
-    }
-    for (int c = c0; c < c1; c += 2) {
-      const int nh = std::min(2, c1 - c);
+    for (int c = c0; c < c1; c += ph ? 2 : 4) {
+      const int nh = std::min(ph ? 2 : 4, c1 - c);
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (S.passes % 8 == 0 && S.ev_free.size() >= 2) {
         e1 = S.ev_free.back();
@@ -651,8 +645,11 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
         S.ev_free.pop_back();
         S.ev_mh.push_back({e0, e1});
       }
-      HIP_TRY(h, bse::mh_apply(h->L, ar, mat_ptrs(h), nh, col(V, c), ld2, ld, mhpart, col(MV, c), 1.0, S.s, e0,
-                               e1));
+      if (ph)
+        HIP_TRY(h, bse::mh_apply(h->L, ar, mat_ptrs(h), nh, col(V, c), ld2, ld, mhpart, col(MV, c), 1.0, S.s, e0,
+                                 e1));
+      else
+        HIP_TRY(h, bse::ma_apply(h->L, ar, mat_ptrs(h), nh, col(V, c), ld2, mhpart, col(MV, c), S.s, e0, e1));
       ++S.passes;
       S.mh_vectors += nh;
     }
