@@ -49,6 +49,11 @@ hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const d
                   const double2* vb, int conjb, double sb, double2* part, double2* out,
                   hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
+// Row slices per block of the one-vector pass, and the size (complex
+// entries) of its partial buffer.
+int mv_slices(const Layout& L);
+size_t mv_part_elems(const Layout& L);
+
 // Full-H products [A x_q + B y_q; bsign conj(A conj(y_q) + B conj(x_q))]
 // (bsign = 1: M v_q; bsign = -1: H v_q) for nh (1 or 2) vectors in one read
 // of the stored A and B, FP64 arithmetic (ar: AR_C128, AR_HILO or AR_HI64).

@@ -91,14 +91,70 @@ struct Elem<AR_HILO> {
 
 // ----------------------------------------------------------------- matvec
 //
-// One workgroup (4 waves) per stored R x R block (P, Q).  Wave w walks the
-// columns [w R/4, (w+1) R/4); lane l owns rows l + 64 q.  For each column c
-// the lane loads its R/64 entries (one contiguous 64-lane segment per load),
-// adds A_rc * x_c into its row accumulators and conj(A_rc) * x_r into the
-// column sum, which a wavefront reduction completes.  Row sums of the four
-// waves are combined through LDS.  Outputs are per-block partial vectors
-// (rows and columns) in FP64; a second kernel sums them in a fixed order, so
+// One workgroup (4 waves) per stored R x R block (P, Q) and slice of RS =
+// min(R, 256) rows (grid.y = R / RS slices: the per-lane row state stays
+// small enough for 4 waves per SIMD).  Wave w walks the columns
+// [w R/4, (w+1) R/4) of the block; in each column a lane owns VW adjacent
+// rows per 64 VW-row group (VW = 2 for the complex64 triangles: 16-byte
+// loads), so every load instruction reads one contiguous 64 VW-entry
+// segment.  The lane adds A_rc x_c into its row accumulators and
+// conj(A_rc) x_r into the column sum, which a wavefront reduction completes.
+// Row sums of the four waves are combined through LDS.  Outputs are
+// per-block partial vectors in FP64 (rows: rowpart[blk][R]; columns:
+// colpart[blk][slice][R]); mv_reduce_kernel sums them in a fixed order, so
 // the result is deterministic and each block is read once.
+template <int AR, int VW>
+struct Loader;
+template <int AR>
+struct Loader<AR, 1> {
+  using T = typename Elem<AR>::T;
+  __device__ static __forceinline__ void load(const void* p, const void* q, size_t i, T* re, T* im) {
+    Elem<AR>::load(p, q, i, re[0], im[0]);
+  }
+};
+typedef float nf4 __attribute__((ext_vector_type(4)));
+template <>
+struct Loader<AR_HI, 2> {
+  __device__ static __forceinline__ void load(const void* p, const void*, size_t i, float* re, float* im) {
+    const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(static_cast<const nf2*>(p) + i));
+    re[0] = v.x;
+    im[0] = v.y;
+    re[1] = v.z;
+    im[1] = v.w;
+  }
+};
+template <>
+struct Loader<AR_HI64, 2> {
+  __device__ static __forceinline__ void load(const void* p, const void*, size_t i, double* re, double* im) {
+    const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(static_cast<const nf2*>(p) + i));
+    re[0] = (double)v.x;
+    im[0] = (double)v.y;
+    re[1] = (double)v.z;
+    im[1] = (double)v.w;
+  }
+};
+template <>
+struct Loader<AR_HILO, 2> {
+  __device__ static __forceinline__ void load(const void* p, const void* q, size_t i, double* re, double* im) {
+    const nf4 h = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(static_cast<const nf2*>(p) + i));
+    const nf4 l = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(static_cast<const nf2*>(q) + i));
+    re[0] = (double)h.x + (double)l.x;
+    im[0] = (double)h.y + (double)l.y;
+    re[1] = (double)h.z + (double)l.z;
+    im[1] = (double)h.w + (double)l.w;
+  }
+};
+
+// entries per lane-load: two complex64 (16 bytes) where a slice has >= 128 rows
+template <int R, int AR>
+struct MvShape {
+  static constexpr int RS = R < 256 ? R : 256;
+  static constexpr int NS = R / RS;
+  static constexpr int VW = (AR != AR_C128 && RS >= 128) ? 2 : 1;
+  static constexpr int G = RS / (64 * VW);
+  static constexpr int RPL = G * VW;
+};
+
 template <int R, int AR, int BM>
 __global__ void __launch_bounds__(kThreads)
     mv_block_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
@@ -107,40 +163,46 @@ __global__ void __launch_bounds__(kThreads)
                     int conja, const double2* __restrict__ vb, int conjb, double sb,
                     double2* __restrict__ rowpart, double2* __restrict__ colpart) {
   using T = typename Elem<AR>::T;
-  constexpr int RPL = R / 64;
+  using Sh = MvShape<R, AR>;
+  constexpr int RS = Sh::RS, NS = Sh::NS, VW = Sh::VW, G = Sh::G, RPL = Sh::RPL;
   constexpr int CPW = R / 4;
-  __shared__ double2 sh[4][R];
+  __shared__ double2 sh[4][RS];
 
   const int blk = blockIdx.x;
+  const int slice = blockIdx.y;
   const int2 pq = blkmap[blk];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t row0 = (int64_t)pq.x * R, col0 = (int64_t)pq.y * R;
-  const size_t base = (size_t)blk * R * R;
+  const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
+  const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
   const T ca = conja ? T(-1) : T(1);
   const T cb = conjb ? T(-1) : T(1);
   const T tsb = (T)sb;
 
-  // Row-side inputs x_r (and the explicit B input).
+  // Row-side inputs x_r (and the explicit B input); lane row (g, e) is
+  // slice row g 64 VW + lane VW + e.
   T xar[RPL], xai[RPL], xbr[RPL], xbi[RPL];
 #pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const int64_t i = row0 + lane + 64 * q;
-    double2 v = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0);
-    if (i < n) {
-      v = va[i];
-      if (BM == BM_EXPLICIT) w = vb[i];
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const int q = g * VW + e;
+      const int64_t i = row0 + g * 64 * VW + lane * VW + e;
+      double2 v = make_double2(0.0, 0.0), w = make_double2(0.0, 0.0);
+      if (i < n) {
+        v = va[i];
+        if (BM == BM_EXPLICIT) w = vb[i];
+      }
+      xar[q] = (T)v.x;
+      xai[q] = ca * (T)v.y;
+      if (BM == BM_EXPLICIT) {
+        xbr[q] = tsb * (T)w.x;
+        xbi[q] = tsb * cb * (T)w.y;
+      } else {
+        xbr[q] = T(0);
+        xbi[q] = T(0);
+      }
     }
-    xar[q] = (T)v.x;
-    xai[q] = ca * (T)v.y;
-    if (BM == BM_EXPLICIT) {
-      xbr[q] = tsb * (T)w.x;
-      xbi[q] = tsb * cb * (T)w.y;
-    } else {
-      xbr[q] = T(0);
-      xbi[q] = T(0);
-    }
-  }
 
   T rr[RPL], ri[RPL];
 #pragma unroll
@@ -168,29 +230,34 @@ __global__ void __launch_bounds__(kThreads)
       yci = tsb * cb * (T)wj.y;
     }
     T cr = T(0), ci = T(0), dr = T(0), di = T(0);
-    const size_t cbase = base + (size_t)c * R + lane;
+    const size_t cbase = base + (size_t)c * R + lane * VW;
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      T ar, ai;
-      Elem<AR>::load(a0, a1, cbase + 64 * q, ar, ai);
-      // row r: A_rc x_c
-      rr[q] += ar * xcr - ai * xci;
-      ri[q] += ar * xci + ai * xcr;
-      // column c: conj(A_rc) x_r
-      cr += ar * xar[q] + ai * xai[q];
-      ci += ar * xai[q] - ai * xar[q];
-      if (BM != BM_NONE) {
-        T br, bi;
-        Elem<AR>::load(b0, b1, cbase + 64 * q, br, bi);
-        rr[q] += br * ycr - bi * yci;
-        ri[q] += br * yci + bi * ycr;
-        if (BM == BM_CONJ) {
-          // column c: B_rc conj(x_r) (the sign sb is applied after the sum)
-          dr += br * xar[q] + bi * xai[q];
-          di += bi * xar[q] - br * xai[q];
-        } else {
-          dr += br * xbr[q] - bi * xbi[q];
-          di += br * xbi[q] + bi * xbr[q];
+    for (int g = 0; g < G; ++g) {
+      T are[VW], aim[VW], bre[VW], bim[VW];
+      Loader<AR, VW>::load(a0, a1, cbase + g * 64 * VW, are, aim);
+      if (BM != BM_NONE) Loader<AR, VW>::load(b0, b1, cbase + g * 64 * VW, bre, bim);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int q = g * VW + e;
+        const T ar = are[e], ai = aim[e];
+        // row r: A_rc x_c
+        rr[q] += ar * xcr - ai * xci;
+        ri[q] += ar * xci + ai * xcr;
+        // column c: conj(A_rc) x_r
+        cr += ar * xar[q] + ai * xai[q];
+        ci += ar * xai[q] - ai * xar[q];
+        if (BM != BM_NONE) {
+          const T br = bre[e], bi = bim[e];
+          rr[q] += br * ycr - bi * yci;
+          ri[q] += br * yci + bi * ycr;
+          if (BM == BM_CONJ) {
+            // column c: B_rc conj(x_r) (the sign sb is applied after the sum)
+            dr += br * xar[q] + bi * xai[q];
+            di += bi * xar[q] - br * xai[q];
+          } else {
+            dr += br * xbr[q] - bi * xbi[q];
+            di += br * xbi[q] + bi * xbr[q];
+          }
         }
       }
     }
@@ -203,20 +270,25 @@ __global__ void __launch_bounds__(kThreads)
     }
     cr = wave_sum(cr);
     ci = wave_sum(ci);
-    if (lane == 0) colpart[(size_t)blk * R + c] = make_double2((double)cr, (double)ci);
+    if (lane == 0) colpart[((size_t)blk * NS + slice) * R + c] = make_double2((double)cr, (double)ci);
   }
 
 #pragma unroll
-  for (int q = 0; q < RPL; ++q) sh[wave][lane + 64 * q] = make_double2((double)rr[q], (double)ri[q]);
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const int q = g * VW + e;
+      sh[wave][g * 64 * VW + lane * VW + e] = make_double2((double)rr[q], (double)ri[q]);
+    }
   __syncthreads();
-  for (int r = threadIdx.x; r < R; r += kThreads) {
-    double2 s = sh[0][r];
+  for (int r = threadIdx.x; r < RS; r += kThreads) {
+    double2 t = sh[0][r];
 #pragma unroll
     for (int w = 1; w < 4; ++w) {
-      s.x += sh[w][r].x;
-      s.y += sh[w][r].y;
+      t.x += sh[w][r].x;
+      t.y += sh[w][r].y;
     }
-    rowpart[(size_t)blk * R + r] = s;
+    rowpart[(size_t)blk * R + slice * RS + r] = t;
   }
 }
 
@@ -224,7 +296,7 @@ __global__ void __launch_bounds__(kThreads)
 //        + sum over the blocks of panel column P of their column partials.
 __global__ void __launch_bounds__(kThreads)
     mv_reduce_kernel(const double2* __restrict__ rowpart, const double2* __restrict__ colpart,
-                     int R, int nb, int64_t n, double2* __restrict__ out) {
+                     int R, int NS, int nb, int64_t n, double2* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   const int P = (int)(i / R), r = (int)(i % R);
@@ -237,9 +309,11 @@ __global__ void __launch_bounds__(kThreads)
   }
   for (int Q = 0; Q <= P; ++Q) {
     const int64_t qs = (int64_t)Q * nb - (int64_t)Q * (Q - 1) / 2;
-    const double2 v = colpart[(size_t)(qs + (P - Q)) * R + r];
-    sx += v.x;
-    sy += v.y;
+    for (int sl = 0; sl < NS; ++sl) {
+      const double2 v = colpart[((size_t)(qs + (P - Q)) * NS + sl) * R + r];
+      sx += v.x;
+      sy += v.y;
+    }
   }
   out[i] = make_double2(sx, sy);
 }
@@ -527,7 +601,8 @@ hipError_t launch_mv(const Layout& L, const MatPtrs& m, const double2* va, int c
                      const double2* vb, int conjb, double sb, double2* part, hipStream_t s) {
   double2* rowpart = part;
   double2* colpart = part + (size_t)L.nblk * L.R;
-  hipLaunchKernelGGL((mv_block_kernel<R, AR, BM>), dim3((unsigned)L.nblk), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL((mv_block_kernel<R, AR, BM>), dim3((unsigned)L.nblk, (unsigned)MvShape<R, AR>::NS),
+                     dim3(kThreads), 0, s,
                      m.a, m.alo, m.b, m.blo, L.blkmap, L.n, va, conja, vb, conjb, sb, rowpart,
                      colpart);
   return hipGetLastError();
@@ -1209,9 +1284,13 @@ hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const d
   const double2* rowpart = part;
   const double2* colpart = part + (size_t)L.nblk * L.R;
   hipLaunchKernelGGL(mv_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, s, rowpart, colpart, L.R, L.nb, L.n, out);
+                     dim3(kThreads), 0, s, rowpart, colpart, L.R, mv_slices(L), L.nb, L.n, out);
   return hipGetLastError();
 }
+
+int mv_slices(const Layout& L) { return L.R < 256 ? 1 : L.R / 256; }
+
+size_t mv_part_elems(const Layout& L) { return (size_t)L.nblk * L.R * (1 + mv_slices(L)); }
 
 size_t mh_part_elems(const Layout& L, int nh) {
   const int ns = L.R < 256 ? 1 : L.R / 256;

@@ -918,7 +918,7 @@ bse_status bse_create(bse_handle* out, bse_kind kind, int64_t n, bse_storage sto
     if (ph && (!alloc(&h->b, el * 8) || !alloc(&h->blo, el * 8)))
       return cleanup(BSE_ERR_OUT_OF_MEMORY);
   }
-  if (!alloc((void**)&h->part, sizeof(double2) * 2 * (size_t)L.nblk * L.R))
+  if (!alloc((void**)&h->part, sizeof(double2) * bse::mv_part_elems(L)))
     return cleanup(BSE_ERR_OUT_OF_MEMORY);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(BSE_ERR_DEVICE);
   *out = h;
