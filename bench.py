@@ -95,6 +95,7 @@ def main():
     p.add_argument("--check", choices=["on", "off"], default="on",
                    help="oracle FP64 residuals of sampled pairs (streaming, CPU)")
     p.add_argument("--chunk-gb", type=float, default=2.0)
+    p.add_argument("--block", type=int, default=0, help="TDA Lanczos block size (0: automatic)")
     p.add_argument("--precision", choices=["auto", "fp64"], default="auto",
                    help="auto: the mixed path where the workload uses it; fp64: FP64 passes only")
     p.add_argument("--mode", choices=["solve", "passbench", "copy"], default="solve",
@@ -119,6 +120,7 @@ def main():
         nel = int(args.copy_gb * 2 ** 30 / 8)
         a = torch.ones(nel, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
+        b.copy_(a)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -126,8 +128,17 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
+        # read-only stream of the same buffer (the pass kernels mostly read)
+        a.sum()
+        torch.cuda.synchronize()
+        e0.record()
+        s_ = a.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_r = e0.elapsed_time(e1)
         print(json.dumps({"mode": "copy", "bytes_read": nel * 8, "bytes_written": nel * 8, "ms": ms,
-                          "GBps": 2 * nel * 8 / (ms * 1e-3) / 1e9}), flush=True)
+                          "GBps": 2 * nel * 8 / (ms * 1e-3) / 1e9, "read_only_ms": ms_r,
+                          "read_only_GBps": nel * 8 / (ms_r * 1e-3) / 1e9, "check": float(s_)}), flush=True)
         return
 
     w = dict(synth.WORKLOADS[args.workload])
@@ -172,12 +183,12 @@ def main():
         return
 
     for i in range(args.warmup):
-        solver.solve(k, tol, precision=precision)
+        solver.solve(k, tol, precision=precision, block=args.block)
         log(f"  warmup {i} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        omega, X, Y, st = solver.solve(k, tol, precision=precision)
+        omega, X, Y, st = solver.solve(k, tol, precision=precision, block=args.block)
         log(f"  step {i}: {st['ms_total'] / 1e3:.2f} s, passes {st['passes']}, restarts {st['restarts']}, "
             f"max rel residual {st['max_rel_residual']:.2e}")
     torch.cuda.synchronize()
@@ -211,9 +222,11 @@ def main():
                    "storage": storage, "precision": precision, "block_edge": None},
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": f"mv_block_kernel ({kernel_dtype})", "bytes_per_launch": bytes_launch,
+                     "kernel": (f"mv_block_kernel ({kernel_dtype})" if st["block"] <= 1 else
+                                f"mk_block_kernel ({kernel_dtype}, {st['block']} vectors)"),
+                     "bytes_per_launch": bytes_launch,
                      "ms_per_launch": ms_launch},
-        "solve": {k_: st[k_] for k_ in ("passes", "restarts", "steps_fp32", "steps_fp64", "ms_fp32_phase",
+        "solve": {k_: st[k_] for k_ in ("passes", "block", "restarts", "steps_fp32", "steps_fp64", "ms_fp32_phase",
                                         "ms_fp64_phase", "ms_final", "max_rel_residual", "n_converged")},
         "setup_s": t_setup,
     }
@@ -222,7 +235,7 @@ def main():
     if args.fp64 == "on" and precision == "mixed":
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        om64, X64, Y64, st64 = solver.solve(k, tol, precision="fp64")
+        om64, X64, Y64, st64 = solver.solve(k, tol, precision="fp64", block=args.block)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         log(f"  fp64 path: {t64:.2f} s, passes {st64['passes']}, max rel residual {st64['max_rel_residual']:.2e}")

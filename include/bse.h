@@ -91,7 +91,11 @@ typedef struct {
   int32_t fp32_arith;   /* MIXED bulk passes over the complex64 triangles: 0 (default) FP64
                            products and sums; 1 complex FP32 products and in-block sums
                            (FP64 across blocks).  Both read 8 bytes per entry. */
-  int32_t reserved_;
+  int32_t block;        /* TDA: block size b of the Lanczos iteration, 1..4 vectors per read of
+                           the triangle (0: 4 for N >= 2048, else 1; reduced to 1 when the basis
+                           would not leave room for b >= 2); ncv and keep are rounded up to
+                           multiples of b.  PH: ignored (b = 1: the folded iteration's basis is
+                           K1-orthogonal to its partner space only when grown from one vector). */
 } bse_solve_opts;
 
 /* Statistics of the last bse_solve (host struct). */
@@ -106,7 +110,7 @@ typedef struct {
   double ms_fp64_phase;     /* time spent iterating with the FP64 operator */
   double ms_final;          /* eigenvector assembly + FP64 residual check */
   double max_rel_residual;  /* max over the k pairs of ||H v - omega v|| / (|omega| ||v||) */
-  double bytes_per_pass_fp32; /* algorithmic bytes of one pass over hi: hi triangles + in/out vectors */
+  double bytes_per_pass_fp32; /* algorithmic bytes of one pass over hi: hi triangles + block in/out vectors */
   double bytes_per_pass_fp64; /* algorithmic bytes of one FP64 pass: c128 (or hi+lo) triangles + vectors */
   int64_t samples_fp32;     /* hi-only block-matvec launches timed with HIP events (every 8th pass) */
   int64_t samples_fp64;     /* FP64 block-matvec launches timed with HIP events (every 8th pass) */
@@ -115,6 +119,8 @@ typedef struct {
   int64_t samples_fused;    /* PH FP64 refinement: timed fused full-H launches (every 8th pass) */
   double ms_block_fused;    /* summed duration of the timed fused launches */
   int64_t fused_vectors;    /* vectors multiplied by H in the refinement (two per fused launch) */
+  int32_t block;            /* Lanczos block size used (vectors per read of the triangles) */
+  int32_t reserved_;
 } bse_stats;
 
 /* Component of a matrix for bse_strength: the scalar returned for a
@@ -163,8 +169,9 @@ bse_status bse_set_packed(bse_handle h, bse_block which, int64_t j0, int64_t j1,
  * bse_apply -- y = op(x) for nvec vectors, columns of length N (2N for
  * BSE_OP_H, stored as [top; bottom]), complex128, device.  precision selects
  * the FP64 operator (c128, or hi+lo), the FP32 operator (MIXED: hi only) or
- * FP64 arithmetic on hi (HI_FP64); the last two need HILO storage.  One pass
- * over the stored triangles per vector.
+ * FP64 arithmetic on hi (HI_FP64); the last two need HILO storage.  Vectors
+ * are processed up to four (A, K1, K2) or two (H, FP64 arithmetic) per read
+ * of the stored triangles.
  * Errors: INVALID_ARG (K1/K2/H on a TDA handle, hi-only without HILO, nulls).
  */
 bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t nvec, const void* x,

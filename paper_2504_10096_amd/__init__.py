@@ -38,7 +38,7 @@ EXPORTS = ["bse_create", "bse_set_packed", "bse_apply", "bse_solve", "bse_backwa
 class SolveOpts(ctypes.Structure):
     _fields_ = [("ncv", ctypes.c_int32), ("keep", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("switch_tol", ctypes.c_double), ("start_seed", ctypes.c_uint64),
-                ("fp32_arith", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("fp32_arith", ctypes.c_int32), ("block", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -50,7 +50,7 @@ class Stats(ctypes.Structure):
                 ("samples_fp32", ctypes.c_int64), ("samples_fp64", ctypes.c_int64),
                 ("ms_block_fp32", ctypes.c_double), ("ms_block_fp64", ctypes.c_double),
                 ("samples_fused", ctypes.c_int64), ("ms_block_fused", ctypes.c_double),
-                ("fused_vectors", ctypes.c_int64)]
+                ("fused_vectors", ctypes.c_int64), ("block", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -201,18 +201,19 @@ class Solver:
         return y
 
     def solve(self, k, tol, precision="fp64", ncv=0, keep=0, max_restarts=0, switch_tol=0.0, seed=1,
-              raise_not_converged=True, fp32_arith=False):
+              raise_not_converged=True, fp32_arith=False, block=0):
         """Lowest k pairs.  Returns (omega[k] f64, X[k, N] c128, Y[k, N] c128 or None, stats dict);
         row c of X/Y is pair c (column c of the column-major N x k ABI layout).  With
         precision="mixed", fp32_arith selects complex FP32 arithmetic for the bulk passes
-        (default: FP64 arithmetic on the FP32-stored triangles)."""
+        (default: FP64 arithmetic on the FP32-stored triangles).  block: vectors per read of the
+        triangles in the Lanczos iteration (0: automatic)."""
         k = int(k)
         dev = self.device
         omega = torch.empty(k, dtype=torch.float64, device=dev)
         X = torch.empty((k, self.n), dtype=torch.complex128, device=dev)
         Y = torch.empty((k, self.n), dtype=torch.complex128, device=dev) if self.kind == PSEUDO_HERMITIAN else None
         opts = SolveOpts(int(ncv), int(keep), int(max_restarts), PREC_MIXED if precision == "mixed" else PREC_FP64,
-                         float(switch_tol), int(seed), 1 if fp32_arith else 0, 0)
+                         float(switch_tol), int(seed), 1 if fp32_arith else 0, int(block))
         stats = Stats()
         with torch.cuda.device(dev):
             st = load_library().bse_solve(self._h, k, float(tol), ctypes.byref(opts), _dev_ptr(omega),

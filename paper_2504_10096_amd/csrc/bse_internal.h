@@ -61,15 +61,17 @@ size_t mv_part_elems(const Layout& L);
 // each.  part: mh_part_elems(L, nh) complex entries.  ev0 / ev1 (optional)
 // are recorded around the block kernel.
 size_t mh_part_elems(const Layout& L, int nh);
+size_t mk_part_elems(const Layout& L, int nv);
 hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const double2* V, int64_t ldv,
                     int64_t ldh, double2* part, double2* MV, double bsign, hipStream_t s,
                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
-// A x_q for nv (1..4) vectors in one read of the stored A, FP64 arithmetic
-// (ar: AR_C128, AR_HILO or AR_HI64); column q of V and MV at q ldv.  part:
-// mh_part_elems(L, 2) complex entries suffice (nv <= 2 nh).
-hipError_t ma_apply(const Layout& L, Arith ar, const MatPtrs& m, int nv, const double2* V, int64_t ldv,
-                    double2* part, double2* MV, hipStream_t s, hipEvent_t ev0 = nullptr,
+// Multi-vector pass: out_q = A x_q (bm = BM_NONE) or A x_q + sb B conj(x_q)
+// (bm = BM_CONJ) for nv (1..4) vectors in one read of the stored triangles,
+// in the arithmetic ar; column q of V at q ldv, of out at q ldo.  part:
+// mk_part_elems(L, nv) complex entries (it covers every smaller nv too).
+hipError_t mk_apply(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, int nv, const double2* V, int64_t ldv,
+                    double sb, double2* part, double2* out, int64_t ldo, hipStream_t s, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);
 
 // Copy packed-upper columns [j0, j1) into block storage (see Layout).
@@ -114,6 +116,11 @@ hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s);
 // PH eigenvectors: X = (w u + p) / (2 sqrt(w)), Y = conj(w u - p) / (2 sqrt(w)).
 hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const double* omega, int k,
                       int64_t n, double2* X, double2* Y, int64_t ldo, hipStream_t s);
+
+// T[:, q] += H[:, q] for q < ncols, rows < cnt (leading dimensions ldT,
+// ldh); real_only adds the real parts only.
+hipError_t acc_cols(double2* T, int64_t ldT, const double2* H, int64_t ldh, int cnt, int ncols, int real_only,
+                    hipStream_t s);
 
 // Complex C (M x N) = A (M x K) B (K x N), column-major, FP64 MFMA.
 hipError_t zgemm_mfma(int64_t M, int N, int K, const double2* A, int64_t lda, const double2* B,

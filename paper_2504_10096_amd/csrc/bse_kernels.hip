@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "bse_internal.h"
 
 namespace bse {
@@ -446,18 +448,34 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// A x_q for NV vectors in one read of A (the TDA counterpart of
-// mh_block_kernel, same slicing and partial layout): row r gains A_rc x_c,
-// column c gains conj(A_rc) x_r.
+// rows per workgroup slice of the multi-vector pass (register budget)
+__host__ __device__ constexpr int mk_rows(int nv) { return nv >= 3 ? 128 : 256; }
+
+// Multi-vector pass: out_q = A x_q (BM_NONE) or A x_q + sb B conj(x_q)
+// (BM_CONJ: K1 for sb = 1, K2 for sb = -1) for NV vectors in one read of the
+// triangles.  Row r gains A_rc x_c (+ sb B_rc conj(x_c)), column c gains
+// conj(A_rc) x_r (+ sb B_rc conj(x_r)).  Same slicing, lane layout and
+// partial layout as mv_block_kernel, with NV outputs:
+// rowpart[q][blk][R], colpart[q][blk][slice][R].
 template <int R, int AR, int NV>
+struct MkShape {
+  static constexpr int RS = R < mk_rows(NV) ? R : mk_rows(NV);
+  static constexpr int NS = R / RS;
+  static constexpr int VW = (AR != AR_C128 && RS >= 128) ? 2 : 1;
+  static constexpr int G = RS / (64 * VW);
+  static constexpr int RPL = G * VW;
+};
+
+template <int R, int AR, int BM, int NV>
 __global__ void __launch_bounds__(kThreads)
-    ma_block_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
+    mk_block_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
+                    const void* __restrict__ b0, const void* __restrict__ b1,
                     const int2* __restrict__ blkmap, int64_t nblk, int64_t n,
-                    const double2* __restrict__ V, int64_t ldv,
+                    const double2* __restrict__ V, int64_t ldv, double sb,
                     double2* __restrict__ rowpart, double2* __restrict__ colpart) {
-  constexpr int RS = R < 256 ? R : 256;
-  constexpr int NS = R / RS;
-  constexpr int RPL = RS / 64;
+  using T = typename Elem<AR>::T;
+  using Sh = MkShape<R, AR, NV>;
+  constexpr int RS = Sh::RS, NS = Sh::NS, VW = Sh::VW, G = Sh::G, RPL = Sh::RPL;
   constexpr int CPW = R / 4;
   __shared__ double2 sh[4][RS];
 
@@ -468,56 +486,90 @@ __global__ void __launch_bounds__(kThreads)
   const int lane = threadIdx.x & 63;
   const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
   const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
+  const T tsb = (T)sb;
 
-  double xr[NV][RPL], xi[NV][RPL], rr[NV][RPL], ri[NV][RPL];
+  T xr[NV][RPL], xi[NV][RPL], rr[NV][RPL], ri[NV][RPL];
 #pragma unroll
-  for (int q = 0; q < NV; ++q)
+  for (int v = 0; v < NV; ++v)
 #pragma unroll
-    for (int p = 0; p < RPL; ++p) {
-      const int64_t i = row0 + lane + 64 * p;
-      const double2 x = (i < n) ? V[(size_t)q * ldv + i] : make_double2(0.0, 0.0);
-      xr[q][p] = x.x;
-      xi[q][p] = x.y;
-      rr[q][p] = 0.0;
-      ri[q][p] = 0.0;
-    }
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int q = g * VW + e;
+        const int64_t i = row0 + g * 64 * VW + lane * VW + e;
+        const double2 x = (i < n) ? V[(size_t)v * ldv + i] : make_double2(0.0, 0.0);
+        xr[v][q] = (T)x.x;
+        xi[v][q] = (T)x.y;
+        rr[v][q] = T(0);
+        ri[v][q] = T(0);
+      }
 
   for (int cc = 0; cc < CPW; ++cc) {
     const int c = wave * CPW + cc;
     const int64_t j = col0 + c;
-    double cxr[NV], cxi[NV], sr[NV], si[NV];
+    T cxr[NV], cxi[NV], sr[NV], si[NV], tr[NV], ti[NV];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const double2 x = (j < n) ? V[(size_t)q * ldv + j] : make_double2(0.0, 0.0);
-      cxr[q] = x.x;
-      cxi[q] = x.y;
-      sr[q] = 0.0;
-      si[q] = 0.0;
+    for (int v = 0; v < NV; ++v) {
+      const double2 x = (j < n) ? V[(size_t)v * ldv + j] : make_double2(0.0, 0.0);
+      cxr[v] = (T)x.x;
+      cxi[v] = (T)x.y;
+      sr[v] = T(0);
+      si[v] = T(0);
+      tr[v] = T(0);
+      ti[v] = T(0);
     }
-    const size_t cbase = base + (size_t)c * R + lane;
+    const size_t cbase = base + (size_t)c * R + lane * VW;
 #pragma unroll
-    for (int p = 0; p < RPL; ++p) {
-      double ar, ai;
-      Elem<AR>::load(a0, a1, cbase + 64 * p, ar, ai);
+    for (int g = 0; g < G; ++g) {
+      T are[VW], aim[VW], bre[VW], bim[VW];
+      Loader<AR, VW>::load(a0, a1, cbase + g * 64 * VW, are, aim);
+      if (BM == BM_CONJ) Loader<AR, VW>::load(b0, b1, cbase + g * 64 * VW, bre, bim);
 #pragma unroll
-      for (int q = 0; q < NV; ++q) {
-        rr[q][p] += ar * cxr[q] - ai * cxi[q];
-        ri[q][p] += ar * cxi[q] + ai * cxr[q];
-        sr[q] += ar * xr[q][p] + ai * xi[q][p];
-        si[q] += ar * xi[q][p] - ai * xr[q][p];
+      for (int e = 0; e < VW; ++e) {
+        const int q = g * VW + e;
+        const T ar = are[e], ai = aim[e];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          // row r: A_rc x_c; column c: conj(A_rc) x_r
+          rr[v][q] += ar * cxr[v] - ai * cxi[v];
+          ri[v][q] += ar * cxi[v] + ai * cxr[v];
+          sr[v] += ar * xr[v][q] + ai * xi[v][q];
+          si[v] += ar * xi[v][q] - ai * xr[v][q];
+        }
+        if (BM == BM_CONJ) {
+          const T br = bre[e], bi = bim[e];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            // row r: B_rc conj(x_c) (times sb); column c: B_rc conj(x_r) (times sb after the sum)
+            rr[v][q] += tsb * (br * cxr[v] + bi * cxi[v]);
+            ri[v][q] += tsb * (bi * cxr[v] - br * cxi[v]);
+            tr[v] += br * xr[v][q] + bi * xi[v][q];
+            ti[v] += bi * xr[v][q] - br * xi[v][q];
+          }
+        }
       }
     }
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
-      if (lane == 0) colpart[(((size_t)q * nblk + blk) * NS + slice) * R + c] = make_double2(tr, ti);
+    for (int v = 0; v < NV; ++v) {
+      if (BM == BM_CONJ) {
+        sr[v] += tsb * tr[v];
+        si[v] += tsb * ti[v];
+      }
+      const T ur = wave_sum(sr[v]), ui = wave_sum(si[v]);
+      if (lane == 0)
+        colpart[(((size_t)v * nblk + blk) * NS + slice) * R + c] = make_double2((double)ur, (double)ui);
     }
   }
 
 #pragma unroll
-  for (int q = 0; q < NV; ++q) {
+  for (int v = 0; v < NV; ++v) {
 #pragma unroll
-    for (int p = 0; p < RPL; ++p) sh[wave][lane + 64 * p] = make_double2(rr[q][p], ri[q][p]);
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int q = g * VW + e;
+        sh[wave][g * 64 * VW + lane * VW + e] = make_double2((double)rr[v][q], (double)ri[v][q]);
+      }
     __syncthreads();
     for (int r = threadIdx.x; r < RS; r += kThreads) {
       double2 t = sh[0][r];
@@ -526,7 +578,7 @@ __global__ void __launch_bounds__(kThreads)
         t.x += sh[w][r].x;
         t.y += sh[w][r].y;
       }
-      rowpart[((size_t)q * nblk + blk) * R + slice * RS + r] = t;
+      rowpart[((size_t)v * nblk + blk) * R + slice * RS + r] = t;
     }
     __syncthreads();
   }
@@ -534,7 +586,7 @@ __global__ void __launch_bounds__(kThreads)
 
 // Sum of the partials of mh_block_kernel (pairs != 0: output 2q goes to the
 // top of column q of MV, output 2q+1 conjugated and times bsign to its
-// bottom; bsign = 1: M v, -1: H v) or of ma_block_kernel (pairs == 0:
+// bottom; bsign = 1: M v, -1: H v) or of mk_block_kernel (pairs == 0:
 // output q to column q).  Grid (ceil(n / 256), outputs).
 __global__ void __launch_bounds__(kThreads)
     mh_reduce_kernel(const double2* __restrict__ rowpart, const double2* __restrict__ colpart, int R, int NS,
@@ -992,6 +1044,20 @@ __global__ void __launch_bounds__(kThreads)
   Y[(size_t)c * ldo + i] = make_double2(s * (w * u.x - p.x), -s * (w * u.y - p.y));
 }
 
+// T[:, q] += H[:, q] (rows < cnt, columns < ncols); real_only drops Im(H).
+__global__ void __launch_bounds__(kThreads)
+    acc_cols_kernel(double2* __restrict__ T, int64_t ldT, const double2* __restrict__ H, int64_t ldh, int cnt,
+                    int real_only) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= cnt) return;
+  const double2 v = H[(size_t)q * ldh + i];
+  double2 t = T[(size_t)q * ldT + i];
+  t.x += v.x;
+  if (!real_only) t.y += v.y;
+  T[(size_t)q * ldT + i] = t;
+}
+
 // ---------------------------------------------- FP64 refinement (full H)
 // Columns of length 2N stored as [top (ld); bottom (ld)], column stride 2 ld.
 
@@ -1297,6 +1363,15 @@ size_t mh_part_elems(const Layout& L, int nh) {
   return (size_t)2 * nh * L.nblk * L.R * (1 + ns);
 }
 
+size_t mk_part_elems(const Layout& L, int nv) {
+  size_t mx = 0;
+  for (int v = 1; v <= nv; ++v) {
+    const int ns = L.R < mk_rows(v) ? 1 : L.R / mk_rows(v);
+    mx = std::max(mx, (size_t)v * L.nblk * L.R * (1 + ns));
+  }
+  return mx;
+}
+
 hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const double2* V, int64_t ldv,
                     int64_t ldh, double2* part, double2* MV, double bsign, hipStream_t s, hipEvent_t ev0,
                     hipEvent_t ev1) {
@@ -1335,45 +1410,58 @@ hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const d
   return hipGetLastError();
 }
 
-template <int R, int AR>
-hipError_t launch_ma(int nv, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv, double2* part,
+template <int R, int AR, int BM, int NV>
+hipError_t launch_mk(const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv, double sb, double2* part,
                      hipStream_t s) {
-  constexpr int NS = R < 256 ? 1 : R / 256;
+  using Sh = MkShape<R, AR, NV>;
   double2* rowpart = part;
-  double2* colpart = part + (size_t)nv * L.nblk * R;
-  const dim3 grid((unsigned)L.nblk, (unsigned)NS);
-  switch (nv) {
-    case 1:
-      hipLaunchKernelGGL((ma_block_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, L.blkmap, L.nblk,
-                         L.n, V, ldv, rowpart, colpart);
-      break;
-    case 2:
-      hipLaunchKernelGGL((ma_block_kernel<R, AR, 2>), grid, dim3(kThreads), 0, s, m.a, m.alo, L.blkmap, L.nblk,
-                         L.n, V, ldv, rowpart, colpart);
-      break;
-    case 3:
-      hipLaunchKernelGGL((ma_block_kernel<R, AR, 3>), grid, dim3(kThreads), 0, s, m.a, m.alo, L.blkmap, L.nblk,
-                         L.n, V, ldv, rowpart, colpart);
-      break;
-    default:
-      hipLaunchKernelGGL((ma_block_kernel<R, AR, 4>), grid, dim3(kThreads), 0, s, m.a, m.alo, L.blkmap, L.nblk,
-                         L.n, V, ldv, rowpart, colpart);
-      break;
-  }
+  double2* colpart = part + (size_t)NV * L.nblk * R;
+  hipLaunchKernelGGL((mk_block_kernel<R, AR, BM, NV>), dim3((unsigned)L.nblk, (unsigned)Sh::NS), dim3(kThreads),
+                     0, s, m.a, m.alo, m.b, m.blo, L.blkmap, L.nblk, L.n, V, ldv, sb, rowpart, colpart);
   return hipGetLastError();
 }
 
-template <int R>
-hipError_t dispatch_ma(Arith ar, int nv, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv,
-                       double2* part, hipStream_t s) {
-  if (ar == AR_C128) return launch_ma<R, AR_C128>(nv, L, m, V, ldv, part, s);
-  if (ar == AR_HI64) return launch_ma<R, AR_HI64>(nv, L, m, V, ldv, part, s);
-  return launch_ma<R, AR_HILO>(nv, L, m, V, ldv, part, s);
+template <int R, int AR, int BM>
+hipError_t dispatch_mk_nv(int nv, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv, double sb,
+                          double2* part, hipStream_t s) {
+  switch (nv) {
+    case 1:
+      return launch_mk<R, AR, BM, 1>(L, m, V, ldv, sb, part, s);
+    case 2:
+      return launch_mk<R, AR, BM, 2>(L, m, V, ldv, sb, part, s);
+    case 3:
+      return launch_mk<R, AR, BM, 3>(L, m, V, ldv, sb, part, s);
+    default:
+      return launch_mk<R, AR, BM, 4>(L, m, V, ldv, sb, part, s);
+  }
 }
 
-hipError_t ma_apply(const Layout& L, Arith ar, const MatPtrs& m, int nv, const double2* V, int64_t ldv,
-                    double2* part, double2* MV, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-  if (nv < 1 || nv > 4 || ar == AR_HI) return hipErrorInvalidValue;
+template <int R, int AR>
+hipError_t dispatch_mk_bm(BMode bm, int nv, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv,
+                          double sb, double2* part, hipStream_t s) {
+  if (bm == BM_CONJ) return dispatch_mk_nv<R, AR, BM_CONJ>(nv, L, m, V, ldv, sb, part, s);
+  return dispatch_mk_nv<R, AR, BM_NONE>(nv, L, m, V, ldv, sb, part, s);
+}
+
+template <int R>
+hipError_t dispatch_mk(Arith ar, BMode bm, int nv, const Layout& L, const MatPtrs& m, const double2* V,
+                       int64_t ldv, double sb, double2* part, hipStream_t s) {
+  switch (ar) {
+    case AR_C128:
+      return dispatch_mk_bm<R, AR_C128>(bm, nv, L, m, V, ldv, sb, part, s);
+    case AR_HI:
+      return dispatch_mk_bm<R, AR_HI>(bm, nv, L, m, V, ldv, sb, part, s);
+    case AR_HI64:
+      return dispatch_mk_bm<R, AR_HI64>(bm, nv, L, m, V, ldv, sb, part, s);
+    default:
+      return dispatch_mk_bm<R, AR_HILO>(bm, nv, L, m, V, ldv, sb, part, s);
+  }
+}
+
+hipError_t mk_apply(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, int nv, const double2* V, int64_t ldv,
+                    double sb, double2* part, double2* out, int64_t ldo, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1) {
+  if (nv < 1 || nv > 4 || bm == BM_EXPLICIT) return hipErrorInvalidValue;
   hipError_t e;
   if (ev0) {
     e = hipEventRecord(ev0, s);
@@ -1381,16 +1469,16 @@ hipError_t ma_apply(const Layout& L, Arith ar, const MatPtrs& m, int nv, const d
   }
   switch (L.R) {
     case 64:
-      e = dispatch_ma<64>(ar, nv, L, m, V, ldv, part, s);
+      e = dispatch_mk<64>(ar, bm, nv, L, m, V, ldv, sb, part, s);
       break;
     case 128:
-      e = dispatch_ma<128>(ar, nv, L, m, V, ldv, part, s);
+      e = dispatch_mk<128>(ar, bm, nv, L, m, V, ldv, sb, part, s);
       break;
     case 256:
-      e = dispatch_ma<256>(ar, nv, L, m, V, ldv, part, s);
+      e = dispatch_mk<256>(ar, bm, nv, L, m, V, ldv, sb, part, s);
       break;
     case 512:
-      e = dispatch_ma<512>(ar, nv, L, m, V, ldv, part, s);
+      e = dispatch_mk<512>(ar, bm, nv, L, m, V, ldv, sb, part, s);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1400,11 +1488,11 @@ hipError_t ma_apply(const Layout& L, Arith ar, const MatPtrs& m, int nv, const d
     e = hipEventRecord(ev1, s);
     if (e != hipSuccess) return e;
   }
-  const int ns = L.R < 256 ? 1 : L.R / 256;
+  const int ns = L.R < mk_rows(nv) ? 1 : L.R / mk_rows(nv);
   const double2* rowpart = part;
   const double2* colpart = part + (size_t)nv * L.nblk * L.R;
   hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)nv),
-                     dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, MV, ldv, (int64_t)0, 1.0,
+                     dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, out, ldo, (int64_t)0, 1.0,
                      0);
   return hipGetLastError();
 }
@@ -1485,6 +1573,14 @@ hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const doub
   if (k == 0) return hipSuccess;
   hipLaunchKernelGGL(ph_vectors_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)k),
                      dim3(kThreads), 0, s, U, P, ld, omega, n, X, Y, ldo);
+  return hipGetLastError();
+}
+
+hipError_t acc_cols(double2* T, int64_t ldT, const double2* H, int64_t ldh, int cnt, int ncols, int real_only,
+                    hipStream_t s) {
+  if (cnt <= 0 || ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(acc_cols_kernel, dim3((unsigned)((cnt + kThreads - 1) / kThreads), (unsigned)ncols),
+                     dim3(kThreads), 0, s, T, ldT, H, ldh, cnt, real_only);
   return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ struct bse_handle_s {
 namespace {
 
 using bse::Arith;
+using cplx = std::complex<double>;
 
 struct DevBuf {
   void* p = nullptr;
@@ -82,7 +83,8 @@ bse::MatPtrs mat_ptrs(const bse_handle_s* h) {
 // Workspace of the fused full-H products, kept with the handle.
 bse_status ensure_mhpart(bse_handle h) {
   if (h->mhpart) return BSE_OK;
-  if (hipMalloc((void**)&h->mhpart, sizeof(double2) * bse::mh_part_elems(h->L, 2)) != hipSuccess) {
+  const size_t el = std::max(bse::mh_part_elems(h->L, 2), bse::mk_part_elems(h->L, 4));
+  if (hipMalloc((void**)&h->mhpart, sizeof(double2) * el) != hipSuccess) {
     h->mhpart = nullptr;
     return fail(h, BSE_ERR_OUT_OF_MEMORY, "full-H workspace");
   }
@@ -93,11 +95,12 @@ Arith fp64_arith(const bse_handle_s* h) {
   return h->storage == BSE_STORE_C128 ? bse::AR_C128 : bse::AR_HILO;
 }
 
-double bytes_per_pass(const bse_handle_s* h, Arith ar) {
+// Algorithmic bytes of one read of the triangles with nv vectors in and out.
+double bytes_per_pass(const bse_handle_s* h, Arith ar, int nv) {
   const double e = (ar == bse::AR_HI || ar == bse::AR_HI64) ? 8.0 : 16.0;
   const double tri = e * (double)h->n * (double)(h->n + 1) / 2.0;
   const int nt = h->kind == BSE_PSEUDO_HERMITIAN ? 2 : 1;
-  return nt * tri + 2.0 * 16.0 * (double)h->n;
+  return nt * tri + 2.0 * 16.0 * (double)h->n * nv;
 }
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -122,17 +125,24 @@ struct Solver {
   double tol;
   hipStream_t s;
   // device buffers
-  DevBuf bufU, bufU2, bufP, bufP2, bufKP, bufKP2, bufY, bufZ, bufH1, bufH2, bufH3, bufPart, bufRed,
-      bufAlpha, bufBeta, bufFlag, bufS, bufNrm, bufW, bufTmp, bufRes, bufTh;
-  double2 *U, *U2, *P, *P2, *KP, *KP2, *Y, *Z, *H1, *H2, *H3, *W, *Tmp;
+  DevBuf bufU, bufU2, bufP, bufP2, bufKP, bufKP2, bufY, bufZ, bufH1, bufH3, bufPart, bufRed, bufTc, bufFlag,
+      bufS, bufNrm, bufW, bufTmp, bufRes, bufTh;
+  double2 *U, *U2, *P, *P2, *KP, *KP2, *Y, *Z, *H1, *H3, *W, *Tmp;
   double* th_dev;  // Ritz values of the kept vectors (PH partner scaling)
   int ny = 0;      // PH: columns of the partner basis Y (Z = K1 Y)
   double2* cpart;
-  double *red, *alpha, *beta, *S, *nrm, *res;
+  double *red, *S, *nrm, *res;
   int* flag;
+  // block Lanczos: block size b; projected-matrix coefficients Tc
+  // ((m + b) x (m + b), column-major, ldT = m + b): column c holds the
+  // orthogonalization coefficients of the product of basis column c
+  int b = 1;
+  int ldT = 0;
+  double2* Tc;
+  int ncolmax = 0;  // columns of one coefficient vector in H1 / H3
   // projected matrix state
-  int nka = 0;  // arrow size (kept Ritz vectors)
-  std::vector<double> theta_keep, arrow;
+  int nka = 0;  // kept Ritz vectors at the front of the basis
+  std::vector<double> theta_keep;
   // statistics
   int64_t steps32 = 0, steps64 = 0, passes = 0;
   int restarts = 0;
@@ -191,30 +201,30 @@ void harvest_events(Solver& S) {
 bse_status alloc_solver(Solver& S) {
   bse_handle h = S.h;
   const size_t col = (size_t)S.ld * sizeof(double2);
-  const int ncolmax = 2 * S.m + 4;
+  const int nc = S.m + S.b;  // basis columns: m plus the next block
+  S.ncolmax = 2 * nc + 4;
+  S.ldT = nc;
   struct {
     DevBuf* b;
     size_t bytes;
   } req[] = {
-      {&S.bufU, col * (S.m + 1)},
-      {&S.bufU2, col * (S.m + 1)},
-      {&S.bufP, S.ph ? col * (S.m + 1) : 0},
-      {&S.bufP2, S.ph ? col * (S.m + 1) : 0},
-      {&S.bufKP, S.ph ? col * (S.m + 1) : 0},
-      {&S.bufKP2, S.ph ? col * (S.m + 1) : 0},
-      {&S.bufY, S.ph ? col * (S.m + 1) : 0},
-      {&S.bufZ, S.ph ? col * (S.m + 1) : 0},
-      {&S.bufH1, sizeof(double2) * ncolmax},
-      {&S.bufH2, sizeof(double2) * ncolmax},
-      {&S.bufH3, sizeof(double2) * ncolmax},
-      {&S.bufTh, sizeof(double) * (S.m + 2)},
-      {&S.bufPart, sizeof(double2) * (size_t)bse::nchunks(S.n) * ncolmax},
+      {&S.bufU, col * nc},
+      {&S.bufU2, col * nc},
+      {&S.bufP, S.ph ? col * nc : 0},
+      {&S.bufP2, S.ph ? col * nc : 0},
+      {&S.bufKP, S.ph ? col * nc : 0},
+      {&S.bufKP2, S.ph ? col * nc : 0},
+      {&S.bufY, S.ph ? col * nc : 0},
+      {&S.bufZ, S.ph ? col * nc : 0},
+      {&S.bufH1, sizeof(double2) * (size_t)S.ncolmax * S.b},
+      {&S.bufH3, sizeof(double2) * (size_t)S.ncolmax},
+      {&S.bufTh, sizeof(double) * (nc + 2)},
+      {&S.bufTc, sizeof(double2) * (size_t)nc * nc},
+      {&S.bufPart, sizeof(double2) * (size_t)bse::nchunks(S.n) * S.ncolmax},
       {&S.bufRed, sizeof(double) * 2 * ((size_t)bse::nchunks(S.n) + 8)},
-      {&S.bufAlpha, sizeof(double) * (S.m + 1)},
-      {&S.bufBeta, sizeof(double) * (S.m + 1)},
       {&S.bufFlag, sizeof(int) * 4},
-      {&S.bufS, sizeof(double) * (size_t)(S.m + 2) * (S.m + 2)},
-      {&S.bufNrm, sizeof(double) * (2 * (size_t)S.m + 8)},
+      {&S.bufS, sizeof(double2) * (size_t)(nc + 2) * (nc + 2)},
+      {&S.bufNrm, sizeof(double) * (2 * (size_t)nc + 8)},
       {&S.bufW, col * 2},
       {&S.bufTmp, col * 2},
       {&S.bufRes, sizeof(double) * 16},
@@ -232,13 +242,11 @@ bse_status alloc_solver(Solver& S) {
   S.Y = (double2*)S.bufY.p;
   S.Z = (double2*)S.bufZ.p;
   S.H1 = (double2*)S.bufH1.p;
-  S.H2 = (double2*)S.bufH2.p;
   S.H3 = (double2*)S.bufH3.p;
   S.th_dev = (double*)S.bufTh.p;
+  S.Tc = (double2*)S.bufTc.p;
   S.cpart = (double2*)S.bufPart.p;
   S.red = (double*)S.bufRed.p;
-  S.alpha = (double*)S.bufAlpha.p;
-  S.beta = (double*)S.bufBeta.p;
   S.flag = (int*)S.bufFlag.p;
   S.S = (double*)S.bufS.p;
   S.nrm = (double*)S.bufNrm.p;
@@ -251,8 +259,9 @@ bse_status alloc_solver(Solver& S) {
     S.ev_free.push_back(e);
   }
   HIP_TRY(h, hipMemsetAsync(S.flag, 0, sizeof(int) * 4, S.s));
-  HIP_TRY(h, hipMemsetAsync(S.U, 0, col * (S.m + 1), S.s));
-  if (S.ph) HIP_TRY(h, hipMemsetAsync(S.P, 0, col * (S.m + 1), S.s));
+  HIP_TRY(h, hipMemsetAsync(S.U, 0, col * nc, S.s));
+  HIP_TRY(h, hipMemsetAsync(S.Tc, 0, sizeof(double2) * (size_t)nc * nc, S.s));
+  if (S.ph) HIP_TRY(h, hipMemsetAsync(S.P, 0, col * nc, S.s));
   return BSE_OK;
 }
 
@@ -284,75 +293,139 @@ bse_status pass(Solver& S, Arith ar, int op /*0: A, 1: K1, 2: K2*/, const double
   return BSE_OK;
 }
 
-// Start (or phase-switch) vector in column 0, normalized; PH also P[:, 0] = K1 U[:, 0].
-bse_status init_basis(Solver& S, Arith ar) {
+// Multi-vector pass: out[:, q] = K(v[:, q]) for nv <= 4 columns in one read
+// of the triangles (op 0: A, 1: K1, 2: K2); the single-vector kernel for nv = 1.
+bse_status passes_n(Solver& S, Arith ar, int op, int nv, const double2* v, double2* out) {
+  if (nv == 1) return pass(S, ar, op, v, out);
   bse_handle h = S.h;
-  if (S.ph) {
-    bse_status st = pass(S, ar, 1, S.U, S.P);
-    if (st) return st;
-    HIP_TRY(h, bse::scale_start(S.U, S.P, S.n, S.flag, S.red, S.s));
-  } else {
-    HIP_TRY(h, bse::scale_start(S.U, nullptr, S.n, S.flag, S.red, S.s));
+  if (bse_status e = ensure_mhpart(h)) return e;
+  bse::MatPtrs mm = mat_ptrs(h);
+  if (ar == bse::AR_HI || ar == bse::AR_HI64) {
+    mm.alo = nullptr;
+    mm.blo = nullptr;
   }
-  S.nka = 0;
-  S.ny = 0;
-  S.theta_keep.clear();
-  S.arrow.clear();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (S.passes % 8 == 0 && S.ev_free.size() >= 2) {
+    e1 = S.ev_free.back();
+    S.ev_free.pop_back();
+    e0 = S.ev_free.back();
+    S.ev_free.pop_back();
+    S.ev_pending.push_back({{e0, e1}, ar == bse::AR_HI || ar == bse::AR_HI64});
+  }
+  const bse::BMode bm = op == 0 ? bse::BM_NONE : bse::BM_CONJ;
+  HIP_TRY(h, bse::mk_apply(h->L, ar, bm, mm, nv, v, S.ld, op == 2 ? -1.0 : 1.0, h->mhpart, out, S.ld, S.s, e0, e1));
+  ++S.passes;
   return BSE_OK;
 }
 
-// Lanczos step j: new basis column j + 1.
-bse_status step(Solver& S, Arith ar, int j) {
+// Orthonormalize basis columns [c, c + nb) among themselves (TDA: Euclidean,
+// PH: K1 metric through P = K1 U), CGS twice per column.  With rec >= 0 the
+// coefficients are those of the product of block [rec, rec + nb): column
+// rec + q of Tc gains rows c .. c + q (the upper triangular factor).
+bse_status orth_block(Solver& S, int c, int nb, int rec) {
   bse_handle h = S.h;
-  double2* w = S.U + (size_t)(j + 1) * S.ld;
+  for (int q = 0; q < nb; ++q) {
+    double2* w = S.U + (size_t)(c + q) * S.ld;
+    double2* z = S.ph ? S.P + (size_t)(c + q) * S.ld : nullptr;
+    for (int it = 0; it < 2 && q > 0; ++it) {
+      const double2* G = S.ph ? S.P + (size_t)c * S.ld : S.U + (size_t)c * S.ld;
+      HIP_TRY(h, bse::cdot(G, q, nullptr, 0, S.ld, w, S.n, S.cpart, S.H3, S.s));
+      HIP_TRY(h, bse::cgemv_sub(S.U + (size_t)c * S.ld, q, nullptr, 0, S.ph ? S.P + (size_t)c * S.ld : nullptr,
+                                nullptr, S.ld, S.H3, S.ph ? 1 : 0, w, z, S.n, S.s));
+      if (rec >= 0)
+        HIP_TRY(h, bse::acc_cols(S.Tc + (size_t)(rec + q) * S.ldT + c, S.ldT, S.H3, S.ncolmax, q, 1, S.ph ? 1 : 0,
+                                 S.s));
+    }
+    double* bt = rec >= 0 ? (double*)(S.Tc + (size_t)(rec + q) * S.ldT + c + q) : nullptr;
+    HIP_TRY(h, bse::normalize(w, z, S.n, nullptr, nullptr, 0, nullptr, bt, 0, S.flag, S.red, S.s));
+  }
+  return BSE_OK;
+}
+
+// Start block in columns [0, b): seeded random vectors, orthonormalized
+// (PH: K1-orthonormal, with P = K1 U).
+bse_status init_basis(Solver& S, Arith ar, uint64_t seed) {
+  bse_handle h = S.h;
+  for (int q = 0; q < S.b; ++q) HIP_TRY(h, bse::start_vector(S.U + (size_t)q * S.ld, S.n, seed + q, S.s));
+  if (S.ph) {
+    bse_status st = passes_n(S, ar, 1, S.b, S.U, S.P);
+    if (st) return st;
+  }
+  if (bse_status st = orth_block(S, 0, S.b, -1)) return st;
+  S.nka = 0;
+  S.ny = 0;
+  S.theta_keep.clear();
+  return BSE_OK;
+}
+
+// Block Lanczos step: basis block [c0, c0 + b) -> next block [c0 + b, c0 + 2b).
+// TDA: W = A U_J, CGS2 against the basis.  PH (K1 metric, operator K2 K1):
+// W = K2 P_J, CGS against [U, Y] (Y the partner space), Z_W = K1 W, CGS2
+// with both updated.  Then the block is orthonormalized in itself.  The
+// coefficients of every CGS round are summed into the columns of Tc.
+bse_status step(Solver& S, Arith ar, int c0) {
+  bse_handle h = S.h;
+  const int b = S.b;
+  const int cn = c0 + b;  // basis columns so far
+  double2* W = S.U + (size_t)cn * S.ld;
   bse_status st;
   if (!S.ph) {
-    st = pass(S, ar, 0, S.U + (size_t)j * S.ld, w);
-    if (st) return st;
+    if ((st = passes_n(S, ar, 0, b, S.U + (size_t)c0 * S.ld, W))) return st;
     for (int it = 0; it < 2; ++it) {
-      double2* hh = it == 0 ? S.H1 : S.H2;
-      HIP_TRY(h, bse::cdot(S.U, j + 1, nullptr, 0, S.ld, w, S.n, S.cpart, hh, S.s));
-      HIP_TRY(h, bse::cgemv_sub(S.U, j + 1, nullptr, 0, nullptr, nullptr, S.ld, hh, 0, w, nullptr,
-                                S.n, S.s));
+      for (int q = 0; q < b; ++q) {
+        double2* hq = S.H1 + (size_t)q * S.ncolmax;
+        double2* w = W + (size_t)q * S.ld;
+        HIP_TRY(h, bse::cdot(S.U, cn, nullptr, 0, S.ld, w, S.n, S.cpart, hq, S.s));
+        HIP_TRY(h, bse::cgemv_sub(S.U, cn, nullptr, 0, nullptr, nullptr, S.ld, hq, 0, w, nullptr, S.n, S.s));
+      }
+      HIP_TRY(h, bse::acc_cols(S.Tc + (size_t)c0 * S.ldT, S.ldT, S.H1, S.ncolmax, cn, b, 0, S.s));
     }
-    HIP_TRY(h, bse::normalize(w, nullptr, S.n, S.H1, S.H2, j, S.alpha, S.beta, j, S.flag, S.red, S.s));
   } else {
     // Structure: on the real 2N-space every omega^2 of K2 K1 is double, the
     // second copy of an eigenvector u being its partner i K1 u / omega.  A
     // Krylov basis is K1-orthogonal to the partners i P of its own vectors
     // in exact arithmetic; rounding would seed the second copy of converged
     // pairs.  The partner space is kept explicitly as a K1-orthonormal Y
-    // with Z = K1 Y, using K1(i p) = i K2 p and the K2 p_j every step
+    // with Z = K1 Y, using K1(i p) = i K2 p and the K2 p every step
     // computes anyway (KP), and each new vector is K1-orthogonalized against
     // [U, Y]: no extra pass over the matrix.
-    double2* z = S.P + (size_t)(j + 1) * S.ld;
-    double2* kp = S.KP + (size_t)j * S.ld;
-    st = pass(S, ar, 2, S.P + (size_t)j * S.ld, kp);  // K2 p_j
-    if (st) return st;
-    // partner of column j: y = i p_j, K1 y = i K2 p_j
-    double2* y = S.Y + (size_t)S.ny * S.ld;
-    double2* zy = S.Z + (size_t)S.ny * S.ld;
-    HIP_TRY(h, bse::times_i(S.P + (size_t)j * S.ld, S.ld, y, S.ld, S.n, 1, nullptr, 0, S.s));
-    HIP_TRY(h, bse::times_i(kp, S.ld, zy, S.ld, S.n, 1, nullptr, 0, S.s));
-    HIP_TRY(h, bse::cdot(S.P, j + 1, S.Z, S.ny, S.ld, y, S.n, S.cpart, S.H3, S.s));
-    HIP_TRY(h, bse::cgemv_sub(S.U, j + 1, S.Y, S.ny, S.P, S.Z, S.ld, S.H3, 1, y, zy, S.n, S.s));
-    HIP_TRY(h, bse::scale_start(y, zy, S.n, S.flag, S.red, S.s));
-    ++S.ny;
-    // w = K2 p_j, K1-orthogonalized against [U, Y] (CGS2)
-    HIP_TRY(h, hipMemcpyAsync(w, kp, sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
-    HIP_TRY(h, bse::cdot(S.P, j + 1, S.Z, S.ny, S.ld, w, S.n, S.cpart, S.H1, S.s));
-    HIP_TRY(h, bse::cgemv_sub(S.U, j + 1, S.Y, S.ny, nullptr, nullptr, S.ld, S.H1, 1, w, nullptr, S.n,
-                              S.s));
-    st = pass(S, ar, 1, w, z);  // z = K1 w
-    if (st) return st;
-    HIP_TRY(h, bse::cdot(S.P, j + 1, S.Z, S.ny, S.ld, w, S.n, S.cpart, S.H2, S.s));
-    HIP_TRY(h, bse::cgemv_sub(S.U, j + 1, S.Y, S.ny, S.P, S.Z, S.ld, S.H2, 1, w, z, S.n, S.s));
-    HIP_TRY(h, bse::normalize(w, z, S.n, S.H1, S.H2, j, S.alpha, S.beta, j, S.flag, S.red, S.s));
+    double2* kp = S.KP + (size_t)c0 * S.ld;
+    if ((st = passes_n(S, ar, 2, b, S.P + (size_t)c0 * S.ld, kp))) return st;  // K2 P_J
+    for (int q = 0; q < b; ++q) {
+      // partner of column c0 + q: y = i p, K1 y = i K2 p
+      double2* y = S.Y + (size_t)S.ny * S.ld;
+      double2* zy = S.Z + (size_t)S.ny * S.ld;
+      HIP_TRY(h, bse::times_i(S.P + (size_t)(c0 + q) * S.ld, S.ld, y, S.ld, S.n, 1, nullptr, 0, S.s));
+      HIP_TRY(h, bse::times_i(kp + (size_t)q * S.ld, S.ld, zy, S.ld, S.n, 1, nullptr, 0, S.s));
+      HIP_TRY(h, bse::cdot(S.P, cn, S.Z, S.ny, S.ld, y, S.n, S.cpart, S.H3, S.s));
+      HIP_TRY(h, bse::cgemv_sub(S.U, cn, S.Y, S.ny, S.P, S.Z, S.ld, S.H3, 1, y, zy, S.n, S.s));
+      HIP_TRY(h, bse::scale_start(y, zy, S.n, S.flag, S.red, S.s));
+      ++S.ny;
+    }
+    // W = K2 P_J, K1-orthogonalized against [U, Y] (CGS2)
+    HIP_TRY(h, bse::copy_cols(kp, S.ld, W, S.ld, S.n, b, S.s));
+    for (int q = 0; q < b; ++q) {
+      double2* hq = S.H1 + (size_t)q * S.ncolmax;
+      double2* w = W + (size_t)q * S.ld;
+      HIP_TRY(h, bse::cdot(S.P, cn, S.Z, S.ny, S.ld, w, S.n, S.cpart, hq, S.s));
+      HIP_TRY(h, bse::cgemv_sub(S.U, cn, S.Y, S.ny, nullptr, nullptr, S.ld, hq, 1, w, nullptr, S.n, S.s));
+    }
+    HIP_TRY(h, bse::acc_cols(S.Tc + (size_t)c0 * S.ldT, S.ldT, S.H1, S.ncolmax, cn, b, 1, S.s));
+    double2* zw = S.P + (size_t)cn * S.ld;
+    if ((st = passes_n(S, ar, 1, b, W, zw))) return st;  // Z_W = K1 W
+    for (int q = 0; q < b; ++q) {
+      double2* hq = S.H1 + (size_t)q * S.ncolmax;
+      double2* w = W + (size_t)q * S.ld;
+      HIP_TRY(h, bse::cdot(S.P, cn, S.Z, S.ny, S.ld, w, S.n, S.cpart, hq, S.s));
+      HIP_TRY(h, bse::cgemv_sub(S.U, cn, S.Y, S.ny, S.P, S.Z, S.ld, hq, 1, w, zw + (size_t)q * S.ld, S.n, S.s));
+    }
+    HIP_TRY(h, bse::acc_cols(S.Tc + (size_t)c0 * S.ldT, S.ldT, S.H1, S.ncolmax, cn, b, 1, S.s));
   }
+  if ((st = orth_block(S, cn, b, c0))) return st;
   if (ar == bse::AR_HI || ar == bse::AR_HI64)
-    ++S.steps32;
+    S.steps32 += b;
   else
-    ++S.steps64;
+    S.steps64 += b;
   return BSE_OK;
 }
 
@@ -372,63 +445,89 @@ bse_status check_flag(Solver& S) {
 struct RitzInfo {
   std::vector<double> theta;  // m ascending
   std::vector<double> est;    // k estimates (relative)
-  double bm = 0.0;
 };
 
-// Restart: eigen-decompose T, rotate the basis to the lowest `keep` Ritz
-// vectors (MFMA GEMM), move the residual vector to column keep, estimate
-// residuals of the k wanted pairs.
-bse_status restart(Solver& S, RitzInfo& R, bool last) {
+// Restart: assemble the projected matrix T = U^H K1 K2 K1 U (PH, real
+// symmetric) or U^H A U (TDA, Hermitian) from the recorded coefficients,
+// eigen-decompose it, rotate the basis to the lowest `keep` Ritz vectors
+// (MFMA GEMM), move the next block behind them and estimate the residuals of
+// the k wanted pairs from the coupling of the last block to the next one.
+bse_status restart(Solver& S, RitzInfo& R) {
   bse_handle h = S.h;
-  const int m = S.m;
-  std::vector<double> al(m), be(m);
-  HIP_TRY(h, hipMemcpyAsync(al.data(), S.alpha, sizeof(double) * m, hipMemcpyDeviceToHost, S.s));
-  HIP_TRY(h, hipMemcpyAsync(be.data(), S.beta, sizeof(double) * m, hipMemcpyDeviceToHost, S.s));
+  const int m = S.m, b = S.b, ldT = S.ldT, nka = S.nka;
+  if (nka >= m) return fail(h, BSE_ERR_BAD_STATE, "thick restart needs ncv > keep");
+  std::vector<double2> tc((size_t)ldT * ldT);
+  HIP_TRY(h, hipMemcpyAsync(tc.data(), S.Tc, sizeof(double2) * tc.size(), hipMemcpyDeviceToHost, S.s));
   bse_status st = check_flag(S);
   if (st) return st;
-  std::vector<double> T((size_t)m * m, 0.0), th(m), Z((size_t)m * m);
-  if (S.nka >= m) return fail(h, BSE_ERR_BAD_STATE, "thick restart needs ncv > keep");
-  for (int i = 0; i < S.nka; ++i) {
-    T[(size_t)i * m + i] = S.theta_keep[i];
-    T[(size_t)S.nka * m + i] = S.arrow[i];
-    T[(size_t)i * m + S.nka] = S.arrow[i];
-  }
-  for (int j = S.nka; j < m; ++j) {
-    T[(size_t)j * m + j] = al[j];
-    if (j + 1 < m) {
-      T[(size_t)(j + 1) * m + j] = be[j];
-      T[(size_t)j * m + j + 1] = be[j];
+  // filled entries: column c >= nka holds rows [0, cn(c)) from the CGS rounds
+  // and rows cn(c) + p, p <= c - c0(c), of the block factor; the kept block
+  // is diag(theta_keep).  T is the symmetric (Hermitian) average of them.
+  auto c0_of = [&](int c) { return nka + ((c - nka) / b) * b; };
+  auto filled = [&](int i, int c) {
+    if (c < nka) return i < nka;
+    const int c0 = c0_of(c), cn = c0 + b;
+    return i < cn || (i < cn + b && i - cn <= c - c0);
+  };
+  auto val = [&](int i, int c) -> cplx {
+    if (c < nka) return i == c ? cplx(S.theta_keep[i], 0.0) : cplx(0.0);
+    const double2 v = tc[(size_t)c * ldT + i];
+    return cplx(v.x, S.ph ? 0.0 : v.y);
+  };
+  std::vector<cplx> T((size_t)m * m);
+  for (int c = 0; c < m; ++c)
+    for (int i = 0; i < m; ++i) {
+      const bool f1 = filled(i, c), f2 = filled(c, i);
+      cplx v = 0.0;
+      if (f1 && f2)
+        v = 0.5 * (val(i, c) + std::conj(val(c, i)));
+      else if (f1)
+        v = val(i, c);
+      else if (f2)
+        v = std::conj(val(c, i));
+      if (i == c) v = v.real();
+      T[(size_t)c * m + i] = v;
     }
+  for (cplx v : T)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+      return fail(h, BSE_ERR_NONFINITE, "non-finite projected matrix");
+  std::vector<double> th(m);
+  std::vector<cplx> Zc((size_t)m * m);
+  std::vector<double> Zr;
+  if (S.ph) {
+    std::vector<double> Tr((size_t)m * m);
+    Zr.resize((size_t)m * m);
+    for (size_t t = 0; t < Tr.size(); ++t) Tr[t] = T[t].real();
+    if (!bse::sym_eig(m, Tr.data(), th.data(), Zr.data()))
+      return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
+    for (size_t t = 0; t < Zr.size(); ++t) Zc[t] = Zr[t];
+  } else {
+    if (!bse::herm_eig(m, reinterpret_cast<double2*>(T.data()), th.data(), reinterpret_cast<double2*>(Zc.data())))
+      return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
   }
-  for (double v : T)
-    if (!std::isfinite(v)) return fail(h, BSE_ERR_NONFINITE, "non-finite projected matrix");
-  if (!bse::sym_eig(m, T.data(), th.data(), Z.data()))
-    return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
-  if (S.trace && S.ph && th[0] <= 0.0)
-    fprintf(stderr, "{\"nonpositive_theta\": [%.6e, %.6e, %.6e], \"beta_last\": %.3e}\n", th[0], th[1 % m],
-            th[2 % m], be[m - 1]);
   if (S.ph && th[0] <= 0.0)
     return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE,
                 "non-positive folded Ritz value omega^2: M is not positive definite");
-  const double bm = be[m - 1];
-  const int keep = last ? S.k : S.keep;
-  // U2[:, 0:keep] = U[:, 0:m] Z[:, 0:keep]   (real GEMM on interleaved data)
-  HIP_TRY(h, hipMemcpyAsync(S.S, Z.data(), sizeof(double) * (size_t)m * keep, hipMemcpyHostToDevice,
-                            S.s));
-  HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.U, 2 * S.ld, S.S, m,
-                                (double*)S.U2, 2 * S.ld, S.s));
-  HIP_TRY(h, hipMemcpyAsync(S.U2 + (size_t)keep * S.ld, S.U + (size_t)m * S.ld,
-                            sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
+  const int keep = S.keep;
+  // U2[:, 0:keep] = U[:, 0:m] Z[:, 0:keep]; the next block follows
+  if (S.ph) {
+    HIP_TRY(h, hipMemcpyAsync(S.S, Zr.data(), sizeof(double) * (size_t)m * keep, hipMemcpyHostToDevice, S.s));
+    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.U, 2 * S.ld, S.S, m, (double*)S.U2,
+                                  2 * S.ld, S.s));
+    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.P, 2 * S.ld, S.S, m, (double*)S.P2,
+                                  2 * S.ld, S.s));
+    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.KP, 2 * S.ld, S.S, m, (double*)S.KP2,
+                                  2 * S.ld, S.s));
+    HIP_TRY(h, bse::copy_cols(S.P + (size_t)m * S.ld, S.ld, S.P2 + (size_t)keep * S.ld, S.ld, S.n, b, S.s));
+    std::swap(S.P, S.P2);
+    std::swap(S.KP, S.KP2);
+  } else {
+    HIP_TRY(h, hipMemcpyAsync(S.S, Zc.data(), sizeof(double2) * (size_t)m * keep, hipMemcpyHostToDevice, S.s));
+    HIP_TRY(h, bse::zgemm_mfma(S.n, keep, m, S.U, S.ld, (const double2*)S.S, m, S.U2, S.ld, S.s));
+  }
+  HIP_TRY(h, bse::copy_cols(S.U + (size_t)m * S.ld, S.ld, S.U2 + (size_t)keep * S.ld, S.ld, S.n, b, S.s));
   std::swap(S.U, S.U2);
   if (S.ph) {
-    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.P, 2 * S.ld, S.S, m,
-                                  (double*)S.P2, 2 * S.ld, S.s));
-    HIP_TRY(h, hipMemcpyAsync(S.P2 + (size_t)keep * S.ld, S.P + (size_t)m * S.ld,
-                              sizeof(double2) * S.n, hipMemcpyDeviceToDevice, S.s));
-    std::swap(S.P, S.P2);
-    HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.KP, 2 * S.ld, S.S, m,
-                                  (double*)S.KP2, 2 * S.ld, S.s));
-    std::swap(S.KP, S.KP2);
     // partners of the kept Ritz vectors, i p~_a / omega_a, are K1-orthonormal
     // with K1 image i K2 p~_a / omega_a
     HIP_TRY(h, hipMemcpyAsync(S.th_dev, th.data(), sizeof(double) * keep, hipMemcpyHostToDevice, S.s));
@@ -436,37 +535,50 @@ bse_status restart(Solver& S, RitzInfo& R, bool last) {
     HIP_TRY(h, bse::times_i(S.KP, S.ld, S.Z, S.ld, S.n, keep, S.th_dev, 1, S.s));
     S.ny = keep;
   }
-  R.theta = th;
-  R.bm = bm;
-  R.est.assign(S.k, 0.0);
-  if (!S.ph) {
-    for (int i = 0; i < S.k; ++i) {
-      const double den = std::max(fabs(th[i]), 1e-300);
-      R.est[i] = fabs(bm * Z[(size_t)i * m + m - 1]) / den;
+  // residual of Ritz pair i: U_next c_i with c_i = F z_i(last block), F the
+  // factor of the last block's product on the next block
+  std::vector<cplx> F((size_t)b * b, 0.0);  // F[p][q], row m + p, column m - b + q
+  for (int q = 0; q < b; ++q)
+    for (int p = 0; p <= q; ++p) {
+      const double2 v = tc[(size_t)(m - b + q) * ldT + m + p];
+      F[(size_t)q * b + p] = cplx(v.x, S.ph ? 0.0 : v.y);
     }
-  } else {
-    // ||u~_i||^2, ||p~_i||^2 and ||u_{m+1}||^2 for the relative H residual
-    std::vector<double> nu(S.k + 1), np(S.k);
-    // partials of colnorms: nchunks(n) * k doubles, held in the CGS workspace
-    double* cp = (double*)S.cpart;
+  // Gram of the next block (Euclidean; TDA: identity by construction)
+  std::vector<double2> gn((size_t)b * b);
+  double* cp = (double*)S.cpart;
+  std::vector<double> nu(S.k), np(S.k);
+  if (S.ph) {
+    for (int q = 0; q < b; ++q)
+      HIP_TRY(h, bse::cdot(S.U + (size_t)keep * S.ld, b, nullptr, 0, S.ld, S.U + (size_t)(keep + q) * S.ld, S.n,
+                           S.cpart, S.H1 + (size_t)q * b, S.s));
+    HIP_TRY(h, hipMemcpyAsync(gn.data(), S.H1, sizeof(double2) * b * b, hipMemcpyDeviceToHost, S.s));
     HIP_TRY(h, bse::colnorms(S.U, S.k, S.ld, S.n, cp, S.nrm, S.s));
-    HIP_TRY(h, bse::colnorms(S.U + (size_t)keep * S.ld, 1, S.ld, S.n, cp, S.nrm + S.k, S.s));
-    HIP_TRY(h, hipMemcpyAsync(nu.data(), S.nrm, sizeof(double) * (S.k + 1), hipMemcpyDeviceToHost,
-                              S.s));
+    HIP_TRY(h, hipMemcpyAsync(nu.data(), S.nrm, sizeof(double) * S.k, hipMemcpyDeviceToHost, S.s));
     HIP_TRY(h, bse::colnorms(S.P, S.k, S.ld, S.n, cp, S.nrm, S.s));
     HIP_TRY(h, hipMemcpyAsync(np.data(), S.nrm, sizeof(double) * S.k, hipMemcpyDeviceToHost, S.s));
-    HIP_TRY(h, hipStreamSynchronize(S.s));
-    for (int i = 0; i < S.k; ++i) {
+  }
+  HIP_TRY(h, hipMemsetAsync(S.Tc, 0, sizeof(double2) * (size_t)ldT * ldT, S.s));
+  HIP_TRY(h, hipStreamSynchronize(S.s));
+  R.theta = th;
+  R.est.assign(S.k, 0.0);
+  for (int i = 0; i < S.k; ++i) {
+    std::vector<cplx> ci(b, 0.0);
+    for (int p = 0; p < b; ++p)
+      for (int q = p; q < b; ++q) ci[p] += F[(size_t)q * b + p] * Zc[(size_t)i * m + m - b + q];
+    double r2 = 0.0;
+    if (S.ph) {
+      for (int p = 0; p < b; ++p)
+        for (int q = 0; q < b; ++q) r2 += ci[p].real() * ci[q].real() * gn[(size_t)q * b + p].x;
       const double w = sqrt(std::max(th[i], 1e-300));
       const double den = w * sqrt(w * w * nu[i] + np[i]);
-      R.est[i] = fabs(bm * Z[(size_t)i * m + m - 1]) * sqrt(nu[S.k]) / std::max(den, 1e-300);
+      R.est[i] = sqrt(std::max(r2, 0.0)) / std::max(den, 1e-300);
+    } else {
+      for (int p = 0; p < b; ++p) r2 += std::norm(ci[p]);
+      R.est[i] = sqrt(r2) / std::max(fabs(th[i]), 1e-300);
     }
   }
-  // next cycle: T = [diag(theta_keep), arrow; arrow^T, .]
   S.nka = keep;
   S.theta_keep.assign(th.begin(), th.begin() + keep);
-  S.arrow.resize(keep);
-  for (int i = 0; i < keep; ++i) S.arrow[i] = bm * Z[(size_t)i * m + m - 1];
   ++S.restarts;
   return BSE_OK;
 }
@@ -519,7 +631,6 @@ bse_status finalize(Solver& S, const RitzInfo& R, double* omega, double2* X, dou
 // ---------------------------------------------------------------------
 // Small dense complex helpers (host, column-major s x s, leading dimension s).
 // ---------------------------------------------------------------------
-using cplx = std::complex<double>;
 
 // a = L L^H; the lower triangle of a receives L.  False if a is not positive definite.
 bool zchol(int s, cplx* a) {
@@ -649,7 +760,8 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
         HIP_TRY(h, bse::mh_apply(h->L, ar, mat_ptrs(h), nh, col(V, c), ld2, ld, mhpart, col(MV, c), 1.0, S.s, e0,
                                  e1));
       else
-        HIP_TRY(h, bse::ma_apply(h->L, ar, mat_ptrs(h), nh, col(V, c), ld2, mhpart, col(MV, c), S.s, e0, e1));
+        HIP_TRY(h, bse::mk_apply(h->L, ar, bse::BM_NONE, mat_ptrs(h), nh, col(V, c), ld2, 0.0, mhpart, col(MV, c),
+                                 ld2, S.s, e0, e1));
       ++S.passes;
       S.mh_vectors += nh;
     }
@@ -987,6 +1099,18 @@ bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t n
     }
     return BSE_OK;
   }
+  if (op != BSE_OP_H && nvec > 1) {
+    // up to four vectors per read of the triangles
+    if (bse_status st = ensure_mhpart(h)) return st;
+    const bse::BMode bm = op == BSE_OP_A ? bse::BM_NONE : bse::BM_CONJ;
+    const double sb = op == BSE_OP_K2 ? -1.0 : 1.0;
+    for (int64_t c = 0; c < nvec; c += 4) {
+      const int nv = (int)std::min<int64_t>(4, nvec - c);
+      HIP_TRY(h, bse::mk_apply(h->L, ar, bm, mp, nv, xv + (size_t)c * n, n, sb, h->mhpart, yv + (size_t)c * n, n,
+                               h->stream));
+    }
+    return BSE_OK;
+  }
   for (int64_t c = 0; c < nvec; ++c) {
     if (op == BSE_OP_H) {
       const double2* xt = xv + (size_t)c * 2 * n;
@@ -1025,12 +1149,20 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   if (mixed && h->storage != BSE_STORE_HILO)
     return fail(h, BSE_ERR_INVALID_ARG, "mixed precision needs HILO storage");
   const int64_t n = h->n;
+  if (o.block < 0 || o.block > 4) return fail(h, BSE_ERR_INVALID_ARG, "block must be in [0, 4]");
   int m = o.ncv > 0 ? o.ncv : (int)round_up(std::max(2 * k, k + 32), 16);
   m = (int)std::min<int64_t>(m, n);
   if (m < k) return fail(h, BSE_ERR_INVALID_ARG, "ncv must be at least k");
+  // block size (TDA): several vectors per read of the triangles once the
+  // matrix is large; the basis and the kept set are whole blocks.  The
+  // pseudo-Hermitian iteration keeps b = 1: its basis is K1-orthogonal to
+  // its own partner space only when it grows from a single vector.
+  int b = ph ? 1 : (o.block > 0 ? o.block : (n >= 2048 ? 4 : 1));
+  if (b > 1 && ((int)round_up(m, b) < k + b || (int64_t)round_up(m, b) + b > n / 2)) b = 1;
+  m = (int)round_up(m, b);
   int keep = o.keep > 0 ? o.keep : k + (m - k) / 2;
-  keep = std::max(keep, k);
-  if (keep >= m) keep = (m > k) ? m - 1 : m;
+  keep = (int)round_up(std::max(keep, k), b);
+  if (keep >= m) keep = (m > k) ? m - b : m;
   const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 400;
   const double switch_tol = o.switch_tol > 0 ? o.switch_tol : 1e-6;
   const uint64_t seed = o.start_seed ? o.start_seed : 1;
@@ -1044,6 +1176,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   S.k = k;
   S.m = m;
   S.keep = keep;
+  S.b = b;
   S.tol = tol;
   S.s = h->stream;
   if (const char* tr = getenv("BSE_TRACE")) S.trace = tr[0] == '1';
@@ -1054,8 +1187,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   Arith ar = mixed ? bulk : fp64_arith(h);
   double tol_int = mixed ? std::max(switch_tol, tol) : tol;
   double t_phase = now_ms(), ms32 = 0.0, ms64 = 0.0;
-  HIP_TRY(h, bse::start_vector(S.U, n, seed, S.s));
-  st = init_basis(S, ar);
+  st = init_basis(S, ar, seed);
   if (st) return st;
   int jstart = 0;
   RitzInfo R;
@@ -1065,11 +1197,11 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   int nconv_final = 0;
   double ms_final = 0.0;
   for (int cyc = 0; cyc < max_restarts; ++cyc) {
-    for (int j = jstart; j < m; ++j) {
-      st = step(S, ar, j);
+    for (int c0 = jstart; c0 < m; c0 += b) {
+      st = step(S, ar, c0);
       if (st) return st;
     }
-    st = restart(S, R, false);
+    st = restart(S, R);
     if (st) return st;
     jstart = S.keep;
     const bool full_space = S.keep >= m;
@@ -1166,8 +1298,9 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
     stats->ms_fp64_phase = ms64 - ms_final;
     stats->ms_final = ms_final;
     stats->max_rel_residual = max_rel;
-    stats->bytes_per_pass_fp32 = mixed ? bytes_per_pass(h, bse::AR_HI) : 0.0;
-    stats->bytes_per_pass_fp64 = bytes_per_pass(h, fp64_arith(h));
+    stats->bytes_per_pass_fp32 = mixed ? bytes_per_pass(h, bse::AR_HI, b) : 0.0;
+    stats->bytes_per_pass_fp64 = bytes_per_pass(h, fp64_arith(h), b);
+    stats->block = b;
     stats->samples_fp32 = S.samples32;
     stats->samples_fp64 = S.samples64;
     stats->ms_block_fp32 = S.ms_blk32;

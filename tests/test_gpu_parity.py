@@ -73,6 +73,26 @@ def test_matvec_parity(block, storage, monkeypatch):
     s.close()
 
 
+@pytest.mark.parametrize("nvec", [1, 2, 4, 5])
+def test_matvec_multi_vector_counts(nvec):
+    # one, several and a ragged number of vectors per read of the triangles, FP32 arithmetic too
+    n = 777
+    rng = np.random.default_rng(17)
+    A, B = random_herm(rng, n), random_sym(rng, n, 0.5)
+    ap, bp = pack_upper(A), pack_upper(B)
+    s = make_solver("ph", ap, bp, "hilo")
+    x = rng.standard_normal((nvec, n)) + 1j * rng.standard_normal((nvec, n))
+    xh = rng.standard_normal((nvec, 2 * n)) + 1j * rng.standard_normal((nvec, 2 * n))
+    for prec in ["fp64", "fp32"]:
+        tol = 2e-6 if prec == "fp32" else 1e-13
+        for op in ["A", "K1", "K2", "H"]:
+            xin = xh if op == "H" else x
+            got = host(s.apply(op, dev(xin), precision=prec))
+            ref = oracle.apply_dense(op, ap, xin, bp)
+            assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < tol, (op, prec, nvec)
+    s.close()
+
+
 def test_matvec_tda_handle_and_c64_input(monkeypatch):
     n = 333
     rng = np.random.default_rng(3)
@@ -331,6 +351,34 @@ def test_mixed_fp32_arith_ph_loose_tol():
     assert np.max(np.abs(host(om) - ref) / ref) < tol
     assert oracle.residual_ph(ap, bp, host(om), host(X).T, host(Y).T).max() <= tol * 1.01
     assert st["steps_fp32"] > 0
+    s.close()
+
+
+@pytest.mark.parametrize("block", [2, 3, 4])
+def test_block_tda_matches_oracle(block):
+    n, k = 1500, 12
+    m = synth.Matrix(n, 33, ph=False)
+    ap = m.pack_host(0)
+    ref, _ = oracle.tda(ap, k, vectors=False)
+    s = make_solver("tda", ap, storage="hilo")
+    for prec, tol in [("fp64", 1e-10), ("mixed", 1e-8)]:
+        lam, X, _, st = s.solve(k, tol, precision=prec, block=block)
+        assert st["block"] == block
+        assert np.max(np.abs(host(lam) - ref) / np.abs(ref)) < max(tol, 1e-10)
+        assert oracle.residual_tda(ap, host(lam), host(X).T).max() <= tol * 1.01
+        print("block", block, prec, st["passes"], st["steps_fp32"] + st["steps_fp64"], flush=True)
+    s.close()
+
+
+def test_block_ignored_for_ph():
+    n, k = 600, 6
+    m = synth.Matrix(n, 34, ph=True)
+    ap, bp = m.pack_host(0), m.pack_host(1)
+    s = make_solver("ph", ap, bp)
+    om, X, Y, st = s.solve(k, 1e-10, block=4)
+    assert st["block"] == 1
+    ref, _, _ = oracle.ph(ap, bp, k, vectors=False)
+    assert np.max(np.abs(host(om) - ref) / ref) < 1e-10
     s.close()
 
 
