@@ -96,6 +96,8 @@ def main():
                    help="oracle FP64 residuals of sampled pairs (streaming, CPU)")
     p.add_argument("--chunk-gb", type=float, default=2.0)
     p.add_argument("--block", type=int, default=0, help="TDA Lanczos block size (0: automatic)")
+    p.add_argument("--ncv", type=int, default=0, help="Lanczos basis size (0: default)")
+    p.add_argument("--keep", type=int, default=0, help="Ritz vectors kept at a restart (0: default)")
     p.add_argument("--precision", choices=["auto", "fp64"], default="auto",
                    help="auto: the mixed path where the workload uses it; fp64: FP64 passes only")
     p.add_argument("--mode", choices=["solve", "passbench", "copy"], default="solve",
@@ -183,12 +185,12 @@ def main():
         return
 
     for i in range(args.warmup):
-        solver.solve(k, tol, precision=precision, block=args.block)
+        solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep)
         log(f"  warmup {i} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        omega, X, Y, st = solver.solve(k, tol, precision=precision, block=args.block)
+        omega, X, Y, st = solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep)
         log(f"  step {i}: {st['ms_total'] / 1e3:.2f} s, passes {st['passes']}, restarts {st['restarts']}, "
             f"max rel residual {st['max_rel_residual']:.2e}")
     torch.cuda.synchronize()
@@ -235,7 +237,7 @@ def main():
     if args.fp64 == "on" and precision == "mixed":
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        om64, X64, Y64, st64 = solver.solve(k, tol, precision="fp64", block=args.block)
+        om64, X64, Y64, st64 = solver.solve(k, tol, precision="fp64", block=args.block, ncv=args.ncv, keep=args.keep)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         log(f"  fp64 path: {t64:.2f} s, passes {st64['passes']}, max rel residual {st64['max_rel_residual']:.2e}")

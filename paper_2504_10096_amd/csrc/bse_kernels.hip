@@ -93,9 +93,9 @@ struct Elem<AR_HILO> {
 
 // ----------------------------------------------------------------- matvec
 //
-// One workgroup (4 waves) per stored R x R block (P, Q) and slice of RS =
-// min(R, 256) rows (grid.y = R / RS slices: the per-lane row state stays
-// small enough for 4 waves per SIMD).  Wave w walks the columns
+// One workgroup (4 waves) per stored R x R block (P, Q) (the kernel also
+// takes row slices of RS < R rows, grid.y = R / RS; one slice measured as
+// fast and halves the column partials).  Wave w walks the columns
 // [w R/4, (w+1) R/4) of the block; in each column a lane owns VW adjacent
 // rows per 64 VW-row group (VW = 2 for the complex64 triangles: 16-byte
 // loads), so every load instruction reads one contiguous 64 VW-entry
@@ -150,7 +150,7 @@ struct Loader<AR_HILO, 2> {
 // entries per lane-load: two complex64 (16 bytes) where a slice has >= 128 rows
 template <int R, int AR>
 struct MvShape {
-  static constexpr int RS = R < 256 ? R : 256;
+  static constexpr int RS = R;
   static constexpr int NS = R / RS;
   static constexpr int VW = (AR != AR_C128 && RS >= 128) ? 2 : 1;
   static constexpr int G = RS / (64 * VW);
@@ -771,15 +771,19 @@ __global__ void __launch_bounds__(kThreads)
 // h[c] = sum over chunks of part[chunk * ncol + c], chunks in order.
 __global__ void __launch_bounds__(kThreads)
     colsum_kernel(const double2* __restrict__ part, int64_t nch, int ncol, double2* __restrict__ h) {
-  const int c = blockIdx.x * kThreads + threadIdx.x;
+  // one wavefront per column: lanes stride over the chunks, then a fixed-order
+  // wavefront reduction (deterministic)
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (c >= ncol) return;
   double sr = 0.0, si = 0.0;
-  for (int64_t k = 0; k < nch; ++k) {
+  for (int64_t k = lane; k < nch; k += 64) {
     const double2 v = part[(size_t)k * ncol + c];
     sr += v.x;
     si += v.y;
   }
-  h[c] = make_double2(sr, si);
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) h[c] = make_double2(sr, si);
 }
 
 // w[i] -= sum_c V[i, c] h[c];  z[i] -= sum_c P[i, c] h[c] (optional).
@@ -1007,11 +1011,12 @@ __global__ void __launch_bounds__(kThreads)
 
 __global__ void __launch_bounds__(kThreads)
     colsum_real_kernel(const double* __restrict__ part, int64_t nch, int ncol, double* __restrict__ h) {
-  const int c = blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (c >= ncol) return;
   double s = 0.0;
-  for (int64_t k = 0; k < nch; ++k) s += part[(size_t)k * ncol + c];
-  h[c] = s;
+  for (int64_t k = lane; k < nch; k += 64) s += part[(size_t)k * ncol + c];
+  s = wave_sum(s);
+  if (lane == 0) h[c] = s;
 }
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
@@ -1354,7 +1359,7 @@ hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const d
   return hipGetLastError();
 }
 
-int mv_slices(const Layout& L) { return L.R < 256 ? 1 : L.R / 256; }
+int mv_slices(const Layout&) { return 1; }
 
 size_t mv_part_elems(const Layout& L) { return (size_t)L.nblk * L.R * (1 + mv_slices(L)); }
 
@@ -1513,8 +1518,7 @@ hipError_t cdot(const double2* V0, int n0, const double2* V1, int n1, int64_t ld
   const int64_t nch = nchunks(n);
   hipLaunchKernelGGL(cdot_part_kernel, dim3((unsigned)nch, (unsigned)((ncol + 63) / 64)),
                      dim3(kThreads), 0, s, V0, n0, V1, n1, ld, w, n, part);
-  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((ncol + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, s, part, nch, ncol, h);
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((ncol + 3) / 4)), dim3(kThreads), 0, s, part, nch, ncol, h);
   return hipGetLastError();
 }
 
@@ -1557,8 +1561,8 @@ hipError_t colnorms(const double2* V, int ncol, int64_t ld, int64_t n, double* p
   const int64_t nch = nchunks(n);
   hipLaunchKernelGGL(colnorm_part_kernel, dim3((unsigned)nch), dim3(kThreads), 0, s, V, ncol, ld, n,
                      part);
-  hipLaunchKernelGGL(colsum_real_kernel, dim3((unsigned)((ncol + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, s, part, nch, ncol, nrm);
+  hipLaunchKernelGGL(colsum_real_kernel, dim3((unsigned)((ncol + 3) / 4)), dim3(kThreads), 0, s, part, nch, ncol,
+                     nrm);
   return hipGetLastError();
 }
 
