@@ -294,6 +294,247 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// Wavefront sum with DPP row shifts and row broadcasts (no LDS traffic);
+// the total is returned to every lane (read from lane 63).
+__device__ __forceinline__ double dpp_shift(double v, int ctrl_id) {
+  // the DPP control must be a constant: dispatch on the few used here
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int rlo, rhi;
+  switch (ctrl_id) {
+    case 0:
+      rlo = __builtin_amdgcn_update_dpp(0, lo, 0x111, 0xf, 0xf, false);  // row_shr:1
+      rhi = __builtin_amdgcn_update_dpp(0, hi, 0x111, 0xf, 0xf, false);
+      break;
+    case 1:
+      rlo = __builtin_amdgcn_update_dpp(0, lo, 0x112, 0xf, 0xf, false);  // row_shr:2
+      rhi = __builtin_amdgcn_update_dpp(0, hi, 0x112, 0xf, 0xf, false);
+      break;
+    case 2:
+      rlo = __builtin_amdgcn_update_dpp(0, lo, 0x114, 0xf, 0xf, false);  // row_shr:4
+      rhi = __builtin_amdgcn_update_dpp(0, hi, 0x114, 0xf, 0xf, false);
+      break;
+    case 3:
+      rlo = __builtin_amdgcn_update_dpp(0, lo, 0x118, 0xf, 0xf, false);  // row_shr:8
+      rhi = __builtin_amdgcn_update_dpp(0, hi, 0x118, 0xf, 0xf, false);
+      break;
+    case 4:
+      rlo = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xa, 0xf, false);  // row_bcast:15
+      rhi = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xa, 0xf, false);
+      break;
+    default:
+      rlo = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xc, 0xf, false);  // row_bcast:31
+      rhi = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xc, 0xf, false);
+      break;
+  }
+  return __hiloint2double(rhi, rlo);
+}
+
+__device__ __forceinline__ double dpp_wave_sum(double v) {
+  v += dpp_shift(v, 0);
+  v += dpp_shift(v, 1);
+  v += dpp_shift(v, 2);
+  v += dpp_shift(v, 3);
+  v += dpp_shift(v, 4);
+  v += dpp_shift(v, 5);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Raw 16-byte loads of one column segment: complex64 pairs (hi, and lo for
+// HILO) or one complex128 entry; converted after the next column's loads
+// have been issued.
+template <int AR>
+struct RawCol;
+template <>
+struct RawCol<AR_HI> {
+  nf4 h;
+};
+template <>
+struct RawCol<AR_HI64> {
+  nf4 h;
+};
+template <>
+struct RawCol<AR_HILO> {
+  nf4 h, l;
+};
+template <>
+struct RawCol<AR_C128> {
+  nd2 h;
+};
+
+template <int AR>
+__device__ __forceinline__ void raw_load(const void* p, const void* q, size_t i, RawCol<AR>& r) {
+  if constexpr (AR == AR_C128) {
+    r.h = __builtin_nontemporal_load(static_cast<const nd2*>(p) + i);
+  } else {
+    r.h = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(static_cast<const nf2*>(p) + i));
+    if constexpr (AR == AR_HILO)
+      r.l = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(static_cast<const nf2*>(q) + i));
+  }
+}
+
+template <int AR, typename T>
+__device__ __forceinline__ void raw_get(const RawCol<AR>& r, int e, T& re, T& im) {
+  if constexpr (AR == AR_C128) {
+    re = r.h.x;
+    im = r.h.y;
+  } else if constexpr (AR == AR_HILO) {
+    re = e ? (double)r.h.z + (double)r.l.z : (double)r.h.x + (double)r.l.x;
+    im = e ? (double)r.h.w + (double)r.l.w : (double)r.h.y + (double)r.l.y;
+  } else {
+    re = (T)(e ? r.h.z : r.h.x);
+    im = (T)(e ? r.h.w : r.h.y);
+  }
+}
+
+// One-vector pass, streaming form: same blocks, slices and partial layout as
+// mv_block_kernel, but the loads of column c + 1 are issued before column c
+// is consumed (two columns in flight per wave in registers), the column
+// sums use DPP reductions, and they are kept one per lane and stored per 64
+// columns, so the column loop has no branches.
+template <int R, int AR, int BM>
+__global__ void __launch_bounds__(kThreads)
+    mv_stream_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
+                     const void* __restrict__ b0, const void* __restrict__ b1,
+                     const int2* __restrict__ blkmap, int64_t n, const double2* __restrict__ va,
+                     int conja, const double2* __restrict__ vb, int conjb, double sb,
+                     double2* __restrict__ rowpart, double2* __restrict__ colpart) {
+  using T = typename Elem<AR>::T;
+  using Sh = MvShape<R, AR>;
+  constexpr int RS = Sh::RS, NS = Sh::NS, VW = Sh::VW, G = Sh::G, RPL = Sh::RPL;
+  constexpr int CPW = R / 4;
+  constexpr int CH = CPW < 64 ? CPW : 64;
+  static_assert(AR == AR_C128 ? VW == 1 : VW == 2, "stream layout (R >= 128)");
+  __shared__ double2 sh[4][RS];
+
+  const int blk = blockIdx.x;
+  const int slice = blockIdx.y;
+  const int2 pq = blkmap[blk];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
+  const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
+  const T ca = conja ? T(-1) : T(1);
+  const T cbs = conjb ? T(-1) : T(1);
+  const T tsb = (T)sb;
+
+  T xar[RPL], xai[RPL], xbr[RPL], xbi[RPL], rr[RPL], ri[RPL];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const int q = g * VW + e;
+      const int64_t i = row0 + g * 64 * VW + lane * VW + e;
+      const bool in = i < n;
+      const int64_t ii = in ? i : 0;
+      double2 v = va[ii], w = make_double2(0.0, 0.0);
+      if (BM == BM_EXPLICIT) w = vb[ii];
+      xar[q] = in ? (T)v.x : T(0);
+      xai[q] = in ? ca * (T)v.y : T(0);
+      xbr[q] = (BM == BM_EXPLICIT && in) ? tsb * (T)w.x : T(0);
+      xbi[q] = (BM == BM_EXPLICIT && in) ? tsb * cbs * (T)w.y : T(0);
+      rr[q] = T(0);
+      ri[q] = T(0);
+    }
+
+  const size_t lbase = base + (size_t)wave * CPW * R + lane * VW;
+  RawCol<AR> ca_[G], cbm[G], na_[G], nbm[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    raw_load<AR>(a0, a1, lbase + g * 64 * VW, ca_[g]);
+    if (BM != BM_NONE) raw_load<AR>(b0, b1, lbase + g * 64 * VW, cbm[g]);
+  }
+  for (int cb = 0; cb < CPW; cb += CH) {
+    double2 keep = make_double2(0.0, 0.0);
+#pragma unroll 2
+    for (int c2 = 0; c2 < CH; ++c2) {
+      const int cc = cb + c2;
+      // next column's loads first (the last column reloads itself: in bounds)
+      const int cn = cc + 1 < CPW ? cc + 1 : cc;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        raw_load<AR>(a0, a1, lbase + (size_t)cn * R + g * 64 * VW, na_[g]);
+        if (BM != BM_NONE) raw_load<AR>(b0, b1, lbase + (size_t)cn * R + g * 64 * VW, nbm[g]);
+      }
+      const int c = wave * CPW + cc;
+      const int64_t j = col0 + c;
+      const bool in = j < n;
+      const int64_t jj = in ? j : 0;
+      double2 vj = va[jj], wj = make_double2(0.0, 0.0);
+      if (BM == BM_EXPLICIT) wj = vb[jj];
+      const T xcr = in ? (T)vj.x : T(0), xci = in ? ca * (T)vj.y : T(0);
+      T ycr = T(0), yci = T(0);
+      if (BM == BM_CONJ) {
+        ycr = tsb * xcr;
+        yci = -tsb * xci;
+      } else if (BM == BM_EXPLICIT) {
+        ycr = in ? tsb * (T)wj.x : T(0);
+        yci = in ? tsb * cbs * (T)wj.y : T(0);
+      }
+      T cr = T(0), ci = T(0), dr = T(0), di = T(0);
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const int q = g * VW + e;
+          T ar, ai;
+          raw_get<AR, T>(ca_[g], e, ar, ai);
+          rr[q] += ar * xcr - ai * xci;
+          ri[q] += ar * xci + ai * xcr;
+          cr += ar * xar[q] + ai * xai[q];
+          ci += ar * xai[q] - ai * xar[q];
+          if (BM != BM_NONE) {
+            T br, bi;
+            raw_get<AR, T>(cbm[g], e, br, bi);
+            rr[q] += br * ycr - bi * yci;
+            ri[q] += br * yci + bi * ycr;
+            if (BM == BM_CONJ) {
+              dr += br * xar[q] + bi * xai[q];
+              di += bi * xar[q] - br * xai[q];
+            } else {
+              dr += br * xbr[q] - bi * xbi[q];
+              di += br * xbi[q] + bi * xbr[q];
+            }
+          }
+        }
+      if (BM == BM_CONJ) {
+        cr += tsb * dr;
+        ci += tsb * di;
+      } else if (BM == BM_EXPLICIT) {
+        cr += dr;
+        ci += di;
+      }
+      const double sr = dpp_wave_sum((double)cr), si = dpp_wave_sum((double)ci);
+      keep = lane == c2 ? make_double2(sr, si) : keep;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        ca_[g] = na_[g];
+        if (BM != BM_NONE) cbm[g] = nbm[g];
+      }
+    }
+    if (lane < CH) colpart[((size_t)blk * NS + slice) * R + wave * CPW + cb + lane] = keep;
+  }
+
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const int q = g * VW + e;
+      sh[wave][g * 64 * VW + lane * VW + e] = make_double2((double)rr[q], (double)ri[q]);
+    }
+  __syncthreads();
+  for (int r = threadIdx.x; r < RS; r += kThreads) {
+    double2 t = sh[0][r];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      t.x += sh[w][r].x;
+      t.y += sh[w][r].y;
+    }
+    rowpart[(size_t)blk * R + slice * RS + r] = t;
+  }
+}
+
 // out[i] = sum over the blocks of panel row P = i / R of their row partials
 //        + sum over the blocks of panel column P of their column partials.
 __global__ void __launch_bounds__(kThreads)
@@ -379,6 +620,7 @@ __global__ void __launch_bounds__(kThreads)
       ri[o][p] = 0.0;
     }
 
+#pragma unroll 2
   for (int cc = 0; cc < CPW; ++cc) {
     const int c = wave * CPW + cc;
     const int64_t j = col0 + c;
@@ -504,6 +746,9 @@ __global__ void __launch_bounds__(kThreads)
         ri[v][q] = T(0);
       }
 
+  // several columns per iteration keep enough loads in flight
+  constexpr int UNR = (BM == BM_CONJ ? 4 : 8) / G > 0 ? (BM == BM_CONJ ? 4 : 8) / G : 1;
+#pragma unroll UNR
   for (int cc = 0; cc < CPW; ++cc) {
     const int c = wave * CPW + cc;
     const int64_t j = col0 + c;
@@ -653,10 +898,14 @@ hipError_t launch_mv(const Layout& L, const MatPtrs& m, const double2* va, int c
                      const double2* vb, int conjb, double sb, double2* part, hipStream_t s) {
   double2* rowpart = part;
   double2* colpart = part + (size_t)L.nblk * L.R;
-  hipLaunchKernelGGL((mv_block_kernel<R, AR, BM>), dim3((unsigned)L.nblk, (unsigned)MvShape<R, AR>::NS),
-                     dim3(kThreads), 0, s,
-                     m.a, m.alo, m.b, m.blo, L.blkmap, L.n, va, conja, vb, conjb, sb, rowpart,
-                     colpart);
+  if constexpr (R >= 128)
+    hipLaunchKernelGGL((mv_stream_kernel<R, AR, BM>), dim3((unsigned)L.nblk, (unsigned)MvShape<R, AR>::NS),
+                       dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo, L.blkmap, L.n, va, conja, vb, conjb, sb,
+                       rowpart, colpart);
+  else
+    hipLaunchKernelGGL((mv_block_kernel<R, AR, BM>), dim3((unsigned)L.nblk, (unsigned)MvShape<R, AR>::NS),
+                       dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo, L.blkmap, L.n, va, conja, vb, conjb, sb,
+                       rowpart, colpart);
   return hipGetLastError();
 }
 
