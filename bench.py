@@ -180,6 +180,28 @@ def main():
             nbytes = (2 if ph else 1) * e * n * (n + 1) / 2 + 32 * n
             out[prec] = {"ms_per_pass": ms, "bytes_per_pass": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9}
             log(f"  {prec}: {ms:.3f} ms per pass (block + reduce), {nbytes / (ms * 1e-3) / 1e9:.0f} GB/s")
+        # several vectors per read: 4 through the multi-vector pass, 2 through the fused full-H product
+        tri = (2 if ph else 1) * n * (n + 1) / 2
+        multi = [("hi64", op, 4, 8)] if storage == "hilo" else []
+        multi += [("fp64", op, 4, 16)]
+        if ph:
+            multi += [("fp64", "H", 2, 16)]
+        for prec, mop, nv, e in multi:
+            xm = torch.randn((nv, 2 * n if mop == "H" else n), dtype=torch.complex128, device="cuda")
+            solver.apply(mop, xm, precision=prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.passes):
+                solver.apply(mop, xm, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.passes
+            nbytes = e * tri + 2 * 16 * n * nv * (2 if mop == "H" else 1)
+            key = f"{prec}_{mop}_x{nv}"
+            out[key] = {"ms_per_pass": ms, "bytes_per_pass": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
+                        "ms_per_vector": ms / nv}
+            log(f"  {key}: {ms:.3f} ms per read of the triangles ({ms / nv:.3f} ms per vector)")
         solver.close()
         print(json.dumps(out), flush=True)
         return

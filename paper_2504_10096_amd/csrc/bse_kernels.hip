@@ -691,7 +691,7 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // rows per workgroup slice of the multi-vector pass (register budget)
-__host__ __device__ constexpr int mk_rows(int nv) { return nv >= 3 ? 128 : 256; }
+__host__ __device__ constexpr int mk_rows(int nv) { return nv >= 3 ? 128 : (nv == 2 ? 256 : 512); }
 
 // Multi-vector pass: out_q = A x_q (BM_NONE) or A x_q + sb B conj(x_q)
 // (BM_CONJ: K1 for sb = 1, K2 for sb = -1) for NV vectors in one read of the
@@ -719,6 +719,7 @@ __global__ void __launch_bounds__(kThreads)
   using Sh = MkShape<R, AR, NV>;
   constexpr int RS = Sh::RS, NS = Sh::NS, VW = Sh::VW, G = Sh::G, RPL = Sh::RPL;
   constexpr int CPW = R / 4;
+  constexpr int CH = CPW < 64 ? CPW : 64;
   __shared__ double2 sh[4][RS];
 
   const int blk = blockIdx.x;
@@ -739,70 +740,96 @@ __global__ void __launch_bounds__(kThreads)
       for (int e = 0; e < VW; ++e) {
         const int q = g * VW + e;
         const int64_t i = row0 + g * 64 * VW + lane * VW + e;
-        const double2 x = (i < n) ? V[(size_t)v * ldv + i] : make_double2(0.0, 0.0);
-        xr[v][q] = (T)x.x;
-        xi[v][q] = (T)x.y;
+        const bool in = i < n;
+        const double2 x = V[(size_t)v * ldv + (in ? i : 0)];
+        xr[v][q] = in ? (T)x.x : T(0);
+        xi[v][q] = in ? (T)x.y : T(0);
         rr[v][q] = T(0);
         ri[v][q] = T(0);
       }
 
-  // several columns per iteration keep enough loads in flight
-  constexpr int UNR = (BM == BM_CONJ ? 4 : 8) / G > 0 ? (BM == BM_CONJ ? 4 : 8) / G : 1;
-#pragma unroll UNR
-  for (int cc = 0; cc < CPW; ++cc) {
-    const int c = wave * CPW + cc;
-    const int64_t j = col0 + c;
-    T cxr[NV], cxi[NV], sr[NV], si[NV], tr[NV], ti[NV];
+  // the next column's loads are issued before the current column is consumed
+  const size_t lbase = base + (size_t)wave * CPW * R + lane * VW;
+  RawCol<AR> ca_[G], cbm[G], na_[G], nbm[G];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const double2 x = (j < n) ? V[(size_t)v * ldv + j] : make_double2(0.0, 0.0);
-      cxr[v] = (T)x.x;
-      cxi[v] = (T)x.y;
-      sr[v] = T(0);
-      si[v] = T(0);
-      tr[v] = T(0);
-      ti[v] = T(0);
-    }
-    const size_t cbase = base + (size_t)c * R + lane * VW;
+  for (int g = 0; g < G; ++g) {
+    raw_load<AR>(a0, a1, lbase + g * 64 * VW, ca_[g]);
+    if (BM == BM_CONJ) raw_load<AR>(b0, b1, lbase + g * 64 * VW, cbm[g]);
+  }
+  for (int cb = 0; cb < CPW; cb += CH) {
+    double2 keep[NV];
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      T are[VW], aim[VW], bre[VW], bim[VW];
-      Loader<AR, VW>::load(a0, a1, cbase + g * 64 * VW, are, aim);
-      if (BM == BM_CONJ) Loader<AR, VW>::load(b0, b1, cbase + g * 64 * VW, bre, bim);
+    for (int v = 0; v < NV; ++v) keep[v] = make_double2(0.0, 0.0);
+    for (int c2 = 0; c2 < CH; ++c2) {
+      const int cc = cb + c2;
+      const int cn = cc + 1 < CPW ? cc + 1 : cc;
 #pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        const int q = g * VW + e;
-        const T ar = are[e], ai = aim[e];
+      for (int g = 0; g < G; ++g) {
+        raw_load<AR>(a0, a1, lbase + (size_t)cn * R + g * 64 * VW, na_[g]);
+        if (BM == BM_CONJ) raw_load<AR>(b0, b1, lbase + (size_t)cn * R + g * 64 * VW, nbm[g]);
+      }
+      const int c = wave * CPW + cc;
+      const int64_t j = col0 + c;
+      const bool in = j < n;
+      const int64_t jj = in ? j : 0;
+      T cxr[NV], cxi[NV], sr[NV], si[NV], tr[NV], ti[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          // row r: A_rc x_c; column c: conj(A_rc) x_r
-          rr[v][q] += ar * cxr[v] - ai * cxi[v];
-          ri[v][q] += ar * cxi[v] + ai * cxr[v];
-          sr[v] += ar * xr[v][q] + ai * xi[v][q];
-          si[v] += ar * xi[v][q] - ai * xr[v][q];
-        }
-        if (BM == BM_CONJ) {
-          const T br = bre[e], bi = bim[e];
+      for (int v = 0; v < NV; ++v) {
+        const double2 x = V[(size_t)v * ldv + jj];
+        cxr[v] = in ? (T)x.x : T(0);
+        cxi[v] = in ? (T)x.y : T(0);
+        sr[v] = T(0);
+        si[v] = T(0);
+        tr[v] = T(0);
+        ti[v] = T(0);
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const int q = g * VW + e;
+          T ar, ai;
+          raw_get<AR, T>(ca_[g], e, ar, ai);
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            // row r: B_rc conj(x_c) (times sb); column c: B_rc conj(x_r) (times sb after the sum)
-            rr[v][q] += tsb * (br * cxr[v] + bi * cxi[v]);
-            ri[v][q] += tsb * (bi * cxr[v] - br * cxi[v]);
-            tr[v] += br * xr[v][q] + bi * xi[v][q];
-            ti[v] += bi * xr[v][q] - br * xi[v][q];
+            // row r: A_rc x_c; column c: conj(A_rc) x_r
+            rr[v][q] += ar * cxr[v] - ai * cxi[v];
+            ri[v][q] += ar * cxi[v] + ai * cxr[v];
+            sr[v] += ar * xr[v][q] + ai * xi[v][q];
+            si[v] += ar * xi[v][q] - ai * xr[v][q];
+          }
+          if (BM == BM_CONJ) {
+            T br, bi;
+            raw_get<AR, T>(cbm[g], e, br, bi);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              // row r: B_rc conj(x_c) (times sb); column c: B_rc conj(x_r) (times sb after the sum)
+              rr[v][q] += tsb * (br * cxr[v] + bi * cxi[v]);
+              ri[v][q] += tsb * (bi * cxr[v] - br * cxi[v]);
+              tr[v] += br * xr[v][q] + bi * xi[v][q];
+              ti[v] += bi * xr[v][q] - br * xi[v][q];
+            }
           }
         }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        if (BM == BM_CONJ) {
+          sr[v] += tsb * tr[v];
+          si[v] += tsb * ti[v];
+        }
+        const double ur = dpp_wave_sum((double)sr[v]), ui = dpp_wave_sum((double)si[v]);
+        keep[v] = lane == c2 ? make_double2(ur, ui) : keep[v];
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        ca_[g] = na_[g];
+        if (BM == BM_CONJ) cbm[g] = nbm[g];
       }
     }
+    if (lane < CH) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      if (BM == BM_CONJ) {
-        sr[v] += tsb * tr[v];
-        si[v] += tsb * ti[v];
-      }
-      const T ur = wave_sum(sr[v]), ui = wave_sum(si[v]);
-      if (lane == 0)
-        colpart[(((size_t)v * nblk + blk) * NS + slice) * R + c] = make_double2((double)ur, (double)ui);
+      for (int v = 0; v < NV; ++v)
+        colpart[(((size_t)v * nblk + blk) * NS + slice) * R + wave * CPW + cb + lane] = keep[v];
     }
   }
 
@@ -1667,6 +1694,7 @@ hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const d
 template <int R, int AR, int BM, int NV>
 hipError_t launch_mk(const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv, double sb, double2* part,
                      hipStream_t s) {
+  static_assert(R >= 128, "the multi-vector kernel streams 16-byte segments of at least 128-row slices");
   using Sh = MkShape<R, AR, NV>;
   double2* rowpart = part;
   double2* colpart = part + (size_t)NV * L.nblk * R;
@@ -1723,8 +1751,13 @@ hipError_t mk_apply(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, int n
   }
   switch (L.R) {
     case 64:
-      e = dispatch_mk<64>(ar, bm, nv, L, m, V, ldv, sb, part, s);
-      break;
+      // small matrices: one-vector passes
+      for (int q = 0; q < nv; ++q) {
+        e = matvec(L, ar, bm, m, V + (size_t)q * ldv, 0, nullptr, 0, sb, part, out + (size_t)q * ldo, s,
+                   q == 0 ? ev0 : nullptr, q == nv - 1 ? ev1 : nullptr);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
     case 128:
       e = dispatch_mk<128>(ar, bm, nv, L, m, V, ldv, sb, part, s);
       break;
