@@ -117,6 +117,13 @@ hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s);
 hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const double* omega, int k,
                       int64_t n, double2* X, double2* Y, int64_t ldo, hipStream_t s);
 
+// MV[:, c] (+)= s [omega_c p_c + kp_c; conj(omega_c p_c - kp_c)],
+// s = 1 / (2 sqrt(omega_c)), for c < k: M v of the full-H vector
+// v = s [omega u + p; conj(omega u - p)] from p = K1 u, kp = K2 p (P, KP:
+// leading dimension ld; MV: column stride ldo, bottom at ldh).
+hipError_t ph_mvectors(const double2* P, const double2* KP, int64_t ld, const double* omega, int k, int64_t n,
+                       double2* MV, int64_t ldo, int64_t ldh, int add, hipStream_t s);
+
 // T[:, q] += H[:, q] for q < ncols, rows < cnt (leading dimensions ldT,
 // ldh); real_only adds the real parts only.
 hipError_t acc_cols(double2* T, int64_t ldT, const double2* H, int64_t ldh, int cnt, int ncols, int real_only,

@@ -1325,6 +1325,33 @@ __global__ void __launch_bounds__(kThreads)
   Y[(size_t)c * ldo + i] = make_double2(s * (w * u.x - p.x), -s * (w * u.y - p.y));
 }
 
+// MV[:, c] (+)= s [omega p + kp; conj(omega p - kp)], s = 1 / (2 sqrt(omega)):
+// M v for v = s [omega u + p; conj(omega u - p)] from p = K1 u and kp = K2 p
+// (columns of length 2 ld, top and bottom halves; add != 0 accumulates).
+__global__ void __launch_bounds__(kThreads)
+    ph_mvectors_kernel(const double2* __restrict__ P, const double2* __restrict__ KP, int64_t ld,
+                       const double* __restrict__ omega, int64_t n, double2* __restrict__ MV, int64_t ldo,
+                       int64_t ldh, int add) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const double w = omega[c];
+  const double s = 0.5 / sqrt(w);
+  const double2 p = P[(size_t)c * ld + i], kp = KP[(size_t)c * ld + i];
+  double2 t = make_double2(s * (w * p.x + kp.x), s * (w * p.y + kp.y));
+  double2 b = make_double2(s * (w * p.x - kp.x), -s * (w * p.y - kp.y));
+  const size_t it = (size_t)c * ldo + i, ib = it + ldh;
+  if (add) {
+    const double2 t0 = MV[it], b0 = MV[ib];
+    t.x += t0.x;
+    t.y += t0.y;
+    b.x += b0.x;
+    b.y += b0.y;
+  }
+  MV[it] = t;
+  MV[ib] = b;
+}
+
 // T[:, q] += H[:, q] (rows < cnt, columns < ncols); real_only drops Im(H).
 __global__ void __launch_bounds__(kThreads)
     acc_cols_kernel(double2* __restrict__ T, int64_t ldT, const double2* __restrict__ H, int64_t ldh, int cnt,
@@ -1859,6 +1886,14 @@ hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const doub
   if (k == 0) return hipSuccess;
   hipLaunchKernelGGL(ph_vectors_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)k),
                      dim3(kThreads), 0, s, U, P, ld, omega, n, X, Y, ldo);
+  return hipGetLastError();
+}
+
+hipError_t ph_mvectors(const double2* P, const double2* KP, int64_t ld, const double* omega, int k, int64_t n,
+                       double2* MV, int64_t ldo, int64_t ldh, int add, hipStream_t s) {
+  if (k == 0) return hipSuccess;
+  hipLaunchKernelGGL(ph_mvectors_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)k),
+                     dim3(kThreads), 0, s, P, KP, ld, omega, n, MV, ldo, ldh, add);
   return hipGetLastError();
 }
 

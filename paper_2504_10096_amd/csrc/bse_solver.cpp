@@ -693,7 +693,7 @@ struct RefineOut {
 // the vectors: TDA orthonormal; PH sqrt(omega) times the top and bottom of
 // v, normalized so that X^H X - Y^H Y = 1 per pair.
 bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double tol, int max_iter,
-                    double* omega, double2* X, double2* Y, RefineOut& out) {
+                    Arith bulk_ar, double* omega, double2* X, double2* Y, RefineOut& out) {
   bse_handle h = S.h;
   const Arith ar = fp64_arith(h);
   const int k = S.k;
@@ -745,7 +745,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   auto col = [&](double2* base, int c) { return base + (size_t)c * ld2; };
   // M v = [A x + B y; conj(A conj(y) + B conj(x))] for columns [c0, c1),
   // two vectors per read of the stored A and B (TDA: A v, four per read)
-  auto mapply = [&](int c0, int c1) -> bse_status {
+  auto mapply = [&](int c0, int c1, Arith mar, const bse::MatPtrs& mmp) -> bse_status {
     for (int c = c0; c < c1; c += ph ? 2 : 4) {
       const int nh = std::min(ph ? 2 : 4, c1 - c);
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -757,11 +757,10 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
         S.ev_mh.push_back({e0, e1});
       }
       if (ph)
-        HIP_TRY(h, bse::mh_apply(h->L, ar, mat_ptrs(h), nh, col(V, c), ld2, ld, mhpart, col(MV, c), 1.0, S.s, e0,
-                                 e1));
+        HIP_TRY(h, bse::mh_apply(h->L, mar, mmp, nh, col(V, c), ld2, ld, mhpart, col(MV, c), 1.0, S.s, e0, e1));
       else
-        HIP_TRY(h, bse::mk_apply(h->L, ar, bse::BM_NONE, mat_ptrs(h), nh, col(V, c), ld2, 0.0, mhpart, col(MV, c),
-                                 ld2, S.s, e0, e1));
+        HIP_TRY(h, bse::mk_apply(h->L, mar, bse::BM_NONE, mmp, nh, col(V, c), ld2, 0.0, mhpart, col(MV, c), ld2, S.s,
+                                 e0, e1));
       ++S.passes;
       S.mh_vectors += nh;
     }
@@ -816,7 +815,24 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     HIP_TRY(h, bse::copy_cols(S.U, ld, V, ld2, n, s0, S.s));
   }
   bse_status st;
-  if ((st = mapply(0, s0))) return st;
+  const bse::MatPtrs exact = mat_ptrs(h);
+  bse::MatPtrs lo_only = exact;
+  lo_only.a = exact.alo;
+  lo_only.b = exact.blo;
+  lo_only.alo = lo_only.blo = nullptr;
+  // M V of the starting vectors.  PH: from the iteration's own products,
+  // M v = s [omega p + kp; conj(omega p - kp)] with p = K1 u, kp = K2 p; exact
+  // when the iteration ran on the FP64 operator, and completed by one read of
+  // the lo triangles (M = M_hi + M_lo) after FP64 arithmetic on hi.  After
+  // complex FP32 arithmetic, or for TDA, by FP64 passes.
+  if (ph && bulk_ar != bse::AR_HI) {
+    if (bulk_ar == bse::AR_HI64) {
+      if ((st = mapply(0, s0, bse::AR_HI64, lo_only))) return st;
+    }
+    HIP_TRY(h, bse::ph_mvectors(S.P, S.KP, ld, Om, s0, n, MV, ld2, ld, bulk_ar == bse::AR_HI64 ? 1 : 0, S.s));
+  } else {
+    if ((st = mapply(0, s0, ar, exact))) return st;
+  }
   if ((st = gram(0, s0))) return st;
   int s = s0;
   std::vector<double> om(k), rr(k), vv(k);
@@ -942,7 +958,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
       ++s;
     }
     if (s == s_old) break;  // no new direction: stagnation
-    if ((st = mapply(s_old, s))) return st;
+    if ((st = mapply(s_old, s, ar, exact))) return st;
     if ((st = gram(s_old, s))) return st;
   }
   out.converged = false;
@@ -1234,7 +1250,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
       const int s0 = from32 ? std::min(S.keep, k + std::max(4, k / 8)) : k;
       RefineOut ro;
       const double tf = now_ms();
-      st = refine_h(S, s0, R.theta, tol, 200, omega, (double2*)x, ph ? (double2*)y : nullptr, ro);
+      st = refine_h(S, s0, R.theta, tol, 200, ar, omega, (double2*)x, ph ? (double2*)y : nullptr, ro);
       if (st) return st;
       ms_final += now_ms() - tf;
       rel = ro.rel;
