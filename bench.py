@@ -98,6 +98,7 @@ def main():
     p.add_argument("--block", type=int, default=0, help="TDA Lanczos block size (0: automatic)")
     p.add_argument("--ncv", type=int, default=0, help="Lanczos basis size (0: default)")
     p.add_argument("--keep", type=int, default=0, help="Ritz vectors kept at a restart (0: default)")
+    p.add_argument("--refine-start", type=int, default=0, help="Ritz vectors starting the refinement (0: default)")
     p.add_argument("--precision", choices=["auto", "fp64"], default="auto",
                    help="auto: the mixed path where the workload uses it; fp64: FP64 passes only")
     p.add_argument("--mode", choices=["solve", "passbench", "copy"], default="solve",
@@ -217,12 +218,14 @@ def main():
         return
 
     for i in range(args.warmup):
-        solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep)
+        solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep,
+                                  refine_start=args.refine_start)
         log(f"  warmup {i} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        omega, X, Y, st = solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep)
+        omega, X, Y, st = solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep,
+                                  refine_start=args.refine_start)
         log(f"  step {i}: {st['ms_total'] / 1e3:.2f} s, passes {st['passes']}, restarts {st['restarts']}, "
             f"max rel residual {st['max_rel_residual']:.2e}")
     torch.cuda.synchronize()
@@ -269,7 +272,8 @@ def main():
     if args.fp64 == "on" and precision == "mixed":
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        om64, X64, Y64, st64 = solver.solve(k, tol, precision="fp64", block=args.block, ncv=args.ncv, keep=args.keep)
+        om64, X64, Y64, st64 = solver.solve(k, tol, precision="fp64", block=args.block, ncv=args.ncv, keep=args.keep,
+                                  refine_start=args.refine_start)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         log(f"  fp64 path: {t64:.2f} s, passes {st64['passes']}, max rel residual {st64['max_rel_residual']:.2e}")

@@ -96,6 +96,10 @@ typedef struct {
                            for b >= 2); ncv and keep are rounded up to multiples of b.  PH:
                            ignored (b = 1: the folded iteration's basis is K1-orthogonal to its
                            partner space only when grown from one vector). */
+  int32_t refine_start; /* Ritz vectors of the iteration that start the FP64 refinement
+                           (0: k after an FP64 iteration, min(keep, k + max(4, k/8)) after the
+                           bulk phase of MIXED; at most keep) */
+  int32_t reserved_;
 } bse_solve_opts;
 
 /* Statistics of the last bse_solve (host struct). */

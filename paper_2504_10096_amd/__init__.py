@@ -38,7 +38,8 @@ EXPORTS = ["bse_create", "bse_set_packed", "bse_apply", "bse_solve", "bse_backwa
 class SolveOpts(ctypes.Structure):
     _fields_ = [("ncv", ctypes.c_int32), ("keep", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("switch_tol", ctypes.c_double), ("start_seed", ctypes.c_uint64),
-                ("fp32_arith", ctypes.c_int32), ("block", ctypes.c_int32)]
+                ("fp32_arith", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("refine_start", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -201,7 +202,7 @@ class Solver:
         return y
 
     def solve(self, k, tol, precision="fp64", ncv=0, keep=0, max_restarts=0, switch_tol=0.0, seed=1,
-              raise_not_converged=True, fp32_arith=False, block=0):
+              raise_not_converged=True, fp32_arith=False, block=0, refine_start=0):
         """Lowest k pairs.  Returns (omega[k] f64, X[k, N] c128, Y[k, N] c128 or None, stats dict);
         row c of X/Y is pair c (column c of the column-major N x k ABI layout).  With
         precision="mixed", fp32_arith selects complex FP32 arithmetic for the bulk passes
@@ -213,7 +214,7 @@ class Solver:
         X = torch.empty((k, self.n), dtype=torch.complex128, device=dev)
         Y = torch.empty((k, self.n), dtype=torch.complex128, device=dev) if self.kind == PSEUDO_HERMITIAN else None
         opts = SolveOpts(int(ncv), int(keep), int(max_restarts), PREC_MIXED if precision == "mixed" else PREC_FP64,
-                         float(switch_tol), int(seed), 1 if fp32_arith else 0, int(block))
+                         float(switch_tol), int(seed), 1 if fp32_arith else 0, int(block), int(refine_start), 0)
         stats = Stats()
         with torch.cuda.device(dev):
             st = load_library().bse_solve(self._h, k, float(tol), ctypes.byref(opts), _dev_ptr(omega),

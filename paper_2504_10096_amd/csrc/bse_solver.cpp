@@ -1247,7 +1247,8 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
         ms32 += now_ms() - t_phase;
         t_phase = now_ms();
       }
-      const int s0 = from32 ? std::min(S.keep, k + std::max(4, k / 8)) : k;
+      int s0 = from32 ? std::min(S.keep, k + std::max(4, k / 8)) : k;
+      if (o.refine_start > 0) s0 = std::max(k, std::min(S.keep, (int)o.refine_start));
       RefineOut ro;
       const double tf = now_ms();
       st = refine_h(S, s0, R.theta, tol, 200, ar, omega, (double2*)x, ph ? (double2*)y : nullptr, ro);
