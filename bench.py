@@ -26,6 +26,28 @@ METRIC = "time to lowest-k BSE pairs at N=1e5, mixed vs FP64 at 1e-8 residual; m
 HBM_PEAK_GBPS = 8000.0
 
 
+def counter_traffic(kernel_name):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary, or
+    None when there is none for this kernel or the kernel source changed since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "pmc_mv_stream_kernel_ph_n100000.txt")
+    src = os.path.join(here, "paper_2504_10096_amd", "csrc", "bse_kernels.hip")
+    try:
+        fields = {}
+        for line in open(path):
+            if line.startswith("#") or ":" not in line:
+                continue
+            key, val = line.split(":", 1)
+            fields[key.strip()] = val.strip()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernel") != kernel_name or fields.get("kernel_source_sha256") != sha:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -242,6 +264,12 @@ def main():
         bytes_launch = st["bytes_per_pass_fp64"]
         kernel_dtype = "c128" if storage == "c128" else "hi+lo"
     gbps = bytes_launch / (ms_launch * 1e-3) / 1e9 if ms_launch > 0 else 0.0
+    # measured HBM traffic of the same kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), as a rate
+    # over the same launch duration; null unless this run's dominant kernel is the one counted
+    traffic = tb = None
+    if ph and storage == "hilo" and precision == "mixed" and st["block"] <= 1 and ms_launch > 0 and n == 100000:
+        tb = counter_traffic("mv_stream_kernel<512, 3, 1>")
+        traffic = tb / (ms_launch * 1e-3) / 1e9 if tb else None
     result = {
         "metric": METRIC,
         "value": ms_per_step / 1e3,
@@ -258,10 +286,10 @@ def main():
         "config": {"workload": w["name"], "n": n, "k": k, "tol": tol, "kind": "ph" if ph else "tda",
                    "storage": storage, "precision": precision, "block_edge": None},
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": (f"mv_block_kernel ({kernel_dtype})" if st["block"] <= 1 else
+                     "frac": gbps / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": (f"mv_stream_kernel ({kernel_dtype})" if st["block"] <= 1 else
                                 f"mk_block_kernel ({kernel_dtype}, {st['block']} vectors)"),
-                     "bytes_per_launch": bytes_launch,
+                     "bytes_per_launch": bytes_launch, "traffic_bytes_per_launch": tb,
                      "ms_per_launch": ms_launch},
         "solve": {k_: st[k_] for k_ in ("passes", "block", "restarts", "steps_fp32", "steps_fp64", "ms_fp32_phase",
                                         "ms_fp64_phase", "ms_final", "max_rel_residual", "n_converged")},

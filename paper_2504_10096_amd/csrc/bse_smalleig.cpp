@@ -42,10 +42,11 @@ void tridiagonalize(int m, double* a, double* d, double* e, double* q) {
     // A <- H A H with H = I - 2 v v^T: p = A v, g = v^T p, p -= g v,
     // A -= 2 (v p^T + p v^T)
     double g = 0.0;
-    for (int i = k; i < m; ++i) {
-      double s = 0.0;
-      for (int j = k + 1; j < m; ++j) s += at(a, m, i, j) * v[j];
-      p[i] = s;
+    for (int i = k; i < m; ++i) p[i] = 0.0;
+    for (int j = k + 1; j < m; ++j) {  // p = A v, column by column
+      const double vj = v[j];
+      const double* aj = &at(a, m, 0, j);
+      for (int i = k; i < m; ++i) p[i] += aj[i] * vj;
     }
     for (int i = k + 1; i < m; ++i) g += v[i] * p[i];
     for (int i = k; i < m; ++i) p[i] -= g * v[i];
@@ -130,10 +131,11 @@ void herm_tridiagonalize(int m, cplx* a, double* d, cplx* e, cplx* q) {
     for (int i = k + 1; i < m; ++i) v[i] /= vn;
     // A <- H A H, H = I - 2 v v^H: p = A v, g = v^H p (real), q = p - g v,
     // A -= 2 (v q^H + q v^H)
-    for (int i = k; i < m; ++i) {
-      cplx t = 0.0;
-      for (int j = k + 1; j < m; ++j) t += A(i, j) * v[j];
-      p[i] = t;
+    for (int i = k; i < m; ++i) p[i] = 0.0;
+    for (int j = k + 1; j < m; ++j) {  // p = A v, column by column
+      const cplx vj = v[j];
+      const cplx* aj = &A(0, j);
+      for (int i = k; i < m; ++i) p[i] += aj[i] * vj;
     }
     cplx g = 0.0;
     for (int i = k + 1; i < m; ++i) g += std::conj(v[i]) * p[i];
@@ -204,15 +206,19 @@ bool herm_eig(int m, double2* a, double* w, double2* z) {
   std::vector<int> ord(m);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
-  // eigenvectors Z = Q_h D Q_r
+  // eigenvectors Z = Q_h D Q_r, column by column
+  std::vector<cplx> zc(m);
   for (int c = 0; c < m; ++c) {
     const int oc = ord[c];
     w[c] = d[oc];
-    for (int i = 0; i < m; ++i) {
-      cplx t = 0.0;
-      for (int j = 0; j < m; ++j) t += qh[(size_t)j * m + i] * delta[j] * qr[(size_t)oc * m + j];
-      z[(size_t)c * m + i] = make_double2(t.real(), t.imag());
+    std::fill(zc.begin(), zc.end(), cplx(0.0));
+    for (int j = 0; j < m; ++j) {
+      const cplx f = delta[j] * qr[(size_t)oc * m + j];
+      if (f == 0.0) continue;
+      const cplx* qj = &qh[(size_t)j * m];
+      for (int i = 0; i < m; ++i) zc[i] += qj[i] * f;
     }
+    for (int i = 0; i < m; ++i) z[(size_t)c * m + i] = make_double2(zc[i].real(), zc[i].imag());
   }
   return true;
 }
