@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time to lowest-k BSE pairs at N=1e5, mixed vs FP64 at 1e-8 residual; matvec GB/s"
 HBM_PEAK_GBPS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def counter_traffic(kernel_name):
@@ -117,6 +118,8 @@ def main():
     p.add_argument("--check", choices=["on", "off"], default="on",
                    help="oracle FP64 residuals of sampled pairs (streaming, CPU)")
     p.add_argument("--chunk-gb", type=float, default=2.0)
+    p.add_argument("--grad", choices=["on", "off"], default="on",
+                   help="PH: dL/dalpha and dL/dbeta of the solve through the adjoint")
     p.add_argument("--block", type=int, default=0, help="TDA Lanczos block size (0: automatic)")
     p.add_argument("--ncv", type=int, default=0, help="Lanczos basis size (0: default)")
     p.add_argument("--keep", type=int, default=0, help="Ritz vectors kept at a restart (0: default)")
@@ -295,7 +298,29 @@ def main():
                                         "ms_fp64_phase", "ms_final", "max_rel_residual", "n_converged")},
         "setup_s": t_setup,
     }
+    if st["ms_gemm"] > 0:
+        tf = st["gemm_flops"] / (st["ms_gemm"] * 1e-3) / 1e12
+        result["mfma"] = {"kernel": "dgemm_mfma_kernel / zgemm_mfma_kernel (basis rotations)",
+                          "achieved": tf, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": tf / FP64_MFMA_PEAK_TFLOPS, "ms_total": st["ms_gemm"], "flops": st["gemm_flops"]}
     om_mixed = omega.cpu().numpy()
+
+    if ph and args.grad == "on":
+        # dL/dalpha and dL/dbeta of L = sum_c g_c omega_c through the adjoint's strength scalars:
+        # A = D + alpha Kx - beta W, B = alpha B0
+        t0 = time.perf_counter()
+        g = torch.as_tensor(synth.loss_weights(w["seed"], k))
+        tabs = mat.tables
+        comps = [("A", "lowrank", torch.as_tensor(tabs.x_factor()).cuda(), 1.0 / n),
+                 ("B", "lowrank", torch.as_tensor(tabs.y_factor()).cuda(), mat.b0_scale),
+                 ("A", "diag", torch.as_tensor(tabs.eps + mat.shift).cuda(), 1.0),
+                 ("A", "stored", None, 1.0)]
+        kx, b0, dg, sa = solver.strength(g, comps)
+        torch.cuda.synchronize()
+        result["gradients"] = {"loss": float(g.numpy() @ om_mixed), "dL_dalpha": kx + b0,
+                               "dL_dbeta": -(dg + mat.alpha * kx - sa) / mat.beta,
+                               "seconds": time.perf_counter() - t0}
+        log(f"  dL/dalpha {kx + b0:.10g}, dL/dbeta {result['gradients']['dL_dbeta']:.10g}")
 
     if args.fp64 == "on" and precision == "mixed":
         torch.cuda.synchronize()

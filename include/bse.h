@@ -125,6 +125,8 @@ typedef struct {
   int64_t fused_vectors;    /* vectors multiplied by H in the refinement (two per fused launch) */
   int32_t block;            /* Lanczos block size used (vectors per read of the triangles) */
   int32_t reserved_;
+  double ms_gemm;           /* summed duration of the basis-rotation GEMMs (restarts, refinement; MFMA) */
+  double gemm_flops;        /* their algorithmic flops (real: 2 M N K; complex: 8 M N K) */
 } bse_stats;
 
 /* Component of a matrix for bse_strength: the scalar returned for a

@@ -51,7 +51,8 @@ class Stats(ctypes.Structure):
                 ("samples_fp32", ctypes.c_int64), ("samples_fp64", ctypes.c_int64),
                 ("ms_block_fp32", ctypes.c_double), ("ms_block_fp64", ctypes.c_double),
                 ("samples_fused", ctypes.c_int64), ("ms_block_fused", ctypes.c_double),
-                ("fused_vectors", ctypes.c_int64), ("block", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("fused_vectors", ctypes.c_int64), ("block", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("ms_gemm", ctypes.c_double), ("gemm_flops", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -151,6 +151,9 @@ struct Solver {
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, bool>> ev_pending;  // (pair, is_fp32)
   int64_t samples32 = 0, samples64 = 0;
+  // rotation GEMMs (restart and refinement, MFMA), timed with their flops
+  std::vector<std::pair<std::pair<hipEvent_t, hipEvent_t>, double>> ev_gemm;
+  double ms_gemm = 0.0, gemm_flops = 0.0;
   // fused full-H launches of the refinement, timed separately
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_mh;
   int64_t samples_mh = 0, mh_vectors = 0;
@@ -165,6 +168,10 @@ struct Solver {
     for (auto& p : ev_mh) {
       ev_free.push_back(p.first);
       ev_free.push_back(p.second);
+    }
+    for (auto& p : ev_gemm) {
+      ev_free.push_back(p.first.first);
+      ev_free.push_back(p.first.second);
     }
     for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
   }
@@ -196,6 +203,26 @@ void harvest_events(Solver& S) {
     S.ev_free.push_back(p.second);
   }
   S.ev_mh.clear();
+  for (auto& p : S.ev_gemm) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p.first.first, p.first.second) == hipSuccess) {
+      S.ms_gemm += ms;
+      S.gemm_flops += p.second;
+    }
+    S.ev_free.push_back(p.first.first);
+    S.ev_free.push_back(p.first.second);
+  }
+  S.ev_gemm.clear();
+}
+
+// Event pair around a group of GEMMs (nullptr events when the pool is empty).
+std::pair<hipEvent_t, hipEvent_t> gemm_events(Solver& S) {
+  if (S.ev_free.size() < 2) return {nullptr, nullptr};
+  hipEvent_t e1 = S.ev_free.back();
+  S.ev_free.pop_back();
+  hipEvent_t e0 = S.ev_free.back();
+  S.ev_free.pop_back();
+  return {e0, e1};
 }
 
 bse_status alloc_solver(Solver& S) {
@@ -510,20 +537,31 @@ bse_status restart(Solver& S, RitzInfo& R) {
                 "non-positive folded Ritz value omega^2: M is not positive definite");
   const int keep = S.keep;
   // U2[:, 0:keep] = U[:, 0:m] Z[:, 0:keep]; the next block follows
+  const auto ge = gemm_events(S);
   if (S.ph) {
     HIP_TRY(h, hipMemcpyAsync(S.S, Zr.data(), sizeof(double) * (size_t)m * keep, hipMemcpyHostToDevice, S.s));
+    if (ge.first) HIP_TRY(h, hipEventRecord(ge.first, S.s));
     HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.U, 2 * S.ld, S.S, m, (double*)S.U2,
                                   2 * S.ld, S.s));
     HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.P, 2 * S.ld, S.S, m, (double*)S.P2,
                                   2 * S.ld, S.s));
     HIP_TRY(h, bse::dgemm_tn_mfma(2 * S.n, keep, m, (const double*)S.KP, 2 * S.ld, S.S, m, (double*)S.KP2,
                                   2 * S.ld, S.s));
+    if (ge.first) {
+      HIP_TRY(h, hipEventRecord(ge.second, S.s));
+      S.ev_gemm.push_back({ge, 3.0 * 2.0 * (2.0 * S.n) * keep * m});
+    }
     HIP_TRY(h, bse::copy_cols(S.P + (size_t)m * S.ld, S.ld, S.P2 + (size_t)keep * S.ld, S.ld, S.n, b, S.s));
     std::swap(S.P, S.P2);
     std::swap(S.KP, S.KP2);
   } else {
     HIP_TRY(h, hipMemcpyAsync(S.S, Zc.data(), sizeof(double2) * (size_t)m * keep, hipMemcpyHostToDevice, S.s));
+    if (ge.first) HIP_TRY(h, hipEventRecord(ge.first, S.s));
     HIP_TRY(h, bse::zgemm_mfma(S.n, keep, m, S.U, S.ld, (const double2*)S.S, m, S.U2, S.ld, S.s));
+    if (ge.first) {
+      HIP_TRY(h, hipEventRecord(ge.second, S.s));
+      S.ev_gemm.push_back({ge, 8.0 * S.n * keep * m});
+    }
   }
   HIP_TRY(h, bse::copy_cols(S.U + (size_t)m * S.ld, S.ld, S.U2 + (size_t)keep * S.ld, S.ld, S.n, b, S.s));
   std::swap(S.U, S.U2);
@@ -894,8 +932,14 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     }
     zlhsolve(s, L.data(), Yc.data(), sk);  // coefficients with Yc^H G Yc = I
     HIP_TRY(h, hipMemcpyAsync(Cd, Yc.data(), sizeof(double2) * (size_t)s * sk, hipMemcpyHostToDevice, S.s));
+    const auto ge = gemm_events(S);
+    if (ge.first) HIP_TRY(h, hipEventRecord(ge.first, S.s));
     HIP_TRY(h, bse::zgemm_mfma(ld2, sk, s, V, ld2, Cd, s, V2, ld2, S.s));
     HIP_TRY(h, bse::zgemm_mfma(ld2, sk, s, MV, ld2, Cd, s, MV2, ld2, S.s));
+    if (ge.first) {
+      HIP_TRY(h, hipEventRecord(ge.second, S.s));
+      S.ev_gemm.push_back({ge, 2.0 * 8.0 * (double)n2 * sk * s});
+    }
     std::swap(V, V2);
     std::swap(MV, MV2);
     s = sk;
@@ -1322,6 +1366,8 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
     stats->samples_fp64 = S.samples64;
     stats->ms_block_fp32 = S.ms_blk32;
     stats->ms_block_fp64 = S.ms_blk64;
+    stats->ms_gemm = S.ms_gemm;
+    stats->gemm_flops = S.gemm_flops;
     stats->samples_fused = S.samples_mh;
     stats->ms_block_fused = S.ms_mh;
     stats->fused_vectors = S.mh_vectors;
@@ -1489,28 +1535,43 @@ bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse
         }
         sum += w[p] * v;
       }
-    } else {  // STORED: quadratic forms with the stored FP64 block
+    } else if (!tb) {
+      // STORED A: quadratic forms x^H A x (+ conj(y)^H A conj(y)) with the
+      // stored FP64 block, up to four vectors per read of the triangle
+      if (bse_status e = ensure_mhpart(h)) return e;
+      DevBuf vin, vout;
+      HIP_TRY(h, hipMalloc(&vin.p, sizeof(double2) * 4 * (size_t)n));
+      HIP_TRY(h, hipMalloc(&vout.p, sizeof(double2) * 4 * (size_t)n));
+      double2* vi = (double2*)vin.p;
+      double2* vo = (double2*)vout.p;
+      const int nvec = ph ? 2 * k : k;
+      for (int v0 = 0; v0 < nvec; v0 += 4) {
+        const int nv = std::min(4, nvec - v0);
+        for (int q2 = 0; q2 < nv; ++q2) {
+          const int v = v0 + q2, p = ph ? v / 2 : v;
+          if (ph && (v & 1))
+            HIP_TRY(h, bse::conj_copy(h->Y + (size_t)p * n, vi + (size_t)q2 * n, n, 1.0, st));
+          else
+            HIP_TRY(h, hipMemcpyAsync(vi + (size_t)q2 * n, h->X + (size_t)p * n, sizeof(double2) * n,
+                                      hipMemcpyDeviceToDevice, st));
+        }
+        HIP_TRY(h, bse::mk_apply(h->L, ar, bse::BM_NONE, mp, nv, vi, n, 0.0, h->mhpart, vo, n, st));
+        for (int q2 = 0; q2 < nv; ++q2) {
+          const int v = v0 + q2, p = ph ? v / 2 : v;
+          double2 d1;
+          if ((sst = dotc(vi + (size_t)q2 * n, vo + (size_t)q2 * n, &d1))) return sst;
+          sum += w[p] * d1.x;
+        }
+      }
+    } else {  // STORED B: 2 Re(x^H B y) with the stored FP64 block, one pass per pair
       for (int p = 0; p < k; ++p) {
         const double2* xc = h->X + (size_t)p * n;
         double2 d1;
-        if (!tb) {
-          HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_NONE, mp, xc, 0, nullptr, 0, 0.0, h->part, t2, st));
-          if ((sst = dotc(xc, t2, &d1))) return sst;
-          double v = d1.x;
-          if (ph) {
-            HIP_TRY(h, bse::conj_copy(h->Y + (size_t)p * n, t1, n, 1.0, st));
-            HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_NONE, mp, t1, 0, nullptr, 0, 0.0, h->part, t2, st));
-            if ((sst = dotc(t1, t2, &d1))) return sst;
-            v += d1.x;
-          }
-          sum += w[p] * v;
-        } else {
-          // B y alone: A * 0 + B y
-          HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, (const double2*)zero.p, 0,
-                                 h->Y + (size_t)p * n, 0, 1.0, h->part, t2, st));
-          if ((sst = dotc(xc, t2, &d1))) return sst;
-          sum += w[p] * 2.0 * d1.x;
-        }
+        // B y alone: A * 0 + B y
+        HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, (const double2*)zero.p, 0, h->Y + (size_t)p * n, 0,
+                               1.0, h->part, t2, st));
+        if ((sst = dotc(xc, t2, &d1))) return sst;
+        sum += w[p] * 2.0 * d1.x;
       }
     }
     out[q] = c.scale * sum;

@@ -1,0 +1,103 @@
+"""Full-size workloads on the GPU, checked by what holds at any size: the
+oracle's streaming FP64 residual of sampled pairs, agreement of the mixed and
+FP64 paths, and finite differences of the eigenvalue-weighted loss against
+the adjoint's strength scalars."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2504_10096_amd as bse
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def generated_solver(mat, storage, alpha=None, beta=None, chunk_entries=1 << 26):
+    """Solver filled by the device generator, packed columns in chunks."""
+    s = bse.Solver("ph" if mat.ph else "tda", mat.n, storage=storage)
+    gen = synth.DeviceGen(mat, alpha=alpha, beta=beta)
+    staging = torch.empty(chunk_entries, dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    for which, name in enumerate(["A", "B"] if mat.ph else ["A"]):
+        j0 = 0
+        while j0 < mat.n:
+            base = j0 * (j0 + 1)
+            j1 = int((-1 + math.sqrt(1 + 4 * (base + 2 * chunk_entries))) // 2)
+            j1 = max(j0 + 1, min(mat.n, j1))
+            while (j1 * (j1 + 1) - base) // 2 > chunk_entries and j1 > j0 + 1:
+                j1 -= 1
+            gen.pack(which, j0, j1, staging.data_ptr(), stream)
+            s.set_packed_raw(name, staging.data_ptr(), j0, j1)
+            j0 = j1
+    torch.cuda.synchronize()
+    gen.close()
+    return s
+
+
+def test_workload_tda_n32768_k64_mixed_and_fp64():
+    w = synth.WORKLOADS[2]
+    mat = synth.workload_matrix(2)
+    k, tol = w["k"], w["tol"]
+    print(f"workload {w['name']}", flush=True)
+    s = generated_solver(mat, "hilo")
+    lam_m, X_m, _, st_m = s.solve(k, tol, precision="mixed")
+    lam_d, X_d, _, st_d = s.solve(k, tol)
+    lm, ld = host(lam_m), host(lam_d)
+    print("mixed", st_m["passes"], st_m["ms_total"], "fp64", st_d["passes"], st_d["ms_total"], flush=True)
+    assert st_m["max_rel_residual"] <= tol and st_d["max_rel_residual"] <= tol
+    # both paths find the same k eigenvalues (error ~ residual^2 / gap)
+    assert np.max(np.abs(lm - ld) / np.abs(ld)) < 1e-9
+    # the oracle's FP64 operator (regenerated on the CPU) confirms sampled residuals
+    idx = [0, k // 2, k - 1]
+    rel = oracle.residual_generated(mat, lm[idx], host(X_m)[idx].T)
+    assert np.max(rel) <= tol * 1.01, rel
+    s.close()
+
+
+def test_workload_ph_n16384_k32_gradient_fd():
+    w = synth.WORKLOADS[3]
+    mat = synth.workload_matrix(3)
+    k = w["k"]
+    print(f"workload {w['name']}", flush=True)
+    g = synth.loss_weights(w["seed"], k)
+    s = generated_solver(mat, "c128")
+    om, X, Y, st = s.solve(k, 1e-12)
+    assert st["max_rel_residual"] <= 1e-12
+    n = mat.n
+    t = mat.tables
+    xf = torch.as_tensor(t.x_factor()).cuda()
+    yf = torch.as_tensor(t.y_factor()).cuda()
+    comps = [("A", "lowrank", xf, 1.0 / n), ("B", "lowrank", yf, mat.b0_scale),
+             ("A", "diag", torch.as_tensor(t.eps + mat.shift).cuda(), 1.0), ("A", "stored", None, 1.0),
+             ("B", "stored", None, 1.0)]
+    kx, b0, dg, sa, sbb = s.strength(torch.as_tensor(g), comps)
+    # A = D + alpha Kx - beta W, B = alpha B0: dL/dalpha = <G_A, Kx> + <G_B, B0>,
+    # dL/dbeta = -<G_A, W> with W = (D + alpha Kx - A) / beta
+    d_alpha = kx + b0
+    d_beta = -(dg + mat.alpha * kx - sa) / mat.beta
+    # Euler: L = <G_A, A> + <G_B, B>
+    L0 = float(g @ host(om))
+    assert abs(sa + sbb - L0) < 1e-10 * abs(L0)
+    s.close()
+    h = 1e-4
+    fd = {}
+    for name, kw in [("alpha", "alpha"), ("beta", "beta")]:
+        vals = []
+        for sign in (1, -1):
+            v = getattr(mat, name) + sign * h
+            s2 = generated_solver(mat, "c128", **{kw: v})
+            om2, _, _, st2 = s2.solve(k, 1e-12)
+            assert st2["max_rel_residual"] <= 1e-12
+            vals.append(float(g @ host(om2)))
+            s2.close()
+        fd[name] = (vals[0] - vals[1]) / (2 * h)
+    print("d_alpha", d_alpha, fd["alpha"], "d_beta", d_beta, fd["beta"], flush=True)
+    assert abs(d_alpha - fd["alpha"]) <= 1e-6 * max(1.0, abs(d_alpha))
+    assert abs(d_beta - fd["beta"]) <= 1e-6 * max(1.0, abs(d_beta))
