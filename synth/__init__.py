@@ -251,6 +251,13 @@ def test_vectors(seed, n, nvec):
     return rng.standard_normal((n, nvec)) + 1j * rng.standard_normal((n, nvec))
 
 
+def dipole(seed, n):
+    """Seeded synthetic dipole vector for optical spectra: N i.i.d. circular complex normal
+    entries CN(0, 1) (real and imaginary parts N(0, 1/2)), Philox-keyed like test_vectors."""
+    rng = np.random.Generator(np.random.Philox(key=seed + 0x5D1))
+    return (rng.standard_normal(n) + 1j * rng.standard_normal(n)) * np.sqrt(0.5)
+
+
 def packed_index(i, j):
     """Offset of (i, j), i <= j, in LAPACK-'U' packed storage."""
     return i + j * (j + 1) // 2
