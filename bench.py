@@ -124,6 +124,10 @@ def main():
     p.add_argument("--ncv", type=int, default=0, help="Lanczos basis size (0: default)")
     p.add_argument("--keep", type=int, default=0, help="Ritz vectors kept at a restart (0: default)")
     p.add_argument("--refine-start", type=int, default=0, help="Ritz vectors starting the refinement (0: default)")
+    p.add_argument("--haydock", choices=["on", "off"], default="on",
+                   help="also time a Lanczos-Haydock spectrum of the same matrix")
+    p.add_argument("--variant", type=int, default=0, choices=[0, 1],
+                   help="PH iteration: 0 K1-metric Lanczos on K2 K1, 1 Lanczos on H in the M inner product")
     p.add_argument("--precision", choices=["auto", "fp64"], default="auto",
                    help="auto: the mixed path where the workload uses it; fp64: FP64 passes only")
     p.add_argument("--mode", choices=["solve", "passbench", "copy"], default="solve",
@@ -244,13 +248,13 @@ def main():
 
     for i in range(args.warmup):
         solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep,
-                                  refine_start=args.refine_start)
+                                  refine_start=args.refine_start, variant=args.variant)
         log(f"  warmup {i} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         omega, X, Y, st = solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep,
-                                  refine_start=args.refine_start)
+                                  refine_start=args.refine_start, variant=args.variant)
         log(f"  step {i}: {st['ms_total'] / 1e3:.2f} s, passes {st['passes']}, restarts {st['restarts']}, "
             f"max rel residual {st['max_rel_residual']:.2e}")
     torch.cuda.synchronize()
@@ -287,7 +291,8 @@ def main():
         "dtype": "c64/f64" if precision == "mixed" else "f64",
         "data": "synthetic (seeded BSE-shaped recipe, generated on device)",
         "config": {"workload": w["name"], "n": n, "k": k, "tol": tol, "kind": "ph" if ph else "tda",
-                   "storage": storage, "precision": precision, "block_edge": None},
+                   "storage": storage, "precision": precision, "block_edge": None,
+                   "variant": ("lanczos_h_m_metric" if args.variant == 1 else "k1_metric_folded") if ph else None},
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": gbps / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": (f"mv_stream_kernel ({kernel_dtype})" if st["block"] <= 1 else
@@ -322,11 +327,32 @@ def main():
                                "seconds": time.perf_counter() - t0}
         log(f"  dL/dalpha {kx + b0:.10g}, dL/dbeta {result['gradients']['dL_dbeta']:.10g}")
 
+    if args.haydock == "on":
+        # optical spectrum of the same matrix by the Lanczos-Haydock recursion (one read of the
+        # triangles per TDA step, two per PH step), FP64 arithmetic on the complex64 hi triangles
+        d = torch.as_tensor(synth.dipole(w["seed"], n)).cuda()
+        freq = torch.linspace(0.5, 12.0, 256, dtype=torch.float64, device="cuda")
+        hprec = "hi64" if storage == "hilo" else "fp64"
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        al, be, nn, chi, sth = solver.haydock(d, 2000, tol=1e-6, freq=freq, eta=0.1, precision=hprec)
+        torch.cuda.synchronize()
+        th = time.perf_counter() - t0
+        key = "fp32" if hprec == "hi64" else "fp64"
+        msh = sth[f"ms_block_{key}"] / max(1, sth[f"samples_{key}"])
+        bph = sth[f"bytes_per_pass_{key}"]
+        result["haydock"] = {"precision": hprec, "steps": int(al.numel()), "passes": sth["passes"], "seconds": th,
+                             "tol": 1e-6, "eta": 0.1, "nw": 256, "ms_per_pass": msh,
+                             "GBps": bph / (msh * 1e-3) / 1e9 if msh else 0.0,
+                             "peak_absorption_freq": float(freq[torch.argmax(-chi.imag)].item())}
+        log(f"  haydock: {al.numel()} steps, {sth['passes']} passes, {th:.2f} s")
+        del d, freq, chi
+
     if args.fp64 == "on" and precision == "mixed":
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         om64, X64, Y64, st64 = solver.solve(k, tol, precision="fp64", block=args.block, ncv=args.ncv, keep=args.keep,
-                                  refine_start=args.refine_start)
+                                  refine_start=args.refine_start, variant=args.variant)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         log(f"  fp64 path: {t64:.2f} s, passes {st64['passes']}, max rel residual {st64['max_rel_residual']:.2e}")

@@ -99,7 +99,12 @@ typedef struct {
   int32_t refine_start; /* Ritz vectors of the iteration that start the FP64 refinement
                            (0: k after an FP64 iteration, min(keep, k + max(4, k/8)) after the
                            bulk phase of MIXED; at most keep) */
-  int32_t reserved_;
+  int32_t variant;      /* PH structure-preserving iteration: 0 (default) the K1-metric Lanczos
+                           process on K2 K1, whose Ritz values are omega^2; 1 the Lanczos
+                           process on H in the inner product of M, started from [u; conj(u)]
+                           (zero-diagonal projected matrix, coupled K1- and K2-orthonormal
+                           bases, Ritz values omega).  Both take two reads of the triangles per
+                           step.  TDA: ignored. */
 } bse_solve_opts;
 
 /* Statistics of the last bse_solve (host struct). */
@@ -231,6 +236,60 @@ bse_status bse_backward(bse_handle h, const double* g, void* d_a, void* d_b);
  */
 bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse_component* comps,
                         double* out);
+
+/*
+ * bse_haydock -- optical spectrum without eigenpairs: the Lanczos iteration
+ * with a quadrature (continued fraction) that the paper names as the first
+ * route of the iterative solver, and as the Haydock solver of its
+ * time-complexity comparison, which exploits the pseudo-Hermitian structure.
+ * For a dipole vector d the response is
+ *   TDA: chi(z) = d^H (z - A)^{-1} d;
+ *   PH:  chi(z) = q^H Omega (z - H)^{-1} q, q = [d; conj(d)]
+ *        (resonant and antiresonant poles at +omega_i and -omega_i),
+ * and the absorption is -Im chi(w + i eta).  Recurrences, one read of the
+ * stored triangles per TDA step and two per PH step, no reorthogonalization
+ * (the three-term recurrence, each new vector made orthogonal to the two
+ * before it):
+ *   TDA: Hermitian Lanczos on A from d / ||d||: coefficients alpha_j, beta_j
+ *        with chi(z) ~ ||d||^2 / (z - alpha_1 - beta_1^2 / (z - alpha_2 - ...));
+ *   PH:  Lanczos on K2 K1 in the inner product <u, K1 v> (K1 u = A u + B conj(u),
+ *        K2 p = A p - B conj(p)) from d / sqrt(<d, K1 d>); since
+ *        chi(z) = 2 <d, K1 (z^2 - K2 K1)^{-1} d>, the same fraction in z^2 times
+ *        2 <d, K1 d>.
+ * Arguments:
+ *   d:        device, N complex128 (interleaved re, im), not modified.
+ *   max_iter: iterations (>= 1); alpha, beta: device, max_iter doubles each,
+ *             the first *n_iter written (beta_j couples steps j and j + 1).
+ *   tol:      0: run max_iter steps.  > 0: every 20 steps evaluate chi on the
+ *             grid and stop once max |delta Im chi| <= tol max |Im chi|.
+ *   precision: FP64 (the FP64 operator), HI_FP64 (FP64 arithmetic on the
+ *             complex64 hi triangles, HILO only) or MIXED (complex FP32
+ *             arithmetic on hi, HILO only).
+ *   freq, nw, eta: device frequency grid (nw doubles) and broadening eta > 0;
+ *             chi: device, nw complex128, the response at freq + i eta after
+ *             the last step.  freq and chi may be NULL (nw = 0) when tol = 0.
+ *   norm2:    host: ||d||^2 (TDA) or <d, K1 d> (PH);  n_iter: host, steps done.
+ *   stats:    host, nullable: passes, ms_total, block-kernel samples.
+ * Errors: INVALID_ARG (nulls, max_iter < 1, tol < 0, eta <= 0 with a grid,
+ * precision not allowed by the storage), NOT_POSITIVE_DEFINITE (<w, K1 w> <=
+ * 0, PH), NONFINITE, DEVICE, OUT_OF_MEMORY.  A zero beta_j (an invariant
+ * subspace) ends the fraction there: later coefficients do not enter chi.
+ */
+bse_status bse_haydock(bse_handle h, const void* d, int32_t max_iter, double tol, bse_precision precision,
+                       const double* freq, int32_t nw, double eta, double* alpha, double* beta, double* norm2,
+                       void* chi, int32_t* n_iter, bse_stats* stats);
+
+/*
+ * bse_haydock_spectrum -- chi(w + i eta) on a device grid from n_iter
+ * coefficients of bse_haydock (device alpha, beta), with the scale norm2 it
+ * returned: TDA (kind 0) norm2 times the fraction in z, PH (kind 1) 2 norm2
+ * times the fraction in z^2, truncated after n_iter levels.  Enqueued on
+ * hip_stream (NULL: the default stream) and synchronized before returning.
+ * Errors: INVALID_ARG (nulls, n_iter < 1, nw < 1, eta <= 0, bad kind), DEVICE.
+ */
+bse_status bse_haydock_spectrum(bse_kind kind, int32_t n_iter, const double* alpha, const double* beta,
+                                double norm2, const double* freq, int32_t nw, double eta, void* chi,
+                                void* hip_stream);
 
 /* bse_destroy -- free all device memory of the handle (NULL is a no-op). */
 bse_status bse_destroy(bse_handle h);

@@ -32,14 +32,17 @@ OP_A, OP_K1, OP_K2, OP_H = 0, 1, 2, 3
 COMP_PACKED, COMP_LOWRANK, COMP_DIAG, COMP_STORED = 0, 1, 2, 3
 
 EXPORTS = ["bse_create", "bse_set_packed", "bse_apply", "bse_solve", "bse_backward", "bse_strength",
-           "bse_destroy", "bse_status_string", "bse_last_error"]
+           "bse_haydock", "bse_haydock_spectrum", "bse_destroy", "bse_status_string", "bse_last_error"]
 
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("ncv", ctypes.c_int32), ("keep", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("switch_tol", ctypes.c_double), ("start_seed", ctypes.c_uint64),
                 ("fp32_arith", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("refine_start", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("refine_start", ctypes.c_int32), ("variant", ctypes.c_int32)]
+
+
+VARIANT_FOLDED, VARIANT_COUPLED = 0, 1
 
 
 class Stats(ctypes.Structure):
@@ -96,6 +99,9 @@ def load_library():
         "bse_solve": ([vp, i32, dbl, ctypes.POINTER(SolveOpts), vp, vp, vp, ctypes.POINTER(Stats)], i32),
         "bse_backward": ([vp, vp, vp, vp], i32),
         "bse_strength": ([vp, vp, i32, ctypes.POINTER(Component), ctypes.POINTER(dbl)], i32),
+        "bse_haydock": ([vp, vp, i32, dbl, i32, vp, i32, dbl, vp, vp, ctypes.POINTER(dbl), vp,
+                         ctypes.POINTER(i32), ctypes.POINTER(Stats)], i32),
+        "bse_haydock_spectrum": ([i32, i32, vp, vp, dbl, vp, i32, dbl, vp, vp], i32),
         "bse_destroy": ([vp], i32),
         "bse_status_string": ([i32], ctypes.c_char_p),
         "bse_last_error": ([vp], ctypes.c_char_p),
@@ -203,19 +209,21 @@ class Solver:
         return y
 
     def solve(self, k, tol, precision="fp64", ncv=0, keep=0, max_restarts=0, switch_tol=0.0, seed=1,
-              raise_not_converged=True, fp32_arith=False, block=0, refine_start=0):
+              raise_not_converged=True, fp32_arith=False, block=0, refine_start=0, variant=0):
         """Lowest k pairs.  Returns (omega[k] f64, X[k, N] c128, Y[k, N] c128 or None, stats dict);
         row c of X/Y is pair c (column c of the column-major N x k ABI layout).  With
         precision="mixed", fp32_arith selects complex FP32 arithmetic for the bulk passes
         (default: FP64 arithmetic on the FP32-stored triangles).  block: vectors per read of the
-        triangles in the Lanczos iteration (0: automatic)."""
+        triangles in the Lanczos iteration (0: automatic).  variant (PH): 0 the K1-metric
+        iteration on K2 K1, 1 the Lanczos process on H in the M inner product."""
         k = int(k)
         dev = self.device
         omega = torch.empty(k, dtype=torch.float64, device=dev)
         X = torch.empty((k, self.n), dtype=torch.complex128, device=dev)
         Y = torch.empty((k, self.n), dtype=torch.complex128, device=dev) if self.kind == PSEUDO_HERMITIAN else None
         opts = SolveOpts(int(ncv), int(keep), int(max_restarts), PREC_MIXED if precision == "mixed" else PREC_FP64,
-                         float(switch_tol), int(seed), 1 if fp32_arith else 0, int(block), int(refine_start), 0)
+                         float(switch_tol), int(seed), 1 if fp32_arith else 0, int(block), int(refine_start),
+                         int(variant))
         stats = Stats()
         with torch.cuda.device(dev):
             st = load_library().bse_solve(self._h, k, float(tol), ctypes.byref(opts), _dev_ptr(omega),
@@ -238,6 +246,34 @@ class Solver:
                         "bse_backward")
         return da, db
 
+
+    def haydock(self, d, n_iter, tol=0.0, freq=None, eta=0.1, precision="fp64"):
+        """Lanczos-Haydock recursion from the dipole vector d (N complex).  Returns
+        (alpha[n], beta[n] f64 device tensors, norm2, chi[nw] c128 device tensor or None,
+        stats dict), n the steps done.  chi(z) at z = freq + i eta is the response
+        d^H (z - A)^{-1} d (TDA) or q^H Omega (z - H)^{-1} q, q = [d; conj(d)] (PH).
+        precision: "fp64", "hi64" (FP64 arithmetic on the complex64 hi triangles) or "fp32"."""
+        dev = self.device
+        d = d.to(device=dev, dtype=torch.complex128).contiguous()
+        alpha = torch.zeros(int(n_iter), dtype=torch.float64, device=dev)
+        beta = torch.zeros(int(n_iter), dtype=torch.float64, device=dev)
+        chi = None
+        nw = 0
+        if freq is not None:
+            freq = freq.to(device=dev, dtype=torch.float64).contiguous()
+            nw = freq.numel()
+            chi = torch.empty(nw, dtype=torch.complex128, device=dev)
+        prec = {"fp64": PREC_FP64, "hi64": PREC_HI_FP64, "fp32": PREC_MIXED}[precision]
+        norm2 = ctypes.c_double(0.0)
+        done = ctypes.c_int32(0)
+        stats = Stats()
+        with torch.cuda.device(dev):
+            st = load_library().bse_haydock(self._h, _dev_ptr(d), int(n_iter), float(tol), prec, _dev_ptr(freq),
+                                            nw, float(eta), _dev_ptr(alpha), _dev_ptr(beta), ctypes.byref(norm2),
+                                            _dev_ptr(chi), ctypes.byref(done), ctypes.byref(stats))
+        self._check(st, "bse_haydock")
+        n = done.value
+        return alpha[:n], beta[:n], norm2.value, chi, stats.as_dict()
 
     def strength(self, g, comps):
         """Scalars Re<G, C_q> of L = sum_c g_c omega_c for components given as
@@ -305,3 +341,19 @@ class BSEEigs(torch.autograd.Function):
             raise NotImplementedError("gradients with respect to the eigenvectors are not supported")
         da, db = ctx.solver.backward(g_omega)
         return da, (db if ctx.has_b else None), None, None, None, None
+
+
+def haydock_spectrum(kind, alpha, beta, norm2, freq, eta):
+    """chi(freq + i eta) from Haydock coefficients (device tensors) on their device."""
+    kind_i = PSEUDO_HERMITIAN if kind == "ph" else TDA
+    alpha = alpha.to(torch.float64).contiguous()
+    beta = beta.to(device=alpha.device, dtype=torch.float64).contiguous()
+    freq = freq.to(device=alpha.device, dtype=torch.float64).contiguous()
+    chi = torch.empty(freq.numel(), dtype=torch.complex128, device=alpha.device)
+    with torch.cuda.device(alpha.device):
+        st = load_library().bse_haydock_spectrum(kind_i, alpha.numel(), _dev_ptr(alpha), _dev_ptr(beta),
+                                                 float(norm2), _dev_ptr(freq), freq.numel(), float(eta),
+                                                 _dev_ptr(chi), ctypes.c_void_p(_stream_ptr(alpha.device)))
+    if st != OK:
+        raise BSEError(st, "bse_haydock_spectrum failed")
+    return chi

@@ -88,7 +88,8 @@ inline int64_t nchunks(int64_t n) { return (n + kChunk - 1) / kChunk; }
 hipError_t cdot(const double2* V0, int n0, const double2* V1, int n1, int64_t ld, const double2* w,
                 int64_t n, double2* part, double2* h, hipStream_t s);
 
-// w -= V h (and z -= P h when z != nullptr); real_h: use Re(h) only.
+// w -= V h (and z -= P h when z != nullptr), V = [V0 V1], P = [P0 P1];
+// real_h 1: Re(h) only; 2: Re(h) on V0 / P0 and i Im(h) on V1 / P1.
 hipError_t cgemv_sub(const double2* V0, int n0, const double2* V1, int n1, const double2* P0,
                      const double2* P1, int64_t ld, const double2* h, int real_h, double2* w,
                      double2* z, int64_t n, hipStream_t s);
@@ -192,5 +193,10 @@ hipError_t quad_packed(const double2* X, const double2* Y, int64_t ld, const dou
 // part[b] = sum over rows of block b of d_i sum_c wgt_c (|X_ci|^2 + |Y_ci|^2).
 hipError_t quad_diag(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
                      const double* d, int64_t n, double* part, hipStream_t s);
+
+// chi[f] = scale / (s - alpha_0 - beta_0^2 / (s - alpha_1 - ...)) truncated
+// after n levels, s = z (ph == 0) or z^2, z = freq[f] + i eta, for f < nw.
+hipError_t cfrac(int ph, int n, const double* alpha, const double* beta, double scale, const double* freq,
+                 int nw, double eta, double2* chi, hipStream_t s);
 
 }  // namespace bse

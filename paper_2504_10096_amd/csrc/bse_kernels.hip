@@ -1004,6 +1004,28 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// ------------------------------------------------------- continued fraction
+// One thread per frequency: g = 1 / (s - alpha_{n-1}), then
+// g = 1 / (s - alpha_j - beta_j^2 g) down to j = 0; chi = scale g.  The
+// coefficients are read by every thread of a wave at the same address.
+__global__ void __launch_bounds__(kThreads)
+    cfrac_kernel(int ph, int n, const double* __restrict__ alpha, const double* __restrict__ beta,
+                 double scale, const double* __restrict__ freq, int nw, double eta, double2* __restrict__ chi) {
+  const int f = blockIdx.x * kThreads + threadIdx.x;
+  if (f >= nw) return;
+  const double zr = freq[f], zi = eta;
+  const double sr = ph ? zr * zr - zi * zi : zr, si = ph ? 2.0 * zr * zi : zi;
+  double gr = 0.0, gi = 0.0;
+  for (int j = n - 1; j >= 0; --j) {
+    const double b2 = (j < n - 1) ? beta[j] * beta[j] : 0.0;
+    const double dr = sr - alpha[j] - b2 * gr, di = si - b2 * gi;
+    const double den = dr * dr + di * di;
+    gr = dr / den;
+    gi = -di / den;
+  }
+  chi[f] = make_double2(scale * gr, scale * gi);
+}
+
 // -------------------------------------------------- orthogonalization (CGS)
 // part[chunk * ncol + c] = sum over the 256-row chunk of conj(V[i, c]) w[i].
 // Grid (chunks, ceil(ncol / 64)); wave w of the group handles 16 columns;
@@ -1063,6 +1085,9 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // w[i] -= sum_c V[i, c] h[c];  z[i] -= sum_c P[i, c] h[c] (optional).
+// real_h 1: h[c] -> Re h[c]; 2: Re h[c] on the first n0 columns and
+// i Im h[c] on the others (a real coefficient on each basis vector and on
+// each i-multiple of the second basis).
 __global__ void __launch_bounds__(kThreads)
     cgemv_sub_kernel(const double2* __restrict__ V0, int n0, const double2* __restrict__ V1, int n1,
                      const double2* __restrict__ P0, const double2* __restrict__ P1, int64_t ld,
@@ -1072,7 +1097,10 @@ __global__ void __launch_bounds__(kThreads)
   const int ncol = n0 + n1;
   for (int c = threadIdx.x; c < ncol; c += kThreads) {
     double2 v = h[c];
-    if (real_h) v.y = 0.0;
+    if (real_h == 1 || (real_h == 2 && c < n0))
+      v.y = 0.0;
+    else if (real_h == 2)
+      v.x = 0.0;
     hs[c] = v;
   }
   __syncthreads();
@@ -2004,6 +2032,14 @@ hipError_t grad_packed(const double2* X, const double2* Y, int64_t ld, const dou
                        int64_t n, double2* ga, double2* gb, hipStream_t s) {
   hipLaunchKernelGGL(grad_packed_kernel, dim3((unsigned)n), dim3(kThreads), 0, s, X, Y, ld, wgt, k,
                      ga, gb);
+  return hipGetLastError();
+}
+
+hipError_t cfrac(int ph, int n, const double* alpha, const double* beta, double scale, const double* freq,
+                 int nw, double eta, double2* chi, hipStream_t s) {
+  if (nw <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cfrac_kernel, dim3((unsigned)((nw + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, ph,
+                     n, alpha, beta, scale, freq, nw, eta, chi);
   return hipGetLastError();
 }
 

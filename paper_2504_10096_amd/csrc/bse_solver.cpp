@@ -139,6 +139,14 @@ struct Solver {
   int b = 1;
   int ldT = 0;
   double2* Tc;
+  // PH variant: 0 the folded K1-metric iteration on K2 K1; 1 the Lanczos
+  // process on H in the M inner product (two coupled bases, see step_g).
+  // Variant 1 keeps K1 U in P, the K2-orthonormal basis in KP and its K2
+  // image in Y (rotation partners P2, KP2, Z), and the coefficients of the
+  // K2 P products in Tc2.
+  int variant = 0;
+  DevBuf bufTc2;
+  double2* Tc2 = nullptr;
   int ncolmax = 0;  // columns of one coefficient vector in H1 / H3
   // projected matrix state
   int nka = 0;  // kept Ritz vectors at the front of the basis
@@ -247,6 +255,7 @@ bse_status alloc_solver(Solver& S) {
       {&S.bufH3, sizeof(double2) * (size_t)S.ncolmax},
       {&S.bufTh, sizeof(double) * (nc + 2)},
       {&S.bufTc, sizeof(double2) * (size_t)nc * nc},
+      {&S.bufTc2, S.variant == 1 ? sizeof(double2) * (size_t)nc * nc : 0},
       {&S.bufPart, sizeof(double2) * (size_t)bse::nchunks(S.n) * S.ncolmax},
       {&S.bufRed, sizeof(double) * 2 * ((size_t)bse::nchunks(S.n) + 8)},
       {&S.bufFlag, sizeof(int) * 4},
@@ -272,6 +281,7 @@ bse_status alloc_solver(Solver& S) {
   S.H3 = (double2*)S.bufH3.p;
   S.th_dev = (double*)S.bufTh.p;
   S.Tc = (double2*)S.bufTc.p;
+  S.Tc2 = (double2*)S.bufTc2.p;
   S.cpart = (double2*)S.bufPart.p;
   S.red = (double*)S.bufRed.p;
   S.flag = (int*)S.bufFlag.p;
@@ -288,6 +298,7 @@ bse_status alloc_solver(Solver& S) {
   HIP_TRY(h, hipMemsetAsync(S.flag, 0, sizeof(int) * 4, S.s));
   HIP_TRY(h, hipMemsetAsync(S.U, 0, col * nc, S.s));
   HIP_TRY(h, hipMemsetAsync(S.Tc, 0, sizeof(double2) * (size_t)nc * nc, S.s));
+  if (S.Tc2) HIP_TRY(h, hipMemsetAsync(S.Tc2, 0, sizeof(double2) * (size_t)nc * nc, S.s));
   if (S.ph) HIP_TRY(h, hipMemsetAsync(S.P, 0, col * nc, S.s));
   return BSE_OK;
 }
@@ -621,6 +632,184 @@ bse_status restart(Solver& S, RitzInfo& R) {
   return BSE_OK;
 }
 
+// ---------------------------------------------------------------------
+// Second structure-preserving variant: the Lanczos process on H itself in
+// the inner product of M (H is self-adjoint in it, since Omega H = M),
+// started from a vector of the form [u; conj(u)].  H maps such vectors to
+// ones of the form [p; -conj(p)] and back: with K1 u = A u + B conj(u) and
+// K2 p = A p - B conj(p),
+//   H [u; conj(u)] = [K1 u; -conj(K1 u)],  H [p; -conj(p)] = [K2 p; conj(K2 p)],
+// and the M inner product of two vectors of one form is twice the K1
+// (resp. K2) inner product of their top halves; vectors of the two forms are
+// orthogonal in its real part.  So the tridiagonal matrix of the process has
+// a zero diagonal, and on the tops of the vectors it is a coupled recurrence
+// with a K1-orthonormal basis U and a K2-orthonormal basis P:
+//   K1 U = P B,  K2 P = U B^T + t u_next e^T,
+// B upper triangular (bidiagonal, with one arrow column after a restart).
+// The Ritz values are the positive eigenvalues of [[0, B^T]; [B, 0]], which
+// are the singular values of B; a pair (z, y) of its singular vectors gives
+// u = U z, p = P y with K1 u = w p, K2 p = w u and the eigenvector
+// [u + p; conj(u - p)] of H.  Partner spaces come for free: K1 (i p) =
+// i K2 p and K2 (i u) = i K1 u, so i P is K1-orthonormal with image i K2 P,
+// and i U is K2-orthonormal with image i K1 U; a Krylov basis is orthogonal
+// to them in exact arithmetic, and each new vector is orthogonalized
+// against them as well (the imaginary parts of the same dot products).
+//
+// Buffers: U, P = K1 U, KP = the K2-orthonormal basis, Y = K2 KP; the
+// coefficients of the K1 u_c products in Tc (column c), those of the K2 p_c
+// products in Tc2 (column c).
+
+// Step c: u_c (with K1 u_c) -> p_c (with K2 p_c) -> u_{c+1} (with K1 u_{c+1}).
+bse_status step_g(Solver& S, Arith ar, int c) {
+  bse_handle h = S.h;
+  const int64_t ld = S.ld, n = S.n;
+  double2 *U = S.U, *KU = S.P, *PG = S.KP, *KPG = S.Y;
+  bse_status st;
+  // p side: w = K1 u_c, K2-orthogonal to p_0..p_{c-1} and to i u_0..i u_c
+  double2* w = PG + (size_t)c * ld;
+  double2* kw = KPG + (size_t)c * ld;
+  double2* Bc = S.Tc + (size_t)c * S.ldT;
+  HIP_TRY(h, bse::copy_cols(KU + (size_t)c * ld, ld, w, ld, n, 1, S.s));
+  HIP_TRY(h, bse::cdot(KPG, c, KU, c + 1, ld, w, n, S.cpart, S.H1, S.s));
+  HIP_TRY(h, bse::cgemv_sub(PG, c, U, c + 1, nullptr, nullptr, ld, S.H1, 2, w, nullptr, n, S.s));
+  HIP_TRY(h, bse::acc_cols(Bc, S.ldT, S.H1, S.ncolmax, c, 1, 1, S.s));
+  if ((st = pass(S, ar, 2, w, kw))) return st;  // K2 w
+  HIP_TRY(h, bse::cdot(KPG, c, KU, c + 1, ld, w, n, S.cpart, S.H1, S.s));
+  HIP_TRY(h, bse::cgemv_sub(PG, c, U, c + 1, KPG, KU, ld, S.H1, 2, w, kw, n, S.s));
+  HIP_TRY(h, bse::acc_cols(Bc, S.ldT, S.H1, S.ncolmax, c, 1, 1, S.s));
+  HIP_TRY(h, bse::normalize(w, kw, n, nullptr, nullptr, 0, nullptr, (double*)(Bc + c), 0, S.flag, S.red, S.s));
+  // u side: w = K2 p_c, K1-orthogonal to u_0..u_c and to i p_0..i p_c
+  double2* v = U + (size_t)(c + 1) * ld;
+  double2* kv = KU + (size_t)(c + 1) * ld;
+  double2* Cc = S.Tc2 + (size_t)c * S.ldT;
+  HIP_TRY(h, bse::copy_cols(kw, ld, v, ld, n, 1, S.s));
+  HIP_TRY(h, bse::cdot(KU, c + 1, KPG, c + 1, ld, v, n, S.cpart, S.H1, S.s));
+  HIP_TRY(h, bse::cgemv_sub(U, c + 1, PG, c + 1, nullptr, nullptr, ld, S.H1, 2, v, nullptr, n, S.s));
+  HIP_TRY(h, bse::acc_cols(Cc, S.ldT, S.H1, S.ncolmax, c + 1, 1, 1, S.s));
+  if ((st = pass(S, ar, 1, v, kv))) return st;  // K1 w
+  HIP_TRY(h, bse::cdot(KU, c + 1, KPG, c + 1, ld, v, n, S.cpart, S.H1, S.s));
+  HIP_TRY(h, bse::cgemv_sub(U, c + 1, PG, c + 1, KU, KPG, ld, S.H1, 2, v, kv, n, S.s));
+  HIP_TRY(h, bse::acc_cols(Cc, S.ldT, S.H1, S.ncolmax, c + 1, 1, 1, S.s));
+  HIP_TRY(h, bse::normalize(v, kv, n, nullptr, nullptr, 0, nullptr, (double*)(Cc + c + 1), 0, S.flag, S.red, S.s));
+  if (ar == bse::AR_HI || ar == bse::AR_HI64)
+    S.steps32 += 1;
+  else
+    S.steps64 += 1;
+  return BSE_OK;
+}
+
+// Restart of the coupled recurrence: assemble B from both recorded
+// coefficient sets (K1 u_c on the p basis, and the transpose of K2 p_c on
+// the u basis, averaged where both exist), take the singular triplets of B
+// from the eigenpairs of [[0, B^T]; [B, 0]], rotate U, K1 U by the right
+// and P, K2 P by the left singular vectors of the lowest `keep`, and move
+// u_m behind them.  Afterwards K1 u_i = w_i p_i and K2 p_i = w_i u_i +
+// t y_{m-1,i} u_m for the kept i (t: the coefficient of u_m in K2 p_{m-1}),
+// which bounds the residual of pair i.  R.theta holds w^2, the folded
+// values of the other variant.
+bse_status restart_g(Solver& S, RitzInfo& R) {
+  bse_handle h = S.h;
+  const int m = S.m, ldT = S.ldT, nka = S.nka;
+  if (nka >= m) return fail(h, BSE_ERR_BAD_STATE, "thick restart needs ncv > keep");
+  std::vector<double2> tb((size_t)ldT * ldT), tcv((size_t)ldT * ldT);
+  HIP_TRY(h, hipMemcpyAsync(tb.data(), S.Tc, sizeof(double2) * tb.size(), hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, hipMemcpyAsync(tcv.data(), S.Tc2, sizeof(double2) * tcv.size(), hipMemcpyDeviceToHost, S.s));
+  bse_status st = check_flag(S);
+  if (st) return st;
+  // Bs[i][c]: coefficient of p_i in K1 u_c
+  auto bfill = [&](int i, int c) { return c < nka ? i == c : i <= c; };
+  auto cfill = [&](int c, int i) { return i < nka ? c == i : c <= i + 1; };  // u_c in K2 p_i
+  auto bval = [&](int i, int c) { return c < nka ? S.theta_keep[c] : tb[(size_t)c * ldT + i].x; };
+  auto cval = [&](int c, int i) { return i < nka ? S.theta_keep[i] : tcv[(size_t)i * ldT + c].x; };
+  const int m2 = 2 * m;
+  std::vector<double> J((size_t)m2 * m2, 0.0);
+  for (int c = 0; c < m; ++c)
+    for (int i = 0; i < m; ++i) {
+      const bool f1 = bfill(i, c), f2 = cfill(c, i);
+      double v = 0.0;
+      if (f1 && f2)
+        v = 0.5 * (bval(i, c) + cval(c, i));
+      else if (f1)
+        v = bval(i, c);
+      else if (f2)
+        v = cval(c, i);
+      J[(size_t)c * m2 + (m + i)] = v;  // row p_i, column u_c
+      J[(size_t)(m + i) * m2 + c] = v;  // row u_c, column p_i
+    }
+  for (double v : J)
+    if (!std::isfinite(v)) return fail(h, BSE_ERR_NONFINITE, "non-finite projected matrix");
+  std::vector<double> ev(m2), Ze((size_t)m2 * m2);
+  if (!bse::sym_eig(m2, J.data(), ev.data(), Ze.data()))
+    return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
+  // positive half, ascending: w_j = ev[m + j]; z = sqrt(2) e_top, y = sqrt(2) e_bottom
+  std::vector<double> sg(m), Zr((size_t)m * m), Yr((size_t)m * m);
+  for (int j = 0; j < m; ++j) {
+    sg[j] = ev[m + j];
+    const double* e = Ze.data() + (size_t)(m + j) * m2;
+    double nz = 0.0, ny = 0.0;
+    for (int i = 0; i < m; ++i) {
+      nz += e[i] * e[i];
+      ny += e[m + i] * e[m + i];
+    }
+    nz = 1.0 / sqrt(std::max(nz, 1e-300));
+    ny = 1.0 / sqrt(std::max(ny, 1e-300));
+    for (int i = 0; i < m; ++i) {
+      Zr[(size_t)j * m + i] = e[i] * nz;
+      Yr[(size_t)j * m + i] = e[m + i] * ny;
+    }
+  }
+  if (!(sg[0] > 0.0))
+    return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "non-positive Ritz value omega: M is not positive definite");
+  const int keep = S.keep;
+  HIP_TRY(h, hipMemcpyAsync(S.S, Zr.data(), sizeof(double) * (size_t)m * keep, hipMemcpyHostToDevice, S.s));
+  HIP_TRY(h, hipMemcpyAsync(S.S + (size_t)m * keep, Yr.data(), sizeof(double) * (size_t)m * keep,
+                            hipMemcpyHostToDevice, S.s));
+  const double* Sz = S.S;
+  const double* Sy = S.S + (size_t)m * keep;
+  const auto ge = gemm_events(S);
+  if (ge.first) HIP_TRY(h, hipEventRecord(ge.first, S.s));
+  const int64_t n2 = 2 * S.n, l2 = 2 * S.ld;
+  HIP_TRY(h, bse::dgemm_tn_mfma(n2, keep, m, (const double*)S.U, l2, Sz, m, (double*)S.U2, l2, S.s));
+  HIP_TRY(h, bse::dgemm_tn_mfma(n2, keep, m, (const double*)S.P, l2, Sz, m, (double*)S.P2, l2, S.s));
+  HIP_TRY(h, bse::dgemm_tn_mfma(n2, keep, m, (const double*)S.KP, l2, Sy, m, (double*)S.KP2, l2, S.s));
+  HIP_TRY(h, bse::dgemm_tn_mfma(n2, keep, m, (const double*)S.Y, l2, Sy, m, (double*)S.Z, l2, S.s));
+  if (ge.first) {
+    HIP_TRY(h, hipEventRecord(ge.second, S.s));
+    S.ev_gemm.push_back({ge, 4.0 * 2.0 * (2.0 * S.n) * keep * m});
+  }
+  HIP_TRY(h, bse::copy_cols(S.U + (size_t)m * S.ld, S.ld, S.U2 + (size_t)keep * S.ld, S.ld, S.n, 1, S.s));
+  HIP_TRY(h, bse::copy_cols(S.P + (size_t)m * S.ld, S.ld, S.P2 + (size_t)keep * S.ld, S.ld, S.n, 1, S.s));
+  std::swap(S.U, S.U2);
+  std::swap(S.P, S.P2);
+  std::swap(S.KP, S.KP2);
+  std::swap(S.Y, S.Z);
+  // residual estimates: |t y_{m-1,i}| ||u_m|| / (w_i sqrt(||u_i||^2 + ||p_i||^2))
+  const double t = tcv[(size_t)(m - 1) * ldT + m].x;
+  double* cp = (double*)S.cpart;
+  std::vector<double> nu(S.k), np(S.k), nn(1);
+  HIP_TRY(h, bse::colnorms(S.U, S.k, S.ld, S.n, cp, S.nrm, S.s));
+  HIP_TRY(h, hipMemcpyAsync(nu.data(), S.nrm, sizeof(double) * S.k, hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, bse::colnorms(S.KP, S.k, S.ld, S.n, cp, S.nrm, S.s));
+  HIP_TRY(h, hipMemcpyAsync(np.data(), S.nrm, sizeof(double) * S.k, hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, bse::colnorms(S.U + (size_t)keep * S.ld, 1, S.ld, S.n, cp, S.nrm, S.s));
+  HIP_TRY(h, hipMemcpyAsync(nn.data(), S.nrm, sizeof(double), hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, hipMemsetAsync(S.Tc, 0, sizeof(double2) * (size_t)ldT * ldT, S.s));
+  HIP_TRY(h, hipMemsetAsync(S.Tc2, 0, sizeof(double2) * (size_t)ldT * ldT, S.s));
+  HIP_TRY(h, hipStreamSynchronize(S.s));
+  R.theta.assign(m, 0.0);
+  for (int j = 0; j < m; ++j) R.theta[j] = sg[j] * sg[j];
+  R.est.assign(S.k, 0.0);
+  for (int i = 0; i < S.k; ++i) {
+    const double r = fabs(t * Yr[(size_t)i * m + m - 1]) * sqrt(std::max(nn[0], 0.0));
+    const double den = sg[i] * sqrt(std::max(nu[i] + np[i], 1e-300));
+    R.est[i] = r / std::max(den, 1e-300);
+  }
+  S.nka = keep;
+  S.theta_keep.assign(sg.begin(), sg.begin() + keep);  // variant 1: w, the diagonal of B
+  ++S.restarts;
+  return BSE_OK;
+}
+
 // Eigenvalues and vectors of the k wanted pairs from the current basis
 // (columns 0..k-1 after a restart) and their FP64 residuals.
 bse_status finalize(Solver& S, const RitzInfo& R, double* omega, double2* X, double2* Y,
@@ -843,12 +1032,17 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
       }
     return BSE_OK;
   };
-  // starting vectors: PH v = [omega u + p; conj(omega u - p)] / (2 sqrt(omega)); TDA the Ritz vectors
+  // starting vectors: PH v = [omega u + p; conj(omega u - p)] / (2 sqrt(omega))
+  // with p = K1 u; after the coupled recurrence (variant 1) v = [u + p; conj(u - p)] / 2
+  // with its own p (K1 u = omega p), the same direction.  TDA: the Ritz vectors.
+  const bool coupled = ph && S.variant == 1;
+  const double2* Pv = coupled ? S.KP : S.P;   // p of v
+  const double2* KPv = coupled ? S.Y : S.KP;  // images for M v: K1 u in S.P, and K2 p
   if (ph) {
     std::vector<double> om0(s0);
-    for (int c = 0; c < s0; ++c) om0[c] = sqrt(std::max(theta0[c], 1e-300));
+    for (int c = 0; c < s0; ++c) om0[c] = coupled ? 1.0 : sqrt(std::max(theta0[c], 1e-300));
     HIP_TRY(h, hipMemcpyAsync(Om, om0.data(), sizeof(double) * s0, hipMemcpyHostToDevice, S.s));
-    HIP_TRY(h, bse::ph_vectors(S.U, S.P, ld, Om, s0, n, V, V + ld, ld2, S.s));
+    HIP_TRY(h, bse::ph_vectors(S.U, Pv, ld, Om, s0, n, V, V + ld, ld2, S.s));
   } else {
     HIP_TRY(h, bse::copy_cols(S.U, ld, V, ld2, n, s0, S.s));
   }
@@ -859,7 +1053,9 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   lo_only.b = exact.blo;
   lo_only.alo = lo_only.blo = nullptr;
   // M V of the starting vectors.  PH: from the iteration's own products,
-  // M v = s [omega p + kp; conj(omega p - kp)] with p = K1 u, kp = K2 p; exact
+  // M v = s [omega p + kp; conj(omega p - kp)] with p = K1 u, kp = K2 p
+  // (variant 1: M v = [K1 u + K2 p; conj(K1 u - K2 p)] / 2, the same call
+  // with omega = 1 and its own K2 p); exact
   // when the iteration ran on the FP64 operator, and completed by one read of
   // the lo triangles (M = M_hi + M_lo) after FP64 arithmetic on hi.  After
   // complex FP32 arithmetic, or for TDA, by FP64 passes.
@@ -867,7 +1063,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     if (bulk_ar == bse::AR_HI64) {
       if ((st = mapply(0, s0, bse::AR_HI64, lo_only))) return st;
     }
-    HIP_TRY(h, bse::ph_mvectors(S.P, S.KP, ld, Om, s0, n, MV, ld2, ld, bulk_ar == bse::AR_HI64 ? 1 : 0, S.s));
+    HIP_TRY(h, bse::ph_mvectors(S.P, KPv, ld, Om, s0, n, MV, ld2, ld, bulk_ar == bse::AR_HI64 ? 1 : 0, S.s));
   } else {
     if ((st = mapply(0, s0, ar, exact))) return st;
   }
@@ -1210,6 +1406,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
     return fail(h, BSE_ERR_INVALID_ARG, "mixed precision needs HILO storage");
   const int64_t n = h->n;
   if (o.block < 0 || o.block > 4) return fail(h, BSE_ERR_INVALID_ARG, "block must be in [0, 4]");
+  if (o.variant < 0 || o.variant > 1) return fail(h, BSE_ERR_INVALID_ARG, "variant must be 0 or 1");
   int m = o.ncv > 0 ? o.ncv : (int)round_up(std::max(2 * k, k + 32), 16);
   m = (int)std::min<int64_t>(m, n);
   if (m < k) return fail(h, BSE_ERR_INVALID_ARG, "ncv must be at least k");
@@ -1237,6 +1434,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   S.m = m;
   S.keep = keep;
   S.b = b;
+  S.variant = ph ? o.variant : 0;
   S.tol = tol;
   S.s = h->stream;
   if (const char* tr = getenv("BSE_TRACE")) S.trace = tr[0] == '1';
@@ -1258,10 +1456,10 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   double ms_final = 0.0;
   for (int cyc = 0; cyc < max_restarts; ++cyc) {
     for (int c0 = jstart; c0 < m; c0 += b) {
-      st = step(S, ar, c0);
+      st = S.variant == 1 ? step_g(S, ar, c0) : step(S, ar, c0);
       if (st) return st;
     }
-    st = restart(S, R);
+    st = S.variant == 1 ? restart_g(S, R) : restart(S, R);
     if (st) return st;
     jstart = S.keep;
     const bool full_space = S.keep >= m;
@@ -1577,6 +1775,167 @@ bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse
     out[q] = c.scale * sum;
   }
   return BSE_OK;
+}
+
+bse_status bse_haydock(bse_handle h, const void* d, int32_t max_iter, double tol, bse_precision precision,
+                       const double* freq, int32_t nw, double eta, double* alpha, double* beta, double* norm2,
+                       void* chi, int32_t* n_iter, bse_stats* stats) {
+  if (!h) return BSE_ERR_INVALID_ARG;
+  const double t0 = now_ms();
+  if (!d || !alpha || !beta || !norm2 || !n_iter) return fail(h, BSE_ERR_INVALID_ARG, "null argument");
+  if (max_iter < 1) return fail(h, BSE_ERR_INVALID_ARG, "max_iter must be at least 1");
+  if (!(tol >= 0.0)) return fail(h, BSE_ERR_INVALID_ARG, "tol must be >= 0");
+  const bool grid = nw > 0;
+  if (nw < 0 || (grid && (!freq || !chi || !(eta > 0.0))) || (tol > 0.0 && !grid))
+    return fail(h, BSE_ERR_INVALID_ARG, "a frequency grid (freq, nw > 0, eta > 0, chi) is required");
+  Arith ar;
+  if (precision == BSE_PREC_FP64)
+    ar = fp64_arith(h);
+  else if (precision == BSE_PREC_HI_FP64 || precision == BSE_PREC_MIXED) {
+    if (h->storage != BSE_STORE_HILO)
+      return fail(h, BSE_ERR_INVALID_ARG, "passes over the complex64 triangles need HILO storage");
+    ar = precision == BSE_PREC_HI_FP64 ? bse::AR_HI64 : bse::AR_HI;
+  } else {
+    return fail(h, BSE_ERR_INVALID_ARG, "bad precision");
+  }
+  const bool ph = h->kind == BSE_PSEUDO_HERMITIAN;
+  const int64_t n = h->n;
+  Solver S;
+  S.h = h;
+  S.ph = ph;
+  S.n = n;
+  S.ld = round_up(n, 64);
+  S.s = h->stream;
+  const size_t col = sizeof(double2) * (size_t)S.ld;
+  DevBuf bV, bP, bPart, bH, bRed, bFlag, bN0;
+  struct {
+    DevBuf* b;
+    size_t bytes;
+  } req[] = {
+      {&bV, col * 3},
+      {&bP, ph ? col * 3 : 0},
+      {&bPart, sizeof(double2) * (size_t)bse::nchunks(n) * 2},
+      {&bH, sizeof(double2) * 2},
+      {&bRed, sizeof(double) * ((size_t)bse::nchunks(n) + 8)},
+      {&bFlag, sizeof(int) * 4},
+      {&bN0, sizeof(double) * 2},
+  };
+  for (auto& r : req) {
+    if (r.bytes == 0) continue;
+    HIP_TRY(h, hipMalloc(&r.b->p, r.bytes));
+  }
+  for (int q = 0; q < 64; ++q) {
+    hipEvent_t e;
+    HIP_TRY(h, hipEventCreate(&e));
+    S.ev_free.push_back(e);
+  }
+  double2* V = (double2*)bV.p;  // TDA: v ring; PH: u ring
+  double2* P = (double2*)bP.p;  // PH: K1 u ring
+  double2* Hc = (double2*)bH.p;
+  double2* part = (double2*)bPart.p;
+  double* red = (double*)bRed.p;
+  int* flag = (int*)bFlag.p;
+  double* n0 = (double*)bN0.p;
+  HIP_TRY(h, hipMemsetAsync(V, 0, col * 3, S.s));
+  if (ph) HIP_TRY(h, hipMemsetAsync(P, 0, col * 3, S.s));
+  HIP_TRY(h, hipMemsetAsync(flag, 0, sizeof(int) * 4, S.s));
+  HIP_TRY(h, hipMemcpyAsync(V, d, sizeof(double2) * (size_t)n, hipMemcpyDeviceToDevice, S.s));
+  bse_status st;
+  // first vector: d / ||d|| (TDA), d / sqrt(<d, K1 d>) with its K1 image (PH)
+  if (ph && (st = pass(S, ar, 1, V, P))) return st;
+  HIP_TRY(h, bse::normalize(V, ph ? P : nullptr, n, nullptr, nullptr, 0, nullptr, n0, 0, flag, red, S.s));
+  double nrm = 0.0;
+  int fl = 0;
+  HIP_TRY(h, hipMemcpyAsync(&nrm, n0, sizeof(double), hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, hipStreamSynchronize(S.s));
+  if (fl == 1) return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "<d, K1 d> < 0: M is not positive definite");
+  if (fl == 2 || !std::isfinite(nrm)) return fail(h, BSE_ERR_NONFINITE, "non-finite dipole vector");
+  if (!(nrm > 0.0)) return fail(h, BSE_ERR_INVALID_ARG, "the dipole vector is zero");
+  const double scale = (ph ? 2.0 : 1.0) * nrm * nrm;
+  *norm2 = nrm * nrm;
+  std::vector<double2> prev_chi, cur_chi;
+  int done = 0;
+  auto col_at = [&](double2* base, int j) { return base + (size_t)(((j % 3) + 3) % 3) * S.ld; };
+  for (int j = 0; j < max_iter; ++j) {
+    double2 *v = col_at(V, j), *vp = col_at(V, j - 1), *vn = col_at(V, j + 1);
+    // TDA: w = A v_j; PH: w = K2 p_j = K2 K1 u_j
+    if ((st = pass(S, ar, ph ? 2 : 0, ph ? col_at(P, j) : v, vn))) return st;
+    // coefficients against the previous vector and the current one (K1 inner
+    // product through P for PH), real; subtract them
+    const double2* g0 = ph ? col_at(P, j - 1) : vp;
+    const double2* g1 = ph ? col_at(P, j) : v;
+    if (j == 0) {
+      HIP_TRY(h, bse::cdot(g1, 1, nullptr, 0, S.ld, vn, n, part, Hc, S.s));
+      HIP_TRY(h, bse::cgemv_sub(v, 1, nullptr, 0, nullptr, nullptr, S.ld, Hc, 1, vn, nullptr, n, S.s));
+    } else {
+      HIP_TRY(h, bse::cdot(g0, 1, g1, 1, S.ld, vn, n, part, Hc, S.s));
+      HIP_TRY(h, bse::cgemv_sub(vp, 1, v, 1, nullptr, nullptr, S.ld, Hc, 1, vn, nullptr, n, S.s));
+    }
+    double2* zn = nullptr;
+    if (ph) {
+      zn = col_at(P, j + 1);
+      if ((st = pass(S, ar, 1, vn, zn))) return st;  // K1 w
+    }
+    // alpha_j = Re h[current], beta_j = ||w|| (TDA) or sqrt(<w, K1 w>) (PH)
+    HIP_TRY(h, bse::normalize(vn, zn, n, Hc, nullptr, j == 0 ? 0 : 1, alpha, beta, j, flag, red, S.s));
+    done = j + 1;
+    const bool last = done == max_iter;
+    if (tol > 0.0 && (done % 20 == 0 || last)) {
+      HIP_TRY(h, bse::cfrac(ph ? 1 : 0, done, alpha, beta, scale, freq, nw, eta, (double2*)chi, S.s));
+      cur_chi.resize(nw);
+      HIP_TRY(h, hipMemcpyAsync(cur_chi.data(), chi, sizeof(double2) * nw, hipMemcpyDeviceToHost, S.s));
+      HIP_TRY(h, hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, S.s));
+      HIP_TRY(h, hipStreamSynchronize(S.s));
+      harvest_events(S);
+      if (fl == 1) return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "<w, K1 w> < 0: M is not positive definite");
+      if (fl == 2) return fail(h, BSE_ERR_NONFINITE, "non-finite value in the recurrence");
+      if (!prev_chi.empty()) {
+        double dm = 0.0, am = 0.0;
+        for (int f = 0; f < nw; ++f) {
+          dm = std::max(dm, fabs(cur_chi[f].y - prev_chi[f].y));
+          am = std::max(am, fabs(cur_chi[f].y));
+        }
+        if (dm <= tol * am) break;
+      }
+      prev_chi.swap(cur_chi);
+    }
+  }
+  if (grid) HIP_TRY(h, bse::cfrac(ph ? 1 : 0, done, alpha, beta, scale, freq, nw, eta, (double2*)chi, S.s));
+  HIP_TRY(h, hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, hipStreamSynchronize(S.s));
+  harvest_events(S);
+  if (fl == 1) return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "<w, K1 w> < 0: M is not positive definite");
+  if (fl == 2) return fail(h, BSE_ERR_NONFINITE, "non-finite value in the recurrence");
+  *n_iter = done;
+  if (stats) {
+    *stats = bse_stats{};
+    stats->passes = S.passes;
+    stats->ms_total = now_ms() - t0;
+    const bool hi = ar == bse::AR_HI || ar == bse::AR_HI64;
+    stats->bytes_per_pass_fp32 = hi ? bytes_per_pass(h, ar, 1) : 0.0;
+    stats->bytes_per_pass_fp64 = hi ? 0.0 : bytes_per_pass(h, ar, 1);
+    stats->samples_fp32 = S.samples32;
+    stats->samples_fp64 = S.samples64;
+    stats->ms_block_fp32 = S.ms_blk32;
+    stats->ms_block_fp64 = S.ms_blk64;
+    stats->block = 1;
+  }
+  return BSE_OK;
+}
+
+bse_status bse_haydock_spectrum(bse_kind kind, int32_t n_iter, const double* alpha, const double* beta,
+                                double norm2, const double* freq, int32_t nw, double eta, void* chi,
+                                void* hip_stream) {
+  if ((kind != BSE_TDA && kind != BSE_PSEUDO_HERMITIAN) || n_iter < 1 || nw < 1 || !(eta > 0.0) || !alpha ||
+      !beta || !freq || !chi)
+    return BSE_ERR_INVALID_ARG;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const double scale = (kind == BSE_PSEUDO_HERMITIAN ? 2.0 : 1.0) * norm2;
+  if (bse::cfrac(kind == BSE_PSEUDO_HERMITIAN ? 1 : 0, n_iter, alpha, beta, scale, freq, nw, eta, (double2*)chi,
+                 s) != hipSuccess)
+    return BSE_ERR_DEVICE;
+  return hipStreamSynchronize(s) == hipSuccess ? BSE_OK : BSE_ERR_DEVICE;
 }
 
 }  // extern "C"

@@ -137,8 +137,8 @@ def check_tda(s, ap, k, tol, lam_tol):
     return st
 
 
-def check_ph(s, ap, bp, k, tol, om_tol):
-    om, X, Y, st = s.solve(k, tol)
+def check_ph(s, ap, bp, k, tol, om_tol, **kw):
+    om, X, Y, st = s.solve(k, tol, **kw)
     om, X, Y = host(om), host(X).T, host(Y).T
     ref, Xr, Yr = oracle.ph(ap, bp, k)
     assert np.max(np.abs(om - ref) / ref) < om_tol, (om, ref)
@@ -163,25 +163,27 @@ def test_solve_tda_synth(n, k):
     s.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n,k", [(300, 8), (900, 10)])
-def test_solve_ph_synth(n, k):
-    print(f"ph synth n={n} k={k}", flush=True)
+def test_solve_ph_synth(n, k, variant):
+    print(f"ph synth n={n} k={k} variant={variant}", flush=True)
     m = synth.Matrix(n, 200 + n, ph=True)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s = make_solver("ph", ap, bp)
-    check_ph(s, ap, bp, k, 1e-10, 1e-10)
+    check_ph(s, ap, bp, k, 1e-10, 1e-10, variant=variant)
     s.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n,k", [(200, 6), (640, 10)])
-def test_solve_ph_strong_coupling(n, k):
+def test_solve_ph_strong_coupling(n, k, variant):
     """Generic dense blocks with ||B||_2 = 0.6 lambda_min(A): large Y components."""
-    print(f"ph strong n={n} k={k}", flush=True)
+    print(f"ph strong n={n} k={k} variant={variant}", flush=True)
     rng = np.random.default_rng(n)
     A, B = random_herm(rng, n, lam_min=1.0), random_sym(rng, n, 0.6)
     ap, bp = pack_upper(A), pack_upper(B)
     s = make_solver("ph", ap, bp)
-    check_ph(s, ap, bp, k, 1e-10, 1e-10)
+    check_ph(s, ap, bp, k, 1e-10, 1e-10, variant=variant)
     s.close()
 
 
@@ -207,19 +209,22 @@ def test_tiny_sizes(n):
     s.close()
     s = make_solver("ph", ap, bp)
     check_ph(s, ap, bp, k, 1e-10, 1e-10)
+    check_ph(s, ap, bp, k, 1e-10, 1e-10, variant=1)
     s.close()
 
 
-def test_all_pairs_k_equals_n():
+@pytest.mark.parametrize("variant", [0, 1])
+def test_all_pairs_k_equals_n(variant):
     n = 24
     rng = np.random.default_rng(9)
     A, B = random_herm(rng, n, lam_min=1.0), random_sym(rng, n, 0.5)
     s = make_solver("ph", pack_upper(A), pack_upper(B))
-    check_ph(s, pack_upper(A), pack_upper(B), n, 1e-10, 1e-10)
+    check_ph(s, pack_upper(A), pack_upper(B), n, 1e-10, 1e-10, variant=variant)
     s.close()
 
 
-def test_real_blocks_no_duplicate_pairs():
+@pytest.mark.parametrize("variant", [0, 1])
+def test_real_blocks_no_duplicate_pairs(variant):
     n, k = 150, 10
     rng = np.random.default_rng(4)
     g = rng.standard_normal((n, n))
@@ -229,31 +234,33 @@ def test_real_blocks_no_duplicate_pairs():
     B = (c + c.T) * (0.5 / np.linalg.norm(c + c.T, 2))
     ap, bp = pack_upper(A.astype(complex)), pack_upper(B.astype(complex))
     s = make_solver("ph", ap, bp)
-    check_ph(s, ap, bp, k, 1e-10, 1e-10)
+    check_ph(s, ap, bp, k, 1e-10, 1e-10, variant=variant)
     s.close()
 
 
-def test_b_zero_reduces_to_tda():
+@pytest.mark.parametrize("variant", [0, 1])
+def test_b_zero_reduces_to_tda(variant):
     n, k = 200, 8
     m = synth.Matrix(n, 77, ph=True)
     ap = m.pack_host(0)
     bp = np.zeros_like(ap)
     s = make_solver("ph", ap, bp)
-    om, X, Y, _ = s.solve(k, 1e-10)
+    om, X, Y, _ = s.solve(k, 1e-10, variant=variant)
     ref, _ = oracle.tda(ap, k, vectors=False)
     assert np.max(np.abs(host(om) - ref) / ref) < 1e-10
     assert np.max(np.abs(host(Y))) < 1e-8
     s.close()
 
 
-def test_not_positive_definite():
+@pytest.mark.parametrize("variant", [0, 1])
+def test_not_positive_definite(variant):
     n = 60
     A = np.diag(np.arange(1.0, n + 1)).astype(complex)
     B = np.zeros((n, n), dtype=complex)
     B[0, 0] = 1.6
     s = make_solver("ph", pack_upper(A), pack_upper(B))
     with pytest.raises(bse.NotPositiveDefinite):
-        s.solve(4, 1e-10)
+        s.solve(4, 1e-10, variant=variant)
     s.close()
 
 
@@ -270,6 +277,10 @@ def test_invalid_arguments():
     with pytest.raises(bse.BSEError) as e:
         s.solve(4, 1e-8, precision="mixed")
     assert e.value.status == bse.ERR_INVALID_ARG
+    for v in (-1, 2):
+        with pytest.raises(bse.BSEError) as e:
+            s.solve(4, 1e-8, variant=v)
+        assert e.value.status == bse.ERR_INVALID_ARG
     with pytest.raises(bse.BSEError) as e:
         s.backward(torch.ones(4, dtype=torch.float64, device=DEV))
     assert e.value.status == bse.ERR_BAD_STATE
@@ -325,12 +336,13 @@ def test_mixed_tda_matches_oracle():
     s.close()
 
 
-def test_mixed_ph_matches_oracle():
+@pytest.mark.parametrize("variant", [0, 1])
+def test_mixed_ph_matches_oracle(variant):
     n, k = 900, 10
     m = synth.Matrix(n, 32, ph=True)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s = make_solver("ph", ap, bp, storage="hilo")
-    om, X, Y, st = s.solve(k, 1e-8, precision="mixed")
+    om, X, Y, st = s.solve(k, 1e-8, precision="mixed", variant=variant)
     ref, _, _ = oracle.ph(ap, bp, k, vectors=False)
     assert np.max(np.abs(host(om) - ref) / ref) < 1e-8
     assert oracle.residual_ph(ap, bp, host(om), host(X).T, host(Y).T).max() <= 1e-8 * 1.01
@@ -459,7 +471,8 @@ def _golden(name):
     return mod.load(name)
 
 
-def test_workload_ph_n4096_k32_golden():
+@pytest.mark.parametrize("variant", [0, 1])
+def test_workload_ph_n4096_k32_golden(variant):
     """Pseudo-Hermitian workload N = 4096 (operator 8192), lowest 32 pairs at
     tol 1e-10 against the oracle's stored values; residuals checked by the oracle."""
     w = synth.WORKLOADS[1]
@@ -467,7 +480,7 @@ def test_workload_ph_n4096_k32_golden():
     ap, bp = m.pack_host(0), m.pack_host(1)
     ref = _golden("ph_n4096_k32.txt")
     s = make_solver("ph", ap, bp)
-    om, X, Y, st = s.solve(w["k"], w["tol"])
+    om, X, Y, st = s.solve(w["k"], w["tol"], variant=variant)
     om = host(om)
     print("stats", st, flush=True)
     assert np.max(np.abs(om - ref) / ref) < 1e-10

@@ -101,3 +101,41 @@ def test_workload_ph_n16384_k32_gradient_fd():
     print("d_alpha", d_alpha, fd["alpha"], "d_beta", d_beta, fd["beta"], flush=True)
     assert abs(d_alpha - fd["alpha"]) <= 1e-6 * max(1.0, abs(d_alpha))
     assert abs(d_beta - fd["beta"]) <= 1e-6 * max(1.0, abs(d_beta))
+
+
+def _generated_ops(mat):
+    """The oracle's streaming FP64 operators of a seeded matrix (A; K1, K2)."""
+    if not mat.ph:
+        return lambda v: oracle.apply_generated(mat, v[:, None])[:, 0]
+    return (lambda v: oracle.apply_generated(mat, v[:, None], np.conj(v)[:, None])[:, 0],
+            lambda v: oracle.apply_generated(mat, v[:, None], -np.conj(v)[:, None])[:, 0])
+
+
+@pytest.mark.parametrize("idx,storage", [(2, "hilo"), (3, "c128")])
+def test_workload_haydock_first_steps(idx, storage):
+    """Haydock recurrence at full size (TDA N = 32768 from hi + lo; PH N = 16384 from
+    complex128): the first coefficients against the oracle's recurrence on its streaming
+    FP64 operator, and a converged spectrum that is positive and stable under more steps."""
+    import oracle.haydock as hy
+    w = synth.WORKLOADS[idx]
+    mat = synth.workload_matrix(idx)
+    print(f"haydock workload {w['name']}", flush=True)
+    s = generated_solver(mat, storage)
+    d = synth.dipole(w["seed"], mat.n)
+    steps = 3
+    al, be, nn, _, st = s.haydock(torch.as_tensor(d).cuda(), steps, precision="fp64")
+    ops = _generated_ops(mat)
+    ref = hy.lanczos_tda(ops, d, steps) if not mat.ph else hy.lanczos_ph(ops[0], ops[1], d, steps)
+    assert abs(nn - ref[2]) <= 1e-12 * ref[2]
+    assert np.max(np.abs(host(al) - ref[0])) <= 1e-11 * np.max(np.abs(ref[0]))
+    assert np.max(np.abs(host(be) - ref[1])) <= 1e-11 * np.max(np.abs(ref[1]))
+    freq = torch.linspace(0.5, 12.0, 256, dtype=torch.float64, device="cuda")
+    al, be, nn, chi, st = s.haydock(torch.as_tensor(d).cuda(), 2000, tol=1e-8, freq=freq, eta=0.1)
+    n_done = al.numel()
+    print("steps", n_done, "passes", st["passes"], "ms", st["ms_total"], flush=True)
+    assert n_done < 2000
+    assert torch.all(-chi.imag > 0)
+    more = bse.haydock_spectrum("ph" if mat.ph else "tda", *s.haydock(torch.as_tensor(d).cuda(), n_done + 40)[:3],
+                                freq, 0.1)
+    assert torch.max(torch.abs(more - chi)) <= 1e-6 * torch.max(torch.abs(chi))
+    s.close()
