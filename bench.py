@@ -331,7 +331,9 @@ def main():
         # optical spectrum of the same matrix by the Lanczos-Haydock recursion (one read of the
         # triangles per TDA step, two per PH step), FP64 arithmetic on the complex64 hi triangles
         d = torch.as_tensor(synth.dipole(w["seed"], n)).cuda()
-        freq = torch.linspace(0.5, 12.0, 256, dtype=torch.float64, device="cuda")
+        # 256 frequencies over the spectrum: certified lower bound of A to eps_max + shift + row radius of W
+        f_lo = max(mat.lambda_lb - 1.0, 0.05) if ph else mat.lambda_lb - 1.0
+        freq = torch.linspace(f_lo, mat.shift + 9.0 + mat.beta * mat.r_w, 256, dtype=torch.float64, device="cuda")
         hprec = "hi64" if storage == "hilo" else "fp64"
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -129,7 +129,9 @@ def test_workload_haydock_first_steps(idx, storage):
     assert abs(nn - ref[2]) <= 1e-12 * ref[2]
     assert np.max(np.abs(host(al) - ref[0])) <= 1e-11 * np.max(np.abs(ref[0]))
     assert np.max(np.abs(host(be) - ref[1])) <= 1e-11 * np.max(np.abs(ref[1]))
-    freq = torch.linspace(0.5, 12.0, 256, dtype=torch.float64, device="cuda")
+    # the grid covers the spectrum: certified lower bound to eps_max + shift + row radius of W
+    freq = torch.linspace(max(mat.lambda_lb - 1.0, 0.05), mat.shift + 9.0 + mat.beta * mat.r_w, 256,
+                          dtype=torch.float64, device="cuda")
     al, be, nn, chi, st = s.haydock(torch.as_tensor(d).cuda(), 2000, tol=1e-8, freq=freq, eta=0.1)
     n_done = al.numel()
     print("steps", n_done, "passes", st["passes"], "ms", st["ms_total"], flush=True)
