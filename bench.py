@@ -130,7 +130,7 @@ def main():
                    help="PH iteration: 0 K1-metric Lanczos on K2 K1, 1 Lanczos on H in the M inner product")
     p.add_argument("--precision", choices=["auto", "fp64"], default="auto",
                    help="auto: the mixed path where the workload uses it; fp64: FP64 passes only")
-    p.add_argument("--mode", choices=["solve", "passbench", "copy"], default="solve",
+    p.add_argument("--mode", choices=["solve", "passbench", "copy", "direct"], default="solve",
                    help="solve: the benchmark; passbench: only passes over the stored triangles "
                         "(for counter runs); copy: a plain device copy of known size (counter calibration)")
     p.add_argument("--passes", type=int, default=5, help="passbench: timed passes per precision")
@@ -242,6 +242,37 @@ def main():
             out[key] = {"ms_per_pass": ms, "bytes_per_pass": nbytes, "GBps": nbytes / (ms * 1e-3) / 1e9,
                         "ms_per_vector": ms / nv}
             log(f"  {key}: {ms:.3f} ms per read of the triangles ({ms / nv:.3f} ms per vector)")
+        solver.close()
+        print(json.dumps(out), flush=True)
+        return
+
+    if args.mode == "direct":
+        # dense direct solve of the same matrix (PH: Cholesky of M_r, W = L^T J L, Hermitian
+        # eigensolver of -i W, back-transformation) beside the iterative FP64 solve
+        order = 2 * n if ph else n
+        if order > 32767:
+            sys.exit(f"bench --mode direct: dense order {order} is above 32767; pick a smaller workload or --n")
+        kd = args.k or k
+        solver.direct(kd)  # warm-up (library handles, kernels)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        om_d, _, _, sd = solver.direct(kd)
+        torch.cuda.synchronize()
+        td = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        om_i, _, _, si = solver.solve(kd, 1e-10)
+        torch.cuda.synchronize()
+        ti = time.perf_counter() - t0
+        chol_flops = order ** 3 / 3.0 + 2.0 * order ** 3 if ph else 0.0  # Cholesky + the product L^T (J L)
+        out = {"mode": "direct", "workload": w["name"], "n": n, "order": order, "k": kd, "seconds": td,
+               "form_ms": sd["ms_dense_form"], "factor_ms": sd["ms_dense_factor"], "eig_ms": sd["ms_dense_eig"],
+               "factor_TFLOPs": chol_flops / (sd["ms_dense_factor"] * 1e-3) / 1e12 if ph else None,
+               "max_rel_residual": sd["max_rel_residual"], "iterative_fp64_seconds": ti,
+               "iterative_passes": si["passes"],
+               "max_rel_eig_diff": float(np.max(np.abs(om_d.cpu().numpy() - om_i.cpu().numpy()) /
+                                                np.abs(om_i.cpu().numpy())))}
+        log(f"  direct {td:.2f} s (form {sd['ms_dense_form']:.0f} ms, factor {sd['ms_dense_factor']:.0f} ms, "
+            f"eig {sd['ms_dense_eig']:.0f} ms), iterative FP64 {ti:.2f} s")
         solver.close()
         print(json.dumps(out), flush=True)
         return

@@ -132,6 +132,9 @@ typedef struct {
   int32_t reserved_;
   double ms_gemm;           /* summed duration of the basis-rotation GEMMs (restarts, refinement; MFMA) */
   double gemm_flops;        /* their algorithmic flops (real: 2 M N K; complex: 8 M N K) */
+  double ms_dense_form;     /* bse_direct: forming the dense matrix (A, or M_r) from the triangles */
+  double ms_dense_factor;   /* bse_direct, PH: Cholesky of M_r and the product W = L^T J L */
+  double ms_dense_eig;      /* bse_direct: the Hermitian eigensolver */
 } bse_stats;
 
 /* Component of a matrix for bse_strength: the scalar returned for a
@@ -236,6 +239,31 @@ bse_status bse_backward(bse_handle h, const double* g, void* d_a, void* d_b);
  */
 bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse_component* comps,
                         double* out);
+
+/*
+ * bse_direct -- the lowest k pairs by a dense direct solve on the device,
+ * for when a large part of the spectrum is wanted.  PH: the paper's
+ * structure-preserving route (Sec. 2.1): M_r of Eq. (5) from the stored
+ * A and B (FP64: complex128, or hi + lo), the Cholesky factor M_r = L L^T
+ * (it exists iff M is positive definite), the real skew-symmetric
+ * W = L^T J L of Eq. (6), the eigenpairs of the Hermitian -i W (whose
+ * eigenvalues are the +-omega of H), and the back-transformation
+ * v = Q L^{-T} z with Q of Eq. (4), normalized to X^H X - Y^H Y = 1.  TDA:
+ * the dense Hermitian eigenproblem of A.  The Cholesky factorization and
+ * the Hermitian eigensolver are rocSOLVER calls, W is one rocBLAS product;
+ * forming the dense matrices and the back-transformation are kernels of
+ * this library.  Device memory: 32 (2N)^2 bytes for PH, 16 N^2 for TDA.
+ * Arguments and outputs as bse_solve (omega ascending; x, y column-major
+ * N x k complex128).  stats (nullable): ms_total, ms_fp64_phase (dense
+ * matrices and factorizations), ms_final (back-transformation and the
+ * FP64 residuals), passes (reads of the triangles for the residuals),
+ * max_rel_residual.  The pairs are kept for bse_backward / bse_strength.
+ * Errors: INVALID_ARG (k outside [1, N], nulls, y given for TDA, dense
+ * order 2N (PH) or N (TDA) above 32767), NOT_POSITIVE_DEFINITE (the
+ * Cholesky factorization fails), DEVICE (a library call fails or the
+ * eigensolver does not converge), OUT_OF_MEMORY, NONFINITE.
+ */
+bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, bse_stats* stats);
 
 /*
  * bse_haydock -- optical spectrum without eigenpairs: the Lanczos iteration

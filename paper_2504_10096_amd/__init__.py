@@ -32,7 +32,8 @@ OP_A, OP_K1, OP_K2, OP_H = 0, 1, 2, 3
 COMP_PACKED, COMP_LOWRANK, COMP_DIAG, COMP_STORED = 0, 1, 2, 3
 
 EXPORTS = ["bse_create", "bse_set_packed", "bse_apply", "bse_solve", "bse_backward", "bse_strength",
-           "bse_haydock", "bse_haydock_spectrum", "bse_destroy", "bse_status_string", "bse_last_error"]
+           "bse_direct", "bse_haydock", "bse_haydock_spectrum", "bse_destroy", "bse_status_string",
+           "bse_last_error"]
 
 
 class SolveOpts(ctypes.Structure):
@@ -55,7 +56,9 @@ class Stats(ctypes.Structure):
                 ("ms_block_fp32", ctypes.c_double), ("ms_block_fp64", ctypes.c_double),
                 ("samples_fused", ctypes.c_int64), ("ms_block_fused", ctypes.c_double),
                 ("fused_vectors", ctypes.c_int64), ("block", ctypes.c_int32), ("reserved_", ctypes.c_int32),
-                ("ms_gemm", ctypes.c_double), ("gemm_flops", ctypes.c_double)]
+                ("ms_gemm", ctypes.c_double), ("gemm_flops", ctypes.c_double),
+                ("ms_dense_form", ctypes.c_double), ("ms_dense_factor", ctypes.c_double),
+                ("ms_dense_eig", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -99,6 +102,7 @@ def load_library():
         "bse_solve": ([vp, i32, dbl, ctypes.POINTER(SolveOpts), vp, vp, vp, ctypes.POINTER(Stats)], i32),
         "bse_backward": ([vp, vp, vp, vp], i32),
         "bse_strength": ([vp, vp, i32, ctypes.POINTER(Component), ctypes.POINTER(dbl)], i32),
+        "bse_direct": ([vp, i32, vp, vp, vp, ctypes.POINTER(Stats)], i32),
         "bse_haydock": ([vp, vp, i32, dbl, i32, vp, i32, dbl, vp, vp, ctypes.POINTER(dbl), vp,
                          ctypes.POINTER(i32), ctypes.POINTER(Stats)], i32),
         "bse_haydock_spectrum": ([i32, i32, vp, vp, dbl, vp, i32, dbl, vp, vp], i32),
@@ -246,6 +250,22 @@ class Solver:
                         "bse_backward")
         return da, db
 
+
+    def direct(self, k):
+        """Lowest k pairs by the dense direct solve (PH: the structure-preserving Cholesky /
+        skew-symmetric route).  Returns (omega[k], X[k, N], Y[k, N] or None, stats dict)."""
+        k = int(k)
+        dev = self.device
+        omega = torch.empty(k, dtype=torch.float64, device=dev)
+        X = torch.empty((k, self.n), dtype=torch.complex128, device=dev)
+        Y = torch.empty((k, self.n), dtype=torch.complex128, device=dev) if self.kind == PSEUDO_HERMITIAN else None
+        stats = Stats()
+        with torch.cuda.device(dev):
+            st = load_library().bse_direct(self._h, k, _dev_ptr(omega), _dev_ptr(X), _dev_ptr(Y),
+                                           ctypes.byref(stats))
+        self._check(st, "bse_direct")
+        self.last_stats = stats.as_dict()
+        return omega, X, Y, self.last_stats
 
     def haydock(self, d, n_iter, tol=0.0, freq=None, eta=0.1, precision="fp64"):
         """Lanczos-Haydock recursion from the dipole vector d (N complex).  Returns

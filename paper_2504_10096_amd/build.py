@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbse.so")
-SOURCES = ["bse_kernels.hip", "bse_smalleig.cpp", "bse_solver.cpp"]
+SOURCES = ["bse_kernels.hip", "bse_direct.hip", "bse_smalleig.cpp", "bse_solver.cpp"]
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-result"]
@@ -26,7 +26,10 @@ def build(verbose=False):
             print(" ".join(cmd))
         subprocess.run(cmd, check=True, cwd=CSRC)
         objs.append(obj)
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB, *objs]
+    # rocSOLVER (Cholesky, Hermitian eigensolver) and rocBLAS (dense products) for the
+    # direct structure-preserving solve
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB, *objs,
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.run(cmd, check=True, cwd=CSRC)
     for o in objs:
         os.remove(o)

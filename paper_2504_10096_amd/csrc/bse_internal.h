@@ -194,6 +194,28 @@ hipError_t quad_packed(const double2* X, const double2* Y, int64_t ld, const dou
 hipError_t quad_diag(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
                      const double* d, int64_t n, double* part, hipStream_t s);
 
+// Direct structure-preserving solve (bse_direct.hip).
+//   direct_dense: TDA (m.b == nullptr) the dense Hermitian A into ad, or PH the
+//     2N x 2N real M_r of Eq. (5) into mr; column-major, leading dimension ld;
+//     FP64 values of the stored triangles (hilo: hi + lo).
+//   direct_jl: g = J L for the lower Cholesky factor in l (2N x 2N, whose
+//     strict upper triangle is set to zero).
+//   direct_negi: z = -i w (complex) for the real 2N x 2N w.
+//   direct_split: columns c0.. c0+k-1 of z -> real / imaginary parts in the
+//     2N x 2k real matrix rm (columns 0..k-1 / k..2k-1).
+//   direct_back: X = (x1 - i x2) / sqrt(2), Y = (x1 + i x2) / sqrt(2) from
+//     x = rm (x1 rows 0..N-1, x2 rows N..2N-1), Q of Eq. (4).
+//   scale_cols: column c of x (and y) times f[c].
+hipError_t direct_dense(const Layout& L, bool hilo, const MatPtrs& m, double2* ad, double* mr, int64_t ld,
+                        hipStream_t s);
+hipError_t direct_jl(double* l, int64_t ld, int64_t n, double* g, hipStream_t s);
+hipError_t direct_negi(const double* w, int64_t ld, int64_t n2, double2* z, int64_t ldz, hipStream_t s);
+hipError_t direct_split(const double2* z, int64_t ldz, int64_t n2, int c0, int k, double* rm, int64_t ldr,
+                        hipStream_t s);
+hipError_t direct_back(const double* rm, int64_t ldr, int64_t n, int k, double2* x, double2* y, int64_t ldo,
+                       hipStream_t s);
+hipError_t scale_cols(double2* x, double2* y, int64_t ld, int64_t n, int k, const double* f, hipStream_t s);
+
 // chi[f] = scale / (s - alpha_0 - beta_0^2 / (s - alpha_1 - ...)) truncated
 // after n levels, s = z (ph == 0) or z^2, z = freq[f] + i eta, for f < nw.
 hipError_t cfrac(int ph, int n, const double* alpha, const double* beta, double scale, const double* freq,

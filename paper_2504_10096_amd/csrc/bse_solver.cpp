@@ -21,6 +21,9 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "../../include/bse.h"
 #include "bse_internal.h"
 
@@ -108,6 +111,35 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
       .count();
+}
+
+}  // namespace
+
+namespace {
+
+// Keep the k pairs of a successful solve with the handle for bse_backward and
+// bse_strength.
+bse_status keep_solution(bse_handle h, int k, const double* omega, const void* x, const void* y) {
+  const bool ph = h->kind == BSE_PSEUDO_HERMITIAN;
+  const int64_t n = h->n;
+  void* ptrs[] = {h->X, h->Y, h->omega};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  h->X = h->Y = nullptr;
+  h->omega = nullptr;
+  h->solved = false;
+  HIP_TRY(h, hipMalloc((void**)&h->X, sizeof(double2) * (size_t)n * k));
+  HIP_TRY(h, hipMemcpyAsync(h->X, x, sizeof(double2) * (size_t)n * k, hipMemcpyDeviceToDevice, h->stream));
+  if (ph) {
+    HIP_TRY(h, hipMalloc((void**)&h->Y, sizeof(double2) * (size_t)n * k));
+    HIP_TRY(h, hipMemcpyAsync(h->Y, y, sizeof(double2) * (size_t)n * k, hipMemcpyDeviceToDevice, h->stream));
+  }
+  HIP_TRY(h, hipMalloc((void**)&h->omega, sizeof(double) * k));
+  HIP_TRY(h, hipMemcpyAsync(h->omega, omega, sizeof(double) * k, hipMemcpyDeviceToDevice, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->k = k;
+  h->solved = true;
+  return BSE_OK;
 }
 
 }  // namespace
@@ -1572,24 +1604,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   }
   if (!converged)
     return fail(h, BSE_ERR_NOT_CONVERGED, "max_restarts reached before all pairs met tol");
-  // keep the eigenvectors for bse_backward / bse_strength
-  void* ptrs[] = {h->X, h->Y, h->omega};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  h->X = h->Y = nullptr;
-  h->omega = nullptr;
-  HIP_TRY(h, hipMalloc((void**)&h->X, sizeof(double2) * (size_t)n * k));
-  HIP_TRY(h, hipMemcpyAsync(h->X, x, sizeof(double2) * (size_t)n * k, hipMemcpyDeviceToDevice, S.s));
-  if (ph) {
-    HIP_TRY(h, hipMalloc((void**)&h->Y, sizeof(double2) * (size_t)n * k));
-    HIP_TRY(h, hipMemcpyAsync(h->Y, y, sizeof(double2) * (size_t)n * k, hipMemcpyDeviceToDevice, S.s));
-  }
-  HIP_TRY(h, hipMalloc((void**)&h->omega, sizeof(double) * k));
-  HIP_TRY(h, hipMemcpyAsync(h->omega, omega, sizeof(double) * k, hipMemcpyDeviceToDevice, S.s));
-  HIP_TRY(h, hipStreamSynchronize(S.s));
-  h->k = k;
-  h->solved = true;
-  return BSE_OK;
+  return keep_solution(h, k, omega, x, y);
 }
 
 bse_status bse_backward(bse_handle h, const double* g, void* d_a, void* d_b) {
@@ -1936,6 +1951,186 @@ bse_status bse_haydock_spectrum(bse_kind kind, int32_t n_iter, const double* alp
                  s) != hipSuccess)
     return BSE_ERR_DEVICE;
   return hipStreamSynchronize(s) == hipSuccess ? BSE_OK : BSE_ERR_DEVICE;
+}
+
+bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, bse_stats* stats) {
+  if (!h) return BSE_ERR_INVALID_ARG;
+  const double t0 = now_ms();
+  const bool ph = h->kind == BSE_PSEUDO_HERMITIAN;
+  const int64_t n = h->n, n2 = ph ? 2 * n : n;
+  if (k < 1 || k > n) return fail(h, BSE_ERR_INVALID_ARG, "k must be in [1, N]");
+  if (!omega || !x) return fail(h, BSE_ERR_INVALID_ARG, "omega and x are required");
+  if (ph != (y != nullptr)) return fail(h, BSE_ERR_INVALID_ARG, "y is required for PH and must be NULL for TDA");
+  if (n2 > 32767) return fail(h, BSE_ERR_INVALID_ARG, "the direct solve handles dense orders up to 32767");
+  h->solved = false;
+  const hipStream_t s = h->stream;
+  const bool hilo = h->storage == BSE_STORE_HILO;
+  const bse::MatPtrs mp = mat_ptrs(h);
+  struct Blas {
+    rocblas_handle b = nullptr;
+    ~Blas() {
+      if (b) (void)rocblas_destroy_handle(b);
+    }
+  } blas;
+  if (rocblas_create_handle(&blas.b) != rocblas_status_success || rocblas_set_stream(blas.b, s) != rocblas_status_success)
+    return fail(h, BSE_ERR_DEVICE, "rocBLAS handle");
+  auto rb = [&](rocblas_status e, const char* what) -> bse_status {
+    if (e == rocblas_status_success) return BSE_OK;
+    return fail(h, e == rocblas_status_memory_error ? BSE_ERR_OUT_OF_MEMORY : BSE_ERR_DEVICE,
+                std::string(what) + ": " + rocblas_status_to_string(e));
+  };
+  const size_t sq = (size_t)n2 * n2;
+  DevBuf bMr, bG, bZ, bEv, bE, bInfo, bRm, bF, bW, bRed, bRes;
+  HIP_TRY(h, hipMalloc(&bZ.p, sizeof(double2) * sq));
+  HIP_TRY(h, hipMalloc(&bEv.p, sizeof(double) * n2));
+  HIP_TRY(h, hipMalloc(&bE.p, sizeof(double) * n2));
+  HIP_TRY(h, hipMalloc(&bInfo.p, sizeof(rocblas_int)));
+  HIP_TRY(h, hipMalloc(&bF.p, sizeof(double) * k));
+  double2* Z = (double2*)bZ.p;
+  double* ev = (double*)bEv.p;
+  rocblas_int* info = (rocblas_int*)bInfo.p;
+  rocblas_int inf = 0;
+  double ms_form = 0.0, ms_chol = 0.0, ms_eig = 0.0;
+  int c0 = 0;  // first wanted eigenpair of the Hermitian problem
+  if (!ph) {
+    // TDA: the Hermitian eigenproblem of A
+    HIP_TRY(h, bse::direct_dense(h->L, hilo, mp, Z, nullptr, n, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    ms_form = now_ms() - t0;
+  } else {
+    // M_r of Eq. (5); M_r = L L^T; W = L^T J L (Eq. (6)); Z = -i W
+    HIP_TRY(h, hipMalloc(&bMr.p, sizeof(double) * sq));
+    HIP_TRY(h, hipMalloc(&bG.p, sizeof(double) * sq));
+    double* Mr = (double*)bMr.p;
+    double* G = (double*)bG.p;
+    HIP_TRY(h, bse::direct_dense(h->L, hilo, mp, nullptr, Mr, n2, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    ms_form = now_ms() - t0;
+    const double tc = now_ms();
+    if (bse_status e = rb(rocsolver_dpotrf(blas.b, rocblas_fill_lower, (rocblas_int)n2, Mr, (rocblas_int)n2, info),
+                          "rocsolver_dpotrf"))
+      return e;
+    HIP_TRY(h, hipMemcpyAsync(&inf, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    if (inf != 0)
+      return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "Cholesky of M_r failed: M is not positive definite");
+    HIP_TRY(h, bse::direct_jl(Mr, n2, n, G, s));  // G = J L; the upper triangle of L cleared
+    const double one = 1.0, zero = 0.0;
+    // W = L^T (J L) goes to the first half of Z's memory (L stays for the back-transformation),
+    // then to G, and Z receives -i W
+    double* Wm = reinterpret_cast<double*>(Z);
+    if (bse_status e = rb(rocblas_dgemm(blas.b, rocblas_operation_transpose, rocblas_operation_none,
+                                        (rocblas_int)n2, (rocblas_int)n2, (rocblas_int)n2, &one, Mr,
+                                        (rocblas_int)n2, G, (rocblas_int)n2, &zero, Wm, (rocblas_int)n2),
+                          "rocblas_dgemm"))
+      return e;
+    HIP_TRY(h, hipMemcpyAsync(G, Wm, sizeof(double) * sq, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(h, bse::direct_negi(G, n2, n2, Z, n2, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    ms_chol = now_ms() - tc;
+    c0 = (int)n;  // eigenvalues of -i W ascend: -omega_max .. -omega_min, omega_min .. omega_max
+  }
+  const double te = now_ms();
+  if (bse_status e = rb(rocsolver_zheevd(blas.b, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n2,
+                                         reinterpret_cast<rocblas_double_complex*>(Z), (rocblas_int)n2, ev,
+                                         (double*)bE.p, info),
+                        "rocsolver_zheevd"))
+    return e;
+  HIP_TRY(h, hipMemcpyAsync(&inf, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  if (inf != 0) return fail(h, BSE_ERR_DEVICE, "Hermitian eigensolver did not converge");
+  ms_eig = now_ms() - te;
+  std::vector<double> om(k);
+  HIP_TRY(h, hipMemcpyAsync(om.data(), ev + c0, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
+  if (ph && !(om[0] > 0.0))
+    return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "non-positive omega: M is not positive definite");
+  HIP_TRY(h, hipMemcpyAsync(omega, ev + c0, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+  double2* X = (double2*)x;
+  double2* Y = (double2*)y;
+  if (!ph) {
+    HIP_TRY(h, bse::copy_cols(Z, n, X, n, n, k, s));
+  } else {
+    // x = L^{-T} z for the k wanted columns (real and imaginary parts), v = Q x
+    HIP_TRY(h, hipMalloc(&bRm.p, sizeof(double) * (size_t)n2 * 2 * k));
+    double* Rm = (double*)bRm.p;
+    HIP_TRY(h, bse::direct_split(Z, n2, n2, c0, k, Rm, n2, s));
+    const double one = 1.0;
+    if (bse_status e = rb(rocblas_dtrsm(blas.b, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
+                                        rocblas_diagonal_non_unit, (rocblas_int)n2, (rocblas_int)(2 * k), &one,
+                                        (const double*)bMr.p, (rocblas_int)n2, Rm, (rocblas_int)n2),
+                          "rocblas_dtrsm"))
+      return e;
+    HIP_TRY(h, bse::direct_back(Rm, n2, n, k, X, Y, n, s));
+    // X^H X - Y^H Y = 1 per pair
+    HIP_TRY(h, hipMalloc(&bRed.p, sizeof(double) * ((size_t)bse::nchunks(n) * std::max(k, 2) + 64)));
+    HIP_TRY(h, hipMalloc(&bRes.p, sizeof(double) * 2 * k));
+    double* nr = (double*)bRes.p;
+    HIP_TRY(h, bse::colnorms(X, k, n, n, (double*)bRed.p, nr, s));
+    HIP_TRY(h, bse::colnorms(Y, k, n, n, (double*)bRed.p, nr + k, s));
+    std::vector<double> nrm(2 * k), f(k);
+    HIP_TRY(h, hipMemcpyAsync(nrm.data(), nr, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    for (int c = 0; c < k; ++c) {
+      const double d = nrm[c] - nrm[k + c];
+      if (!(d > 0.0)) return fail(h, BSE_ERR_NONFINITE, "eigenvector with X^H X - Y^H Y <= 0");
+      f[c] = 1.0 / sqrt(d);
+    }
+    HIP_TRY(h, hipMemcpyAsync(bF.p, f.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, bse::scale_cols(X, Y, n, n, k, (const double*)bF.p, s));
+  }
+  // FP64 residuals of the k pairs through the stored operator
+  HIP_TRY(h, hipMalloc(&bW.p, sizeof(double2) * (size_t)round_up(n, 64)));
+  if (!bRed.p) HIP_TRY(h, hipMalloc(&bRed.p, sizeof(double) * ((size_t)bse::nchunks(n) * 2 + 64)));
+  if (!bRes.p) HIP_TRY(h, hipMalloc(&bRes.p, sizeof(double) * 4));
+  double2* Wv = (double2*)bW.p;
+  double* red = (double*)bRed.p;
+  double* res = (double*)bRes.p;
+  const Arith ar = fp64_arith(h);
+  double max_rel = 0.0;
+  int64_t passes = 0;
+  for (int c = 0; c < k; ++c) {
+    double r[4] = {0, 0, 0, 0};
+    const double2* xc = X + (size_t)c * n;
+    if (!ph) {
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_NONE, mp, xc, 0, nullptr, 0, 0.0, h->part, Wv, s));
+      HIP_TRY(h, bse::resid_norms(Wv, xc, 0, om[c], n, red, res, s));
+      HIP_TRY(h, hipMemcpyAsync(r, res, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+      passes += 1;
+    } else {
+      const double2* yc = Y + (size_t)c * n;
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, xc, 0, yc, 0, 1.0, h->part, Wv, s));
+      HIP_TRY(h, bse::resid_norms(Wv, xc, 0, om[c], n, red, res, s));
+      HIP_TRY(h, hipMemcpyAsync(r, res, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, yc, 1, xc, 1, 1.0, h->part, Wv, s));
+      HIP_TRY(h, bse::resid_norms(Wv, yc, 1, -om[c], n, red, res, s));
+      HIP_TRY(h, hipMemcpyAsync(r + 2, res, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+      passes += 2;
+    }
+    HIP_TRY(h, hipStreamSynchronize(s));
+    const double rel = sqrt(r[0] + r[2]) / (std::max(fabs(om[c]), 1e-300) * sqrt(r[1] + r[3]));
+    if (!std::isfinite(rel)) return fail(h, BSE_ERR_NONFINITE, "non-finite residual");
+    max_rel = std::max(max_rel, rel);
+  }
+  if (stats) {
+    *stats = bse_stats{};
+    stats->n_converged = k;
+    stats->passes = passes;
+    stats->ms_total = now_ms() - t0;
+    stats->ms_fp64_phase = ms_form + ms_chol + ms_eig;
+    stats->ms_final = stats->ms_total - stats->ms_fp64_phase;
+    stats->max_rel_residual = max_rel;
+    stats->block = 1;
+    stats->ms_dense_form = ms_form;
+    stats->ms_dense_factor = ms_chol;
+    stats->ms_dense_eig = ms_eig;
+  }
+  if (const char* tr = getenv("BSE_TRACE"))
+    if (tr[0] == '1')
+      fprintf(stderr, "{\"direct\": {\"order\": %lld, \"form_ms\": %.3f, \"cholesky_ms\": %.3f, \"eig_ms\": %.3f, "
+                      "\"total_ms\": %.3f}}\n",
+              (long long)n2, ms_form, ms_chol, ms_eig, now_ms() - t0);
+  return keep_solution(h, k, omega, x, y);
 }
 
 }  // extern "C"
