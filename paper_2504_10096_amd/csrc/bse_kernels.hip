@@ -856,6 +856,168 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// rows per workgroup slice of the streaming full-H kernel (register budget)
+__host__ __device__ constexpr int mh_rows(int nh) { return nh >= 2 ? 128 : 256; }
+
+// Full-H products in the streaming form (R >= 128): the products of
+// mh_block_kernel (outputs 2q: A x_q + B y_q; 2q+1: A conj(y_q) + B conj(x_q),
+// rows and columns), with the layout of mk_block_kernel: 16-byte loads of
+// column segments, the next column's loads issued before the current one is
+// consumed, DPP column sums kept one per lane and stored per 64 columns.
+// Row partials: rowpart[o][blk][R]; column partials: colpart[o][blk][slice][R]
+// with R / mh_rows(NH) slices.
+template <int R, int AR, int NH>
+__global__ void __launch_bounds__(kThreads)
+    mh_stream_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
+                     const void* __restrict__ b0, const void* __restrict__ b1,
+                     const int2* __restrict__ blkmap, int64_t nblk, int64_t n,
+                     const double2* __restrict__ V, int64_t ldv, int64_t ldh,
+                     double2* __restrict__ rowpart, double2* __restrict__ colpart) {
+  constexpr int RS = R < mh_rows(NH) ? R : mh_rows(NH);
+  constexpr int NS = R / RS;
+  constexpr int VW = AR != AR_C128 ? 2 : 1;
+  constexpr int G = RS / (64 * VW);
+  constexpr int RPL = G * VW;
+  constexpr int CPW = R / 4;
+  constexpr int CH = CPW < 64 ? CPW : 64;
+  constexpr int NO = 2 * NH;
+  static_assert(RS >= 128 && G >= 1, "streaming full-H layout");
+  __shared__ double2 sh[4][RS];
+
+  const int blk = blockIdx.x;
+  const int slice = blockIdx.y;
+  const int2 pq = blkmap[blk];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
+  const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
+
+  double xr[NH][RPL], xi[NH][RPL], yr[NH][RPL], yi[NH][RPL], rr[NO][RPL], ri[NO][RPL];
+#pragma unroll
+  for (int q = 0; q < NH; ++q)
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int t = g * VW + e;
+        const int64_t i = row0 + g * 64 * VW + lane * VW + e;
+        const bool in = i < n;
+        const double2 x = V[(size_t)q * ldv + (in ? i : 0)];
+        const double2 y = V[(size_t)q * ldv + ldh + (in ? i : 0)];
+        xr[q][t] = in ? x.x : 0.0;
+        xi[q][t] = in ? x.y : 0.0;
+        yr[q][t] = in ? y.x : 0.0;
+        yi[q][t] = in ? y.y : 0.0;
+      }
+#pragma unroll
+  for (int o = 0; o < NO; ++o)
+#pragma unroll
+    for (int t = 0; t < RPL; ++t) {
+      rr[o][t] = 0.0;
+      ri[o][t] = 0.0;
+    }
+
+  const size_t lbase = base + (size_t)wave * CPW * R + lane * VW;
+  RawCol<AR> ca_[G], cbm[G], na_[G], nbm[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    raw_load<AR>(a0, a1, lbase + g * 64 * VW, ca_[g]);
+    raw_load<AR>(b0, b1, lbase + g * 64 * VW, cbm[g]);
+  }
+  for (int cb = 0; cb < CPW; cb += CH) {
+    double2 keep[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) keep[o] = make_double2(0.0, 0.0);
+    for (int c2 = 0; c2 < CH; ++c2) {
+      const int cc = cb + c2;
+      const int cn = cc + 1 < CPW ? cc + 1 : cc;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        raw_load<AR>(a0, a1, lbase + (size_t)cn * R + g * 64 * VW, na_[g]);
+        raw_load<AR>(b0, b1, lbase + (size_t)cn * R + g * 64 * VW, nbm[g]);
+      }
+      const int c = wave * CPW + cc;
+      const int64_t j = col0 + c;
+      const bool in = j < n;
+      const int64_t jj = in ? j : 0;
+      double cxr[NH], cxi[NH], cyr[NH], cyi[NH], sr[NO], si[NO];
+#pragma unroll
+      for (int q = 0; q < NH; ++q) {
+        const double2 x = V[(size_t)q * ldv + jj];
+        const double2 y = V[(size_t)q * ldv + ldh + jj];
+        cxr[q] = in ? x.x : 0.0;
+        cxi[q] = in ? x.y : 0.0;
+        cyr[q] = in ? y.x : 0.0;
+        cyi[q] = in ? y.y : 0.0;
+      }
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        sr[o] = 0.0;
+        si[o] = 0.0;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const int t = g * VW + e;
+          double ar, ai, br, bi;
+          raw_get<AR, double>(ca_[g], e, ar, ai);
+          raw_get<AR, double>(cbm[g], e, br, bi);
+#pragma unroll
+          for (int q = 0; q < NH; ++q) {
+            // top, row r: A x_c + B y_c
+            rr[2 * q][t] += ar * cxr[q] - ai * cxi[q] + br * cyr[q] - bi * cyi[q];
+            ri[2 * q][t] += ar * cxi[q] + ai * cxr[q] + br * cyi[q] + bi * cyr[q];
+            // bottom (conjugated), row r: A conj(y_c) + B conj(x_c)
+            rr[2 * q + 1][t] += ar * cyr[q] + ai * cyi[q] + br * cxr[q] + bi * cxi[q];
+            ri[2 * q + 1][t] += ai * cyr[q] - ar * cyi[q] + bi * cxr[q] - br * cxi[q];
+            // top, column c: conj(A) x_r + B y_r
+            sr[2 * q] += ar * xr[q][t] + ai * xi[q][t] + br * yr[q][t] - bi * yi[q][t];
+            si[2 * q] += ar * xi[q][t] - ai * xr[q][t] + br * yi[q][t] + bi * yr[q][t];
+            // bottom (conjugated), column c: conj(A) conj(y_r) + B conj(x_r)
+            sr[2 * q + 1] += ar * yr[q][t] - ai * yi[q][t] + br * xr[q][t] + bi * xi[q][t];
+            si[2 * q + 1] += -ar * yi[q][t] - ai * yr[q][t] + bi * xr[q][t] - br * xi[q][t];
+          }
+        }
+#pragma unroll
+      for (int o = 0; o < NO; ++o) {
+        const double ur = dpp_wave_sum(sr[o]), ui = dpp_wave_sum(si[o]);
+        keep[o] = lane == c2 ? make_double2(ur, ui) : keep[o];
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        ca_[g] = na_[g];
+        cbm[g] = nbm[g];
+      }
+    }
+    if (lane < CH) {
+#pragma unroll
+      for (int o = 0; o < NO; ++o)
+        colpart[(((size_t)o * nblk + blk) * NS + slice) * R + wave * CPW + cb + lane] = keep[o];
+    }
+  }
+
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int e = 0; e < VW; ++e)
+        sh[wave][g * 64 * VW + lane * VW + e] = make_double2(rr[o][g * VW + e], ri[o][g * VW + e]);
+    __syncthreads();
+    for (int r = threadIdx.x; r < RS; r += kThreads) {
+      double2 t = sh[0][r];
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        t.x += sh[w][r].x;
+        t.y += sh[w][r].y;
+      }
+      rowpart[((size_t)o * nblk + blk) * R + slice * RS + r] = t;
+    }
+    __syncthreads();
+  }
+}
+
 // Sum of the partials of mh_block_kernel (pairs != 0: output 2q goes to the
 // top of column q of MV, output 2q+1 conjugated and times bsign to its
 // bottom; bsign = 1: M v, -1: H v) or of mk_block_kernel (pairs == 0:
@@ -896,12 +1058,28 @@ __global__ void __launch_bounds__(kThreads)
     MV[(size_t)q * ldv + i] = make_double2(sx, sy);
 }
 
+// Row slices per block of the full-H products with nh vectors.
+int mh_slices(int R, int nh) {
+  if (R < 128) return 1;
+  return R < mh_rows(nh) ? 1 : R / mh_rows(nh);
+}
+
 template <int R, int AR>
 hipError_t launch_mh(int nh, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv, int64_t ldh,
                      double2* part, hipStream_t s) {
-  constexpr int NS = R < 256 ? 1 : R / 256;
   double2* rowpart = part;
   double2* colpart = part + (size_t)2 * nh * L.nblk * R;
+  if constexpr (R >= 128) {
+    const dim3 grid((unsigned)L.nblk, (unsigned)mh_slices(R, nh));
+    if (nh == 1)
+      hipLaunchKernelGGL((mh_stream_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
+                         L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+    else
+      hipLaunchKernelGGL((mh_stream_kernel<R, AR, 2>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
+                         L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+    return hipGetLastError();
+  }
+  constexpr int NS = 1;  // R = 64: one slice per block
   const dim3 grid((unsigned)L.nblk, (unsigned)NS);
   if (nh == 1)
     hipLaunchKernelGGL((mh_block_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo, L.blkmap,
@@ -1084,10 +1262,13 @@ __global__ void __launch_bounds__(kThreads)
   if (lane == 0) h[c] = make_double2(sr, si);
 }
 
-// w[i] -= sum_c V[i, c] h[c];  z[i] -= sum_c P[i, c] h[c] (optional).
+// w[i] -= sum_c V[i, c] h[c];  z[i] -= sum_c P[i, c] h[c] (WithZ).
 // real_h 1: h[c] -> Re h[c]; 2: Re h[c] on the first n0 columns and
 // i Im h[c] on the others (a real coefficient on each basis vector and on
-// each i-multiple of the second basis).
+// each i-multiple of the second basis).  One row per thread; the column
+// loops of the two bases are separate and unrolled so that several loads are
+// in flight per thread (the loop is latency-bound otherwise).
+template <bool WithZ>
 __global__ void __launch_bounds__(kThreads)
     cgemv_sub_kernel(const double2* __restrict__ V0, int n0, const double2* __restrict__ V1, int n1,
                      const double2* __restrict__ P0, const double2* __restrict__ P1, int64_t ld,
@@ -1107,22 +1288,48 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-  for (int c = 0; c < ncol; ++c) {
-    const double2 hc = hs[c];
-    const double2 v = (c < n0) ? V0[(size_t)c * ld + i] : V1[(size_t)(c - n0) * ld + i];
-    ar += v.x * hc.x - v.y * hc.y;
-    ai += v.x * hc.y + v.y * hc.x;
-    if (z) {
-      const double2 p = (c < n0) ? P0[(size_t)c * ld + i] : P1[(size_t)(c - n0) * ld + i];
-      br += p.x * hc.x - p.y * hc.y;
-      bi += p.x * hc.y + p.y * hc.x;
+  for (int part = 0; part < 2; ++part) {
+    const double2* __restrict__ V = part ? V1 : V0;
+    const double2* __restrict__ P = part ? P1 : P0;
+    const int cnt = part ? n1 : n0, off = part ? n0 : 0;
+    int c = 0;
+    // batches of 8 columns: all loads of a batch are issued before the first use
+    for (; c + 8 <= cnt; c += 8) {
+      double2 v[8], q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = V[(size_t)(c + u) * ld + i];
+      if (WithZ) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = P[(size_t)(c + u) * ld + i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double2 hc = hs[off + c + u];
+        ar += v[u].x * hc.x - v[u].y * hc.y;
+        ai += v[u].x * hc.y + v[u].y * hc.x;
+        if (WithZ) {
+          br += q[u].x * hc.x - q[u].y * hc.y;
+          bi += q[u].x * hc.y + q[u].y * hc.x;
+        }
+      }
+    }
+    for (; c < cnt; ++c) {
+      const double2 hc = hs[off + c];
+      const double2 v = V[(size_t)c * ld + i];
+      ar += v.x * hc.x - v.y * hc.y;
+      ai += v.x * hc.y + v.y * hc.x;
+      if (WithZ) {
+        const double2 q = P[(size_t)c * ld + i];
+        br += q.x * hc.x - q.y * hc.y;
+        bi += q.x * hc.y + q.y * hc.x;
+      }
     }
   }
   double2 wv = w[i];
   wv.x -= ar;
   wv.y -= ai;
   w[i] = wv;
-  if (z) {
+  if (WithZ) {
     double2 zv = z[i];
     zv.x -= br;
     zv.y -= bi;
@@ -1695,8 +1902,10 @@ int mv_slices(const Layout&) { return 1; }
 size_t mv_part_elems(const Layout& L) { return (size_t)L.nblk * L.R * (1 + mv_slices(L)); }
 
 size_t mh_part_elems(const Layout& L, int nh) {
-  const int ns = L.R < 256 ? 1 : L.R / 256;
-  return (size_t)2 * nh * L.nblk * L.R * (1 + ns);
+  size_t mx = 0;
+  for (int v = 1; v <= nh; ++v)
+    mx = std::max(mx, (size_t)2 * v * L.nblk * L.R * (1 + mh_slices(L.R, v)));
+  return mx;
 }
 
 size_t mk_part_elems(const Layout& L, int nv) {
@@ -1738,7 +1947,7 @@ hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const d
     e = hipEventRecord(ev1, s);
     if (e != hipSuccess) return e;
   }
-  const int ns = L.R < 256 ? 1 : L.R / 256;
+  const int ns = mh_slices(L.R, nh);
   const double2* rowpart = part;
   const double2* colpart = part + (size_t)2 * nh * L.nblk * L.R;
   hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)(2 * nh)),
@@ -1864,9 +2073,14 @@ hipError_t cgemv_sub(const double2* V0, int n0, const double2* V1, int n1, const
                      double2* z, int64_t n, hipStream_t s) {
   const int ncol = n0 + n1;
   if (ncol == 0) return hipSuccess;
-  hipLaunchKernelGGL(cgemv_sub_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
-                     dim3(kThreads), (size_t)ncol * sizeof(double2), s, V0, n0, V1, n1, P0, P1, ld,
-                     h, real_h, w, z, n);
+  const dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
+  const size_t lds = (size_t)ncol * sizeof(double2);
+  if (z)
+    hipLaunchKernelGGL(cgemv_sub_kernel<true>, grid, dim3(kThreads), lds, s, V0, n0, V1, n1, P0, P1, ld, h, real_h,
+                       w, z, n);
+  else
+    hipLaunchKernelGGL(cgemv_sub_kernel<false>, grid, dim3(kThreads), lds, s, V0, n0, V1, n1, P0, P1, ld, h,
+                       real_h, w, z, n);
   return hipGetLastError();
 }
 
