@@ -690,8 +690,10 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// rows per workgroup slice of the multi-vector pass (register budget)
-__host__ __device__ constexpr int mk_rows(int nv) { return nv >= 3 ? 128 : (nv == 2 ? 256 : 512); }
+// rows per workgroup slice of the multi-vector pass: as many as the
+// register budget allows (four vectors at 256 rows would leave one wave
+// per SIMD)
+__host__ __device__ constexpr int mk_rows(int nv) { return nv >= 4 ? 128 : (nv >= 2 ? 256 : 512); }
 
 // Multi-vector pass: out_q = A x_q (BM_NONE) or A x_q + sb B conj(x_q)
 // (BM_CONJ: K1 for sb = 1, K2 for sb = -1) for NV vectors in one read of the
@@ -760,6 +762,8 @@ __global__ void __launch_bounds__(kThreads)
     double2 keep[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) keep[v] = make_double2(0.0, 0.0);
+    // unrolled by two: see mh_stream_kernel
+#pragma unroll 2
     for (int c2 = 0; c2 < CH; ++c2) {
       const int cc = cb + c2;
       const int cn = cc + 1 < CPW ? cc + 1 : cc;
@@ -768,6 +772,7 @@ __global__ void __launch_bounds__(kThreads)
         raw_load<AR>(a0, a1, lbase + (size_t)cn * R + g * 64 * VW, na_[g]);
         if (BM == BM_CONJ) raw_load<AR>(b0, b1, lbase + (size_t)cn * R + g * 64 * VW, nbm[g]);
       }
+      __builtin_amdgcn_sched_barrier(0);  // see mh_stream_kernel
       const int c = wave * CPW + cc;
       const int64_t j = col0 + c;
       const bool in = j < n;
@@ -856,8 +861,11 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
-// rows per workgroup slice of the streaming full-H kernel (register budget)
-__host__ __device__ constexpr int mh_rows(int nh) { return nh >= 2 ? 128 : 256; }
+// rows per workgroup slice of the streaming full-H kernel: 256 rows spread
+// each column's wavefront reductions (four per vector) over four rows per
+// lane; 128 rows left the kernel bound by those reductions (37 ms vs 30 ms
+// per read for two vectors at N = 1e5)
+__host__ __device__ constexpr int mh_rows(int) { return 256; }
 
 // Full-H products in the streaming form (R >= 128): the products of
 // mh_block_kernel (outputs 2q: A x_q + B y_q; 2q+1: A conj(y_q) + B conj(x_q),
@@ -928,6 +936,9 @@ __global__ void __launch_bounds__(kThreads)
     double2 keep[NO];
 #pragma unroll
     for (int o = 0; o < NO; ++o) keep[o] = make_double2(0.0, 0.0);
+    // unrolled by two so the prefetched registers are renamed, not copied (a
+    // copy would wait for the loads just issued)
+#pragma unroll 2
     for (int c2 = 0; c2 < CH; ++c2) {
       const int cc = cb + c2;
       const int cn = cc + 1 < CPW ? cc + 1 : cc;
@@ -936,6 +947,9 @@ __global__ void __launch_bounds__(kThreads)
         raw_load<AR>(a0, a1, lbase + (size_t)cn * R + g * 64 * VW, na_[g]);
         raw_load<AR>(b0, b1, lbase + (size_t)cn * R + g * 64 * VW, nbm[g]);
       }
+      // keep the loads here: under register pressure the scheduler would sink
+      // them next to their use in the following column
+      __builtin_amdgcn_sched_barrier(0);
       const int c = wave * CPW + cc;
       const int64_t j = col0 + c;
       const bool in = j < n;
