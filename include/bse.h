@@ -284,28 +284,37 @@ bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, 
  *        K2 p = A p - B conj(p)) from d / sqrt(<d, K1 d>); since
  *        chi(z) = 2 <d, K1 (z^2 - K2 K1)^{-1} d>, the same fraction in z^2 times
  *        2 <d, K1 d>.
+ * Several dipole vectors (for instance the three polarizations) advance in
+ * lockstep: each read of the triangles serves up to four of them (the
+ * multi-vector pass), and their recurrences are otherwise independent.
  * Arguments:
- *   d:        device, N complex128 (interleaved re, im), not modified.
- *   max_iter: iterations (>= 1); alpha, beta: device, max_iter doubles each,
- *             the first *n_iter written (beta_j couples steps j and j + 1).
+ *   nd:       number of dipole vectors (>= 1).
+ *   d:        device, N x nd complex128, column-major (interleaved re, im), not
+ *             modified.
+ *   max_iter: iterations (>= 1); alpha, beta: device, nd x max_iter doubles
+ *             each (dipole q at q max_iter), the first *n_iter of each written
+ *             (beta_j couples steps j and j + 1).
  *   tol:      0: run max_iter steps.  > 0: every 20 steps evaluate chi on the
- *             grid and stop once max |delta Im chi| <= tol max |Im chi|.
+ *             grid and stop once max |delta Im chi| <= tol max |Im chi| for
+ *             every dipole.
  *   precision: FP64 (the FP64 operator), HI_FP64 (FP64 arithmetic on the
  *             complex64 hi triangles, HILO only) or MIXED (complex FP32
  *             arithmetic on hi, HILO only).
  *   freq, nw, eta: device frequency grid (nw doubles) and broadening eta > 0;
- *             chi: device, nw complex128, the response at freq + i eta after
- *             the last step.  freq and chi may be NULL (nw = 0) when tol = 0.
- *   norm2:    host: ||d||^2 (TDA) or <d, K1 d> (PH);  n_iter: host, steps done.
+ *             chi: device, nw x nd complex128 (dipole q at q nw), the response
+ *             at freq + i eta after the last step.  freq and chi may be NULL
+ *             (nw = 0) when tol = 0.
+ *   norm2:    host, nd doubles: ||d||^2 (TDA) or <d, K1 d> (PH) per dipole;
+ *             n_iter: host, steps done (the same for every dipole).
  *   stats:    host, nullable: passes, ms_total, block-kernel samples.
- * Errors: INVALID_ARG (nulls, max_iter < 1, tol < 0, eta <= 0 with a grid,
+ * Errors: INVALID_ARG (nulls, nd < 1, max_iter < 1, tol < 0, eta <= 0 with a grid,
  * precision not allowed by the storage), NOT_POSITIVE_DEFINITE (<w, K1 w> <=
  * 0, PH), NONFINITE, DEVICE, OUT_OF_MEMORY.  A zero beta_j (an invariant
  * subspace) ends the fraction there: later coefficients do not enter chi.
  */
-bse_status bse_haydock(bse_handle h, const void* d, int32_t max_iter, double tol, bse_precision precision,
-                       const double* freq, int32_t nw, double eta, double* alpha, double* beta, double* norm2,
-                       void* chi, int32_t* n_iter, bse_stats* stats);
+bse_status bse_haydock(bse_handle h, int32_t nd, const void* d, int32_t max_iter, double tol,
+                       bse_precision precision, const double* freq, int32_t nw, double eta, double* alpha,
+                       double* beta, double* norm2, void* chi, int32_t* n_iter, bse_stats* stats);
 
 /*
  * bse_haydock_spectrum -- chi(w + i eta) on a device grid from n_iter

@@ -103,7 +103,7 @@ def load_library():
         "bse_backward": ([vp, vp, vp, vp], i32),
         "bse_strength": ([vp, vp, i32, ctypes.POINTER(Component), ctypes.POINTER(dbl)], i32),
         "bse_direct": ([vp, i32, vp, vp, vp, ctypes.POINTER(Stats)], i32),
-        "bse_haydock": ([vp, vp, i32, dbl, i32, vp, i32, dbl, vp, vp, ctypes.POINTER(dbl), vp,
+        "bse_haydock": ([vp, i32, vp, i32, dbl, i32, vp, i32, dbl, vp, vp, ctypes.POINTER(dbl), vp,
                          ctypes.POINTER(i32), ctypes.POINTER(Stats)], i32),
         "bse_haydock_spectrum": ([i32, i32, vp, vp, dbl, vp, i32, dbl, vp, vp], i32),
         "bse_destroy": ([vp], i32),
@@ -268,32 +268,40 @@ class Solver:
         return omega, X, Y, self.last_stats
 
     def haydock(self, d, n_iter, tol=0.0, freq=None, eta=0.1, precision="fp64"):
-        """Lanczos-Haydock recursion from the dipole vector d (N complex).  Returns
-        (alpha[n], beta[n] f64 device tensors, norm2, chi[nw] c128 device tensor or None,
-        stats dict), n the steps done.  chi(z) at z = freq + i eta is the response
+        """Lanczos-Haydock recursion from dipole vectors d: (N,) or (nd, N) complex, nd >= 1
+        advancing together (up to four per read of the triangles).  Returns (alpha, beta f64
+        device tensors, norm2, chi c128 device tensor or None, stats dict) with shapes
+        (nd, n), (nd, n), (nd,), (nd, nw) -- or (n,), (n,), float, (nw,) for a 1-D d -- where n
+        is the number of steps done.  chi(z) at z = freq + i eta is the response
         d^H (z - A)^{-1} d (TDA) or q^H Omega (z - H)^{-1} q, q = [d; conj(d)] (PH).
         precision: "fp64", "hi64" (FP64 arithmetic on the complex64 hi triangles) or "fp32"."""
         dev = self.device
-        d = d.to(device=dev, dtype=torch.complex128).contiguous()
-        alpha = torch.zeros(int(n_iter), dtype=torch.float64, device=dev)
-        beta = torch.zeros(int(n_iter), dtype=torch.float64, device=dev)
+        single = d.dim() == 1
+        d = d.to(device=dev, dtype=torch.complex128).reshape(-1, self.n).contiguous()  # row q = dipole q
+        nd = d.shape[0]
+        alpha = torch.zeros((nd, int(n_iter)), dtype=torch.float64, device=dev)
+        beta = torch.zeros((nd, int(n_iter)), dtype=torch.float64, device=dev)
         chi = None
         nw = 0
         if freq is not None:
             freq = freq.to(device=dev, dtype=torch.float64).contiguous()
             nw = freq.numel()
-            chi = torch.empty(nw, dtype=torch.complex128, device=dev)
+            chi = torch.empty((nd, nw), dtype=torch.complex128, device=dev)
         prec = {"fp64": PREC_FP64, "hi64": PREC_HI_FP64, "fp32": PREC_MIXED}[precision]
-        norm2 = ctypes.c_double(0.0)
+        norm2 = (ctypes.c_double * nd)()
         done = ctypes.c_int32(0)
         stats = Stats()
         with torch.cuda.device(dev):
-            st = load_library().bse_haydock(self._h, _dev_ptr(d), int(n_iter), float(tol), prec, _dev_ptr(freq),
-                                            nw, float(eta), _dev_ptr(alpha), _dev_ptr(beta), ctypes.byref(norm2),
-                                            _dev_ptr(chi), ctypes.byref(done), ctypes.byref(stats))
+            st = load_library().bse_haydock(self._h, nd, _dev_ptr(d), int(n_iter), float(tol), prec,
+                                            _dev_ptr(freq), nw, float(eta), _dev_ptr(alpha), _dev_ptr(beta),
+                                            norm2, _dev_ptr(chi), ctypes.byref(done), ctypes.byref(stats))
         self._check(st, "bse_haydock")
         n = done.value
-        return alpha[:n], beta[:n], norm2.value, chi, stats.as_dict()
+        alpha, beta = alpha[:, :n], beta[:, :n]
+        nn = [norm2[q] for q in range(nd)]
+        if single:
+            return alpha[0], beta[0], nn[0], None if chi is None else chi[0], stats.as_dict()
+        return alpha, beta, nn, chi, stats.as_dict()
 
     def strength(self, g, comps):
         """Scalars Re<G, C_q> of L = sum_c g_c omega_c for components given as

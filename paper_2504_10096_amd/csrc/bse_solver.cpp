@@ -1792,11 +1792,12 @@ bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse
   return BSE_OK;
 }
 
-bse_status bse_haydock(bse_handle h, const void* d, int32_t max_iter, double tol, bse_precision precision,
-                       const double* freq, int32_t nw, double eta, double* alpha, double* beta, double* norm2,
-                       void* chi, int32_t* n_iter, bse_stats* stats) {
+bse_status bse_haydock(bse_handle h, int32_t nd, const void* d, int32_t max_iter, double tol,
+                       bse_precision precision, const double* freq, int32_t nw, double eta, double* alpha,
+                       double* beta, double* norm2, void* chi, int32_t* n_iter, bse_stats* stats) {
   if (!h) return BSE_ERR_INVALID_ARG;
   const double t0 = now_ms();
+  if (nd < 1) return fail(h, BSE_ERR_INVALID_ARG, "nd must be at least 1");
   if (!d || !alpha || !beta || !norm2 || !n_iter) return fail(h, BSE_ERR_INVALID_ARG, "null argument");
   if (max_iter < 1) return fail(h, BSE_ERR_INVALID_ARG, "max_iter must be at least 1");
   if (!(tol >= 0.0)) return fail(h, BSE_ERR_INVALID_ARG, "tol must be >= 0");
@@ -1821,24 +1822,28 @@ bse_status bse_haydock(bse_handle h, const void* d, int32_t max_iter, double tol
   S.n = n;
   S.ld = round_up(n, 64);
   S.s = h->stream;
+  // ring of three stages; stage t of dipole q in column t nd + q (the nd vectors of a
+  // stage are adjacent, so one multi-vector pass serves a group of them)
   const size_t col = sizeof(double2) * (size_t)S.ld;
   DevBuf bV, bP, bPart, bH, bRed, bFlag, bN0;
   struct {
     DevBuf* b;
     size_t bytes;
   } req[] = {
-      {&bV, col * 3},
-      {&bP, ph ? col * 3 : 0},
+      {&bV, col * 3 * nd},
+      {&bP, ph ? col * 3 * nd : 0},
       {&bPart, sizeof(double2) * (size_t)bse::nchunks(n) * 2},
-      {&bH, sizeof(double2) * 2},
+      {&bH, sizeof(double2) * 2 * nd},
       {&bRed, sizeof(double) * ((size_t)bse::nchunks(n) + 8)},
       {&bFlag, sizeof(int) * 4},
-      {&bN0, sizeof(double) * 2},
+      {&bN0, sizeof(double) * nd},
   };
   for (auto& r : req) {
     if (r.bytes == 0) continue;
     HIP_TRY(h, hipMalloc(&r.b->p, r.bytes));
   }
+  if (nd > 1)
+    if (bse_status e = ensure_mhpart(h)) return e;
   for (int q = 0; q < 64; ++q) {
     hipEvent_t e;
     HIP_TRY(h, hipEventCreate(&e));
@@ -1851,72 +1856,102 @@ bse_status bse_haydock(bse_handle h, const void* d, int32_t max_iter, double tol
   double* red = (double*)bRed.p;
   int* flag = (int*)bFlag.p;
   double* n0 = (double*)bN0.p;
-  HIP_TRY(h, hipMemsetAsync(V, 0, col * 3, S.s));
-  if (ph) HIP_TRY(h, hipMemsetAsync(P, 0, col * 3, S.s));
+  HIP_TRY(h, hipMemsetAsync(V, 0, col * 3 * nd, S.s));
+  if (ph) HIP_TRY(h, hipMemsetAsync(P, 0, col * 3 * nd, S.s));
   HIP_TRY(h, hipMemsetAsync(flag, 0, sizeof(int) * 4, S.s));
-  HIP_TRY(h, hipMemcpyAsync(V, d, sizeof(double2) * (size_t)n, hipMemcpyDeviceToDevice, S.s));
+  HIP_TRY(h, bse::copy_cols((const double2*)d, n, V, S.ld, n, nd, S.s));
   bse_status st;
-  // first vector: d / ||d|| (TDA), d / sqrt(<d, K1 d>) with its K1 image (PH)
-  if (ph && (st = pass(S, ar, 1, V, P))) return st;
-  HIP_TRY(h, bse::normalize(V, ph ? P : nullptr, n, nullptr, nullptr, 0, nullptr, n0, 0, flag, red, S.s));
-  double nrm = 0.0;
+  auto stage = [&](double2* base, int j) { return base + (size_t)(((j % 3) + 3) % 3) * nd * S.ld; };
+  // out[:, q] = K(v[:, q]) for the nd columns, up to four per read of the triangles
+  auto apply = [&](int op, const double2* v, double2* out) -> bse_status {
+    for (int q0 = 0; q0 < nd; q0 += 4) {
+      const int g = std::min(4, nd - q0);
+      if (bse_status e = passes_n(S, ar, op, g, v + (size_t)q0 * S.ld, out + (size_t)q0 * S.ld)) return e;
+    }
+    return BSE_OK;
+  };
+  // first vectors: d / ||d|| (TDA), d / sqrt(<d, K1 d>) with their K1 images (PH)
+  if (ph && (st = apply(1, V, P))) return st;
+  for (int q = 0; q < nd; ++q)
+    HIP_TRY(h, bse::normalize(V + (size_t)q * S.ld, ph ? P + (size_t)q * S.ld : nullptr, n, nullptr, nullptr, 0,
+                              nullptr, n0 + q, 0, flag, red, S.s));
+  std::vector<double> nrm(nd);
   int fl = 0;
-  HIP_TRY(h, hipMemcpyAsync(&nrm, n0, sizeof(double), hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, hipMemcpyAsync(nrm.data(), n0, sizeof(double) * nd, hipMemcpyDeviceToHost, S.s));
   HIP_TRY(h, hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, S.s));
   HIP_TRY(h, hipStreamSynchronize(S.s));
   if (fl == 1) return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "<d, K1 d> < 0: M is not positive definite");
-  if (fl == 2 || !std::isfinite(nrm)) return fail(h, BSE_ERR_NONFINITE, "non-finite dipole vector");
-  if (!(nrm > 0.0)) return fail(h, BSE_ERR_INVALID_ARG, "the dipole vector is zero");
-  const double scale = (ph ? 2.0 : 1.0) * nrm * nrm;
-  *norm2 = nrm * nrm;
+  for (int q = 0; q < nd; ++q) {
+    if (fl == 2 || !std::isfinite(nrm[q])) return fail(h, BSE_ERR_NONFINITE, "non-finite dipole vector");
+    if (!(nrm[q] > 0.0)) return fail(h, BSE_ERR_INVALID_ARG, "a dipole vector is zero");
+    norm2[q] = nrm[q] * nrm[q];
+  }
   std::vector<double2> prev_chi, cur_chi;
   int done = 0;
-  auto col_at = [&](double2* base, int j) { return base + (size_t)(((j % 3) + 3) % 3) * S.ld; };
+  auto spectra = [&](int nit) -> bse_status {
+    for (int q = 0; q < nd; ++q)
+      HIP_TRY(h, bse::cfrac(ph ? 1 : 0, nit, alpha + (size_t)q * max_iter, beta + (size_t)q * max_iter,
+                            (ph ? 2.0 : 1.0) * norm2[q], freq, nw, eta, (double2*)chi + (size_t)q * nw, S.s));
+    return BSE_OK;
+  };
   for (int j = 0; j < max_iter; ++j) {
-    double2 *v = col_at(V, j), *vp = col_at(V, j - 1), *vn = col_at(V, j + 1);
+    double2 *v = stage(V, j), *vp = stage(V, j - 1), *vn = stage(V, j + 1);
     // TDA: w = A v_j; PH: w = K2 p_j = K2 K1 u_j
-    if ((st = pass(S, ar, ph ? 2 : 0, ph ? col_at(P, j) : v, vn))) return st;
-    // coefficients against the previous vector and the current one (K1 inner
-    // product through P for PH), real; subtract them
-    const double2* g0 = ph ? col_at(P, j - 1) : vp;
-    const double2* g1 = ph ? col_at(P, j) : v;
-    if (j == 0) {
-      HIP_TRY(h, bse::cdot(g1, 1, nullptr, 0, S.ld, vn, n, part, Hc, S.s));
-      HIP_TRY(h, bse::cgemv_sub(v, 1, nullptr, 0, nullptr, nullptr, S.ld, Hc, 1, vn, nullptr, n, S.s));
-    } else {
-      HIP_TRY(h, bse::cdot(g0, 1, g1, 1, S.ld, vn, n, part, Hc, S.s));
-      HIP_TRY(h, bse::cgemv_sub(vp, 1, v, 1, nullptr, nullptr, S.ld, Hc, 1, vn, nullptr, n, S.s));
+    if ((st = apply(ph ? 2 : 0, ph ? stage(P, j) : v, vn))) return st;
+    // per dipole: coefficients against the previous vector and the current one (the K1
+    // inner product through P for PH), real; subtract them
+    for (int q = 0; q < nd; ++q) {
+      const size_t o = (size_t)q * S.ld;
+      const double2* g0 = (ph ? stage(P, j - 1) : vp) + o;
+      const double2* g1 = (ph ? stage(P, j) : v) + o;
+      double2* hq = Hc + 2 * q;
+      if (j == 0) {
+        HIP_TRY(h, bse::cdot(g1, 1, nullptr, 0, S.ld, vn + o, n, part, hq, S.s));
+        HIP_TRY(h, bse::cgemv_sub(v + o, 1, nullptr, 0, nullptr, nullptr, S.ld, hq, 1, vn + o, nullptr, n, S.s));
+      } else {
+        HIP_TRY(h, bse::cdot(g0, 1, g1, 1, S.ld, vn + o, n, part, hq, S.s));
+        HIP_TRY(h, bse::cgemv_sub(vp + o, 1, v + o, 1, nullptr, nullptr, S.ld, hq, 1, vn + o, nullptr, n, S.s));
+      }
     }
     double2* zn = nullptr;
     if (ph) {
-      zn = col_at(P, j + 1);
-      if ((st = pass(S, ar, 1, vn, zn))) return st;  // K1 w
+      zn = stage(P, j + 1);
+      if ((st = apply(1, vn, zn))) return st;  // K1 w
     }
     // alpha_j = Re h[current], beta_j = ||w|| (TDA) or sqrt(<w, K1 w>) (PH)
-    HIP_TRY(h, bse::normalize(vn, zn, n, Hc, nullptr, j == 0 ? 0 : 1, alpha, beta, j, flag, red, S.s));
+    for (int q = 0; q < nd; ++q) {
+      const size_t o = (size_t)q * S.ld;
+      HIP_TRY(h, bse::normalize(vn + o, zn ? zn + o : nullptr, n, Hc + 2 * q, nullptr, j == 0 ? 0 : 1,
+                                alpha + (size_t)q * max_iter, beta + (size_t)q * max_iter, j, flag, red, S.s));
+    }
     done = j + 1;
     const bool last = done == max_iter;
     if (tol > 0.0 && (done % 20 == 0 || last)) {
-      HIP_TRY(h, bse::cfrac(ph ? 1 : 0, done, alpha, beta, scale, freq, nw, eta, (double2*)chi, S.s));
-      cur_chi.resize(nw);
-      HIP_TRY(h, hipMemcpyAsync(cur_chi.data(), chi, sizeof(double2) * nw, hipMemcpyDeviceToHost, S.s));
+      if ((st = spectra(done))) return st;
+      cur_chi.resize((size_t)nw * nd);
+      HIP_TRY(h, hipMemcpyAsync(cur_chi.data(), chi, sizeof(double2) * cur_chi.size(), hipMemcpyDeviceToHost, S.s));
       HIP_TRY(h, hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, S.s));
       HIP_TRY(h, hipStreamSynchronize(S.s));
       harvest_events(S);
       if (fl == 1) return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "<w, K1 w> < 0: M is not positive definite");
       if (fl == 2) return fail(h, BSE_ERR_NONFINITE, "non-finite value in the recurrence");
       if (!prev_chi.empty()) {
-        double dm = 0.0, am = 0.0;
-        for (int f = 0; f < nw; ++f) {
-          dm = std::max(dm, fabs(cur_chi[f].y - prev_chi[f].y));
-          am = std::max(am, fabs(cur_chi[f].y));
+        bool conv = true;
+        for (int q = 0; q < nd && conv; ++q) {
+          double dm = 0.0, am = 0.0;
+          for (int f = 0; f < nw; ++f) {
+            const size_t i = (size_t)q * nw + f;
+            dm = std::max(dm, fabs(cur_chi[i].y - prev_chi[i].y));
+            am = std::max(am, fabs(cur_chi[i].y));
+          }
+          conv = dm <= tol * am;
         }
-        if (dm <= tol * am) break;
+        if (conv) break;
       }
       prev_chi.swap(cur_chi);
     }
   }
-  if (grid) HIP_TRY(h, bse::cfrac(ph ? 1 : 0, done, alpha, beta, scale, freq, nw, eta, (double2*)chi, S.s));
+  if (grid && (st = spectra(done))) return st;
   HIP_TRY(h, hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, S.s));
   HIP_TRY(h, hipStreamSynchronize(S.s));
   harvest_events(S);
@@ -1928,13 +1963,13 @@ bse_status bse_haydock(bse_handle h, const void* d, int32_t max_iter, double tol
     stats->passes = S.passes;
     stats->ms_total = now_ms() - t0;
     const bool hi = ar == bse::AR_HI || ar == bse::AR_HI64;
-    stats->bytes_per_pass_fp32 = hi ? bytes_per_pass(h, ar, 1) : 0.0;
-    stats->bytes_per_pass_fp64 = hi ? 0.0 : bytes_per_pass(h, ar, 1);
+    stats->bytes_per_pass_fp32 = hi ? bytes_per_pass(h, ar, std::min(nd, 4)) : 0.0;
+    stats->bytes_per_pass_fp64 = hi ? 0.0 : bytes_per_pass(h, ar, std::min(nd, 4));
     stats->samples_fp32 = S.samples32;
     stats->samples_fp64 = S.samples64;
     stats->ms_block_fp32 = S.ms_blk32;
     stats->ms_block_fp64 = S.ms_blk64;
-    stats->block = 1;
+    stats->block = std::min(nd, 4);
   }
   return BSE_OK;
 }

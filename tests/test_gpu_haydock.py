@@ -189,3 +189,31 @@ def test_errors():
         s.haydock(dev(d), 4, freq=dev(np.linspace(1, 2, 3)), eta=0.0)
     assert e.value.status == bse.ERR_INVALID_ARG
     s.close()
+
+
+@pytest.mark.parametrize("kind", ["tda", "ph"])
+@pytest.mark.parametrize("nd", [3, 5])
+def test_several_dipoles_match_single_runs(kind, nd):
+    """nd dipoles advancing together (groups of up to four per read of the triangles) give
+    the single-dipole recurrences and spectra; the reads are shared."""
+    n = 700
+    ap, bp, _, (lo, hi) = case(kind, n)
+    D = np.stack([synth.dipole(500 + q, n) for q in range(nd)])
+    freq = np.linspace(max(lo, 0.05), hi, 32)
+    s = make_solver(kind, ap, bp, storage="hilo")
+    for prec in ("fp64", "hi64"):
+        al, be, nn, chi, st = s.haydock(dev(D), 40, freq=dev(freq), eta=ETA, precision=prec)
+        groups = (nd + 3) // 4
+        assert st["passes"] == (40 * groups if kind == "tda" else (1 + 2 * 40) * groups)
+        for q in range(nd):
+            a1, b1, n1, c1, _ = s.haydock(dev(D[q]), 40, freq=dev(freq), eta=ETA, precision=prec)
+            assert np.max(np.abs(host(al[q]) - host(a1))) <= 1e-11 * np.max(np.abs(host(a1))), (prec, q)
+            assert np.max(np.abs(host(be[q]) - host(b1))) <= 1e-11 * np.max(np.abs(host(b1))), (prec, q)
+            assert abs(nn[q] - n1) <= 1e-13 * n1
+            assert np.max(np.abs(host(chi[q]) - host(c1))) <= 1e-10 * np.max(np.abs(host(c1))), (prec, q)
+    # and against the oracle's recurrence
+    al, be, nn, _, _ = s.haydock(dev(D), 20)
+    for q in range(nd):
+        ra, rb, rn = oracle_recurrence(kind, ap, bp, D[q], 20)
+        assert np.max(np.abs(host(al[q]) - ra)) <= 1e-11 * np.max(np.abs(ra))
+    s.close()
