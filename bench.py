@@ -138,8 +138,9 @@ def main():
     args = p.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding of the pass is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the solver runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(sharding the pass over GPUs by panels of blocks, with one all-reduce per pass, is not "
+              "implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
