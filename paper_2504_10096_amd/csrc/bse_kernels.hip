@@ -1761,34 +1761,101 @@ __global__ void __launch_bounds__(64) pair_sum_kernel(const double* __restrict__
   res[1] = b;
 }
 
-// Packed gradient, one workgroup per column j of the upper triangle.
+// Packed gradients on 64 x 64 tiles (I, J), I <= J, of the upper triangle:
+//   G_A(i, j) = sum_c w_c (X_ic conj(X_jc) + conj(Y_ic) Y_jc),
+//   G_B(i, j) = sum_c w_c (X_ic conj(Y_jc) + conj(Y_ic) X_jc),
+// written packed (offset i + j (j + 1) / 2) with off-diagonal entries doubled
+// and the diagonal of G_A real.  The k columns pass through LDS in chunks of
+// 8 (the row side pre-multiplied by the weights); thread t owns rows
+// I 64 + (t & 15) + 16 r and columns J 64 + (t >> 4) + 16 q, r, q < 4, so a
+// store of one (r, q) covers 16 consecutive rows of 4 columns per wavefront.
+constexpr int kGT = 64, kGK = 8;
+
 __global__ void __launch_bounds__(kThreads)
-    grad_packed_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, int64_t ld,
-                       const double* __restrict__ wgt, int k, double2* __restrict__ ga,
-                       double2* __restrict__ gb) {
-  const int64_t j = blockIdx.x;
-  const int64_t off = j * (j + 1) / 2;
-  for (int64_t i = threadIdx.x; i <= j; i += kThreads) {
-    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-    for (int c = 0; c < k; ++c) {
-      const double g = wgt[c];
-      const double2 xi = X[(size_t)c * ld + i], xj = X[(size_t)c * ld + j];
-      // X_i conj(X_j)
-      ar += g * (xi.x * xj.x + xi.y * xj.y);
-      ai += g * (xi.y * xj.x - xi.x * xj.y);
-      if (Y) {
-        const double2 yi = Y[(size_t)c * ld + i], yj = Y[(size_t)c * ld + j];
-        // conj(Y_i) Y_j
-        ar += g * (yi.x * yj.x + yi.y * yj.y);
-        ai += g * (yi.x * yj.y - yi.y * yj.x);
-        // X_i conj(Y_j) + conj(Y_i) X_j
-        br += g * ((xi.x * yj.x + xi.y * yj.y) + (yi.x * xj.x + yi.y * xj.y));
-        bi += g * ((xi.y * yj.x - xi.x * yj.y) + (yi.x * xj.y - yi.y * xj.x));
-      }
+    grad_tile_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, int64_t ld,
+                     const double* __restrict__ wgt, int k, int64_t n, double2* __restrict__ ga,
+                     double2* __restrict__ gb) {
+  __shared__ double2 sxi[kGK][kGT], sxj[kGK][kGT], syi[kGK][kGT], syj[kGK][kGT];
+  // tile (I, J) from the linear index over the upper triangle of tiles, column by column
+  const int64_t b = blockIdx.x;
+  int64_t J = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while (J * (J + 1) / 2 > b) --J;
+  while ((J + 1) * (J + 2) / 2 <= b) ++J;
+  const int64_t I = b - J * (J + 1) / 2;
+  const int64_t i0 = I * kGT, j0 = J * kGT;
+  const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
+  const bool ph = Y != nullptr;
+  double ar[4][4], ai[4][4], br[4][4], bi[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ar[r][q] = 0.0;
+      ai[r][q] = 0.0;
+      br[r][q] = 0.0;
+      bi[r][q] = 0.0;
     }
-    const double f = (i == j) ? 1.0 : 2.0;
-    if (ga) ga[off + i] = (i == j) ? make_double2(ar, 0.0) : make_double2(f * ar, f * ai);
-    if (gb) gb[off + i] = make_double2(f * br, f * bi);
+  for (int c0 = 0; c0 < k; c0 += kGK) {
+    // stage the chunk: 8 x 64 entries of each of X_I, X_J (and Y_I, Y_J); two per thread each
+    for (int e = t; e < kGK * kGT; e += kThreads) {
+      const int kk = e / kGT, rr = e % kGT;
+      const int c = c0 + kk;
+      const int64_t ii = i0 + rr, jj = j0 + rr;
+      const bool cin = c < k;
+      const double w = cin ? wgt[c] : 0.0;
+      double2 xi = make_double2(0.0, 0.0), xj = xi, yi = xi, yj = xi;
+      if (cin && ii < n) {
+        xi = X[(size_t)c * ld + ii];
+        if (ph) yi = Y[(size_t)c * ld + ii];
+      }
+      if (cin && jj < n) {
+        xj = X[(size_t)c * ld + jj];
+        if (ph) yj = Y[(size_t)c * ld + jj];
+      }
+      sxi[kk][rr] = make_double2(w * xi.x, w * xi.y);
+      syi[kk][rr] = make_double2(w * yi.x, w * yi.y);
+      sxj[kk][rr] = xj;
+      syj[kk][rr] = yj;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kGK; ++kk) {
+      double2 xi[4], xj[4], yi[4], yj[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        xi[r] = sxi[kk][tr + 16 * r];
+        yi[r] = syi[kk][tr + 16 * r];
+        xj[r] = sxj[kk][tc + 16 * r];
+        yj[r] = syj[kk][tc + 16 * r];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          // X_i conj(X_j) + conj(Y_i) Y_j
+          ar[r][q] += xi[r].x * xj[q].x + xi[r].y * xj[q].y + yi[r].x * yj[q].x + yi[r].y * yj[q].y;
+          ai[r][q] += xi[r].y * xj[q].x - xi[r].x * xj[q].y + yi[r].x * yj[q].y - yi[r].y * yj[q].x;
+          if (ph) {
+            // X_i conj(Y_j) + conj(Y_i) X_j
+            br[r][q] += xi[r].x * yj[q].x + xi[r].y * yj[q].y + yi[r].x * xj[q].x + yi[r].y * xj[q].y;
+            bi[r][q] += xi[r].y * yj[q].x - xi[r].x * yj[q].y + yi[r].x * xj[q].y - yi[r].y * xj[q].x;
+          }
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t j = j0 + tc + 16 * q;
+    if (j >= n) continue;
+    const int64_t off = j * (j + 1) / 2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = i0 + tr + 16 * r;
+      if (i > j) continue;
+      const double f = i == j ? 1.0 : 2.0;
+      if (ga) ga[off + i] = i == j ? make_double2(ar[r][q], 0.0) : make_double2(f * ar[r][q], f * ai[r][q]);
+      if (gb) gb[off + i] = make_double2(f * br[r][q], f * bi[r][q]);
+    }
   }
 }
 
@@ -2258,8 +2325,9 @@ hipError_t quad_diag(const double2* X, const double2* Y, int64_t ld, const doubl
 
 hipError_t grad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
                        int64_t n, double2* ga, double2* gb, hipStream_t s) {
-  hipLaunchKernelGGL(grad_packed_kernel, dim3((unsigned)n), dim3(kThreads), 0, s, X, Y, ld, wgt, k,
-                     ga, gb);
+  const int64_t nt = (n + kGT - 1) / kGT;
+  hipLaunchKernelGGL(grad_tile_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(kThreads), 0, s, X, Y, ld, wgt, k,
+                     n, ga, gb);
   return hipGetLastError();
 }
 

@@ -408,6 +408,30 @@ def test_backward_tda_parity():
     s.close()
 
 
+@pytest.mark.parametrize("kind", ["tda", "ph"])
+def test_backward_many_tiles_and_chunks(kind):
+    # 11 x 11 output tiles of 64 (ragged last), k = 20 = two full chunks of 8 and a partial one
+    n, k = 700, 20
+    m = synth.Matrix(n, 43, ph=kind == "ph")
+    ap = m.pack_host(0)
+    bp = m.pack_host(1) if kind == "ph" else None
+    s = make_solver(kind, ap, bp)
+    lam, X, Y, _ = s.solve(k, 1e-10)
+    g = synth.loss_weights(44, k)
+    ga, gb = s.backward(torch.as_tensor(g))
+    if kind == "tda":
+        ref = oracle.grad_tda(host(X).T, g)
+        assert np.max(np.abs(host(ga) - ref)) < 1e-12 * np.max(np.abs(ref))
+    else:
+        ra, rb = oracle.grad_ph(host(X).T, host(Y).T, g)
+        assert np.max(np.abs(host(ga) - ra)) < 1e-12 * np.max(np.abs(ra))
+        assert np.max(np.abs(host(gb) - rb)) < 1e-12 * np.max(np.abs(rb))
+        # one block at a time
+        ga_only, gb_none = s.backward(torch.as_tensor(g), want_b=False)
+        assert gb_none is None and torch.equal(ga_only, ga)
+    s.close()
+
+
 def test_backward_ph_parity():
     n, k = 250, 6
     rng = np.random.default_rng(11)
