@@ -185,8 +185,11 @@ hipError_t resid_norms(const double2* out, const double2* v, int cj, double sgn_
 hipError_t grad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
                        int64_t n, double2* ga, double2* gb, hipStream_t s);
 
-// part[j] (j < n) = Re sum_{i<=j} conj(g_ij) C_ij for a packed component C of
-// block A (target_b 0) or B (1); g as in grad_packed, formed on the fly.
+// part[t] (t < quad_packed_parts(n), one per 64 x 64 tile of the upper
+// triangle) = Re sum over the tile's entries i <= j of conj(g_ij) C_ij for a
+// packed component C of block A (target_b 0) or B (1); g as in grad_packed,
+// formed on the fly.
+int64_t quad_packed_parts(int64_t n);
 hipError_t quad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k, int64_t n,
                        const double2* C, int target_b, double* part, hipStream_t s);
 

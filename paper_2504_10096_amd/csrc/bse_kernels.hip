@@ -1769,13 +1769,20 @@ __global__ void __launch_bounds__(64) pair_sum_kernel(const double* __restrict__
 // 8 (the row side pre-multiplied by the weights); thread t owns rows
 // I 64 + (t & 15) + 16 r and columns J 64 + (t >> 4) + 16 q, r, q < 4, so a
 // store of one (r, q) covers 16 consecutive rows of 4 columns per wavefront.
+// MODE 0 writes G_A (ga) and G_B (gb); MODE 1 / 2 instead accumulate, over the
+// tile's entries, Re(conj(g_ij) C_ij) for the packed gradient entry g of G_A /
+// G_B (doubled off the diagonal) and a packed component C of that block, and
+// store the tile's sum in part[tile] (the other block's sums are not formed).
 constexpr int kGT = 64, kGK = 8;
 
+template <int MODE>
 __global__ void __launch_bounds__(kThreads)
     grad_tile_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, int64_t ld,
                      const double* __restrict__ wgt, int k, int64_t n, double2* __restrict__ ga,
-                     double2* __restrict__ gb) {
+                     double2* __restrict__ gb, const double2* __restrict__ C, double* __restrict__ part) {
   __shared__ double2 sxi[kGK][kGT], sxj[kGK][kGT], syi[kGK][kGT], syj[kGK][kGT];
+  __shared__ double sred[4];
+  constexpr bool wantA = MODE != 2, wantB = MODE != 1;
   // tile (I, J) from the linear index over the upper triangle of tiles, column by column
   const int64_t b = blockIdx.x;
   int64_t J = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
@@ -1831,10 +1838,12 @@ __global__ void __launch_bounds__(kThreads)
       for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          // X_i conj(X_j) + conj(Y_i) Y_j
-          ar[r][q] += xi[r].x * xj[q].x + xi[r].y * xj[q].y + yi[r].x * yj[q].x + yi[r].y * yj[q].y;
-          ai[r][q] += xi[r].y * xj[q].x - xi[r].x * xj[q].y + yi[r].x * yj[q].y - yi[r].y * yj[q].x;
-          if (ph) {
+          if (wantA) {
+            // X_i conj(X_j) + conj(Y_i) Y_j
+            ar[r][q] += xi[r].x * xj[q].x + xi[r].y * xj[q].y + yi[r].x * yj[q].x + yi[r].y * yj[q].y;
+            ai[r][q] += xi[r].y * xj[q].x - xi[r].x * xj[q].y + yi[r].x * yj[q].y - yi[r].y * yj[q].x;
+          }
+          if (wantB && ph) {
             // X_i conj(Y_j) + conj(Y_i) X_j
             br[r][q] += xi[r].x * yj[q].x + xi[r].y * yj[q].y + yi[r].x * xj[q].x + yi[r].y * xj[q].y;
             bi[r][q] += xi[r].y * yj[q].x - xi[r].x * yj[q].y + yi[r].x * xj[q].y - yi[r].y * xj[q].x;
@@ -1843,6 +1852,7 @@ __global__ void __launch_bounds__(kThreads)
     }
     __syncthreads();
   }
+  double acc = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t j = j0 + tc + 16 * q;
@@ -1853,52 +1863,23 @@ __global__ void __launch_bounds__(kThreads)
       const int64_t i = i0 + tr + 16 * r;
       if (i > j) continue;
       const double f = i == j ? 1.0 : 2.0;
-      if (ga) ga[off + i] = i == j ? make_double2(ar[r][q], 0.0) : make_double2(f * ar[r][q], f * ai[r][q]);
-      if (gb) gb[off + i] = make_double2(f * br[r][q], f * bi[r][q]);
+      if (MODE == 0) {
+        if (ga) ga[off + i] = i == j ? make_double2(ar[r][q], 0.0) : make_double2(f * ar[r][q], f * ai[r][q]);
+        if (gb) gb[off + i] = make_double2(f * br[r][q], f * bi[r][q]);
+      } else {
+        const double2 cv = C[off + i];
+        const double gr = MODE == 1 ? ar[r][q] : br[r][q];
+        const double gi = MODE == 1 ? (i == j ? 0.0 : ai[r][q]) : bi[r][q];
+        acc += f * (gr * cv.x + gi * cv.y);
+      }
     }
+  }
+  if (MODE != 0) {
+    acc = block_sum(acc, sred);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
   }
 }
 
-// part[j] = Re sum_{i <= j} conj(g_ij) C_ij over column j of a packed
-// component C, with g the packed gradient entry (off-diagonal 2 G_ij, diagonal
-// G_ii) of block A (target_b == 0) or B (target_b == 1), formed on the fly.
-__global__ void __launch_bounds__(kThreads)
-    quad_packed_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, int64_t ld,
-                       const double* __restrict__ wgt, int k, const double2* __restrict__ C, int target_b,
-                       double* __restrict__ part) {
-  __shared__ double sh[4];
-  const int64_t j = blockIdx.x;
-  const int64_t off = j * (j + 1) / 2;
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i <= j; i += kThreads) {
-    double gr = 0.0, gi = 0.0;
-    for (int c = 0; c < k; ++c) {
-      const double g = wgt[c];
-      const double2 xi = X[(size_t)c * ld + i], xj = X[(size_t)c * ld + j];
-      if (!target_b) {
-        gr += g * (xi.x * xj.x + xi.y * xj.y);
-        gi += g * (xi.y * xj.x - xi.x * xj.y);
-        if (Y) {
-          const double2 yi = Y[(size_t)c * ld + i], yj = Y[(size_t)c * ld + j];
-          gr += g * (yi.x * yj.x + yi.y * yj.y);
-          gi += g * (yi.x * yj.y - yi.y * yj.x);
-        }
-      } else {
-        const double2 yi = Y[(size_t)c * ld + i], yj = Y[(size_t)c * ld + j];
-        gr += g * ((xi.x * yj.x + xi.y * yj.y) + (yi.x * xj.x + yi.y * xj.y));
-        gi += g * ((xi.y * yj.x - xi.x * yj.y) + (yi.x * xj.y - yi.y * xj.x));
-      }
-    }
-    const double f = (i == j) ? 1.0 : 2.0;
-    const double2 cv = C[off + i];
-    if (i == j && !target_b)
-      acc += gr * cv.x;
-    else
-      acc += f * (gr * cv.x + gi * cv.y);
-  }
-  acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[j] = acc;
-}
 
 // part[block] = sum_i d_i sum_c wgt_c (|X_ci|^2 + |Y_ci|^2) over the block's rows.
 __global__ void __launch_bounds__(kThreads)
@@ -2311,8 +2292,13 @@ hipError_t resid_norms(const double2* out, const double2* v, int cj, double sgn_
 
 hipError_t quad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k, int64_t n,
                        const double2* C, int target_b, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(quad_packed_kernel, dim3((unsigned)n), dim3(kThreads), 0, s, X, Y, ld, wgt, k, C,
-                     target_b, part);
+  const dim3 grid((unsigned)quad_packed_parts(n));
+  if (target_b)
+    hipLaunchKernelGGL(grad_tile_kernel<2>, grid, dim3(kThreads), 0, s, X, Y, ld, wgt, k, n, nullptr, nullptr, C,
+                       part);
+  else
+    hipLaunchKernelGGL(grad_tile_kernel<1>, grid, dim3(kThreads), 0, s, X, Y, ld, wgt, k, n, nullptr, nullptr, C,
+                       part);
   return hipGetLastError();
 }
 
@@ -2326,9 +2312,14 @@ hipError_t quad_diag(const double2* X, const double2* Y, int64_t ld, const doubl
 hipError_t grad_packed(const double2* X, const double2* Y, int64_t ld, const double* wgt, int k,
                        int64_t n, double2* ga, double2* gb, hipStream_t s) {
   const int64_t nt = (n + kGT - 1) / kGT;
-  hipLaunchKernelGGL(grad_tile_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(kThreads), 0, s, X, Y, ld, wgt, k,
-                     n, ga, gb);
+  hipLaunchKernelGGL(grad_tile_kernel<0>, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(kThreads), 0, s, X, Y, ld, wgt,
+                     k, n, ga, gb, nullptr, nullptr);
   return hipGetLastError();
+}
+
+int64_t quad_packed_parts(int64_t n) {
+  const int64_t nt = (n + kGT - 1) / kGT;
+  return nt * (nt + 1) / 2;
 }
 
 hipError_t cfrac(int ph, int n, const double* alpha, const double* beta, double scale, const double* freq,

@@ -1672,7 +1672,7 @@ bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse
     if (comps[q].form == BSE_COMP_LOWRANK) maxrank = std::max<int64_t>(maxrank, comps[q].rank);
   DevBuf wgt, part, tmp, tmp2, zero, hv, cpart;
   HIP_TRY(h, hipMalloc(&wgt.p, sizeof(double) * k));
-  HIP_TRY(h, hipMalloc(&part.p, sizeof(double) * std::max<int64_t>(n, nch * k)));
+  HIP_TRY(h, hipMalloc(&part.p, sizeof(double) * std::max<int64_t>({n, nch * k, bse::quad_packed_parts(n)})));
   HIP_TRY(h, hipMalloc(&tmp.p, sizeof(double2) * n));
   HIP_TRY(h, hipMalloc(&tmp2.p, sizeof(double2) * n));
   HIP_TRY(h, hipMalloc(&zero.p, sizeof(double2) * n));
@@ -1712,8 +1712,8 @@ bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse
     if (c.form == BSE_COMP_PACKED) {
       HIP_TRY(h, bse::quad_packed(h->X, ph ? h->Y : nullptr, n, (const double*)wgt.p, k, n,
                                   (const double2*)c.data, tb ? 1 : 0, (double*)part.p, st));
-      std::vector<double> ph_(n);
-      HIP_TRY(h, hipMemcpyAsync(ph_.data(), part.p, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+      std::vector<double> ph_(bse::quad_packed_parts(n));
+      HIP_TRY(h, hipMemcpyAsync(ph_.data(), part.p, sizeof(double) * ph_.size(), hipMemcpyDeviceToHost, st));
       HIP_TRY(h, hipStreamSynchronize(st));
       for (double v : ph_) sum += v;
     } else if (c.form == BSE_COMP_DIAG) {
