@@ -1,0 +1,242 @@
+"""The solver's driver (bse_solver.cpp) on the CPU: the same source compiled with
+g++ against a host backend of the kernel launchers (tests/native/host_backend.cpp,
+plain loops), so that restarts, the FP64 refinement, both pseudo-Hermitian
+variants, the Haydock recurrence and every error path run in the CPU suite.
+Results are checked against the oracle.  Failure injection is forced from the
+host (indefinite M, a NaN entry, a one-restart budget, invalid arguments); no
+GPU is involved.  This backend is test infrastructure, not a fallback: the
+package never loads it."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.haydock as hy
+import synth
+from conftest import pack_upper, random_herm, random_sym
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_2504_10096_amd", "csrc")
+
+OK, INVALID, OOM, DEVICE, NOT_PD, NOT_CONV, NONFINITE, BAD_STATE = range(8)
+vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("ncv", i32), ("keep", i32), ("max_restarts", i32), ("precision", i32), ("switch_tol", dbl),
+                ("start_seed", ctypes.c_uint64), ("fp32_arith", i32), ("block", i32), ("refine_start", i32),
+                ("variant", i32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_converged", i32), ("restarts", i32), ("steps_fp32", i64), ("steps_fp64", i64),
+                ("passes", i64), ("ms_total", dbl), ("ms_fp32_phase", dbl), ("ms_fp64_phase", dbl),
+                ("ms_final", dbl), ("max_rel_residual", dbl), ("bytes_per_pass_fp32", dbl),
+                ("bytes_per_pass_fp64", dbl), ("samples_fp32", i64), ("samples_fp64", i64),
+                ("ms_block_fp32", dbl), ("ms_block_fp64", dbl), ("samples_fused", i64), ("ms_block_fused", dbl),
+                ("fused_vectors", i64), ("block", i32), ("reserved_", i32), ("ms_gemm", dbl), ("gemm_flops", dbl),
+                ("ms_dense_form", dbl), ("ms_dense_factor", dbl), ("ms_dense_eig", dbl)]
+
+
+@pytest.fixture(scope="module")
+def lib(tmp_path_factory):
+    so = str(tmp_path_factory.mktemp("hostdrv") / "libbse_hostdrv.so")
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-fcx-limited-range", "-w", os.path.join(HERE, "native", "host_backend.cpp"),
+           os.path.join(CSRC, "bse_solver.cpp"), os.path.join(CSRC, "bse_smalleig.cpp"), "-o", so,
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib", "-Wl,-Bsymbolic"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("host compiler or ROCm libraries unavailable: " + r.stderr[-300:])
+    L = ctypes.CDLL(so)
+    L.bse_create.argtypes = [ctypes.POINTER(vp), i32, i64, i32, vp]
+    L.bse_set_packed.argtypes = [vp, i32, i64, i64, vp, i32]
+    L.bse_solve.argtypes = [vp, i32, dbl, ctypes.POINTER(Opts), vp, vp, vp, ctypes.POINTER(Stats)]
+    L.bse_haydock.argtypes = [vp, i32, vp, i32, dbl, i32, vp, i32, dbl, vp, vp, ctypes.POINTER(dbl), vp,
+                              ctypes.POINTER(i32), ctypes.POINTER(Stats)]
+    L.bse_backward.argtypes = [vp, vp, vp, vp]
+    L.bse_destroy.argtypes = [vp]
+    L.bse_last_error.argtypes = [vp]
+    L.bse_last_error.restype = ctypes.c_char_p
+    return L
+
+
+class Handle:
+    def __init__(self, L, kind, ap, bp=None, storage=0):
+        self.L, self.kind = L, kind
+        self.n = int(round(((8 * len(ap) + 1) ** 0.5 - 1) / 2))
+        self.h = vp()
+        assert L.bse_create(ctypes.byref(self.h), kind, self.n, storage, None) == OK
+        self.keep = [np.ascontiguousarray(ap, dtype=np.complex128)]
+        assert L.bse_set_packed(self.h, 0, 0, self.n, self.keep[0].ctypes.data, 1) == OK
+        if bp is not None:
+            self.keep.append(np.ascontiguousarray(bp, dtype=np.complex128))
+            assert L.bse_set_packed(self.h, 1, 0, self.n, self.keep[1].ctypes.data, 1) == OK
+
+    def solve(self, k, tol, **kw):
+        om = np.zeros(k)
+        X = np.zeros((k, self.n), complex)
+        Y = np.zeros((k, self.n), complex) if self.kind else None
+        o = Opts(kw.get("ncv", 0), kw.get("keep", 0), kw.get("max_restarts", 0), kw.get("precision", 0), 0.0, 1,
+                 kw.get("fp32_arith", 0), kw.get("block", 0), 0, kw.get("variant", 0))
+        st = Stats()
+        rc = self.L.bse_solve(self.h, k, tol, ctypes.byref(o), om.ctypes.data, X.ctypes.data,
+                              None if Y is None else Y.ctypes.data, ctypes.byref(st))
+        return rc, om, X.T, None if Y is None else Y.T, st
+
+    def haydock(self, D, n_iter):
+        D = np.ascontiguousarray(np.atleast_2d(D), dtype=np.complex128)
+        nd = D.shape[0]
+        al, be = np.zeros((nd, n_iter)), np.zeros((nd, n_iter))
+        nn, done, st = (dbl * nd)(), i32(0), Stats()
+        rc = self.L.bse_haydock(self.h, nd, D.ctypes.data, n_iter, 0.0, 0, None, 0, 0.1, al.ctypes.data,
+                                be.ctypes.data, nn, None, ctypes.byref(done), ctypes.byref(st))
+        return rc, al[:, :done.value], be[:, :done.value], list(nn), st
+
+    def error(self):
+        return self.L.bse_last_error(self.h).decode()
+
+    def close(self):
+        self.L.bse_destroy(self.h)
+
+
+def ph_case(n=120, seed=5):
+    m = synth.Matrix(n, seed, ph=True)
+    return m.pack_host(0), m.pack_host(1)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("storage,precision,fp32,tol", [(0, 0, 0, 1e-10), (1, 1, 0, 1e-8), (1, 1, 1, 1e-8)])
+def test_ph_solve_matches_oracle(lib, variant, storage, precision, fp32, tol):
+    ap, bp = ph_case()
+    h = Handle(lib, 1, ap, bp, storage)
+    rc, om, X, Y, st = h.solve(5, tol, variant=variant, precision=precision, fp32_arith=fp32, ncv=32)
+    assert rc == OK, h.error()
+    ref, _, _ = oracle.ph(ap, bp, 5, vectors=False)
+    assert np.max(np.abs(om - ref) / ref) < tol
+    assert oracle.residual_ph(ap, bp, om, X, Y).max() <= tol * 1.01
+    nrm = np.sum(np.abs(X) ** 2, axis=0) - np.sum(np.abs(Y) ** 2, axis=0)
+    assert np.max(np.abs(nrm - 1)) < 1e-9
+    assert st.restarts >= 1 and st.passes > 0
+    h.close()
+
+
+@pytest.mark.parametrize("block", [1, 2])
+def test_tda_solve_matches_oracle(lib, block):
+    m = synth.Matrix(150, 6, ph=False)
+    ap = m.pack_host(0)
+    h = Handle(lib, 0, ap)
+    rc, lam, X, _, st = h.solve(6, 1e-10, block=block, ncv=32)
+    assert rc == OK, h.error()
+    ref, _ = oracle.tda(ap, 6, vectors=False)
+    assert np.max(np.abs(lam - ref) / np.abs(ref)) < 1e-10
+    assert oracle.residual_tda(ap, lam, X).max() <= 1e-10 * 1.01
+    assert st.block == block
+    h.close()
+
+
+def test_backward_through_host_driver(lib):
+    ap, bp = ph_case(80, 7)
+    h = Handle(lib, 1, ap, bp)
+    rc, om, X, Y, _ = h.solve(4, 1e-12)
+    assert rc == OK
+    g = synth.loss_weights(3, 4)
+    m = len(ap)
+    ga, gb = np.zeros(m, complex), np.zeros(m, complex)
+    assert lib.bse_backward(h.h, g.ctypes.data, ga.ctypes.data, gb.ctypes.data) == OK
+    ra, rb = oracle.grad_ph(X, Y, g)
+    assert np.max(np.abs(ga - ra)) < 1e-12 * np.max(np.abs(ra))
+    assert np.max(np.abs(gb - rb)) < 1e-12 * np.max(np.abs(rb))
+    h.close()
+
+
+def test_not_positive_definite_is_reported(lib):
+    n = 60
+    A = np.diag(np.arange(1.0, n + 1)).astype(complex)
+    B = np.zeros((n, n), dtype=complex)
+    B[0, 0] = 1.6  # ||B|| > lambda_min(A): M indefinite
+    for variant in (0, 1):
+        h = Handle(lib, 1, pack_upper(A), pack_upper(B))
+        rc, *_ = h.solve(4, 1e-10, variant=variant)
+        assert rc == NOT_PD, (variant, rc, h.error())
+        d = np.zeros(n, complex)
+        d[0] = 1j  # <d, K1 d> = 1 - 1.6 < 0
+        rc, *_ = h.haydock(d, 4)
+        assert rc == NOT_PD
+        h.close()
+
+
+def test_not_converged_returns_best(lib):
+    m = synth.Matrix(200, 9, ph=False)
+    ap = m.pack_host(0)
+    h = Handle(lib, 0, ap)
+    rc, lam, X, _, st = h.solve(8, 1e-13, max_restarts=1, ncv=24)
+    assert rc == NOT_CONV
+    assert st.restarts == 1 and st.n_converged < 8
+    assert np.all(np.isfinite(lam)) and np.all(np.isfinite(X))
+    # the partial results are Ritz pairs of a subspace: each value is its vector's
+    # Rayleigh quotient and, by interlacing, not below the matching eigenvalue
+    ref, _ = oracle.tda(ap, 8, vectors=False)
+    AX = oracle.apply_dense("A", ap, X.T).T
+    rq = np.real(np.sum(np.conj(X) * AX, axis=0)) / np.sum(np.abs(X) ** 2, axis=0)
+    assert np.max(np.abs(rq - lam)) < 1e-10 * np.max(np.abs(lam))
+    assert np.all(lam >= ref - 1e-10)
+    h.close()
+
+
+def test_nonfinite_input_is_reported(lib):
+    n = 40
+    A = random_herm(np.random.default_rng(2), n)
+    A[3, 7] = np.nan
+    A[7, 3] = np.nan
+    h = Handle(lib, 0, pack_upper(A))
+    rc, *_ = h.solve(3, 1e-10)
+    assert rc == NONFINITE, h.error()
+    h.close()
+
+
+def test_invalid_arguments(lib):
+    ap = pack_upper(random_herm(np.random.default_rng(1), 30))
+    h = Handle(lib, 0, ap)
+    for k, tol in [(0, 1e-8), (31, 1e-8), (3, 0.0), (3, -1.0)]:
+        rc, *_ = h.solve(k, tol)
+        assert rc == INVALID, (k, tol)
+    rc, *_ = h.solve(3, 1e-8, variant=2)
+    assert rc == INVALID
+    rc, *_ = h.solve(3, 1e-8, precision=1)  # mixed needs hi + lo storage
+    assert rc == INVALID
+    g = np.ones(3)
+    assert lib.bse_backward(h.h, g.ctypes.data, None, None) == BAD_STATE  # before a solve
+    om, X, Y = np.zeros(3), np.zeros((3, 30), complex), np.zeros((3, 30), complex)
+    assert lib.bse_solve(h.h, 3, 1e-8, None, om.ctypes.data, X.ctypes.data, Y.ctypes.data, None) == INVALID
+    assert lib.bse_solve(h.h, 3, 1e-8, None, None, X.ctypes.data, None, None) == INVALID
+    rc, *_ = h.haydock(np.zeros(30, complex), 4)  # zero dipole
+    assert rc == INVALID
+    h.close()
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_haydock_several_dipoles(lib, kind):
+    rng = np.random.default_rng(kind)
+    n = 90
+    A, B = random_herm(rng, n, lam_min=1.0), random_sym(rng, n, 0.5)
+    ap, bp = pack_upper(A), pack_upper(B)
+    h = Handle(lib, kind, ap, bp if kind else None)
+    D = np.stack([synth.dipole(30 + q, n) for q in range(5)])  # a group of four and one more
+    rc, al, be, nn, st = h.haydock(D, 12)
+    assert rc == OK, h.error()
+    assert st.passes == (12 * 2 if kind == 0 else (1 + 2 * 12) * 2)
+    for q in range(5):
+        if kind == 0:
+            ra, rb, rn = hy.lanczos_tda(hy.dense_ops(ap), D[q], 12)
+        else:
+            k1, k2 = hy.dense_ops(ap, bp)
+            ra, rb, rn = hy.lanczos_ph(k1, k2, D[q], 12)
+        assert np.max(np.abs(al[q] - ra)) <= 1e-11 * np.max(np.abs(ra))
+        assert np.max(np.abs(be[q] - rb)) <= 1e-11 * np.max(np.abs(rb))
+        assert abs(nn[q] - rn) <= 1e-12 * rn
+    h.close()
