@@ -130,7 +130,7 @@ def main():
                    help="PH iteration: 0 K1-metric Lanczos on K2 K1, 1 Lanczos on H in the M inner product")
     p.add_argument("--precision", choices=["auto", "fp64"], default="auto",
                    help="auto: the mixed path where the workload uses it; fp64: FP64 passes only")
-    p.add_argument("--mode", choices=["solve", "passbench", "copy", "direct"], default="solve",
+    p.add_argument("--mode", choices=["solve", "passbench", "copy", "direct", "nsweep"], default="solve",
                    help="solve: the benchmark; passbench: only passes over the stored triangles "
                         "(for counter runs); copy: a plain device copy of known size (counter calibration)")
     p.add_argument("--passes", type=int, default=5, help="passbench: timed passes per precision")
@@ -182,6 +182,37 @@ def main():
                           "read_only_GBps": nel * 8 / (ms_r * 1e-3) / 1e9, "elementwise_copy_ms": ms_m,
                           "elementwise_copy_GBps": 2 * nel * 8 / (ms_m * 1e-3) / 1e9, "check": float(s_)}),
               flush=True)
+        return
+
+    if args.mode == "nsweep":
+        # time to k pairs of the benchmark recipe at the paper's three matrix sizes, and the
+        # fit log10 t = A log10 N + B of the paper's time-complexity analysis
+        w = dict(synth.WORKLOADS[4])
+        k, tol = args.k or w["k"], w["tol"]
+        stream = torch.cuda.current_stream().cuda_stream
+        rows = []
+        for n in (10368, 36288, 103680):
+            mat = synth.Matrix(n, w["seed"], True)
+            solver = bse.Solver("ph", n, storage="hilo")
+            fill_from_generator(solver, mat, int(args.chunk_gb * 2 ** 30 / 16), stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, _, st = solver.solve(k, tol, precision="mixed")
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            rows.append({"n": n, "seconds": t, "passes": st["passes"], "restarts": st["restarts"],
+                         "max_rel_residual": st["max_rel_residual"]})
+            log(f"  nsweep N={n}: {t:.2f} s, {st['passes']} passes")
+            solver.close()
+            del solver
+            torch.cuda.empty_cache()
+        ln = np.log10([r["n"] for r in rows])
+        lt = np.log10([r["seconds"] for r in rows])
+        A, B = np.polyfit(ln, lt, 1)
+        lp = np.log10([r["passes"] for r in rows])
+        Ap, _ = np.polyfit(ln, lp, 1)
+        print(json.dumps({"mode": "nsweep", "k": k, "tol": tol, "precision": "mixed", "runs": rows,
+                          "fit_log10_t": {"A": A, "B": B}, "fit_log10_passes": {"A": Ap}}), flush=True)
         return
 
     w = dict(synth.WORKLOADS[args.workload])
