@@ -29,7 +29,7 @@ def build(verbose=False):
     # rocSOLVER (Cholesky, Hermitian eigensolver) and rocBLAS (dense products) for the
     # direct structure-preserving solve
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB, *objs,
-           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.run(cmd, check=True, cwd=CSRC)
     for o in objs:
         os.remove(o)

@@ -6,11 +6,27 @@
 // the Hermitian case, whose tridiagonal is made real by a diagonal phase
 // similarity), then implicit symmetric QR steps with the Wilkinson shift and
 // Givens bulge chasing (Golub and Van Loan, Matrix Computations, Sec. 8.3).
+//
+// The O(m^3) loops run on a small pool of host threads: each element of
+// p = A v (a dot product with one column, A being symmetric / Hermitian),
+// the columns of the rank-2 updates and of the reflector accumulation, and
+// the rows of the eigenvector matrix under the QR rotations (the iteration
+// records its rotations; they are applied afterwards in one pass, each
+// panel of rows taking all of them in order).  Every output element is computed by one
+// thread in a fixed order, so the results do not depend on the number of
+// threads.
+#include <immintrin.h>
 #include <math.h>
+#include <stdlib.h>
 
 #include <algorithm>
+#include <atomic>
 #include <complex>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "bse_internal.h"
@@ -20,6 +36,89 @@ namespace bse {
 namespace {
 
 inline double& at(double* a, int m, int i, int j) { return a[(size_t)j * m + i]; }
+
+// Persistent worker threads; run(n, grain, f) calls f(i0, i1) on disjoint
+// chunks of [0, n) and returns when all are done.  Between regions a worker
+// spins for a while (the reduction issues one region per column, a few
+// microseconds apart) and then sleeps on a condition variable.  The pool
+// lives until the process ends.  Threads: OMP_NUM_THREADS if set, else the
+// hardware count, at most 16.
+class Pool {
+ public:
+  using Fn = std::function<void(int64_t, int64_t)>;
+  static Pool& get() {
+    static Pool* p = new Pool();
+    return *p;
+  }
+  int threads() const { return nthreads_; }
+  void run(int64_t n, int64_t grain, const Fn& f) {
+    if (nthreads_ <= 1 || n <= grain) {
+      f(0, n);
+      return;
+    }
+    std::lock_guard<std::mutex> one(run_m_);  // one region at a time
+    job_ = &f;
+    n_ = n;
+    chunk_ = std::max<int64_t>(grain, (n + 4 * nthreads_ - 1) / (4 * nthreads_));
+    next_.store(0, std::memory_order_relaxed);
+    pending_.store(nthreads_ - 1, std::memory_order_relaxed);
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      gen_.fetch_add(1, std::memory_order_release);
+    }
+    cv_.notify_all();
+    work();
+    while (pending_.load(std::memory_order_acquire) != 0) _mm_pause();
+    job_ = nullptr;
+  }
+
+ private:
+  Pool() {
+    int nt = (int)std::thread::hardware_concurrency();
+    if (const char* e = getenv("OMP_NUM_THREADS")) nt = atoi(e);
+    nthreads_ = std::max(1, std::min(nt, 16));
+    for (int t = 1; t < nthreads_; ++t) std::thread([this] { loop(); }).detach();
+  }
+  void work() {
+    for (;;) {
+      const int64_t i0 = next_.fetch_add(chunk_, std::memory_order_relaxed);
+      if (i0 >= n_) break;
+      (*job_)(i0, std::min(n_, i0 + chunk_));
+    }
+  }
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      int spins = 0;
+      while (gen_.load(std::memory_order_acquire) == seen) {
+        if (++spins < 200000) {
+          _mm_pause();
+          continue;
+        }
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != seen; });
+      }
+      seen = gen_.load(std::memory_order_acquire);
+      work();
+      pending_.fetch_sub(1, std::memory_order_acq_rel);
+    }
+  }
+  int nthreads_ = 1;
+  std::mutex run_m_, m_;
+  std::condition_variable cv_;
+  const Fn* job_ = nullptr;
+  int64_t n_ = 0, chunk_ = 1;
+  // one cache line each: the chunk counter, the completion count and the
+  // generation that idle workers poll
+  alignas(64) std::atomic<int64_t> next_{0};
+  alignas(64) std::atomic<int> pending_{0};
+  alignas(64) std::atomic<uint64_t> gen_{0};
+};
+
+template <class F>
+void par(int64_t n, int64_t grain, F&& f) {
+  Pool::get().run(n, grain, Pool::Fn(f));
+}
 
 // a = Q T Q^T with T tridiagonal (diag d, off e); q receives Q.
 void tridiagonalize(int m, double* a, double* d, double* e, double* q) {
@@ -42,16 +141,23 @@ void tridiagonalize(int m, double* a, double* d, double* e, double* q) {
     // A <- H A H with H = I - 2 v v^T: p = A v, g = v^T p, p -= g v,
     // A -= 2 (v p^T + p v^T)
     double g = 0.0;
-    for (int i = k; i < m; ++i) p[i] = 0.0;
-    for (int j = k + 1; j < m; ++j) {  // p = A v, column by column
-      const double vj = v[j];
-      const double* aj = &at(a, m, 0, j);
-      for (int i = k; i < m; ++i) p[i] += aj[i] * vj;
-    }
+    par(m - k, 16, [&](int64_t t0, int64_t t1) {  // p_i = sum_j A(j, i) v_j (A symmetric)
+      for (int64_t t = t0; t < t1; ++t) {
+        const int i = k + (int)t;
+        const double* ai = &at(a, m, 0, i);
+        double sum = 0.0;
+        for (int j = k + 1; j < m; ++j) sum += ai[j] * v[j];
+        p[i] = sum;
+      }
+    });
     for (int i = k + 1; i < m; ++i) g += v[i] * p[i];
     for (int i = k; i < m; ++i) p[i] -= g * v[i];
-    for (int j = k; j < m; ++j)
-      for (int i = k; i < m; ++i) at(a, m, i, j) -= 2.0 * (v[i] * p[j] + p[i] * v[j]);
+    par(m - k, 16, [&](int64_t t0, int64_t t1) {
+      for (int64_t t = t0; t < t1; ++t) {
+        const int j = k + (int)t;
+        for (int i = k; i < m; ++i) at(a, m, i, j) -= 2.0 * (v[i] * p[j] + p[i] * v[j]);
+      }
+    });
     for (int i = k + 1; i < m; ++i) vs[(size_t)k * m + i] = v[i];
   }
   for (int i = 0; i < m; ++i) d[i] = at(a, m, i, i);
@@ -59,20 +165,29 @@ void tridiagonalize(int m, double* a, double* d, double* e, double* q) {
   // Q = H_0 H_1 ... H_{m-3}: apply to the identity from the right-most factor.
   for (size_t t = 0; t < (size_t)m * m; ++t) q[t] = 0.0;
   for (int i = 0; i < m; ++i) at(q, m, i, i) = 1.0;
-  for (int k = m - 3; k >= 0; --k) {
-    const double* vk = &vs[(size_t)k * m];
-    for (int c = 0; c < m; ++c) {
-      double s = 0.0;
-      for (int i = k + 1; i < m; ++i) s += vk[i] * at(q, m, i, c);
-      if (s == 0.0) continue;
-      for (int i = k + 1; i < m; ++i) at(q, m, i, c) -= 2.0 * s * vk[i];
-    }
-  }
+  // each column of Q independently, reflectors in order; H_k leaves e_c
+  // unchanged for k >= c (reflector k is zero in rows 0..k)
+  par(m, 8, [&](int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c)
+      for (int k = std::min(m - 3, (int)c - 1); k >= 0; --k) {
+        const double* vk = &vs[(size_t)k * m];
+        double s = 0.0;
+        for (int i = k + 1; i < m; ++i) s += vk[i] * at(q, m, i, (int)c);
+        if (s == 0.0) continue;
+        for (int i = k + 1; i < m; ++i) at(q, m, i, (int)c) -= 2.0 * s * vk[i];
+      }
+  });
 }
 
+// Plane rotation in columns (k, k+1): [x_k, x_{k+1}] <- [c x_k - s x_{k+1}, s x_k + c x_{k+1}].
+struct Rot {
+  double c, s;
+  int k;
+};
+
 // One implicit QR step with Wilkinson shift on the unreduced block [lo, hi]
-// of the tridiagonal (d, e); rotations are accumulated into q's columns.
-void qr_step(int m, int lo, int hi, double* d, double* e, double* q) {
+// of the tridiagonal (d, e); the rotations are appended to rots.
+void qr_step(int lo, int hi, double* d, double* e, std::vector<Rot>& rots) {
   const double t = 0.5 * (d[hi - 1] - d[hi]);
   const double b2 = e[hi - 1] * e[hi - 1];
   const double sg = t >= 0.0 ? 1.0 : -1.0;
@@ -98,12 +213,38 @@ void qr_step(int m, int lo, int hi, double* d, double* e, double* q) {
       x = e[k];
       z = bulge;
     }
-    for (int i = 0; i < m; ++i) {
-      const double qk = at(q, m, i, k), q1 = at(q, m, i, k + 1);
-      at(q, m, i, k) = c * qk - s * q1;
-      at(q, m, i, k + 1) = s * qk + c * q1;
-    }
+    rots.push_back(Rot{c, s, k});
   }
+}
+
+// q <- q G_1 G_2 ... for q (m x m, column-major, real or complex).  Rows
+// are independent under column rotations: q is cut into panels of
+// 128 / sizeof(T) rows, each panel is copied to a buffer laid out column by
+// column (one 128-byte line per column, the whole panel in L1) and takes
+// every rotation in order; the panels are split over the pool.
+template <class T>
+void apply_rotations(int m, T* q, const std::vector<Rot>& rots) {
+  constexpr int R = 128 / (int)sizeof(T);
+  const int np = (m + R - 1) / R;
+  par(np, 1, [&](int64_t p0, int64_t p1) {
+    std::vector<T> pan((size_t)m * R);
+    for (int64_t p = p0; p < p1; ++p) {
+      const int i0 = (int)p * R, nr = std::min(R, m - i0);
+      for (int j = 0; j < m; ++j)
+        for (int r = 0; r < R; ++r) pan[(size_t)j * R + r] = r < nr ? q[(size_t)j * m + i0 + r] : T(0);
+      for (const Rot& g : rots) {
+        T* qa = &pan[(size_t)g.k * R];
+        T* qb = qa + R;
+        for (int r = 0; r < R; ++r) {
+          const T qk = qa[r], q1 = qb[r];
+          qa[r] = g.c * qk - g.s * q1;
+          qb[r] = g.s * qk + g.c * q1;
+        }
+      }
+      for (int j = 0; j < m; ++j)
+        for (int r = 0; r < nr; ++r) q[(size_t)j * m + i0 + r] = pan[(size_t)j * R + r];
+    }
+  });
 }
 
 // Complex Hermitian a (column-major, m x m) = Q T Q^H, T tridiagonal with
@@ -131,40 +272,50 @@ void herm_tridiagonalize(int m, cplx* a, double* d, cplx* e, cplx* q) {
     for (int i = k + 1; i < m; ++i) v[i] /= vn;
     // A <- H A H, H = I - 2 v v^H: p = A v, g = v^H p (real), q = p - g v,
     // A -= 2 (v q^H + q v^H)
-    for (int i = k; i < m; ++i) p[i] = 0.0;
-    for (int j = k + 1; j < m; ++j) {  // p = A v, column by column
-      const cplx vj = v[j];
-      const cplx* aj = &A(0, j);
-      for (int i = k; i < m; ++i) p[i] += aj[i] * vj;
-    }
+    par(m - k, 16, [&](int64_t t0, int64_t t1) {  // p_i = sum_j conj(A(j, i)) v_j (A Hermitian)
+      for (int64_t t = t0; t < t1; ++t) {
+        const int i = k + (int)t;
+        const cplx* ai = &A(0, i);
+        cplx sum = 0.0;
+        for (int j = k + 1; j < m; ++j) sum += std::conj(ai[j]) * v[j];
+        p[i] = sum;
+      }
+    });
     cplx g = 0.0;
     for (int i = k + 1; i < m; ++i) g += std::conj(v[i]) * p[i];
     for (int i = k; i < m; ++i) p[i] -= g.real() * v[i];
-    for (int j = k; j < m; ++j)
-      for (int i = k; i < m; ++i) A(i, j) -= 2.0 * (v[i] * std::conj(p[j]) + p[i] * std::conj(v[j]));
+    par(m - k, 16, [&](int64_t t0, int64_t t1) {
+      for (int64_t t = t0; t < t1; ++t) {
+        const int j = k + (int)t;
+        for (int i = k; i < m; ++i) A(i, j) -= 2.0 * (v[i] * std::conj(p[j]) + p[i] * std::conj(v[j]));
+      }
+    });
     for (int i = k + 1; i < m; ++i) vs[(size_t)k * m + i] = v[i];
   }
   for (int i = 0; i < m; ++i) d[i] = A(i, i).real();
   for (int i = 0; i + 1 < m; ++i) e[i] = A(i + 1, i);
   for (size_t t = 0; t < (size_t)m * m; ++t) q[t] = 0.0;
   for (int i = 0; i < m; ++i) q[(size_t)i * m + i] = 1.0;
-  for (int k = m - 3; k >= 0; --k) {
-    const cplx* vk = &vs[(size_t)k * m];
-    for (int c = 0; c < m; ++c) {
-      cplx t = 0.0;
-      for (int i = k + 1; i < m; ++i) t += std::conj(vk[i]) * q[(size_t)c * m + i];
-      if (t == 0.0) continue;
-      for (int i = k + 1; i < m; ++i) q[(size_t)c * m + i] -= 2.0 * t * vk[i];
-    }
-  }
+  par(m, 8, [&](int64_t c0, int64_t c1) {  // as in the real case: skip k >= c
+    for (int64_t c = c0; c < c1; ++c)
+      for (int k = std::min(m - 3, (int)c - 1); k >= 0; --k) {
+        const cplx* vk = &vs[(size_t)k * m];
+        cplx t = 0.0;
+        for (int i = k + 1; i < m; ++i) t += std::conj(vk[i]) * q[(size_t)c * m + i];
+        if (t == 0.0) continue;
+        for (int i = k + 1; i < m; ++i) q[(size_t)c * m + i] -= 2.0 * t * vk[i];
+      }
+  });
 }
 
-// Tridiagonal QR iteration on (d, e) accumulating rotations into q (m x m).
-bool tridiag_qr(int m, double* d, double* e, double* q) {
+// Tridiagonal QR iteration on (d, e); the rotations are recorded in rots
+// (q <- q G_1 G_2 ... turns the reducing basis into eigenvectors).
+bool tridiag_qr(int m, double* d, double* e, std::vector<Rot>& rots) {
   const double eps = 2.220446049250313e-16;
   int hi = m - 1;
   long iters = 0;
   const long max_iters = 60L * m;
+  rots.reserve((size_t)m * m);
   while (hi > 0) {
     if (fabs(e[hi - 1]) <= eps * (fabs(d[hi - 1]) + fabs(d[hi]))) {
       e[hi - 1] = 0.0;
@@ -174,7 +325,7 @@ bool tridiag_qr(int m, double* d, double* e, double* q) {
     int lo = hi - 1;
     while (lo > 0 && fabs(e[lo - 1]) > eps * (fabs(d[lo - 1]) + fabs(d[lo]))) --lo;
     if (lo > 0) e[lo - 1] = 0.0;
-    qr_step(m, lo, hi, d, e, q);
+    qr_step(lo, hi, d, e, rots);
     if (++iters > max_iters) return false;
   }
   return true;
@@ -186,7 +337,7 @@ bool herm_eig(int m, double2* a, double* w, double2* z) {
   if (m <= 0) return true;
   std::vector<cplx> ac((size_t)m * m), qh((size_t)m * m);
   for (size_t t = 0; t < (size_t)m * m; ++t) ac[t] = cplx(a[t].x, a[t].y);
-  std::vector<double> d(m), e(m, 0.0), qr((size_t)m * m, 0.0);
+  std::vector<double> d(m), e(m, 0.0);
   std::vector<cplx> ec(m, 0.0);
   if (m == 1) {
     d[0] = ac[0].real();
@@ -201,23 +352,18 @@ bool herm_eig(int m, double2* a, double* w, double2* z) {
     e[k] = ae;
     delta[k + 1] = ae > 0.0 ? delta[k] * (ec[k] / ae) : delta[k];
   }
-  for (int i = 0; i < m; ++i) qr[(size_t)i * m + i] = 1.0;
-  if (!tridiag_qr(m, d.data(), e.data(), qr.data())) return false;
+  std::vector<Rot> rots;
+  if (!tridiag_qr(m, d.data(), e.data(), rots)) return false;
+  // eigenvectors Z = Q_h D Q_r: scale the columns of Q_h by delta, then rotate
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) qh[(size_t)j * m + i] *= delta[j];
+  apply_rotations(m, qh.data(), rots);
   std::vector<int> ord(m);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });
-  // eigenvectors Z = Q_h D Q_r, column by column
-  std::vector<cplx> zc(m);
   for (int c = 0; c < m; ++c) {
-    const int oc = ord[c];
-    w[c] = d[oc];
-    std::fill(zc.begin(), zc.end(), cplx(0.0));
-    for (int j = 0; j < m; ++j) {
-      const cplx f = delta[j] * qr[(size_t)oc * m + j];
-      if (f == 0.0) continue;
-      const cplx* qj = &qh[(size_t)j * m];
-      for (int i = 0; i < m; ++i) zc[i] += qj[i] * f;
-    }
+    w[c] = d[ord[c]];
+    const cplx* zc = &qh[(size_t)ord[c] * m];
     for (int i = 0; i < m; ++i) z[(size_t)c * m + i] = make_double2(zc[i].real(), zc[i].imag());
   }
   return true;
@@ -232,7 +378,9 @@ bool sym_eig(int m, double* a, double* w, double* z) {
   }
   std::vector<double> d(m), e(m, 0.0), q((size_t)m * m);
   tridiagonalize(m, a, d.data(), e.data(), q.data());
-  if (!tridiag_qr(m, d.data(), e.data(), q.data())) return false;
+  std::vector<Rot> rots;
+  if (!tridiag_qr(m, d.data(), e.data(), rots)) return false;
+  apply_rotations(m, q.data(), rots);
   std::vector<int> ord(m);
   std::iota(ord.begin(), ord.end(), 0);
   std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return d[x] < d[y]; });

@@ -45,7 +45,7 @@ class Stats(ctypes.Structure):
 @pytest.fixture(scope="module")
 def lib(tmp_path_factory):
     so = str(tmp_path_factory.mktemp("hostdrv") / "libbse_hostdrv.so")
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+    cmd = ["g++", "-O2", "-std=c++17", "-pthread", "-shared", "-fPIC", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
            "-fcx-limited-range", "-w", os.path.join(HERE, "native", "host_backend.cpp"),
            os.path.join(CSRC, "bse_solver.cpp"), os.path.join(CSRC, "bse_smalleig.cpp"), "-o", so,
            "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib", "-Wl,-Bsymbolic"]

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 @pytest.fixture(scope="module")
 def driver(tmp_path_factory):
     exe = str(tmp_path_factory.mktemp("smalleig") / "smalleig")
-    cmd = ["g++", "-O2", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+    cmd = ["g++", "-O2", "-std=c++17", "-pthread", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
            os.path.join(HERE, "native", "smalleig_driver.cpp"),
            os.path.join(ROOT, "paper_2504_10096_amd", "csrc", "bse_smalleig.cpp"), "-o", exe]
     r = subprocess.run(cmd, capture_output=True, text=True)
