@@ -341,6 +341,55 @@ __device__ __forceinline__ double dpp_wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Wave-local LDS between lanes of one wavefront: the writes of every lane
+// are ordered before the reads that follow (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Column sums of NV per-lane partials (4 <= NV <= 8) over the 64 lanes of a
+// wavefront, through LDS instead of NV separate wavefront reductions:
+// every lane writes its partials value-major to stage (row stride
+// kStageLd doubles); lane (j, p) = (lane / LPV, lane % LPV), with LPV = 64 /
+// NP and NP = NV rounded up to 4 or 8, adds value j of lanes p, p + LPV,
+// ..., p + (NP - 1) LPV; a DPP butterfly over the LPV lanes of value j (lane
+// xor 1, xor 2, mirror within 8, mirror within 16) completes the sum, which
+// goes to colsum[j * 64 + c].  Fixed order: deterministic.  colsum holds
+// (NV + 1) rows of 64 when NV < NP.
+// The stride 72 puts the 16 lanes of each read phase on distinct banks.
+constexpr int kStageLd = 72;
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+template <int NV>
+__device__ __forceinline__ void lds_colsum(const double (&v)[NV], double* stage, double* colsum, int c,
+                                           int lane) {
+  static_assert(NV >= 4 && NV <= 8, "lds_colsum: 4..8 values");
+  constexpr int NP = NV <= 4 ? 4 : 8;
+  constexpr int LPV = 64 / NP;
+#pragma unroll
+  for (int j = 0; j < NV; ++j) stage[j * kStageLd + lane] = v[j];
+  wave_lds_sync();
+  const int j = lane / LPV, p = lane % LPV;
+  const int jj = j < NV ? j : 0;
+  double t = 0.0;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) t += stage[jj * kStageLd + p + LPV * m];
+  t += dpp_f64<0xB1>(t);                     // quad_perm [1,0,3,2]: lane xor 1
+  t += dpp_f64<0x4E>(t);                     // quad_perm [2,3,0,1]: lane xor 2
+  t += dpp_f64<0x141>(t);                    // row_half_mirror: 8-lane groups
+  if (LPV == 16) t += dpp_f64<0x140>(t);     // row_mirror: 16-lane rows
+  // every lane of a group stores the same sum (no branch); the padding
+  // groups of NV < NP store to row NV, which is never read
+  colsum[(j < NV ? j : NV) * 64 + c] = t;
+  wave_lds_sync();
+}
+
 // Raw 16-byte loads of one column segment: complex64 pairs (hi, and lo for
 // HILO) or one complex128 entry; converted after the next column's loads
 // have been issued.
@@ -722,7 +771,14 @@ __global__ void __launch_bounds__(kThreads)
   constexpr int RS = Sh::RS, NS = Sh::NS, VW = Sh::VW, G = Sh::G, RPL = Sh::RPL;
   constexpr int CPW = R / 4;
   constexpr int CH = CPW < 64 ? CPW : 64;
-  __shared__ double2 sh[4][RS];
+  // two or more vectors: column sums through LDS (lds_colsum); the same
+  // memory combines the row sums after the column loop
+  constexpr int NVAL = 2 * NV;
+  constexpr bool LCS = NVAL >= 4;
+  constexpr int CSW = LCS ? NVAL * kStageLd + (NVAL + 1) * 64 : 0;
+  constexpr int LDS2 = (4 * CSW > 8 * RS ? 4 * CSW : 8 * RS) / 2;
+  __shared__ double2 lds[LDS2];
+  double2(*sh)[RS] = reinterpret_cast<double2(*)[RS]>(lds);
 
   const int blk = blockIdx.x;
   const int slice = blockIdx.y;
@@ -732,6 +788,8 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
   const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
   const T tsb = (T)sb;
+  double* stage = reinterpret_cast<double*>(lds) + wave * CSW;
+  double* colsum = stage + NVAL * kStageLd;
 
   T xr[NV][RPL], xi[NV][RPL], rr[NV][RPL], ri[NV][RPL];
 #pragma unroll
@@ -822,8 +880,21 @@ __global__ void __launch_bounds__(kThreads)
           sr[v] += tsb * tr[v];
           si[v] += tsb * ti[v];
         }
-        const double ur = dpp_wave_sum((double)sr[v]), ui = dpp_wave_sum((double)si[v]);
-        keep[v] = lane == c2 ? make_double2(ur, ui) : keep[v];
+      }
+      if constexpr (LCS) {
+        double vals[LCS ? NVAL : 4];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          vals[2 * v] = (double)sr[v];
+          vals[2 * v + 1] = (double)si[v];
+        }
+        lds_colsum<NVAL>(vals, stage, colsum, c2, lane);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double ur = dpp_wave_sum((double)sr[v]), ui = dpp_wave_sum((double)si[v]);
+          keep[v] = lane == c2 ? make_double2(ur, ui) : keep[v];
+        }
       }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
@@ -834,9 +905,11 @@ __global__ void __launch_bounds__(kThreads)
     if (lane < CH) {
 #pragma unroll
       for (int v = 0; v < NV; ++v)
-        colpart[(((size_t)v * nblk + blk) * NS + slice) * R + wave * CPW + cb + lane] = keep[v];
+        colpart[(((size_t)v * nblk + blk) * NS + slice) * R + wave * CPW + cb + lane] =
+            LCS ? make_double2(colsum[(2 * v) * 64 + lane], colsum[(2 * v + 1) * 64 + lane]) : keep[v];
     }
   }
+  __syncthreads();  // the row-sum combine below reuses the column-sum LDS of every wave
 
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -890,7 +963,13 @@ __global__ void __launch_bounds__(kThreads)
   constexpr int CH = CPW < 64 ? CPW : 64;
   constexpr int NO = 2 * NH;
   static_assert(RS >= 128 && G >= 1, "streaming full-H layout");
-  __shared__ double2 sh[4][RS];
+  // LDS: per wave the column-sum stage and the 64 column sums of the current
+  // chunk; after the column loop the same memory combines the row sums
+  constexpr int NVAL = 2 * NO;
+  constexpr int CSW = NVAL * kStageLd + (NVAL + 1) * 64;
+  constexpr int LDS2 = (4 * CSW > 8 * RS ? 4 * CSW : 8 * RS) / 2;
+  __shared__ double2 lds[LDS2];
+  double2(*sh)[RS] = reinterpret_cast<double2(*)[RS]>(lds);
 
   const int blk = blockIdx.x;
   const int slice = blockIdx.y;
@@ -899,6 +978,8 @@ __global__ void __launch_bounds__(kThreads)
   const int lane = threadIdx.x & 63;
   const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
   const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
+  double* stage = reinterpret_cast<double*>(lds) + wave * CSW;
+  double* colsum = stage + NVAL * kStageLd;
 
   double xr[NH][RPL], xi[NH][RPL], yr[NH][RPL], yi[NH][RPL], rr[NO][RPL], ri[NO][RPL];
 #pragma unroll
@@ -933,9 +1014,6 @@ __global__ void __launch_bounds__(kThreads)
     raw_load<AR>(b0, b1, lbase + g * 64 * VW, cbm[g]);
   }
   for (int cb = 0; cb < CPW; cb += CH) {
-    double2 keep[NO];
-#pragma unroll
-    for (int o = 0; o < NO; ++o) keep[o] = make_double2(0.0, 0.0);
     // unrolled by two so the prefetched registers are renamed, not copied (a
     // copy would wait for the loads just issued)
 #pragma unroll 2
@@ -993,11 +1071,13 @@ __global__ void __launch_bounds__(kThreads)
             si[2 * q + 1] += -ar * yi[q][t] - ai * yr[q][t] + bi * xr[q][t] - br * xi[q][t];
           }
         }
+      double vals[NVAL];
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
-        const double ur = dpp_wave_sum(sr[o]), ui = dpp_wave_sum(si[o]);
-        keep[o] = lane == c2 ? make_double2(ur, ui) : keep[o];
+        vals[2 * o] = sr[o];
+        vals[2 * o + 1] = si[o];
       }
+      lds_colsum<NVAL>(vals, stage, colsum, c2, lane);
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         ca_[g] = na_[g];
@@ -1007,9 +1087,11 @@ __global__ void __launch_bounds__(kThreads)
     if (lane < CH) {
 #pragma unroll
       for (int o = 0; o < NO; ++o)
-        colpart[(((size_t)o * nblk + blk) * NS + slice) * R + wave * CPW + cb + lane] = keep[o];
+        colpart[(((size_t)o * nblk + blk) * NS + slice) * R + wave * CPW + cb + lane] =
+            make_double2(colsum[(2 * o) * 64 + lane], colsum[(2 * o + 1) * 64 + lane]);
     }
   }
+  __syncthreads();  // the row-sum combine below reuses the column-sum LDS of every wave
 
 #pragma unroll
   for (int o = 0; o < NO; ++o) {
