@@ -92,8 +92,9 @@ typedef struct {
                            products and sums; 1 complex FP32 products and in-block sums
                            (FP64 across blocks).  Both read 8 bytes per entry. */
   int32_t block;        /* TDA: block size b of the Lanczos iteration, 1..4 vectors per read of
-                           the triangle (0: 1; reduced to 1 when the basis would not leave room
-                           for b >= 2); ncv and keep are rounded up to multiples of b.  PH:
+                           the triangle (0: 2 for N >= 16384, else 1; reduced to 1 when the
+                           basis would not leave room for b >= 2); ncv and keep are rounded
+                           up to multiples of b.  PH:
                            ignored (b = 1: the folded iteration's basis is K1-orthogonal to its
                            partner space only when grown from one vector). */
   int32_t refine_start; /* Ritz vectors of the iteration that start the FP64 refinement

@@ -390,6 +390,13 @@ __device__ __forceinline__ void lds_colsum(const double (&v)[NV], double* stage,
   wave_lds_sync();
 }
 
+// acc += a b with one rounding; the multi-vector kernels accumulate every
+// product this way (a separate multiply and add per product, as plain
+// expressions compile to, costs half again the VALU work of these
+// VALU-heavy loops)
+__device__ __forceinline__ void mac(double& acc, double a, double b) { acc = __builtin_fma(a, b, acc); }
+__device__ __forceinline__ void mac(float& acc, float a, float b) { acc = __builtin_fmaf(a, b, acc); }
+
 // Raw 16-byte loads of one column segment: complex64 pairs (hi, and lo for
 // HILO) or one complex128 entry; converted after the next column's loads
 // have been issued.
@@ -586,28 +593,51 @@ __global__ void __launch_bounds__(kThreads)
 
 // out[i] = sum over the blocks of panel row P = i / R of their row partials
 //        + sum over the blocks of panel column P of their column partials.
+// The nb + 1 terms of a row (row partials Q = P..nb-1, then column partials
+// Q = 0..P, slice by slice) are cut into four consecutive ranges: lane l of
+// wave w sums range w of row blockIdx.x * 64 + l in order, and the four
+// range sums are added in wave order (fixed order: deterministic).  A
+// workgroup covers 64 rows of one panel (R is a multiple of 64), so the
+// loop bounds are uniform per wave; a thread per row with the whole loop
+// left too few loads in flight.
 __global__ void __launch_bounds__(kThreads)
     mv_reduce_kernel(const double2* __restrict__ rowpart, const double2* __restrict__ colpart,
                      int R, int NS, int nb, int64_t n, double2* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const int P = (int)(i / R), r = (int)(i % R);
+  __shared__ double2 sh[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   double sx = 0.0, sy = 0.0;
-  const int64_t pstart = (int64_t)P * nb - (int64_t)P * (P - 1) / 2;
-  for (int Q = P; Q < nb; ++Q) {
-    const double2 v = rowpart[(size_t)(pstart + (Q - P)) * R + r];
-    sx += v.x;
-    sy += v.y;
-  }
-  for (int Q = 0; Q <= P; ++Q) {
-    const int64_t qs = (int64_t)Q * nb - (int64_t)Q * (Q - 1) / 2;
-    for (int sl = 0; sl < NS; ++sl) {
+  if (i < n) {
+    const int P = (int)(i / R), r = (int)(i % R);
+    const int nrow = nb - P;
+    const int len = nrow + (P + 1) * NS;
+    const int t0 = (int)((int64_t)len * wave / 4), t1 = (int)((int64_t)len * (wave + 1) / 4);
+    const int64_t pstart = (int64_t)P * nb - (int64_t)P * (P - 1) / 2;
+    for (int t = t0; t < (t1 < nrow ? t1 : nrow); ++t) {  // row partials, Q = P + t
+      const double2 v = rowpart[(size_t)(pstart + t) * R + r];
+      sx += v.x;
+      sy += v.y;
+    }
+    for (int t = (t0 > nrow ? t0 : nrow); t < t1; ++t) {  // column partials, u = Q NS + slice
+      const int u = t - nrow;
+      const int Q = NS == 1 ? u : u / NS, sl = u - Q * NS;
+      const int64_t qs = (int64_t)Q * nb - (int64_t)Q * (Q - 1) / 2;
       const double2 v = colpart[((size_t)(qs + (P - Q)) * NS + sl) * R + r];
       sx += v.x;
       sy += v.y;
     }
   }
-  out[i] = make_double2(sx, sy);
+  sh[wave][lane] = make_double2(sx, sy);
+  __syncthreads();
+  if (wave == 0 && i < n) {
+    double2 t = sh[0][lane];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      t.x += sh[w][lane].x;
+      t.y += sh[w][lane].y;
+    }
+    out[i] = t;
+  }
 }
 
 // ------------------------------------------------- full-H products (FP64)
@@ -835,12 +865,14 @@ __global__ void __launch_bounds__(kThreads)
       const int64_t j = col0 + c;
       const bool in = j < n;
       const int64_t jj = in ? j : 0;
-      T cxr[NV], cxi[NV], sr[NV], si[NV], tr[NV], ti[NV];
+      T cxr[NV], cxi[NV], bxr[NV], bxi[NV], sr[NV], si[NV], tr[NV], ti[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const double2 x = V[(size_t)v * ldv + jj];
         cxr[v] = in ? (T)x.x : T(0);
         cxi[v] = in ? (T)x.y : T(0);
+        bxr[v] = tsb * cxr[v];  // sb = +-1: exact
+        bxi[v] = tsb * cxi[v];
         sr[v] = T(0);
         si[v] = T(0);
         tr[v] = T(0);
@@ -856,21 +888,30 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             // row r: A_rc x_c; column c: conj(A_rc) x_r
-            rr[v][q] += ar * cxr[v] - ai * cxi[v];
-            ri[v][q] += ar * cxi[v] + ai * cxr[v];
-            sr[v] += ar * xr[v][q] + ai * xi[v][q];
-            si[v] += ar * xi[v][q] - ai * xr[v][q];
+            mac(rr[v][q], ar, cxr[v]);
+            mac(rr[v][q], -ai, cxi[v]);
+            mac(ri[v][q], ar, cxi[v]);
+            mac(ri[v][q], ai, cxr[v]);
+            mac(sr[v], ar, xr[v][q]);
+            mac(sr[v], ai, xi[v][q]);
+            mac(si[v], ar, xi[v][q]);
+            mac(si[v], -ai, xr[v][q]);
           }
           if (BM == BM_CONJ) {
             T br, bi;
             raw_get<AR, T>(cbm[g], e, br, bi);
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-              // row r: B_rc conj(x_c) (times sb); column c: B_rc conj(x_r) (times sb after the sum)
-              rr[v][q] += tsb * (br * cxr[v] + bi * cxi[v]);
-              ri[v][q] += tsb * (bi * cxr[v] - br * cxi[v]);
-              tr[v] += br * xr[v][q] + bi * xi[v][q];
-              ti[v] += bi * xr[v][q] - br * xi[v][q];
+              // row r: sb B_rc conj(x_c), with sb folded into x_c; column c:
+              // B_rc conj(x_r) (times sb after the sum)
+              mac(rr[v][q], br, bxr[v]);
+              mac(rr[v][q], bi, bxi[v]);
+              mac(ri[v][q], bi, bxr[v]);
+              mac(ri[v][q], -br, bxi[v]);
+              mac(tr[v], br, xr[v][q]);
+              mac(tr[v], bi, xi[v][q]);
+              mac(ti[v], bi, xr[v][q]);
+              mac(ti[v], -br, xi[v][q]);
             }
           }
         }
@@ -1057,18 +1098,46 @@ __global__ void __launch_bounds__(kThreads)
           raw_get<AR, double>(cbm[g], e, br, bi);
 #pragma unroll
           for (int q = 0; q < NH; ++q) {
+            double* r0r = &rr[2 * q][t];
+            double* r0i = &ri[2 * q][t];
+            double* r1r = &rr[2 * q + 1][t];
+            double* r1i = &ri[2 * q + 1][t];
             // top, row r: A x_c + B y_c
-            rr[2 * q][t] += ar * cxr[q] - ai * cxi[q] + br * cyr[q] - bi * cyi[q];
-            ri[2 * q][t] += ar * cxi[q] + ai * cxr[q] + br * cyi[q] + bi * cyr[q];
+            mac(*r0r, ar, cxr[q]);
+            mac(*r0r, -ai, cxi[q]);
+            mac(*r0r, br, cyr[q]);
+            mac(*r0r, -bi, cyi[q]);
+            mac(*r0i, ar, cxi[q]);
+            mac(*r0i, ai, cxr[q]);
+            mac(*r0i, br, cyi[q]);
+            mac(*r0i, bi, cyr[q]);
             // bottom (conjugated), row r: A conj(y_c) + B conj(x_c)
-            rr[2 * q + 1][t] += ar * cyr[q] + ai * cyi[q] + br * cxr[q] + bi * cxi[q];
-            ri[2 * q + 1][t] += ai * cyr[q] - ar * cyi[q] + bi * cxr[q] - br * cxi[q];
+            mac(*r1r, ar, cyr[q]);
+            mac(*r1r, ai, cyi[q]);
+            mac(*r1r, br, cxr[q]);
+            mac(*r1r, bi, cxi[q]);
+            mac(*r1i, ai, cyr[q]);
+            mac(*r1i, -ar, cyi[q]);
+            mac(*r1i, bi, cxr[q]);
+            mac(*r1i, -br, cxi[q]);
             // top, column c: conj(A) x_r + B y_r
-            sr[2 * q] += ar * xr[q][t] + ai * xi[q][t] + br * yr[q][t] - bi * yi[q][t];
-            si[2 * q] += ar * xi[q][t] - ai * xr[q][t] + br * yi[q][t] + bi * yr[q][t];
+            mac(sr[2 * q], ar, xr[q][t]);
+            mac(sr[2 * q], ai, xi[q][t]);
+            mac(sr[2 * q], br, yr[q][t]);
+            mac(sr[2 * q], -bi, yi[q][t]);
+            mac(si[2 * q], ar, xi[q][t]);
+            mac(si[2 * q], -ai, xr[q][t]);
+            mac(si[2 * q], br, yi[q][t]);
+            mac(si[2 * q], bi, yr[q][t]);
             // bottom (conjugated), column c: conj(A) conj(y_r) + B conj(x_r)
-            sr[2 * q + 1] += ar * yr[q][t] - ai * yi[q][t] + br * xr[q][t] + bi * xi[q][t];
-            si[2 * q + 1] += -ar * yi[q][t] - ai * yr[q][t] + bi * xr[q][t] - br * xi[q][t];
+            mac(sr[2 * q + 1], ar, yr[q][t]);
+            mac(sr[2 * q + 1], -ai, yi[q][t]);
+            mac(sr[2 * q + 1], br, xr[q][t]);
+            mac(sr[2 * q + 1], bi, xi[q][t]);
+            mac(si[2 * q + 1], -ar, yi[q][t]);
+            mac(si[2 * q + 1], -ai, yr[q][t]);
+            mac(si[2 * q + 1], bi, xr[q][t]);
+            mac(si[2 * q + 1], -br, xi[q][t]);
           }
         }
       double vals[NVAL];
@@ -2036,8 +2105,8 @@ hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const d
   }
   const double2* rowpart = part;
   const double2* colpart = part + (size_t)L.nblk * L.R;
-  hipLaunchKernelGGL(mv_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads)),
-                     dim3(kThreads), 0, s, rowpart, colpart, L.R, mv_slices(L), L.nb, L.n, out);
+  hipLaunchKernelGGL(mv_reduce_kernel, dim3((unsigned)((L.n + 63) / 64)), dim3(kThreads), 0, s, rowpart, colpart,
+                     L.R, mv_slices(L), L.nb, L.n, out);
   return hipGetLastError();
 }
 

@@ -1442,11 +1442,14 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   int m = o.ncv > 0 ? o.ncv : (int)round_up(std::max(2 * k, k + 32), 16);
   m = (int)std::min<int64_t>(m, n);
   if (m < k) return fail(h, BSE_ERR_INVALID_ARG, "ncv must be at least k");
-  // block size (TDA, on request): several vectors per read of the triangle;
-  // the basis and the kept set are whole blocks.  The
-  // pseudo-Hermitian iteration keeps b = 1: its basis is K1-orthogonal to
+  // block size (TDA): several vectors per read of the triangle; the basis
+  // and the kept set are whole blocks.  Automatic: b = 2 from N = 16384 on,
+  // where reading the triangle dominates a step and two vectors per read
+  // cost little more than one; b = 1 below, where launches and
+  // orthogonalization dominate and the block's extra products do not pay.
+  // The pseudo-Hermitian iteration keeps b = 1: its basis is K1-orthogonal to
   // its own partner space only when it grows from a single vector.
-  int b = ph ? 1 : (o.block > 0 ? o.block : 1);
+  int b = ph ? 1 : (o.block > 0 ? o.block : (n >= 16384 ? 2 : 1));
   if (b > 1 && ((int)round_up(m, b) < k + b || (int64_t)round_up(m, b) + b > n / 2)) b = 1;
   m = (int)round_up(m, b);
   int keep = o.keep > 0 ? o.keep : k + (m - k) / 2;
