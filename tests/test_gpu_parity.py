@@ -73,14 +73,17 @@ def test_matvec_parity(block, storage, monkeypatch):
     s.close()
 
 
+@pytest.mark.parametrize("block", [None, 128, 512])
 @pytest.mark.parametrize("nvec", [1, 2, 4, 5])
-def test_matvec_multi_vector_counts(nvec):
-    # one, several and a ragged number of vectors per read of the triangles, FP32 arithmetic too
+def test_matvec_multi_vector_counts(nvec, block, monkeypatch):
+    # one, several and a ragged number of vectors per read of the triangles, FP32 arithmetic
+    # too; block edges 128 and 512 run the streaming multi-vector kernels (LDS column sums)
     n = 777
+    print(f"multi-vector parity nvec={nvec} block={block}", flush=True)
     rng = np.random.default_rng(17)
     A, B = random_herm(rng, n), random_sym(rng, n, 0.5)
     ap, bp = pack_upper(A), pack_upper(B)
-    s = make_solver("ph", ap, bp, "hilo")
+    s = make_solver("ph", ap, bp, "hilo", block, monkeypatch)
     x = rng.standard_normal((nvec, n)) + 1j * rng.standard_normal((nvec, n))
     xh = rng.standard_normal((nvec, 2 * n)) + 1j * rng.standard_normal((nvec, 2 * n))
     for prec in ["fp64", "fp32"]:
