@@ -536,21 +536,31 @@ __global__ void __launch_bounds__(kThreads)
           const int q = g * VW + e;
           T ar, ai;
           raw_get<AR, T>(ca_[g], e, ar, ai);
-          rr[q] += ar * xcr - ai * xci;
-          ri[q] += ar * xci + ai * xcr;
-          cr += ar * xar[q] + ai * xai[q];
-          ci += ar * xai[q] - ai * xar[q];
+          mac(rr[q], ar, xcr);
+          mac(rr[q], -ai, xci);
+          mac(ri[q], ar, xci);
+          mac(ri[q], ai, xcr);
+          mac(cr, ar, xar[q]);
+          mac(cr, ai, xai[q]);
+          mac(ci, ar, xai[q]);
+          mac(ci, -ai, xar[q]);
           if (BM != BM_NONE) {
             T br, bi;
             raw_get<AR, T>(cbm[g], e, br, bi);
-            rr[q] += br * ycr - bi * yci;
-            ri[q] += br * yci + bi * ycr;
+            mac(rr[q], br, ycr);
+            mac(rr[q], -bi, yci);
+            mac(ri[q], br, yci);
+            mac(ri[q], bi, ycr);
             if (BM == BM_CONJ) {
-              dr += br * xar[q] + bi * xai[q];
-              di += bi * xar[q] - br * xai[q];
+              mac(dr, br, xar[q]);
+              mac(dr, bi, xai[q]);
+              mac(di, bi, xar[q]);
+              mac(di, -br, xai[q]);
             } else {
-              dr += br * xbr[q] - bi * xbi[q];
-              di += br * xbi[q] + bi * xbr[q];
+              mac(dr, br, xbr[q]);
+              mac(dr, -bi, xbi[q]);
+              mac(di, br, xbi[q]);
+              mac(di, bi, xbr[q]);
             }
           }
         }
