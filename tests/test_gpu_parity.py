@@ -86,12 +86,15 @@ def test_matvec_multi_vector_counts(nvec, block, monkeypatch):
     s = make_solver("ph", ap, bp, "hilo", block, monkeypatch)
     x = rng.standard_normal((nvec, n)) + 1j * rng.standard_normal((nvec, n))
     xh = rng.standard_normal((nvec, 2 * n)) + 1j * rng.standard_normal((nvec, 2 * n))
-    for prec in ["fp64", "fp32"]:
+    # hi64: FP64 arithmetic on the complex64-rounded triangles, the oracle applied to them
+    ap32, bp32 = (v.astype(np.complex64).astype(np.complex128) for v in (ap, bp))
+    for prec in ["fp64", "fp32", "hi64"]:
         tol = 2e-6 if prec == "fp32" else 1e-13
         for op in ["A", "K1", "K2", "H"]:
             xin = xh if op == "H" else x
             got = host(s.apply(op, dev(xin), precision=prec))
-            ref = oracle.apply_dense(op, ap, xin, bp)
+            ref = (oracle.apply_dense(op, ap32, xin, bp32) if prec == "hi64"
+                   else oracle.apply_dense(op, ap, xin, bp))
             assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < tol, (op, prec, nvec)
     s.close()
 
