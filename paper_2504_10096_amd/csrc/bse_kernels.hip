@@ -445,10 +445,11 @@ __device__ __forceinline__ void raw_get(const RawCol<AR>& r, int e, T& re, T& im
 }
 
 // One-vector pass, streaming form: same blocks, slices and partial layout as
-// mv_block_kernel, but the loads of column c + 1 are issued before column c
-// is consumed (two columns in flight per wave in registers), the column
-// sums use DPP reductions, and they are kept one per lane and stored per 64
-// columns, so the column loop has no branches.
+// mv_block_kernel, but the four waves interleave columns (wave w takes
+// columns w, w + 4, ...), the loads of a wave's next column are issued
+// before its current one is consumed (two columns in flight per wave in
+// registers), the column sums use DPP reductions, and they are kept one per
+// lane and stored per 64 columns, so the column loop has no branches.
 template <int R, int AR, int BM>
 __global__ void __launch_bounds__(kThreads)
     mv_stream_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
@@ -494,7 +495,9 @@ __global__ void __launch_bounds__(kThreads)
       ri[q] = T(0);
     }
 
-  const size_t lbase = base + (size_t)wave * CPW * R + lane * VW;
+  // the four waves interleave columns (wave w takes columns 4 cc + w), so a
+  // workgroup reads 4 adjacent columns, 16 KB of each array, at a time
+  const size_t lbase = base + (size_t)wave * R + lane * VW;
   RawCol<AR> ca_[G], cbm[G], na_[G], nbm[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -510,10 +513,10 @@ __global__ void __launch_bounds__(kThreads)
       const int cn = cc + 1 < CPW ? cc + 1 : cc;
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        raw_load<AR>(a0, a1, lbase + (size_t)cn * R + g * 64 * VW, na_[g]);
-        if (BM != BM_NONE) raw_load<AR>(b0, b1, lbase + (size_t)cn * R + g * 64 * VW, nbm[g]);
+        raw_load<AR>(a0, a1, lbase + (size_t)cn * 4 * R + g * 64 * VW, na_[g]);
+        if (BM != BM_NONE) raw_load<AR>(b0, b1, lbase + (size_t)cn * 4 * R + g * 64 * VW, nbm[g]);
       }
-      const int c = wave * CPW + cc;
+      const int c = cc * 4 + wave;
       const int64_t j = col0 + c;
       const bool in = j < n;
       const int64_t jj = in ? j : 0;
@@ -579,7 +582,7 @@ __global__ void __launch_bounds__(kThreads)
         if (BM != BM_NONE) cbm[g] = nbm[g];
       }
     }
-    if (lane < CH) colpart[((size_t)blk * NS + slice) * R + wave * CPW + cb + lane] = keep;
+    if (lane < CH) colpart[((size_t)blk * NS + slice) * R + (cb + lane) * 4 + wave] = keep;
   }
 
 #pragma unroll
@@ -1057,7 +1060,12 @@ __global__ void __launch_bounds__(kThreads)
       ri[o][t] = 0.0;
     }
 
-  const size_t lbase = base + (size_t)wave * CPW * R + lane * VW;
+  // hi + lo: the four waves interleave columns (wave w takes columns
+  // 4 cc + w; measured 27.4 vs 28.3 ms per read); the lo-only products keep
+  // contiguous column ranges per wave (16.5 vs 17.5 ms)
+  constexpr bool IL = AR == AR_HILO;
+  constexpr int CST = IL ? 4 : 1;  // column stride of a wave
+  const size_t lbase = base + (size_t)wave * (IL ? 1 : CPW) * R + lane * VW;
   RawCol<AR> ca_[G], cbm[G], na_[G], nbm[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) {
@@ -1073,13 +1081,13 @@ __global__ void __launch_bounds__(kThreads)
       const int cn = cc + 1 < CPW ? cc + 1 : cc;
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        raw_load<AR>(a0, a1, lbase + (size_t)cn * R + g * 64 * VW, na_[g]);
-        raw_load<AR>(b0, b1, lbase + (size_t)cn * R + g * 64 * VW, nbm[g]);
+        raw_load<AR>(a0, a1, lbase + (size_t)cn * CST * R + g * 64 * VW, na_[g]);
+        raw_load<AR>(b0, b1, lbase + (size_t)cn * CST * R + g * 64 * VW, nbm[g]);
       }
       // keep the loads here: under register pressure the scheduler would sink
       // them next to their use in the following column
       __builtin_amdgcn_sched_barrier(0);
-      const int c = wave * CPW + cc;
+      const int c = IL ? cc * 4 + wave : wave * CPW + cc;
       const int64_t j = col0 + c;
       const bool in = j < n;
       const int64_t jj = in ? j : 0;
@@ -1166,7 +1174,7 @@ __global__ void __launch_bounds__(kThreads)
     if (lane < CH) {
 #pragma unroll
       for (int o = 0; o < NO; ++o)
-        colpart[(((size_t)o * nblk + blk) * NS + slice) * R + wave * CPW + cb + lane] =
+        colpart[(((size_t)o * nblk + blk) * NS + slice) * R + (IL ? (cb + lane) * 4 + wave : wave * CPW + cb + lane)] =
             make_double2(colsum[(2 * o) * 64 + lane], colsum[(2 * o + 1) * 64 + lane]);
     }
   }
