@@ -55,7 +55,7 @@ int mv_slices(const Layout& L);
 size_t mv_part_elems(const Layout& L);
 
 // Full-H products [A x_q + B y_q; bsign conj(A conj(y_q) + B conj(x_q))]
-// (bsign = 1: M v_q; bsign = -1: H v_q) for nh (1 or 2) vectors in one read
+// (bsign = 1: M v_q; bsign = -1: H v_q) for nh (1 to 4) vectors in one read
 // of the stored A and B, FP64 arithmetic (ar: AR_C128, AR_HILO or AR_HI64).
 // Column q of V (and MV): top at q ldv, bottom at q ldv + ldh, n entries
 // each.  part: mh_part_elems(L, nh) complex entries.  ev0 / ev1 (optional)

@@ -349,17 +349,21 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Column sums of NV per-lane partials (4 <= NV <= 8) over the 64 lanes of a
-// wavefront, through LDS instead of NV separate wavefront reductions:
+// Column sums of NV per-lane partials (4 <= NV <= 16) over the 64 lanes of
+// a wavefront, through LDS instead of NV separate wavefront reductions:
 // every lane writes its partials value-major to stage (row stride
-// kStageLd doubles); lane (j, p) = (lane / LPV, lane % LPV), with LPV = 64 /
-// NP and NP = NV rounded up to 4 or 8, adds value j of lanes p, p + LPV,
-// ..., p + (NP - 1) LPV; a DPP butterfly over the LPV lanes of value j (lane
-// xor 1, xor 2, mirror within 8, mirror within 16) completes the sum, which
-// goes to colsum[j * 64 + c].  Fixed order: deterministic.  colsum holds
-// (NV + 1) rows of 64 when NV < NP.
-// The stride 72 puts the 16 lanes of each read phase on distinct banks.
-constexpr int kStageLd = 72;
+// stage_ld(NV) doubles); lane (j, p) = (lane / LPV, lane % LPV), with LPV =
+// 64 / NP and NP = NV rounded up to 4, 8 or 16, adds value j of lanes p,
+// p + LPV, ..., p + (NP - 1) LPV; a DPP butterfly over the LPV lanes of
+// value j (lane xor 1, xor 2, then mirror within 8 and within 16 as LPV
+// requires) completes the sum, which goes to colsum[j * 64 + c].  Fixed
+// order: deterministic.  colsum holds (NV + 1) rows of 64 when NV < NP.
+// The stride puts the lanes of each 16-lane read phase on distinct banks
+// (72 for two value groups per phase, 68 for four).
+__host__ __device__ constexpr int colsum_np(int nv) { return nv <= 4 ? 4 : (nv <= 8 ? 8 : 16); }
+__host__ __device__ constexpr int stage_ld(int nv) { return colsum_np(nv) == 16 ? 68 : 72; }
+// doubles of LDS per wave for NV values: the stage and the column sums
+__host__ __device__ constexpr int colsum_lds(int nv) { return nv * stage_ld(nv) + (nv + 1) * 64; }
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
@@ -369,20 +373,21 @@ __device__ __forceinline__ double dpp_f64(double x) {
 template <int NV>
 __device__ __forceinline__ void lds_colsum(const double (&v)[NV], double* stage, double* colsum, int c,
                                            int lane) {
-  static_assert(NV >= 4 && NV <= 8, "lds_colsum: 4..8 values");
-  constexpr int NP = NV <= 4 ? 4 : 8;
+  static_assert(NV >= 4 && NV <= 16, "lds_colsum: 4..16 values");
+  constexpr int NP = colsum_np(NV);
   constexpr int LPV = 64 / NP;
+  constexpr int LD = stage_ld(NV);
 #pragma unroll
-  for (int j = 0; j < NV; ++j) stage[j * kStageLd + lane] = v[j];
+  for (int j = 0; j < NV; ++j) stage[j * LD + lane] = v[j];
   wave_lds_sync();
   const int j = lane / LPV, p = lane % LPV;
   const int jj = j < NV ? j : 0;
   double t = 0.0;
 #pragma unroll
-  for (int m = 0; m < NP; ++m) t += stage[jj * kStageLd + p + LPV * m];
+  for (int m = 0; m < NP; ++m) t += stage[jj * LD + p + LPV * m];
   t += dpp_f64<0xB1>(t);                     // quad_perm [1,0,3,2]: lane xor 1
   t += dpp_f64<0x4E>(t);                     // quad_perm [2,3,0,1]: lane xor 2
-  t += dpp_f64<0x141>(t);                    // row_half_mirror: 8-lane groups
+  if (LPV >= 8) t += dpp_f64<0x141>(t);      // row_half_mirror: 8-lane groups
   if (LPV == 16) t += dpp_f64<0x140>(t);     // row_mirror: 16-lane rows
   // every lane of a group stores the same sum (no branch); the padding
   // groups of NV < NP store to row NV, which is never read
@@ -818,7 +823,7 @@ __global__ void __launch_bounds__(kThreads)
   // memory combines the row sums after the column loop
   constexpr int NVAL = 2 * NV;
   constexpr bool LCS = NVAL >= 4;
-  constexpr int CSW = LCS ? NVAL * kStageLd + (NVAL + 1) * 64 : 0;
+  constexpr int CSW = LCS ? colsum_lds(NVAL) : 0;
   constexpr int LDS2 = (4 * CSW > 8 * RS ? 4 * CSW : 8 * RS) / 2;
   __shared__ double2 lds[LDS2];
   double2(*sh)[RS] = reinterpret_cast<double2(*)[RS]>(lds);
@@ -832,7 +837,7 @@ __global__ void __launch_bounds__(kThreads)
   const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
   const T tsb = (T)sb;
   double* stage = reinterpret_cast<double*>(lds) + wave * CSW;
-  double* colsum = stage + NVAL * kStageLd;
+  double* colsum = stage + NVAL * stage_ld(NVAL);
 
   T xr[NV][RPL], xi[NV][RPL], rr[NV][RPL], ri[NV][RPL];
 #pragma unroll
@@ -992,7 +997,7 @@ __global__ void __launch_bounds__(kThreads)
 // each column's wavefront reductions (four per vector) over four rows per
 // lane; 128 rows left the kernel bound by those reductions (37 ms vs 30 ms
 // per read for two vectors at N = 1e5)
-__host__ __device__ constexpr int mh_rows(int) { return 256; }
+__host__ __device__ constexpr int mh_rows(int nh) { return nh >= 3 ? 128 : 256; }
 
 // Full-H products in the streaming form (R >= 128): the products of
 // mh_block_kernel (outputs 2q: A x_q + B y_q; 2q+1: A conj(y_q) + B conj(x_q),
@@ -1020,7 +1025,7 @@ __global__ void __launch_bounds__(kThreads)
   // LDS: per wave the column-sum stage and the 64 column sums of the current
   // chunk; after the column loop the same memory combines the row sums
   constexpr int NVAL = 2 * NO;
-  constexpr int CSW = NVAL * kStageLd + (NVAL + 1) * 64;
+  constexpr int CSW = colsum_lds(NVAL);
   constexpr int LDS2 = (4 * CSW > 8 * RS ? 4 * CSW : 8 * RS) / 2;
   __shared__ double2 lds[LDS2];
   double2(*sh)[RS] = reinterpret_cast<double2(*)[RS]>(lds);
@@ -1033,7 +1038,7 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
   const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
   double* stage = reinterpret_cast<double*>(lds) + wave * CSW;
-  double* colsum = stage + NVAL * kStageLd;
+  double* colsum = stage + NVAL * stage_ld(NVAL);
 
   double xr[NH][RPL], xi[NH][RPL], yr[NH][RPL], yi[NH][RPL], rr[NO][RPL], ri[NO][RPL];
 #pragma unroll
@@ -1257,19 +1262,32 @@ hipError_t launch_mh(int nh, const Layout& L, const MatPtrs& m, const double2* V
     if (nh == 1)
       hipLaunchKernelGGL((mh_stream_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
                          L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
-    else
+    else if (nh == 2)
       hipLaunchKernelGGL((mh_stream_kernel<R, AR, 2>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
+                         L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+    else if (nh == 3)
+      hipLaunchKernelGGL((mh_stream_kernel<R, AR, 3>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
+                         L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+    else
+      hipLaunchKernelGGL((mh_stream_kernel<R, AR, 4>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
                          L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
     return hipGetLastError();
   }
   constexpr int NS = 1;  // R = 64: one slice per block
   const dim3 grid((unsigned)L.nblk, (unsigned)NS);
-  if (nh == 1)
-    hipLaunchKernelGGL((mh_block_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo, L.blkmap,
-                       L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
-  else
-    hipLaunchKernelGGL((mh_block_kernel<R, AR, 2>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo, L.blkmap,
-                       L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+  // at most two vectors per launch here; vectors 2q, 2q + 1 write outputs
+  // 4q .. 4q + 3 of the same partial layout
+  for (int q0 = 0; q0 < nh; q0 += 2) {
+    const double2* Vq = V + (size_t)q0 * ldv;
+    double2* rp = rowpart + (size_t)2 * q0 * L.nblk * R;
+    double2* cp = colpart + (size_t)2 * q0 * L.nblk * NS * R;
+    if (nh - q0 == 1)
+      hipLaunchKernelGGL((mh_block_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
+                         L.blkmap, L.nblk, L.n, Vq, ldv, ldh, rp, cp);
+    else
+      hipLaunchKernelGGL((mh_block_kernel<R, AR, 2>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
+                         L.blkmap, L.nblk, L.n, Vq, ldv, ldh, rp, cp);
+  }
   return hipGetLastError();
 }
 
@@ -2151,7 +2169,7 @@ size_t mk_part_elems(const Layout& L, int nv) {
 hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const double2* V, int64_t ldv,
                     int64_t ldh, double2* part, double2* MV, double bsign, hipStream_t s, hipEvent_t ev0,
                     hipEvent_t ev1) {
-  if (nh < 1 || nh > 2 || ar == AR_HI) return hipErrorInvalidValue;
+  if (nh < 1 || nh > 4 || ar == AR_HI) return hipErrorInvalidValue;
   hipError_t e;
   if (ev0) {
     e = hipEventRecord(ev0, s);

@@ -86,7 +86,7 @@ bse::MatPtrs mat_ptrs(const bse_handle_s* h) {
 // Workspace of the fused full-H products, kept with the handle.
 bse_status ensure_mhpart(bse_handle h) {
   if (h->mhpart) return BSE_OK;
-  const size_t el = std::max(bse::mh_part_elems(h->L, 2), bse::mk_part_elems(h->L, 4));
+  const size_t el = std::max(bse::mh_part_elems(h->L, 4), bse::mk_part_elems(h->L, 4));
   if (hipMalloc((void**)&h->mhpart, sizeof(double2) * el) != hipSuccess) {
     h->mhpart = nullptr;
     return fail(h, BSE_ERR_OUT_OF_MEMORY, "full-H workspace");
@@ -1003,10 +1003,10 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   HIP_TRY(h, bse::diag_a(h->L, ar, h->a, h->alo, D, S.s));
   auto col = [&](double2* base, int c) { return base + (size_t)c * ld2; };
   // M v = [A x + B y; conj(A conj(y) + B conj(x))] for columns [c0, c1),
-  // two vectors per read of the stored A and B (TDA: A v, four per read)
+  // four vectors per read of the stored A and B (TDA: A v, four per read)
   auto mapply = [&](int c0, int c1, Arith mar, const bse::MatPtrs& mmp) -> bse_status {
-    for (int c = c0; c < c1; c += ph ? 2 : 4) {
-      const int nh = std::min(ph ? 2 : 4, c1 - c);
+    for (int c = c0; c < c1; c += 4) {
+      const int nh = std::min(4, c1 - c);
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (S.passes % 8 == 0 && S.ev_free.size() >= 2) {
         e1 = S.ev_free.back();
@@ -1378,10 +1378,10 @@ bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t n
   const double2* xv = (const double2*)x;
   double2* yv = (double2*)y;
   if (op == BSE_OP_H && ar != bse::AR_HI) {
-    // fused: two vectors per read of A and B
+    // fused: up to four vectors per read of A and B
     if (bse_status st = ensure_mhpart(h)) return st;
-    for (int64_t c = 0; c < nvec; c += 2) {
-      const int nh = (int)std::min<int64_t>(2, nvec - c);
+    for (int64_t c = 0; c < nvec; c += 4) {
+      const int nh = (int)std::min<int64_t>(4, nvec - c);
       HIP_TRY(h, bse::mh_apply(h->L, ar, mp, nh, xv + (size_t)c * 2 * n, 2 * n, n, h->mhpart,
                                yv + (size_t)c * 2 * n, -1.0, h->stream));
     }

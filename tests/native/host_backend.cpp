@@ -143,7 +143,7 @@ size_t mk_part_elems(const Layout& L, int nv) { return (size_t)nv * L.nblk * L.R
 
 hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const double2* V, int64_t ldv,
                     int64_t ldh, double2* part, double2* MV, double bsign, hipStream_t s, hipEvent_t, hipEvent_t) {
-  if (nh < 1 || nh > 2 || ar == AR_HI) return hipErrorInvalidValue;
+  if (nh < 1 || nh > 4 || ar == AR_HI) return hipErrorInvalidValue;
   for (int q = 0; q < nh; ++q) {
     const double2* x = V + (size_t)q * ldv;
     double2* o = MV + (size_t)q * ldv;
