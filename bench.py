@@ -124,6 +124,9 @@ def main():
     p.add_argument("--ncv", type=int, default=0, help="Lanczos basis size (0: default)")
     p.add_argument("--keep", type=int, default=0, help="Ritz vectors kept at a restart (0: default)")
     p.add_argument("--refine-start", type=int, default=0, help="Ritz vectors starting the refinement (0: default)")
+    p.add_argument("--switch-tol", type=float, default=0.0,
+                   help="mixed: residual estimate at which the bulk phase hands over to the FP64 refinement "
+                        "(0: default)")
     p.add_argument("--haydock", choices=["on", "off"], default="on",
                    help="also time a Lanczos-Haydock spectrum of the same matrix")
     p.add_argument("--variant", type=int, default=0, choices=[0, 1],
@@ -311,13 +314,15 @@ def main():
 
     for i in range(args.warmup):
         solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep,
-                                  refine_start=args.refine_start, variant=args.variant)
+                                  refine_start=args.refine_start, variant=args.variant,
+                                  switch_tol=args.switch_tol)
         log(f"  warmup {i} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         omega, X, Y, st = solver.solve(k, tol, precision=precision, block=args.block, ncv=args.ncv, keep=args.keep,
-                                  refine_start=args.refine_start, variant=args.variant)
+                                  refine_start=args.refine_start, variant=args.variant,
+                                  switch_tol=args.switch_tol)
         log(f"  step {i}: {st['ms_total'] / 1e3:.2f} s, passes {st['passes']}, restarts {st['restarts']}, "
             f"max rel residual {st['max_rel_residual']:.2e}")
     torch.cuda.synchronize()
@@ -420,7 +425,8 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         om64, X64, Y64, st64 = solver.solve(k, tol, precision="fp64", block=args.block, ncv=args.ncv, keep=args.keep,
-                                  refine_start=args.refine_start, variant=args.variant)
+                                  refine_start=args.refine_start, variant=args.variant,
+                                  switch_tol=args.switch_tol)
         torch.cuda.synchronize()
         t64 = time.perf_counter() - t0
         log(f"  fp64 path: {t64:.2f} s, passes {st64['passes']}, max rel residual {st64['max_rel_residual']:.2e}")
