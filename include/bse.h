@@ -185,8 +185,7 @@ bse_status bse_set_packed(bse_handle h, bse_block which, int64_t j0, int64_t j1,
  * BSE_OP_H, stored as [top; bottom]), complex128, device.  precision selects
  * the FP64 operator (c128, or hi+lo), the FP32 operator (MIXED: hi only) or
  * FP64 arithmetic on hi (HI_FP64); the last two need HILO storage.  Vectors
- * are processed up to four per read (H with FP64 arithmetic included)
- * of the stored triangles.
+ * are processed up to four per read of the stored triangles.
  * Errors: INVALID_ARG (K1/K2/H on a TDA handle, hi-only without HILO, nulls).
  */
 bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t nvec, const void* x,
