@@ -959,7 +959,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   const bool ph = S.ph;
   // PH columns hold [top (ld); bottom (ld)]; TDA columns are plain N-vectors
   const int64_t n = S.n, ld = S.ld, ld2 = ph ? 2 * S.ld : S.ld, n2 = ph ? S.ld + S.n : S.n;
-  const int cap = (int)std::min<int64_t>(ph ? 2 * n : n, std::max(s0, k) + 2 * k + 16);
+  const int cap = (int)std::min<int64_t>(ph ? 2 * n : n, std::max(s0, k) + 3 * k + 16);
   if (s0 < k || s0 > cap) return fail(h, BSE_ERR_BAD_STATE, "refinement start size");
   DevBuf bV, bMV, bV2, bMV2, bR, bPart, bH, bD, bOm, bC, bG, bSt, bSb, bNrm;
   if (bse_status e = ensure_mhpart(h)) return e;
