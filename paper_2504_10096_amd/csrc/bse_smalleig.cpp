@@ -18,6 +18,7 @@
 #include <immintrin.h>
 #include <math.h>
 #include <stdlib.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <atomic>
@@ -47,8 +48,19 @@ class Pool {
  public:
   using Fn = std::function<void(int64_t, int64_t)>;
   static Pool& get() {
-    static Pool* p = new Pool();
-    return *p;
+    // a child made by fork() has none of the parent's worker threads, so it
+    // starts a pool of its own (the parent's object is left as it was)
+    static std::atomic<Pool*> cur{nullptr};
+    static std::mutex make;
+    Pool* q = cur.load(std::memory_order_acquire);
+    if (q && q->pid_ == getpid()) return *q;
+    std::lock_guard<std::mutex> lk(make);
+    q = cur.load(std::memory_order_acquire);
+    if (!q || q->pid_ != getpid()) {
+      q = new Pool();
+      cur.store(q, std::memory_order_release);
+    }
+    return *q;
   }
   int threads() const { return nthreads_; }
   void run(int64_t n, int64_t grain, const Fn& f) {
@@ -73,7 +85,7 @@ class Pool {
   }
 
  private:
-  Pool() {
+  Pool() : pid_(getpid()) {
     int nt = (int)std::thread::hardware_concurrency();
     if (const char* e = getenv("OMP_NUM_THREADS")) nt = atoi(e);
     nthreads_ = std::max(1, std::min(nt, 16));
@@ -103,6 +115,7 @@ class Pool {
       pending_.fetch_sub(1, std::memory_order_acq_rel);
     }
   }
+  pid_t pid_;
   int nthreads_ = 1;
   std::mutex run_m_, m_;
   std::condition_variable cv_;

@@ -81,3 +81,20 @@ def test_herm_eig_degenerate_and_real(driver):
     b = b + b.T
     w, z = run(driver, "h", b.astype(complex))
     assert np.abs(w - np.linalg.eigvalsh(b)).max() <= 1e-13 * np.abs(w).max()
+
+
+def test_thread_pool_after_fork(tmp_path):
+    """A child made by fork() after the pool has started gets a pool of its own (no wait for
+    the parent's worker threads) and the same result."""
+    exe = str(tmp_path / "smalleig_fork")
+    cmd = ["g++", "-O2", "-std=c++17", "-pthread", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+           "-I", os.path.join(ROOT, "paper_2504_10096_amd", "csrc"),
+           os.path.join(HERE, "native", "smalleig_fork.cpp"),
+           os.path.join(ROOT, "paper_2504_10096_amd", "csrc", "bse_smalleig.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        pytest.skip("host compiler unavailable: " + r.stderr[-300:])
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120, env={**os.environ, "OMP_NUM_THREADS": "4"})
+    assert out.returncode == 0, out.stdout + out.stderr
+    vals = dict(line.split() for line in out.stdout.strip().splitlines())
+    assert vals["parent"] == vals["child"]
