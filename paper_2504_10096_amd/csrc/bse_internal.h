@@ -176,6 +176,15 @@ bool sym_eig(int m, double* a, double* w, double* z);
 // converge.
 bool herm_eig(int m, double2* a, double* w, double2* z);
 
+// Host FP64 Cholesky and triangular solves for the projected pencil (s x s,
+// column-major complex): zchol overwrites the lower triangle of a Hermitian
+// positive definite a with L (a = L L^H; false if a pivot is not positive);
+// zlsolve X <- L^{-1} X and zlhsolve X <- L^{-H} X for c columns of X
+// (leading dimension s).
+bool zchol(int s, double2* a);
+void zlsolve(int s, const double2* l, double2* x, int c);
+void zlhsolve(int s, const double2* l, double2* x, int c);
+
 // Residual pieces of one vector: part2[2*chunk] = ||out - sgn*om*(cj ? conj(v) : v)||^2 over the
 // chunk, part2[2*chunk+1] = ||v||^2; res[0..1] = sums over chunks.
 hipError_t resid_norms(const double2* out, const double2* v, int cj, double sgn_om, int64_t n,

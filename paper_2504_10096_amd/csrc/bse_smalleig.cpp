@@ -404,4 +404,66 @@ bool sym_eig(int m, double* a, double* w, double* z) {
   return true;
 }
 
+// Cholesky a = L L^H of a Hermitian positive definite matrix (s x s,
+// column-major, lower triangle read and overwritten by L, strict upper
+// triangle untouched).  Left-looking by columns: column j takes the updates
+// of columns p < j in order, each a contiguous column (the rows split over
+// the pool); then the pivot and the scaling.  Returns false if a pivot is not
+// positive.
+bool zchol(int s, double2* a2) {
+  cplx* a = reinterpret_cast<cplx*>(a2);
+  for (int j = 0; j < s; ++j) {
+    cplx* aj = a + (size_t)j * s;
+    par(s - j, 64, [&](int64_t i0, int64_t i1) {
+      for (int p = 0; p < j; ++p) {
+        const cplx* ap = a + (size_t)p * s;
+        const cplx f = std::conj(ap[j]);
+        for (int64_t i = j + i0; i < j + i1; ++i) aj[i] -= ap[i] * f;
+      }
+    });
+    const double d = aj[j].real();
+    if (!(d > 0.0)) return false;
+    const double r = sqrt(d);
+    aj[j] = r;
+    for (int i = j + 1; i < s; ++i) aj[i] /= r;
+  }
+  return true;
+}
+
+// X <- L^{-1} X for c columns (X s x c, leading dimension s): forward
+// substitution by columns of L (contiguous), the columns of X over the pool.
+void zlsolve(int s, const double2* l2, double2* x2, int c) {
+  const cplx* l = reinterpret_cast<const cplx*>(l2);
+  cplx* x = reinterpret_cast<cplx*>(x2);
+  par(c, 1, [&](int64_t q0, int64_t q1) {
+    for (int64_t q = q0; q < q1; ++q) {
+      cplx* xq = x + (size_t)q * s;
+      for (int p = 0; p < s; ++p) {
+        const cplx* lp = l + (size_t)p * s;
+        xq[p] /= lp[p].real();
+        const cplx xp = xq[p];
+        for (int i = p + 1; i < s; ++i) xq[i] -= lp[i] * xp;
+      }
+    }
+  });
+}
+
+// X <- L^{-H} X for c columns: backward substitution with dot products along
+// the columns of L (contiguous), the columns of X over the pool.
+void zlhsolve(int s, const double2* l2, double2* x2, int c) {
+  const cplx* l = reinterpret_cast<const cplx*>(l2);
+  cplx* x = reinterpret_cast<cplx*>(x2);
+  par(c, 1, [&](int64_t q0, int64_t q1) {
+    for (int64_t q = q0; q < q1; ++q) {
+      cplx* xq = x + (size_t)q * s;
+      for (int i = s - 1; i >= 0; --i) {
+        const cplx* li = l + (size_t)i * s;
+        cplx t = xq[i];
+        for (int p = i + 1; p < s; ++p) t -= std::conj(li[p]) * xq[p];
+        xq[i] = t / li[i].real();
+      }
+    }
+  });
+}
+
 }  // namespace bse

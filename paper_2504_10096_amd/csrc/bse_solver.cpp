@@ -887,47 +887,6 @@ bse_status finalize(Solver& S, const RitzInfo& R, double* omega, double2* X, dou
   return BSE_OK;
 }
 
-// ---------------------------------------------------------------------
-// Small dense complex helpers (host, column-major s x s, leading dimension s).
-// ---------------------------------------------------------------------
-
-// a = L L^H; the lower triangle of a receives L.  False if a is not positive definite.
-bool zchol(int s, cplx* a) {
-  for (int j = 0; j < s; ++j) {
-    double d = a[(size_t)j * s + j].real();
-    for (int p = 0; p < j; ++p) d -= std::norm(a[(size_t)p * s + j]);
-    if (!(d > 0.0)) return false;
-    d = sqrt(d);
-    a[(size_t)j * s + j] = d;
-    for (int i = j + 1; i < s; ++i) {
-      cplx t = a[(size_t)j * s + i];
-      for (int p = 0; p < j; ++p) t -= a[(size_t)p * s + i] * std::conj(a[(size_t)p * s + j]);
-      a[(size_t)j * s + i] = t / d;
-    }
-  }
-  return true;
-}
-
-// X <- L^{-1} X for c columns (X s x c, leading dimension s).
-void zlsolve(int s, const cplx* l, cplx* x, int c) {
-  for (int q = 0; q < c; ++q)
-    for (int i = 0; i < s; ++i) {
-      cplx t = x[(size_t)q * s + i];
-      for (int p = 0; p < i; ++p) t -= l[(size_t)p * s + i] * x[(size_t)q * s + p];
-      x[(size_t)q * s + i] = t / l[(size_t)i * s + i].real();
-    }
-}
-
-// X <- L^{-H} X.
-void zlhsolve(int s, const cplx* l, cplx* x, int c) {
-  for (int q = 0; q < c; ++q)
-    for (int i = s - 1; i >= 0; --i) {
-      cplx t = x[(size_t)q * s + i];
-      for (int p = i + 1; p < s; ++p) t -= std::conj(l[(size_t)i * s + p]) * x[(size_t)q * s + p];
-      x[(size_t)q * s + i] = t / l[(size_t)i * s + i].real();
-    }
-}
-
 struct RefineOut {
   std::vector<double> omega;  // the k wanted, ascending
   std::vector<double> rel;    // their FP64 relative residuals ||H v - omega v|| / (omega ||v||)
@@ -1119,19 +1078,20 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
         L[(size_t)j * s + i] = G[(size_t)j * cap + i];
         C[(size_t)j * s + i] = Sm[(size_t)j * cap + i];
       }
-    if (!zchol(s, L.data())) {
+    if (!bse::zchol(s, reinterpret_cast<double2*>(L.data()))) {
       if (ph)
         return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "V^H M V is not positive definite: M is not positive definite");
       return fail(h, BSE_ERR_DEVICE, "refinement basis lost rank");
     }
-    zlsolve(s, L.data(), C.data(), s);  // L^{-1} Sm
+    bse::zlsolve(s, reinterpret_cast<double2*>(L.data()), reinterpret_cast<double2*>(C.data()), s);  // L^{-1} Sm
     for (int j = 0; j < s; ++j)         // conjugate transpose: Sm L^{-H}
       for (int i = j; i < s; ++i) {
         const cplx a = C[(size_t)j * s + i], b = C[(size_t)i * s + j];
         C[(size_t)j * s + i] = std::conj(b);
         C[(size_t)i * s + j] = std::conj(a);
       }
-    zlsolve(s, L.data(), C.data(), s);  // L^{-1} Sm L^{-H}
+    bse::zlsolve(s, reinterpret_cast<double2*>(L.data()), reinterpret_cast<double2*>(C.data()),
+                 s);  // L^{-1} Sm L^{-H}
     for (int j = 0; j < s; ++j)
       for (int i = j; i < s; ++i) {
         const cplx v = 0.5 * (C[(size_t)j * s + i] + std::conj(C[(size_t)i * s + j]));
@@ -1158,7 +1118,8 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
       mud[c] = mu[src];
       for (int i = 0; i < s; ++i) Yc[(size_t)c * s + i] = Z[(size_t)src * s + i];
     }
-    zlhsolve(s, L.data(), Yc.data(), sk);  // coefficients with Yc^H G Yc = I
+    bse::zlhsolve(s, reinterpret_cast<double2*>(L.data()), reinterpret_cast<double2*>(Yc.data()),
+                  sk);  // coefficients with Yc^H G Yc = I
     HIP_TRY(h, hipMemcpyAsync(Cd, Yc.data(), sizeof(double2) * (size_t)s * sk, hipMemcpyHostToDevice, S.s));
     const auto ge = gemm_events(S);
     if (ge.first) HIP_TRY(h, hipEventRecord(ge.first, S.s));

@@ -1,6 +1,8 @@
 // Test driver for the host eigensolvers of the library (sym_eig, herm_eig):
 // reads "kind m" and a column-major matrix (real, or re im pairs) from
-// stdin, prints the eigenvalues and eigenvectors.
+// stdin, prints the eigenvalues and eigenvectors.  Kind "c": a Hermitian
+// positive definite G and a complex C (both m x m); prints the status of
+// zchol, then L^{-1} C (zlsolve) and L^{-H} C (zlhsolve).
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <vector>
@@ -12,7 +14,20 @@ int main() {
   int m;
   while (scanf("%7s %d", kind, &m) == 2) {
     std::vector<double> w(m);
-    if (kind[0] == 's') {
+    if (kind[0] == 'c') {
+      std::vector<double2> g((size_t)m * m), c((size_t)m * m);
+      for (auto& v : g) scanf("%lf %lf", &v.x, &v.y);
+      for (auto& v : c) scanf("%lf %lf", &v.x, &v.y);
+      const bool ok = bse::zchol(m, g.data());
+      std::vector<double2> x1 = c, x2 = c;
+      if (ok) {
+        bse::zlsolve(m, g.data(), x1.data(), m);
+        bse::zlhsolve(m, g.data(), x2.data(), m);
+      }
+      printf("%d\n", ok ? 1 : 0);
+      for (auto& v : x1) printf("%.17g %.17g\n", v.x, v.y);
+      for (auto& v : x2) printf("%.17g %.17g\n", v.x, v.y);
+    } else if (kind[0] == 's') {
       std::vector<double> a((size_t)m * m), z((size_t)m * m);
       for (auto& v : a) scanf("%lf", &v);
       const bool ok = bse::sym_eig(m, a.data(), w.data(), z.data());

@@ -98,3 +98,30 @@ def test_thread_pool_after_fork(tmp_path):
     assert out.returncode == 0, out.stdout + out.stderr
     vals = dict(line.split() for line in out.stdout.strip().splitlines())
     assert vals["parent"] == vals["child"]
+
+
+@pytest.mark.parametrize("m", [1, 3, 40, 130])
+def test_cholesky_and_triangular_solves(driver, m):
+    """zchol / zlsolve / zlhsolve against numpy: L lower with a positive diagonal, L L^H = G,
+    L X1 = C, L^H X2 = C; an indefinite G is reported (status 0)."""
+    rng = np.random.default_rng(300 + m)
+    x = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    g = x @ x.conj().T + m * np.eye(m)
+    c = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    body = " ".join(f"{v.real:.17g} {v.imag:.17g}" for v in np.concatenate([g.T.ravel(), c.T.ravel()]))
+    out = subprocess.run([driver], input=f"c {m}\n{body}\n", capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    assert out[0] == "1"
+    vals = np.array([complex(float(a), float(b)) for a, b in (ln.split() for ln in out[1:1 + 2 * m * m])])
+    x1 = vals[:m * m].reshape(m, m).T
+    x2 = vals[m * m:].reshape(m, m).T
+    lref = np.linalg.cholesky(g)
+    scale = np.abs(c).max()
+    assert np.abs(lref @ x1 - c).max() <= 1e-11 * scale * m
+    assert np.abs(lref.conj().T @ x2 - c).max() <= 1e-11 * scale * m
+    # not positive definite: status 0
+    gbad = g - (np.abs(np.linalg.eigvalsh(g)).max() + 1.0) * np.eye(m)
+    body = " ".join(f"{v.real:.17g} {v.imag:.17g}" for v in np.concatenate([gbad.T.ravel(), c.T.ravel()]))
+    out = subprocess.run([driver], input=f"c {m}\n{body}\n", capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    assert out[0] == "0"
