@@ -73,7 +73,7 @@ def test_matvec_parity(block, storage, monkeypatch):
     s.close()
 
 
-@pytest.mark.parametrize("block", [None, 128, 512])
+@pytest.mark.parametrize("block", [None, 128, 256, 512])
 @pytest.mark.parametrize("nvec", [1, 2, 4, 5])
 def test_matvec_multi_vector_counts(nvec, block, monkeypatch):
     # one, several and a ragged number of vectors per read of the triangles, FP32 arithmetic
