@@ -1407,8 +1407,10 @@ __global__ void __launch_bounds__(kThreads)
 
 // -------------------------------------------------- orthogonalization (CGS)
 // part[chunk * ncol + c] = sum over the 256-row chunk of conj(V[i, c]) w[i].
-// Grid (chunks, ceil(ncol / 64)); wave w of the group handles 16 columns;
-// lane l holds rows l + 64 s (s < 4) of w in registers.
+// Grid (chunks, ceil(ncol / 64)); wave w of the group handles 16 columns,
+// four at a time: the 16 loads of four columns are issued together, then the
+// eight wavefront sums (independent chains) follow; lane l holds rows
+// l + 64 s (s < 4) of w in registers.
 __global__ void __launch_bounds__(kThreads)
     cdot_part_kernel(const double2* __restrict__ V0, int n0, const double2* __restrict__ V1,
                      int n1, int64_t ld, const double2* __restrict__ w, int64_t n,
@@ -1417,31 +1419,47 @@ __global__ void __launch_bounds__(kThreads)
   const int64_t r0 = (int64_t)blockIdx.x * kChunk;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double wr[4], wi[4];
+  bool rin[4];
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int64_t i = r0 + lane + 64 * s;
-    const double2 v = (i < n) ? w[i] : make_double2(0.0, 0.0);
+    rin[s] = i < n;
+    const double2 v = rin[s] ? w[i] : make_double2(0.0, 0.0);
     wr[s] = v.x;
     wi[s] = v.y;
   }
   const int cbeg = blockIdx.y * 64 + wave * 16;
-  for (int t = 0; t < 16; ++t) {
-    const int c = cbeg + t;
-    if (c >= ncol) break;
-    const double2* col = (c < n0) ? V0 + (size_t)c * ld : V1 + (size_t)(c - n0) * ld;
-    double sr = 0.0, si = 0.0;
+  const int cend = min(cbeg + 16, ncol);
+  for (int t0 = cbeg; t0 < cend; t0 += 4) {
+    double2 v[4][4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t i = r0 + lane + 64 * s;
-      if (i < n) {
-        const double2 v = col[i];
-        sr += v.x * wr[s] + v.y * wi[s];
-        si += v.x * wi[s] - v.y * wr[s];
+    for (int u = 0; u < 4; ++u) {
+      const int c = t0 + u < cend ? t0 + u : t0;  // past the end: a valid column, result unused
+      const double2* col = (c < n0) ? V0 + (size_t)c * ld : V1 + (size_t)(c - n0) * ld;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[u][s] = rin[s] ? col[r0 + lane + 64 * s] : make_double2(0.0, 0.0);
+    }
+    double sr[4], si[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sr[u] = 0.0;
+      si[u] = 0.0;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        sr[u] += v[u][s].x * wr[s] + v[u][s].y * wi[s];
+        si[u] += v[u][s].x * wi[s] - v[u][s].y * wr[s];
       }
     }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) part[(size_t)blockIdx.x * ncol + c] = make_double2(sr, si);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      sr[u] = wave_sum(sr[u]);
+      si[u] = wave_sum(si[u]);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (t0 + u < cend) part[(size_t)blockIdx.x * ncol + t0 + u] = make_double2(sr[u], si[u]);
+    }
   }
 }
 
