@@ -74,7 +74,7 @@ def test_matvec_parity(block, storage, monkeypatch):
 
 
 @pytest.mark.parametrize("block", [None, 128, 256, 512])
-@pytest.mark.parametrize("nvec", [1, 2, 4, 5])
+@pytest.mark.parametrize("nvec", [1, 2, 3, 4, 5])
 def test_matvec_multi_vector_counts(nvec, block, monkeypatch):
     # one, several and a ragged number of vectors per read of the triangles, FP32 arithmetic
     # too; block edges 128 and 512 run the streaming multi-vector kernels (LDS column sums)
