@@ -136,6 +136,14 @@ typedef struct {
   double ms_dense_form;     /* bse_direct: forming the dense matrix (A, or M_r) from the triangles */
   double ms_dense_factor;   /* bse_direct, PH: Cholesky of M_r and the product W = L^T J L */
   double ms_dense_eig;      /* bse_direct: the Hermitian eigensolver */
+  /* bse_solve, time per phase (ms): */
+  double ms_matvec;   /* passes over the stored triangles in the Lanczos phases: the sampled average
+                         block-kernel duration times the number of passes */
+  double ms_orth;     /* CGS2 orthogonalization and normalization: the sampled average per Lanczos
+                         step (device events, every 8th step) times the number of steps */
+  double ms_small;    /* projected eigensolves of the restarts (host) */
+  double ms_restart;  /* the rest of the restarts: basis rotations (MFMA), residual estimates */
+  double ms_residual; /* eigenvector assembly, FP64 refinement (MIXED) and FP64 residuals */
 } bse_stats;
 
 /* Component of a matrix for bse_strength: the scalar returned for a

@@ -44,6 +44,7 @@ def _load():
             "orc_residual_ph": [i64, _cp, _cp, i64, _cp, _cp, _cp, _cp],
             "orc_grad_tda": [i64, i64, _cp, _cp, _cp],
             "orc_grad_ph": [i64, i64, _cp, _cp, _cp, _cp, _cp],
+            "orc_band_apply": [i64, i64, i64, i64, _cp, i64, _cp, _cp],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -179,34 +180,50 @@ def packed_inner(g, c):
 DEFAULT_BAND = 2432
 
 
-def _apply_direct(mat, x, band, chunk=1024):
-    """W x for the Hermitian direct term, rows in chunks, band-limited."""
+def _direct_band_chunks(mat, band, chunk):
+    """Row chunks (i0, i1, band rows) of the upper band of W, regenerated from the seeded phases."""
+    for i0 in range(0, mat.n, chunk):
+        i1 = min(mat.n, i0 + chunk)
+        yield i0, i1, np.ascontiguousarray(mat.direct_band(i0, i1, band))
+
+
+def _band_apply(n, i0, i1, wb, x, y):
+    """y += (rows i0..i1-1 of the Hermitian band and their mirror) x; x, y: n x nv C-contiguous."""
+    band = wb.shape[1]
+    _check(_load().orc_band_apply(n, i0, i1, band, _p(wb), x.shape[1], _p(x), _p(y)))
+
+
+def _apply_direct(mat, x, band, chunk=4096, cache=None):
+    """W x for the Hermitian direct term, band-limited (|i - j| < band).  ``cache``: a list of
+    (i0, i1, band rows) from ``_direct_band_chunks`` reused across calls."""
     n = mat.n
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    squeeze = x.ndim == 1
+    if squeeze:
+        x = x[:, None].copy()
     y = np.zeros_like(x)
-    for i0 in range(0, n, chunk):
-        i1 = min(n, i0 + chunk)
-        wb = mat.direct_band(i0, i1, band)  # (i1-i0) x band, W[i, i+d]
-        for d in range(band):
-            if i0 + d >= n:
-                break
-            hi = min(i1, n - d)
-            if hi <= i0:
-                break
-            col = wb[: hi - i0, d][:, None]
-            y[i0:hi] += col * x[i0 + d:hi + d]
-            if d > 0:
-                y[i0 + d:hi + d] += np.conj(col) * x[i0:hi]
-    return y
+    chunks = cache if cache is not None else _direct_band_chunks(mat, band, chunk)
+    for i0, i1, wb in chunks:
+        _band_apply(n, i0, i1, wb, x, y)
+    return y[:, 0] if squeeze else y
 
 
-def apply_generated(mat, xa, xb=None, band=DEFAULT_BAND):
+def direct_band_cache(mat, band=DEFAULT_BAND, chunk=4096, max_bytes=8 << 30):
+    """The whole band of W as a list of row chunks, or None when it would exceed max_bytes
+    (callers then regenerate it chunk by chunk on every application)."""
+    if mat.n * band * 16 > max_bytes:
+        return None
+    return list(_direct_band_chunks(mat, band, chunk))
+
+
+def apply_generated(mat, xa, xb=None, band=DEFAULT_BAND, cache=None):
     """A xa (+ B xb) in FP64 for a synth.Matrix, never forming N^2 entries."""
     t = mat.tables
     eps = t.eps + mat.shift
     xf = t.x_factor()
     y = eps[:, None] * xa
     y += mat.alpha * mat.kx_scale * (xf @ (np.conj(xf).T @ xa))
-    y -= mat.beta * _apply_direct(mat, xa, band)
+    y -= mat.beta * _apply_direct(mat, xa, band, cache=cache)
     if xb is not None and mat.ph:
         yf = t.y_factor()
         y += mat.alpha * mat.b0_scale * (yf @ (yf.T @ xb))
@@ -214,19 +231,61 @@ def apply_generated(mat, xa, xb=None, band=DEFAULT_BAND):
 
 
 def residual_generated(mat, om, x, y=None, band=DEFAULT_BAND):
-    """Relative residuals of eigenpairs of a seeded matrix: TDA if y is None, else PH."""
+    """Relative residuals ||H v - omega v|| / (|omega| ||v||) of eigenpairs of a seeded matrix
+    (TDA if y is None: ||A x - lambda x|| / (|lambda| ||x||)), with v = [X; Y] and the bottom block
+    of H v equal to -conj(A conj(Y) + B conj(X)) (paper Eq. (1), anti-resonant block conj(A))."""
     x = np.asarray(x, dtype=np.complex128)
     om = np.asarray(om, dtype=np.float64)
+    cache = direct_band_cache(mat, band)
     if y is None:
-        r = apply_generated(mat, x, band=band) - x * om[None, :]
+        r = apply_generated(mat, x, band=band, cache=cache) - x * om[None, :]
         return np.linalg.norm(r, axis=0) / (np.abs(om) * np.linalg.norm(x, axis=0))
     y = np.asarray(y, dtype=np.complex128)
-    top = apply_generated(mat, x, y, band=band) - x * om[None, :]
-    # bottom = -conj(A conj(Y) + B conj(X)) - omega Y
-    bot = -np.conj(apply_generated(mat, np.conj(y), np.conj(x), band=band)) - y * om[None, :]
+    top = apply_generated(mat, x, y, band=band, cache=cache) - x * om[None, :]
+    bot = -np.conj(apply_generated(mat, np.conj(y), np.conj(x), band=band, cache=cache)) - y * om[None, :]
     rn = np.sqrt(np.linalg.norm(top, axis=0) ** 2 + np.linalg.norm(bot, axis=0) ** 2)
     vn = np.sqrt(np.linalg.norm(x, axis=0) ** 2 + np.linalg.norm(y, axis=0) ** 2)
     return rn / (np.abs(om) * vn)
+
+
+def lambda_min_generated(mat, tol=1e-12, max_steps=4000, check_every=20, seed=0x5EED, band=DEFAULT_BAND):
+    """Smallest eigenvalue of the Hermitian A of a seeded matrix (B is not used), for sizes beyond
+    dense storage.  Plain Lanczos with full reorthogonalization (classical Gram-Schmidt, applied
+    twice against every earlier vector) from a seeded normal start; the Ritz values are the
+    eigenvalues of the tridiagonal projection (numpy's dense symmetric eigensolver on it).  Stops
+    once the smallest Ritz pair's residual |beta_m s_m| is <= tol * max|theta|, then recomputes
+    that residual explicitly with the operator.  Returns (lambda_min, residual norm, steps).
+    For a Hermitian matrix the smallest Ritz value is within that residual of an eigenvalue."""
+    import synth
+    n = mat.n
+    cache = direct_band_cache(mat, band, max_bytes=16 << 30)
+
+    def op(v):
+        return apply_generated(mat, v[:, None], band=band, cache=cache)[:, 0]
+
+    m_max = min(max_steps, n)
+    basis = np.empty((m_max + 1, n), dtype=np.complex128)
+    v = synth.test_vectors(seed, n, 1)[:, 0]
+    basis[0] = v / np.linalg.norm(v)
+    diag, off = [], []
+    for j in range(m_max):
+        w = op(basis[j])
+        diag.append(float(np.real(np.vdot(basis[j], w))))
+        for _ in range(2):
+            h = np.conj(basis[: j + 1]) @ w
+            w = w - h @ basis[: j + 1]
+        b = float(np.linalg.norm(w))
+        m = j + 1
+        if m % check_every == 0 or m == m_max or b == 0.0:
+            t = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+            theta, sv = np.linalg.eigh(t)
+            if abs(b * sv[-1, 0]) <= tol * np.max(np.abs(theta)) or m == m_max or b == 0.0:
+                x = sv[:, 0] @ basis[:m]
+                r = float(np.linalg.norm(op(x) - theta[0] * x) / np.linalg.norm(x))
+                return float(theta[0]), r, m
+        off.append(b)
+        basis[j + 1] = w / b
+    raise AssertionError("unreachable")
 
 
 # ---------------------------------------------------------------------------

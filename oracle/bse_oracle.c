@@ -831,3 +831,63 @@ int orc_grad_ph(int64_t n, int64_t k, const cplx* x, const cplx* y, const double
   free(wgt);
   return ORC_OK;
 }
+
+/* Complex product written out (C's operator also handles infinities through a
+   library call, which dominates these loops; the operands here are finite). */
+static inline cplx cmul(cplx a, cplx b) {
+  double ar = creal(a), ai = cimag(a), br = creal(b), bi = cimag(b);
+  return CMPLX(ar * br - ai * bi, ar * bi + ai * br);
+}
+
+/* ------------------------------------------------------------------ */
+/* Band of a Hermitian matrix applied to vectors (the direct term of    */
+/* the seeded synthetic matrices at sizes beyond dense storage).        */
+/* ------------------------------------------------------------------ */
+
+/*
+ * y += W_rows x, where W is Hermitian and the caller holds the upper band of
+ * rows i0..i1-1: wb[(i - i0) * band + d] = W[i, i + d] for 0 <= d < band
+ * (entries with i + d >= n are ignored).  Those rows contribute
+ *   y[i]     += W[i, i + d] x[i + d]            (d >= 0, the upper part)
+ *   y[i + d] += conj(W[i, i + d]) x[i]          (d >= 1, the mirrored lower part).
+ * x and y are n x nv, row-major (row i holds the nv vectors' entries i).
+ * Both sums are written as gathers, so rows are independent.
+ */
+int orc_band_apply(int64_t n, int64_t i0, int64_t i1, int64_t band, const cplx* wb, int64_t nv,
+                   const cplx* x, cplx* y) {
+  if (n <= 0 || i0 < 0 || i1 > n || i0 >= i1 || band <= 0 || nv <= 0 || !wb || !x || !y)
+    return ORC_INVALID;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = i0; i < i1; ++i) {
+    const cplx* w = wb + (size_t)(i - i0) * band;
+    int64_t dmax = (n - i < band) ? n - i : band;
+    for (int64_t d = 0; d < dmax; ++d) {
+      cplx wij = w[d];
+      const cplx* xr = x + (size_t)(i + d) * nv;
+      cplx* yr = y + (size_t)i * nv;
+      for (int64_t c = 0; c < nv; ++c) yr[c] += cmul(wij, xr[c]);
+    }
+  }
+  /* mirrored part, by tiles of target rows so that each tile is written by one thread and
+     each source row's band is read contiguously */
+  int64_t j1 = (i1 + band - 1 < n) ? i1 + band - 1 : n;
+  const int64_t tile = 256;
+#pragma omp parallel for schedule(static)
+  for (int64_t t0 = i0 + 1; t0 < j1; t0 += tile) {
+    int64_t t1 = (t0 + tile < j1) ? t0 + tile : j1;
+    int64_t lo = (t0 - band + 1 > i0) ? t0 - band + 1 : i0;
+    int64_t hi = (t1 - 1 < i1) ? t1 - 1 : i1; /* source rows i < t1 - 1 + 1 */
+    for (int64_t i = lo; i < hi; ++i) {
+      const cplx* w = wb + (size_t)(i - i0) * band;
+      const cplx* xr = x + (size_t)i * nv;
+      int64_t dlo = (t0 - i > 1) ? t0 - i : 1;
+      int64_t dhi = (t1 - i < band) ? t1 - i : band; /* d < dhi */
+      for (int64_t d = dlo; d < dhi; ++d) {
+        cplx wij = conj(w[d]);
+        cplx* yr = y + (size_t)(i + d) * nv;
+        for (int64_t c = 0; c < nv; ++c) yr[c] += cmul(wij, xr[c]);
+      }
+    }
+  }
+  return ORC_OK;
+}

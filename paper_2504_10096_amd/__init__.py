@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("fused_vectors", ctypes.c_int64), ("block", ctypes.c_int32), ("reserved_", ctypes.c_int32),
                 ("ms_gemm", ctypes.c_double), ("gemm_flops", ctypes.c_double),
                 ("ms_dense_form", ctypes.c_double), ("ms_dense_factor", ctypes.c_double),
-                ("ms_dense_eig", ctypes.c_double)]
+                ("ms_dense_eig", ctypes.c_double), ("ms_matvec", ctypes.c_double), ("ms_orth", ctypes.c_double),
+                ("ms_small", ctypes.c_double), ("ms_restart", ctypes.c_double), ("ms_residual", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

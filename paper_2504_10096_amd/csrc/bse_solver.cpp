@@ -200,6 +200,14 @@ struct Solver {
   double ms_mh = 0.0;
   bool trace = false;  // BSE_TRACE=1: one JSON line per restart on stderr
   double ms_blk32 = 0.0, ms_blk64 = 0.0;
+  int64_t passes32 = 0;  // passes over the hi triangles alone
+  // per-phase times: the orthogonalization of a step (sampled, every 8th
+  // step, as event intervals between and after its passes), the host
+  // projected eigensolves and the rest of the restarts (host wall time after
+  // the stream is idle)
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_orth;
+  int64_t orth_steps = 0, orth_samples = 0;
+  double ms_orth = 0.0, ms_small = 0.0, ms_restart = 0.0;
   ~Solver() {
     for (auto& p : ev_pending) {
       ev_free.push_back(p.first.first);
@@ -212,6 +220,10 @@ struct Solver {
     for (auto& p : ev_gemm) {
       ev_free.push_back(p.first.first);
       ev_free.push_back(p.first.second);
+    }
+    for (auto& p : ev_orth) {
+      ev_free.push_back(p.first);
+      ev_free.push_back(p.second);
     }
     for (hipEvent_t e : ev_free) (void)hipEventDestroy(e);
   }
@@ -253,6 +265,15 @@ void harvest_events(Solver& S) {
     S.ev_free.push_back(p.first.second);
   }
   S.ev_gemm.clear();
+  // orthogonalization intervals: a sampled step contributes one or two pairs,
+  // counted once per step by orth_samples at recording time
+  for (auto& p : S.ev_orth) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) S.ms_orth += ms;
+    S.ev_free.push_back(p.first);
+    S.ev_free.push_back(p.second);
+  }
+  S.ev_orth.clear();
 }
 
 // Event pair around a group of GEMMs (nullptr events when the pool is empty).
@@ -360,6 +381,7 @@ bse_status pass(Solver& S, Arith ar, int op /*0: A, 1: K1, 2: K2*/, const double
                     S.s, e0, e1);
   HIP_TRY(h, e);
   ++S.passes;
+  if (ar == bse::AR_HI || ar == bse::AR_HI64) ++S.passes32;
   return BSE_OK;
 }
 
@@ -385,6 +407,7 @@ bse_status passes_n(Solver& S, Arith ar, int op, int nv, const double2* v, doubl
   const bse::BMode bm = op == 0 ? bse::BM_NONE : bse::BM_CONJ;
   HIP_TRY(h, bse::mk_apply(h->L, ar, bm, mm, nv, v, S.ld, op == 2 ? -1.0 : 1.0, h->mhpart, out, S.ld, S.s, e0, e1));
   ++S.passes;
+  if (ar == bse::AR_HI || ar == bse::AR_HI64) ++S.passes32;
   return BSE_OK;
 }
 
@@ -428,6 +451,32 @@ bse_status init_basis(Solver& S, Arith ar, uint64_t seed) {
   return BSE_OK;
 }
 
+// Sampled timing of a step's orthogonalization: every 8th step records an
+// event where an orthogonalization stretch begins (after a pass) and one
+// where it ends (before the next pass, or at the end of the step).
+struct OrthTimer {
+  Solver& S;
+  bool on;
+  hipEvent_t e0 = nullptr;
+  explicit OrthTimer(Solver& s_) : S(s_), on(s_.orth_steps++ % 8 == 0 && s_.ev_free.size() >= 4) {
+    if (on) ++S.orth_samples;
+  }
+  hipError_t begin() {
+    if (!on || S.ev_free.size() < 2) return hipSuccess;
+    e0 = S.ev_free.back();
+    S.ev_free.pop_back();
+    return hipEventRecord(e0, S.s);
+  }
+  hipError_t end() {
+    if (!e0) return hipSuccess;
+    hipEvent_t e1 = S.ev_free.back();
+    S.ev_free.pop_back();
+    S.ev_orth.push_back({e0, e1});
+    e0 = nullptr;
+    return hipEventRecord(e1, S.s);
+  }
+};
+
 // Block Lanczos step: basis block [c0, c0 + b) -> next block [c0 + b, c0 + 2b).
 // TDA: W = A U_J, CGS2 against the basis.  PH (K1 metric, operator K2 K1):
 // W = K2 P_J, CGS against [U, Y] (Y the partner space), Z_W = K1 W, CGS2
@@ -439,8 +488,10 @@ bse_status step(Solver& S, Arith ar, int c0) {
   const int cn = c0 + b;  // basis columns so far
   double2* W = S.U + (size_t)cn * S.ld;
   bse_status st;
+  OrthTimer ot(S);
   if (!S.ph) {
     if ((st = passes_n(S, ar, 0, b, S.U + (size_t)c0 * S.ld, W))) return st;
+    HIP_TRY(h, ot.begin());
     for (int it = 0; it < 2; ++it) {
       for (int q = 0; q < b; ++q) {
         double2* hq = S.H1 + (size_t)q * S.ncolmax;
@@ -461,6 +512,7 @@ bse_status step(Solver& S, Arith ar, int c0) {
     // [U, Y]: no extra pass over the matrix.
     double2* kp = S.KP + (size_t)c0 * S.ld;
     if ((st = passes_n(S, ar, 2, b, S.P + (size_t)c0 * S.ld, kp))) return st;  // K2 P_J
+    HIP_TRY(h, ot.begin());
     for (int q = 0; q < b; ++q) {
       // partner of column c0 + q: y = i p, K1 y = i K2 p
       double2* y = S.Y + (size_t)S.ny * S.ld;
@@ -482,7 +534,9 @@ bse_status step(Solver& S, Arith ar, int c0) {
     }
     HIP_TRY(h, bse::acc_cols(S.Tc + (size_t)c0 * S.ldT, S.ldT, S.H1, S.ncolmax, cn, b, 1, S.s));
     double2* zw = S.P + (size_t)cn * S.ld;
+    HIP_TRY(h, ot.end());
     if ((st = passes_n(S, ar, 1, b, W, zw))) return st;  // Z_W = K1 W
+    HIP_TRY(h, ot.begin());
     for (int q = 0; q < b; ++q) {
       double2* hq = S.H1 + (size_t)q * S.ncolmax;
       double2* w = W + (size_t)q * S.ld;
@@ -492,6 +546,7 @@ bse_status step(Solver& S, Arith ar, int c0) {
     HIP_TRY(h, bse::acc_cols(S.Tc + (size_t)c0 * S.ldT, S.ldT, S.H1, S.ncolmax, cn, b, 1, S.s));
   }
   if ((st = orth_block(S, cn, b, c0))) return st;
+  HIP_TRY(h, ot.end());
   if (ar == bse::AR_HI || ar == bse::AR_HI64)
     S.steps32 += b;
   else
@@ -530,6 +585,7 @@ bse_status restart(Solver& S, RitzInfo& R) {
   HIP_TRY(h, hipMemcpyAsync(tc.data(), S.Tc, sizeof(double2) * tc.size(), hipMemcpyDeviceToHost, S.s));
   bse_status st = check_flag(S);
   if (st) return st;
+  const double t_rs = now_ms();  // the stream is idle from here
   // filled entries: column c >= nka holds rows [0, cn(c)) from the CGS rounds
   // and rows cn(c) + p, p <= c - c0(c), of the block factor; the kept block
   // is diag(theta_keep).  T is the symmetric (Hermitian) average of them.
@@ -564,6 +620,7 @@ bse_status restart(Solver& S, RitzInfo& R) {
   std::vector<double> th(m);
   std::vector<cplx> Zc((size_t)m * m);
   std::vector<double> Zr;
+  const double t_eig = now_ms();
   if (S.ph) {
     std::vector<double> Tr((size_t)m * m);
     Zr.resize((size_t)m * m);
@@ -575,6 +632,8 @@ bse_status restart(Solver& S, RitzInfo& R) {
     if (!bse::herm_eig(m, reinterpret_cast<double2*>(T.data()), th.data(), reinterpret_cast<double2*>(Zc.data())))
       return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
   }
+  const double ms_eig = now_ms() - t_eig;
+  S.ms_small += ms_eig;
   if (S.ph && th[0] <= 0.0)
     return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE,
                 "non-positive folded Ritz value omega^2: M is not positive definite");
@@ -661,6 +720,7 @@ bse_status restart(Solver& S, RitzInfo& R) {
   S.nka = keep;
   S.theta_keep.assign(th.begin(), th.begin() + keep);
   ++S.restarts;
+  S.ms_restart += now_ms() - t_rs - ms_eig;
   return BSE_OK;
 }
 
@@ -701,11 +761,15 @@ bse_status step_g(Solver& S, Arith ar, int c) {
   double2* w = PG + (size_t)c * ld;
   double2* kw = KPG + (size_t)c * ld;
   double2* Bc = S.Tc + (size_t)c * S.ldT;
+  OrthTimer ot(S);
+  HIP_TRY(h, ot.begin());
   HIP_TRY(h, bse::copy_cols(KU + (size_t)c * ld, ld, w, ld, n, 1, S.s));
   HIP_TRY(h, bse::cdot(KPG, c, KU, c + 1, ld, w, n, S.cpart, S.H1, S.s));
   HIP_TRY(h, bse::cgemv_sub(PG, c, U, c + 1, nullptr, nullptr, ld, S.H1, 2, w, nullptr, n, S.s));
   HIP_TRY(h, bse::acc_cols(Bc, S.ldT, S.H1, S.ncolmax, c, 1, 1, S.s));
+  HIP_TRY(h, ot.end());
   if ((st = pass(S, ar, 2, w, kw))) return st;  // K2 w
+  HIP_TRY(h, ot.begin());
   HIP_TRY(h, bse::cdot(KPG, c, KU, c + 1, ld, w, n, S.cpart, S.H1, S.s));
   HIP_TRY(h, bse::cgemv_sub(PG, c, U, c + 1, KPG, KU, ld, S.H1, 2, w, kw, n, S.s));
   HIP_TRY(h, bse::acc_cols(Bc, S.ldT, S.H1, S.ncolmax, c, 1, 1, S.s));
@@ -718,11 +782,14 @@ bse_status step_g(Solver& S, Arith ar, int c) {
   HIP_TRY(h, bse::cdot(KU, c + 1, KPG, c + 1, ld, v, n, S.cpart, S.H1, S.s));
   HIP_TRY(h, bse::cgemv_sub(U, c + 1, PG, c + 1, nullptr, nullptr, ld, S.H1, 2, v, nullptr, n, S.s));
   HIP_TRY(h, bse::acc_cols(Cc, S.ldT, S.H1, S.ncolmax, c + 1, 1, 1, S.s));
+  HIP_TRY(h, ot.end());
   if ((st = pass(S, ar, 1, v, kv))) return st;  // K1 w
+  HIP_TRY(h, ot.begin());
   HIP_TRY(h, bse::cdot(KU, c + 1, KPG, c + 1, ld, v, n, S.cpart, S.H1, S.s));
   HIP_TRY(h, bse::cgemv_sub(U, c + 1, PG, c + 1, KU, KPG, ld, S.H1, 2, v, kv, n, S.s));
   HIP_TRY(h, bse::acc_cols(Cc, S.ldT, S.H1, S.ncolmax, c + 1, 1, 1, S.s));
   HIP_TRY(h, bse::normalize(v, kv, n, nullptr, nullptr, 0, nullptr, (double*)(Cc + c + 1), 0, S.flag, S.red, S.s));
+  HIP_TRY(h, ot.end());
   if (ar == bse::AR_HI || ar == bse::AR_HI64)
     S.steps32 += 1;
   else
@@ -748,6 +815,7 @@ bse_status restart_g(Solver& S, RitzInfo& R) {
   HIP_TRY(h, hipMemcpyAsync(tcv.data(), S.Tc2, sizeof(double2) * tcv.size(), hipMemcpyDeviceToHost, S.s));
   bse_status st = check_flag(S);
   if (st) return st;
+  const double t_rs = now_ms();  // the stream is idle from here
   // Bs[i][c]: coefficient of p_i in K1 u_c
   auto bfill = [&](int i, int c) { return c < nka ? i == c : i <= c; };
   auto cfill = [&](int c, int i) { return i < nka ? c == i : c <= i + 1; };  // u_c in K2 p_i
@@ -771,8 +839,11 @@ bse_status restart_g(Solver& S, RitzInfo& R) {
   for (double v : J)
     if (!std::isfinite(v)) return fail(h, BSE_ERR_NONFINITE, "non-finite projected matrix");
   std::vector<double> ev(m2), Ze((size_t)m2 * m2);
+  const double t_eig = now_ms();
   if (!bse::sym_eig(m2, J.data(), ev.data(), Ze.data()))
     return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
+  const double ms_eig = now_ms() - t_eig;
+  S.ms_small += ms_eig;
   // positive half, ascending: w_j = ev[m + j]; z = sqrt(2) e_top, y = sqrt(2) e_bottom
   std::vector<double> sg(m), Zr((size_t)m * m), Yr((size_t)m * m);
   for (int j = 0; j < m; ++j) {
@@ -839,6 +910,7 @@ bse_status restart_g(Solver& S, RitzInfo& R) {
   S.nka = keep;
   S.theta_keep.assign(sg.begin(), sg.begin() + keep);  // variant 1: w, the diagonal of B
   ++S.restarts;
+  S.ms_restart += now_ms() - t_rs - ms_eig;
   return BSE_OK;
 }
 
@@ -1565,6 +1637,16 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
     stats->samples_fused = S.samples_mh;
     stats->ms_block_fused = S.ms_mh;
     stats->fused_vectors = S.mh_vectors;
+    // per phase: passes from the sampled block-kernel averages times the pass
+    // counts (the fused refinement reads are part of ms_residual), the
+    // orthogonalization from the sampled steps times the step count
+    const int64_t p32 = S.passes32, p64 = S.passes - S.passes32;
+    stats->ms_matvec = (S.samples32 ? S.ms_blk32 / S.samples32 * p32 : 0.0) +
+                       (S.samples64 ? S.ms_blk64 / S.samples64 * p64 : 0.0);
+    stats->ms_orth = S.orth_samples ? S.ms_orth / S.orth_samples * S.orth_steps : 0.0;
+    stats->ms_small = S.ms_small;
+    stats->ms_restart = S.ms_restart;
+    stats->ms_residual = ms_final;
   }
   if (!converged)
     return fail(h, BSE_ERR_NOT_CONVERGED, "max_restarts reached before all pairs met tol");

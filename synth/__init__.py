@@ -11,6 +11,7 @@ B0 = c Y Y^T (Y: N x 32, E|y|^2 = 1) scaled to a prescribed 2-norm.
 Host (``pack_host``) and device (``DeviceGen``) produce bit-identical entries.
 """
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -23,8 +24,8 @@ NPHASE = 65536
 EPS_LO, EPS_HI = 1.0, 8.0
 X_VAR, Y_VAR = 0.25, 1.0
 W_AMP, W_DECAY = 0.3, 64.0
-LAMBDA_LB_TARGET = 1.0  # certified lower bound of lambda_min(A) for PH workloads (eV)
-B_NORM_FRAC = 0.25      # ||B||_2 = 0.25 * (certified lower bound of lambda_min(A))
+LAMBDA_MIN_TARGET = 1.0  # lambda_min(A) of the pseudo-Hermitian workloads after the shift (eV)
+B_NORM_FRAC = 0.25       # ||B||_2 = 0.25 * lambda_min(A)
 
 STREAM_EPS, STREAM_X, STREAM_Y, STREAM_W, STREAM_LOSS, STREAM_VEC = 1, 2, 3, 4, 5, 6
 
@@ -123,25 +124,71 @@ class Tables:
         return float(_lib_host().syn_sym_factor_norm(self.n, _ptr(self.yr), _ptr(self.yi)))
 
 
-class Matrix:
-    """A seeded synthetic matrix pair: parameters + tables."""
+SHIFTS_FILE = os.path.join(HERE, "shifts.json")
+_shifts = None
 
-    def __init__(self, n, seed, ph, alpha=1.0, beta=1.0, shift=None, b_norm=None, tables=None):
+
+def recorded_lambda_min_raw(n, seed):
+    """lambda_min of the raw block A_raw (no shift, alpha = beta = 1) as recorded in shifts.json
+    (computed once by the FP64 oracle, see oracle/make_shifts.py), or None."""
+    global _shifts
+    if _shifts is None:
+        import json
+        _shifts = json.load(open(SHIFTS_FILE)) if os.path.exists(SHIFTS_FILE) else {}
+    rec = _shifts.get(f"{int(n)}:{int(seed)}")
+    return None if rec is None else float(rec["lambda_min_raw"])
+
+
+def recipe_shift(lambda_min_raw):
+    """s = 1 - lambda_min(A_raw), rounded up to 1e-6 eV (0 if A_raw is already above 1 eV)."""
+    return max(0.0, math.ceil((LAMBDA_MIN_TARGET - float(lambda_min_raw)) * 1e6) / 1e6)
+
+
+class Matrix:
+    """A seeded synthetic matrix pair: parameters + tables.
+
+    Pseudo-Hermitian recipes (``recipe``):
+      "baseline"  s = 1 - lambda_min(A_raw) rounded up to 1e-6 eV, so lambda_min(A) = 1 eV, and
+                  ||B||_2 = 0.25 lambda_min(A).  lambda_min(A_raw) is passed in
+                  (``lambda_min_raw``) or looked up in shifts.json; this module computes no
+                  eigenvalues.
+      "certified" s from a Gershgorin bound of the direct term (lambda_min(A) >= 1 eV without an
+                  eigen-solve, in practice lambda_min(A) ~ 35 eV and weak coupling,
+                  ||B||_2 = 0.25 eV); kept as a named extra workload.
+    TDA matrices are literal (no shift, no B).
+    """
+
+    def __init__(self, n, seed, ph, alpha=1.0, beta=1.0, shift=None, b_norm=None, tables=None,
+                 recipe="baseline", lambda_min_raw=None):
         self.tables = tables if tables is not None else Tables(n, seed)
         self.n, self.seed, self.ph = int(n), int(seed), bool(ph)
         self.alpha, self.beta = float(alpha), float(beta)
         t = self.tables
         self.r_w = t.direct_row_radius()
-        if shift is None:
-            if ph:
-                # certified: lambda_min(A) >= eps_min + s - beta*r_W  (Kx is PSD)
-                shift = max(0.0, LAMBDA_LB_TARGET - (float(t.eps[0]) - self.beta * self.r_w))
+        self.recipe = recipe if ph else "literal"
+        self.lambda_min_raw = None
+        if shift is None and ph:
+            if recipe == "baseline":
+                lm = lambda_min_raw if lambda_min_raw is not None else recorded_lambda_min_raw(n, seed)
+                if lm is None:
+                    raise ValueError(f"no recorded lambda_min(A_raw) for n={n}, seed={seed}: pass "
+                                     "lambda_min_raw= (from the oracle), or run oracle/make_shifts.py "
+                                     f"{n}:{seed}, or use recipe='certified'")
+                self.lambda_min_raw = float(lm)
+                shift = recipe_shift(lm)
+            elif recipe == "certified":
+                # lambda_min(A) >= eps_min + s - beta*r_W  (Kx is PSD)
+                shift = max(0.0, LAMBDA_MIN_TARGET - (float(t.eps[0]) - self.beta * self.r_w))
             else:
-                shift = 0.0
-        self.shift = float(shift)
-        self.lambda_lb = float(t.eps[0]) + self.shift - self.beta * self.r_w
+                raise ValueError(f"unknown recipe {recipe!r}")
+        self.shift = float(shift) if shift is not None else 0.0
+        if self.lambda_min_raw is not None:
+            # lambda_min(A) at alpha = beta = 1 (the shift is fixed under changes of alpha, beta)
+            self.lambda_min_a = self.lambda_min_raw + self.shift
+        else:
+            self.lambda_min_a = float(t.eps[0]) + self.shift - self.beta * self.r_w
         if b_norm is None:
-            b_norm = B_NORM_FRAC * self.lambda_lb if ph else 0.0
+            b_norm = B_NORM_FRAC * self.lambda_min_a if ph else 0.0
         self.b_norm = float(b_norm)
         sig = t.sym_factor_norm() if ph else 1.0
         self.b0_scale = self.b_norm / sig if ph else 0.0
@@ -225,8 +272,8 @@ class DeviceGen:
             pass
 
 
-# Workloads: (kind, N, k, tol, seed).  PH workloads use the certified shift and
-# ||B||_2 = 0.25 * lambda_lb; TDA workloads are literal (no shift, no B).
+# Workloads: (kind, N, k, tol, seed).  PH workloads use the "baseline" recipe (lambda_min(A) = 1 eV,
+# ||B||_2 = 0.25 lambda_min(A)); TDA workloads are literal (no shift, no B).
 WORKLOADS = {
     0: dict(name="tda_n1024_k16", ph=False, n=1024, k=16, tol=1e-10, seed=10096),
     1: dict(name="ph_n4096_k32", ph=True, n=4096, k=32, tol=1e-10, seed=10097),

@@ -9,6 +9,22 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
+def ph_matrix(n, seed, **kw):
+    """Pseudo-Hermitian synthetic matrix by the baseline recipe (lambda_min(A) = 1 eV,
+    ||B||_2 = 0.25 lambda_min(A)), with lambda_min(A_raw) taken from the dense FP64 oracle."""
+    import oracle
+    import synth
+    raw = synth.Matrix(n, seed, ph=False)
+    lam, _ = oracle.tda(raw.pack_host(0), 1, vectors=False)
+    return synth.Matrix(n, seed, ph=True, tables=raw.tables, lambda_min_raw=float(lam[0]), **kw)
+
+
+def synth_matrix(n, seed, ph, **kw):
+    """TDA (literal) or pseudo-Hermitian (baseline recipe) synthetic matrix."""
+    import synth
+    return ph_matrix(n, seed, **kw) if ph else synth.Matrix(n, seed, ph=False, **kw)
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP C-ABI library)")
     config.addinivalue_line("markers", "slow: long CPU test")

@@ -39,7 +39,8 @@ def make_ph4096():
     ap, bp = m.pack_host(0), m.pack_host(1)
     t = time.time()
     om, _, _ = oracle.ph(ap, bp, w["k"], vectors=False)
-    write("ph_n4096_k32.txt", 1, om, {"shift": repr(m.shift), "b_norm": repr(m.b_norm),
+    write("ph_n4096_k32.txt", 1, om, {"recipe": m.recipe, "lambda_min_raw": repr(m.lambda_min_raw),
+                                       "shift": repr(m.shift), "b_norm": repr(m.b_norm),
                                        "oracle_seconds": f"{time.time() - t:.1f}"})
 
 

@@ -16,7 +16,7 @@ import pytest
 import oracle
 import oracle.haydock as hy
 import synth
-from conftest import pack_upper, random_herm, random_sym
+from conftest import pack_upper, ph_matrix, random_herm, random_sym
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -26,20 +26,9 @@ OK, INVALID, OOM, DEVICE, NOT_PD, NOT_CONV, NONFINITE, BAD_STATE = range(8)
 vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 
 
-class Opts(ctypes.Structure):
-    _fields_ = [("ncv", i32), ("keep", i32), ("max_restarts", i32), ("precision", i32), ("switch_tol", dbl),
-                ("start_seed", ctypes.c_uint64), ("fp32_arith", i32), ("block", i32), ("refine_start", i32),
-                ("variant", i32)]
-
-
-class Stats(ctypes.Structure):
-    _fields_ = [("n_converged", i32), ("restarts", i32), ("steps_fp32", i64), ("steps_fp64", i64),
-                ("passes", i64), ("ms_total", dbl), ("ms_fp32_phase", dbl), ("ms_fp64_phase", dbl),
-                ("ms_final", dbl), ("max_rel_residual", dbl), ("bytes_per_pass_fp32", dbl),
-                ("bytes_per_pass_fp64", dbl), ("samples_fp32", i64), ("samples_fp64", i64),
-                ("ms_block_fp32", dbl), ("ms_block_fp64", dbl), ("samples_fused", i64), ("ms_block_fused", dbl),
-                ("fused_vectors", i64), ("block", i32), ("reserved_", i32), ("ms_gemm", dbl), ("gemm_flops", dbl),
-                ("ms_dense_form", dbl), ("ms_dense_factor", dbl), ("ms_dense_eig", dbl)]
+# the ABI structs of include/bse.h, as the binding declares them (kept in one place so that a field
+# added to the header cannot leave a shorter struct here for the library to write past)
+from paper_2504_10096_amd import SolveOpts as Opts, Stats  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -105,7 +94,7 @@ class Handle:
 
 
 def ph_case(n=120, seed=5):
-    m = synth.Matrix(n, seed, ph=True)
+    m = ph_matrix(n, seed)
     return m.pack_host(0), m.pack_host(1)
 
 

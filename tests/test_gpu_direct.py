@@ -10,7 +10,7 @@ import torch
 import oracle
 import paper_2504_10096_amd as bse
 import synth
-from conftest import pack_upper, random_herm, random_sym
+from conftest import pack_upper, ph_matrix, random_herm, random_sym
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +57,7 @@ def check_ph(s, ap, bp, k, tol=1e-12):
 @pytest.mark.parametrize("n,k", [(300, 8), (1000, 12)])
 def test_direct_ph_synth(n, k):
     print(f"direct ph n={n}", flush=True)
-    m = synth.Matrix(n, 200 + n, ph=True)
+    m = ph_matrix(n, 200 + n)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s = make_solver("ph", ap, bp)
     check_ph(s, ap, bp, k)
@@ -152,7 +152,7 @@ def test_direct_workload_ph_n4096_golden():
 
 def test_direct_backward_matches_iterative():
     n, k = 500, 6
-    m = synth.Matrix(n, 55, ph=True)
+    m = ph_matrix(n, 55)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s = make_solver("ph", ap, bp)
     g = torch.as_tensor(synth.loss_weights(3, k))

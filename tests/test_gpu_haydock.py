@@ -11,7 +11,7 @@ import torch
 import oracle.haydock as hy
 import paper_2504_10096_amd as bse
 import synth
-from conftest import pack_upper, random_herm, random_sym
+from conftest import pack_upper, ph_matrix, random_herm, random_sym, synth_matrix
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +48,7 @@ def exact_chi(kind, ap, bp, d, z):
 
 
 def case(kind, n):
-    m = synth.Matrix(n, 400 + n, ph=kind == "ph")
+    m = synth_matrix(n, 400 + n, kind == "ph")
     ap = m.pack_host(0)
     bp = m.pack_host(1) if kind == "ph" else None
     return ap, bp, synth.dipole(n, n), window(m)
@@ -57,7 +57,7 @@ def case(kind, n):
 def window(m):
     """Frequencies covering the spectrum of a seeded matrix: from below its certified lower
     bound to above eps_max + shift + the direct term's row radius."""
-    return m.lambda_lb - 1.0, m.shift + 9.0 + m.beta * m.r_w
+    return m.lambda_min_a - 1.0, m.shift + 9.0 + m.beta * m.r_w
 
 
 @pytest.mark.parametrize("kind", ["tda", "ph"])
@@ -140,7 +140,7 @@ def test_tiny_sizes_fraction_is_exact(n):
 
 def test_b_zero_and_standalone_spectrum():
     n = 400
-    m = synth.Matrix(n, 91, ph=True)
+    m = ph_matrix(n, 91)
     ap = m.pack_host(0)
     bp = np.zeros_like(ap)
     d = synth.dipole(91, n)

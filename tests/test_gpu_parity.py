@@ -13,7 +13,7 @@ import torch
 import oracle
 import paper_2504_10096_amd as bse
 import synth
-from conftest import pack_upper, random_herm, random_sym
+from conftest import pack_upper, ph_matrix, random_herm, random_sym, synth_matrix
 
 pytestmark = pytest.mark.gpu
 
@@ -118,7 +118,7 @@ def test_matvec_tda_handle_and_c64_input(monkeypatch):
 
 def test_chunked_ingest_equals_whole():
     n = 700
-    m = synth.Matrix(n, 21, ph=True)
+    m = ph_matrix(n, 21)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s1 = make_solver("ph", ap, bp)
     s2 = bse.Solver("ph", n)
@@ -173,7 +173,7 @@ def test_solve_tda_synth(n, k):
 @pytest.mark.parametrize("n,k", [(300, 8), (900, 10)])
 def test_solve_ph_synth(n, k, variant):
     print(f"ph synth n={n} k={k} variant={variant}", flush=True)
-    m = synth.Matrix(n, 200 + n, ph=True)
+    m = ph_matrix(n, 200 + n)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s = make_solver("ph", ap, bp)
     check_ph(s, ap, bp, k, 1e-10, 1e-10, variant=variant)
@@ -247,7 +247,7 @@ def test_real_blocks_no_duplicate_pairs(variant):
 @pytest.mark.parametrize("variant", [0, 1])
 def test_b_zero_reduces_to_tda(variant):
     n, k = 200, 8
-    m = synth.Matrix(n, 77, ph=True)
+    m = ph_matrix(n, 77)
     ap = m.pack_host(0)
     bp = np.zeros_like(ap)
     s = make_solver("ph", ap, bp)
@@ -318,7 +318,7 @@ def test_nonfinite_input():
 
 
 def test_deterministic_bitwise():
-    m = synth.Matrix(600, 8, ph=True)
+    m = ph_matrix(600, 8)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s = make_solver("ph", ap, bp)
     a = s.solve(6, 1e-10)
@@ -345,7 +345,7 @@ def test_mixed_tda_matches_oracle():
 @pytest.mark.parametrize("variant", [0, 1])
 def test_mixed_ph_matches_oracle(variant):
     n, k = 900, 10
-    m = synth.Matrix(n, 32, ph=True)
+    m = ph_matrix(n, 32)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s = make_solver("ph", ap, bp, storage="hilo")
     om, X, Y, st = s.solve(k, 1e-8, precision="mixed", variant=variant)
@@ -361,7 +361,7 @@ def test_mixed_fp32_arith_ph_loose_tol():
     # complex FP32 arithmetic in the bulk passes: the FP64 residual of its Ritz pairs sits near
     # 1e-7 for every pair, so a 1e-6 target is met with no refinement sweep beyond the check
     n, k, tol = 900, 10, 1e-6
-    m = synth.Matrix(n, 32, ph=True)
+    m = ph_matrix(n, 32)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s = make_solver("ph", ap, bp, storage="hilo")
     om, X, Y, st = s.solve(k, tol, precision="mixed", fp32_arith=True)
@@ -390,7 +390,7 @@ def test_block_tda_matches_oracle(block):
 
 def test_block_ignored_for_ph():
     n, k = 600, 6
-    m = synth.Matrix(n, 34, ph=True)
+    m = ph_matrix(n, 34)
     ap, bp = m.pack_host(0), m.pack_host(1)
     s = make_solver("ph", ap, bp)
     om, X, Y, st = s.solve(k, 1e-10, block=4)
@@ -418,7 +418,7 @@ def test_backward_tda_parity():
 def test_backward_many_tiles_and_chunks(kind):
     # 11 x 11 output tiles of 64 (ragged last), k = 20 = two full chunks of 8 and a partial one
     n, k = 700, 20
-    m = synth.Matrix(n, 43, ph=kind == "ph")
+    m = synth_matrix(n, 43, kind == "ph")
     ap = m.pack_host(0)
     bp = m.pack_host(1) if kind == "ph" else None
     s = make_solver(kind, ap, bp)
@@ -477,7 +477,7 @@ def test_autograd_function():
 # ------------------------------------------------------------ input generator
 def test_device_generator_bitwise():
     n = 1024
-    m = synth.Matrix(n, 10096, ph=True)
+    m = ph_matrix(n, 10096)
     g = synth.DeviceGen(m)
     for which in (0, 1):
         for j0, j1 in [(0, n), (300, 777)]:
@@ -536,7 +536,7 @@ def test_strength_components(kind):
     """Re<G, C> for packed, low-rank, diagonal and stored components against the
     oracle's packed gradient (same eigenvectors)."""
     n, k = 260, 6
-    m = synth.Matrix(n, 61, ph=(kind == "ph"))
+    m = synth_matrix(n, 61, (kind == "ph"))
     ap = m.pack_host(0)
     bp = m.pack_host(1) if kind == "ph" else None
     s = make_solver(kind, ap, bp)

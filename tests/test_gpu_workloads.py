@@ -58,6 +58,23 @@ def test_workload_tda_n32768_k64_mixed_and_fp64():
     idx = [0, k // 2, k - 1]
     rel = oracle.residual_generated(mat, lm[idx], host(X_m)[idx].T)
     assert np.max(rel) <= tol * 1.01, rel
+    # completeness cross-check: another Krylov process (other start vector) finds the same k
+    lam_s, _, _, st_s = s.solve(k, tol, precision="mixed", seed=7920)
+    assert st_s["max_rel_residual"] <= tol
+    assert np.max(np.abs(host(lam_s) - lm) / np.abs(lm)) < 1e-9
+    s.close()
+
+
+def test_recorded_lambda_min_raw_n16384():
+    """lambda_min of the raw block of the N = 16384 workload (no shift, the matrix the recipe's
+    shift is taken from): the FP64 GPU TDA path at k = 1 against the oracle's recorded value."""
+    w = synth.WORKLOADS[3]
+    raw = synth.Matrix(w["n"], w["seed"], ph=False)
+    ref = synth.recorded_lambda_min_raw(w["n"], w["seed"])
+    s = generated_solver(raw, "c128")
+    lam, X, _, st = s.solve(1, 1e-12)
+    print("lambda_min raw", host(lam)[0], ref, st["passes"], flush=True)
+    assert abs(host(lam)[0] - ref) <= 1e-11 * abs(ref)
     s.close()
 
 
@@ -68,8 +85,15 @@ def test_workload_ph_n16384_k32_gradient_fd():
     print(f"workload {w['name']}", flush=True)
     g = synth.loss_weights(w["seed"], k)
     s = generated_solver(mat, "c128")
-    om, X, Y, st = s.solve(k, 1e-12)
+    om1, X, Y, st = s.solve(k + 1, 1e-12)
     assert st["max_rel_residual"] <= 1e-12
+    om = om1[:k]
+    # the loss's last pair must stay separated from the next one under the +-h perturbations
+    gap = float(om1[k] - om1[k - 1])
+    assert gap > 1e-4, gap
+    # completeness cross-check: another start vector finds the same k + 1 pairs
+    om_s, _, _, st_s = s.solve(k + 1, 1e-10, seed=7921)
+    assert np.max(np.abs(host(om_s) - host(om1)) / host(om1)) < 1e-9
     n = mat.n
     t = mat.tables
     xf = torch.as_tensor(t.x_factor()).cuda()
@@ -86,7 +110,10 @@ def test_workload_ph_n16384_k32_gradient_fd():
     L0 = float(g @ host(om))
     assert abs(sa + sbb - L0) < 1e-10 * abs(L0)
     s.close()
-    h = 1e-4
+    # central differences with h = 1e-6 on alpha and beta: every FD solve is FP64 at tol 1e-12, so
+    # the eigenvalue noise (~1e-15 relative, ~1e-14 in L) is ~1e-8 after division by 2h, far below
+    # the 1e-6 acceptance; the O(h^2) truncation error is smaller still
+    h = 1e-6
     fd = {}
     for name, kw in [("alpha", "alpha"), ("beta", "beta")]:
         vals = []
@@ -130,7 +157,7 @@ def test_workload_haydock_first_steps(idx, storage):
     assert np.max(np.abs(host(al) - ref[0])) <= 1e-11 * np.max(np.abs(ref[0]))
     assert np.max(np.abs(host(be) - ref[1])) <= 1e-11 * np.max(np.abs(ref[1]))
     # the grid covers the spectrum: certified lower bound to eps_max + shift + row radius of W
-    freq = torch.linspace(max(mat.lambda_lb - 1.0, 0.05), mat.shift + 9.0 + mat.beta * mat.r_w, 256,
+    freq = torch.linspace(max(mat.lambda_min_a - 1.0, 0.05), mat.shift + 9.0 + mat.beta * mat.r_w, 256,
                           dtype=torch.float64, device="cuda")
     al, be, nn, chi, st = s.haydock(torch.as_tensor(d).cuda(), 2000, tol=1e-8, freq=freq, eta=0.1)
     n_done = al.numel()

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from conftest import unpack_herm, unpack_sym
+from conftest import ph_matrix, unpack_herm, unpack_sym
 
 
 def test_philox_known_answers():
@@ -29,23 +29,59 @@ def test_tables_distributions():
     assert t.amp[0] == 0.3 and abs(t.amp[64] - 0.3 / np.e) < 1e-15
 
 
-def test_recipe_certified_bounds():
-    """PH recipe: lambda_min(A) >= lambda_lb (certified) and ||B||_2 = 0.25 lambda_lb."""
+def test_recipe_baseline():
+    """Baseline PH recipe: lambda_min(A) = 1 eV (shift from lambda_min(A_raw), rounded up to
+    1e-6 eV), ||B||_2 = 0.25 lambda_min(A), M positive definite.  lambda_min(A_raw) comes from
+    numpy here, so the recipe is checked independently of the oracle that fills shifts.json."""
     n = 400
-    m = synth.Matrix(n, 11, ph=True)
+    raw = synth.Matrix(n, 11, ph=False)
+    lam_raw = np.linalg.eigvalsh(unpack_herm(raw.pack_host(0), n))[0]
+    assert lam_raw < 0  # the raw block is indefinite: the shift is needed
+    m = synth.Matrix(n, 11, ph=True, lambda_min_raw=lam_raw)
     A = unpack_herm(m.pack_host(0), n)
     B = unpack_sym(m.pack_host(1), n)
-    assert np.linalg.eigvalsh(A)[0] >= m.lambda_lb - 1e-12
-    assert abs(m.lambda_lb - 1.0) < 1e-12
-    assert abs(np.linalg.norm(B, 2) - 0.25 * m.lambda_lb) < 1e-12
+    lam = np.linalg.eigvalsh(A)[0]
+    assert 1.0 <= lam <= 1.0 + 1e-6 + 1e-12
+    assert abs(m.shift - (1.0 - lam_raw)) <= 1e-6 and m.shift * 1e6 == round(m.shift * 1e6)
+    assert abs(m.lambda_min_a - lam) < 1e-12
+    assert abs(np.linalg.norm(B, 2) - 0.25 * lam) < 1e-12
+    assert np.max(np.abs(B - B.T)) == 0.0
+    M = np.block([[A, B], [B.conj(), A.conj()]])
+    assert np.linalg.eigvalsh(M)[0] > 0
+    # the recorded table is used when no lambda_min_raw is given, and a size without a record fails
+    with pytest.raises(ValueError):
+        synth.Matrix(n, 11, ph=True)
+
+
+def test_recipe_certified_bounds():
+    """Certified PH recipe (extra workload): lambda_min(A) >= lambda_lb and ||B||_2 = 0.25 lambda_lb."""
+    n = 400
+    m = synth.Matrix(n, 11, ph=True, recipe="certified")
+    A = unpack_herm(m.pack_host(0), n)
+    B = unpack_sym(m.pack_host(1), n)
+    assert np.linalg.eigvalsh(A)[0] >= m.lambda_min_a - 1e-12
+    assert abs(m.lambda_min_a - 1.0) < 1e-12
+    assert abs(np.linalg.norm(B, 2) - 0.25 * m.lambda_min_a) < 1e-12
     assert np.max(np.abs(B - B.T)) == 0.0
     M = np.block([[A, B], [B.conj(), A.conj()]])
     assert np.linalg.eigvalsh(M)[0] > 0
 
 
+def test_recorded_shifts_cover_workloads():
+    """Every PH workload has a recorded lambda_min(A_raw), and at the smoke size it equals the
+    dense eigenvalue of the raw block (numpy)."""
+    for w in synth.WORKLOADS.values():
+        if w["ph"]:
+            assert synth.recorded_lambda_min_raw(w["n"], w["seed"]) is not None, w["name"]
+    n = 320
+    raw = synth.Matrix(n, 10097, ph=False)
+    ref = np.linalg.eigvalsh(unpack_herm(raw.pack_host(0), n))[0]
+    assert abs(synth.recorded_lambda_min_raw(n, 10097) - ref) < 1e-12
+
+
 def test_pack_chunks_consistent():
     n = 97
-    m = synth.Matrix(n, 5, ph=True)
+    m = ph_matrix(n, 5)
     full = m.pack_host(0)
     parts = [m.pack_host(0, j0, j1) for j0, j1 in [(0, 13), (13, 50), (50, 97)]]
     assert np.array_equal(np.concatenate(parts), full)
@@ -54,7 +90,7 @@ def test_pack_chunks_consistent():
 
 def test_entries_follow_recipe():
     n = 150
-    m = synth.Matrix(n, 3, ph=True, alpha=0.7, beta=1.3)
+    m = ph_matrix(n, 3, alpha=0.7, beta=1.3)
     t = m.tables
     A = unpack_herm(m.pack_host(0), n)
     x = t.x_factor()
@@ -70,7 +106,7 @@ def test_entries_follow_recipe():
 
 @pytest.mark.parametrize("n,band", [(300, synth.NPHASE), (700, 160)])
 def test_streaming_operator_matches_dense(n, band):
-    m = synth.Matrix(n, 9, ph=True)
+    m = ph_matrix(n, 9)
     A = unpack_herm(m.pack_host(0), n)
     B = unpack_sym(m.pack_host(1), n)
     xa = synth.test_vectors(1, n, 3)
