@@ -200,6 +200,28 @@ bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t n
                      void* y);
 
 /*
+ * bse_apply_noalloc -- bse_apply for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, layouts and results as bse_apply; the
+ * partial sums of the pass live in a fixed device array of
+ * BSE_NOALLOC_SCRATCH_BYTES held by each GPU the library runs on until the
+ * process ends, and the call allocates and frees nothing.  It runs on the
+ * handle's device (made current for the call).  Calls on one GPU share that
+ * array: calls that overlap in time on one GPU (other host threads, other
+ * streams) race and must be serialized by the caller.
+ * Limit: the partials of one read of the triangles must fit the array: a
+ * one-vector read needs 2 nblk R complex entries (R the block edge, nblk the
+ * number of stored R x R blocks), which allows N up to about 46000; the
+ * four-vector and fused full-H reads need several times that (the error
+ * message names the bytes needed).
+ * Errors: as bse_apply; INVALID_ARG with a message naming the bytes needed
+ * when the array is too small; DEVICE if the array cannot be located.
+ */
+#define BSE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+bse_status bse_apply_noalloc(bse_handle h, bse_op op, bse_precision precision, int64_t nvec,
+                             const void* x, void* y);
+
+/*
  * bse_solve -- the k lowest eigenpairs: TDA, the k smallest eigenvalues of A
  * (ascending); PH, the k smallest positive omega of H (ascending).
  *   omega: device, k doubles.

@@ -31,7 +31,7 @@ BLOCK_A, BLOCK_B = 0, 1
 OP_A, OP_K1, OP_K2, OP_H = 0, 1, 2, 3
 COMP_PACKED, COMP_LOWRANK, COMP_DIAG, COMP_STORED = 0, 1, 2, 3
 
-EXPORTS = ["bse_create", "bse_set_packed", "bse_apply", "bse_solve", "bse_backward", "bse_strength",
+EXPORTS = ["bse_create", "bse_set_packed", "bse_apply", "bse_apply_noalloc", "bse_solve", "bse_backward", "bse_strength",
            "bse_direct", "bse_haydock", "bse_haydock_spectrum", "bse_destroy", "bse_status_string",
            "bse_last_error"]
 
@@ -100,6 +100,7 @@ def load_library():
         "bse_create": ([ctypes.POINTER(vp), i32, i64, i32, vp], i32),
         "bse_set_packed": ([vp, i32, i64, i64, vp, i32], i32),
         "bse_apply": ([vp, i32, i32, i64, vp, vp], i32),
+        "bse_apply_noalloc": ([vp, i32, i32, i64, vp, vp], i32),
         "bse_solve": ([vp, i32, dbl, ctypes.POINTER(SolveOpts), vp, vp, vp, ctypes.POINTER(Stats)], i32),
         "bse_backward": ([vp, vp, vp, vp], i32),
         "bse_strength": ([vp, vp, i32, ctypes.POINTER(Component), ctypes.POINTER(dbl)], i32),
@@ -199,18 +200,27 @@ class Solver:
         self._check(load_library().bse_set_packed(self._h, blk, int(j0), int(j1), ctypes.c_void_p(ptr),
                                                   C64 if c64 else C128), "bse_set_packed")
 
-    def apply(self, op, x, precision="fp64"):
+    def apply(self, op, x, precision="fp64", out=None, noalloc=False):
         """y = op(x); x: (nvec, N) complex128 (nvec, 2N for 'H'), rows are vectors.  precision:
-        "fp64" (FP64 operator), "fp32" (complex FP32 on hi), "hi64" (FP64 arithmetic on hi)."""
+        "fp64" (FP64 operator), "fp32" (complex FP32 on hi), "hi64" (FP64 arithmetic on hi).
+        out: optional preallocated result (same shape as x).  noalloc: call bse_apply_noalloc
+        (the library allocates nothing; partial sums in its fixed per-device array)."""
         opc = {"A": OP_A, "K1": OP_K1, "K2": OP_K2, "H": OP_H}[op]
         length = 2 * self.n if opc == OP_H else self.n
         x = x.reshape(-1, length)
         _dev_ptr(x, torch.complex128, "x")
-        y = torch.empty_like(x)
+        if out is None:
+            y = torch.empty_like(x)
+        else:
+            y = out.reshape(-1, length)
+            if y.shape != x.shape or y.data_ptr() != out.data_ptr():
+                raise ValueError("out must be a contiguous tensor shaped like x")
+            _dev_ptr(y, torch.complex128, "out")
         prec = {"fp64": PREC_FP64, "fp32": PREC_MIXED, "hi64": PREC_HI_FP64}[precision]
+        fn = load_library().bse_apply_noalloc if noalloc else load_library().bse_apply
         with torch.cuda.device(self.device):
-            self._check(load_library().bse_apply(self._h, opc, prec, x.shape[0], _dev_ptr(x), _dev_ptr(y)),
-                        "bse_apply")
+            self._check(fn(self._h, opc, prec, x.shape[0], _dev_ptr(x), _dev_ptr(y)),
+                        "bse_apply_noalloc" if noalloc else "bse_apply")
         return y
 
     def solve(self, k, tol, precision="fp64", ncv=0, keep=0, max_restarts=0, switch_tol=0.0, seed=1,

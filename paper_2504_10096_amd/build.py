@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbse.so")
-SOURCES = ["bse_kernels.hip", "bse_direct.hip", "bse_smalleig.cpp", "bse_solver.cpp"]
+SOURCES = ["bse_kernels.hip", "bse_direct.hip", "bse_noalloc.hip", "bse_smalleig.cpp", "bse_solver.cpp"]
 HIP_FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-result"]

@@ -3,7 +3,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+#include "../../include/bse.h"
 
 namespace bse {
 
@@ -227,6 +230,15 @@ hipError_t direct_split(const double2* z, int64_t ldz, int64_t n2, int c0, int k
 hipError_t direct_back(const double* rm, int64_t ldr, int64_t n, int k, double2* x, double2* y, int64_t ldo,
                        hipStream_t s);
 hipError_t scale_cols(double2* x, double2* y, int64_t ld, int64_t n, int k, const double* f, hipStream_t s);
+
+// bse_apply's work with its partial sums in a caller-supplied workspace ws
+// (ws_elems complex entries) when ws != nullptr -- nothing is allocated then,
+// and a workspace too small for the call is an INVALID_ARG error -- or in the
+// handle's own buffers (ws == nullptr).  handle_device: the device the handle
+// was created on.
+bse_status apply_into(bse_handle h, bse_op op, bse_precision precision, int64_t nvec, const void* x, void* y,
+                      double2* ws, size_t ws_elems);
+int handle_device(const bse_handle_s* h);
 
 // chi[f] = scale / (s - alpha_0 - beta_0^2 / (s - alpha_1 - ...)) truncated
 // after n levels, s = z (ph == 0) or z^2, z = freq[f] + i eta, for f < nw.

@@ -1275,6 +1275,90 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
 // ======================================================================
 // C ABI
 // ======================================================================
+namespace bse {
+
+int handle_device(const bse_handle_s* h) { return h->device; }
+
+bse_status apply_into(bse_handle h, bse_op op, bse_precision precision, int64_t nvec, const void* x, void* y,
+                      double2* ws, size_t ws_elems) {
+  if (!h) return BSE_ERR_INVALID_ARG;
+  if (nvec < 0 || (nvec > 0 && (!x || !y))) return fail(h, BSE_ERR_INVALID_ARG, "bad vectors");
+  if (op != BSE_OP_A && h->kind == BSE_TDA)
+    return fail(h, BSE_ERR_INVALID_ARG, "K1/K2/H need a pseudo-Hermitian handle");
+  if (op < BSE_OP_A || op > BSE_OP_H) return fail(h, BSE_ERR_INVALID_ARG, "bad op");
+  if (precision < BSE_PREC_FP64 || precision > BSE_PREC_HI_FP64)
+    return fail(h, BSE_ERR_INVALID_ARG, "bad precision");
+  if (precision != BSE_PREC_FP64 && h->storage != BSE_STORE_HILO)
+    return fail(h, BSE_ERR_INVALID_ARG, "the hi-only operators need HILO storage");
+  const Arith ar = precision == BSE_PREC_MIXED    ? bse::AR_HI
+                   : precision == BSE_PREC_HI_FP64 ? bse::AR_HI64
+                                                   : fp64_arith(h);
+  const bool fused = op == BSE_OP_H && ar != bse::AR_HI;  // up to four full-H products per read
+  const bool multi = op != BSE_OP_H && nvec > 1;          // up to four vectors per read
+  if (ws) {
+    // caller-supplied workspace: every partial buffer of this call comes from it
+    const int g = (int)std::min<int64_t>(4, std::max<int64_t>(nvec, 1));
+    size_t need = bse::mv_part_elems(h->L);
+    if (fused) need = std::max(need, bse::mh_part_elems(h->L, g));
+    if (multi) need = std::max(need, bse::mk_part_elems(h->L, g));
+    if (need > ws_elems)
+      return fail(h, BSE_ERR_INVALID_ARG,
+                  "workspace too small: this call needs " + std::to_string(need * sizeof(double2)) +
+                      " bytes of partial sums (N = " + std::to_string(h->n) + ", " + std::to_string(g) +
+                      " vectors per read), " + std::to_string(ws_elems * sizeof(double2)) + " available");
+  } else if (fused || multi) {
+    if (bse_status st = ensure_mhpart(h)) return st;
+  }
+  double2* part1 = ws ? ws : h->part;      // one-vector passes
+  double2* partm = ws ? ws : h->mhpart;    // fused and multi-vector passes
+  bse::MatPtrs mp = mat_ptrs(h);
+  if (ar == bse::AR_HI || ar == bse::AR_HI64) {
+    mp.alo = nullptr;
+    mp.blo = nullptr;
+  }
+  const int64_t n = h->n;
+  const double2* xv = (const double2*)x;
+  double2* yv = (double2*)y;
+  if (fused) {
+    for (int64_t c = 0; c < nvec; c += 4) {
+      const int nh = (int)std::min<int64_t>(4, nvec - c);
+      HIP_TRY(h, bse::mh_apply(h->L, ar, mp, nh, xv + (size_t)c * 2 * n, 2 * n, n, partm,
+                               yv + (size_t)c * 2 * n, -1.0, h->stream));
+    }
+    return BSE_OK;
+  }
+  if (multi) {
+    const bse::BMode bm = op == BSE_OP_A ? bse::BM_NONE : bse::BM_CONJ;
+    const double sb = op == BSE_OP_K2 ? -1.0 : 1.0;
+    for (int64_t c = 0; c < nvec; c += 4) {
+      const int nv = (int)std::min<int64_t>(4, nvec - c);
+      HIP_TRY(h, bse::mk_apply(h->L, ar, bm, mp, nv, xv + (size_t)c * n, n, sb, partm, yv + (size_t)c * n, n,
+                               h->stream));
+    }
+    return BSE_OK;
+  }
+  for (int64_t c = 0; c < nvec; ++c) {
+    if (op == BSE_OP_H) {
+      const double2* xt = xv + (size_t)c * 2 * n;
+      const double2* xb = xt + n;
+      double2* yt = yv + (size_t)c * 2 * n;
+      double2* yb = yt + n;
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, xt, 0, xb, 0, 1.0, part1, yt, h->stream));
+      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, xb, 1, xt, 1, 1.0, part1, yb, h->stream));
+      HIP_TRY(h, bse::conj_copy(yb, yb, n, -1.0, h->stream));
+    } else {
+      const double2* xc = xv + (size_t)c * n;
+      double2* yc = yv + (size_t)c * n;
+      const bse::BMode bm = op == BSE_OP_A ? bse::BM_NONE : bse::BM_CONJ;
+      const double sb = op == BSE_OP_K2 ? -1.0 : 1.0;
+      HIP_TRY(h, bse::matvec(h->L, ar, bm, mp, xc, 0, nullptr, 0, sb, part1, yc, h->stream));
+    }
+  }
+  return BSE_OK;
+}
+
+}  // namespace bse
+
 extern "C" {
 
 const char* bse_status_string(bse_status s) {
@@ -1390,66 +1474,7 @@ bse_status bse_set_packed(bse_handle h, bse_block which, int64_t j0, int64_t j1,
 
 bse_status bse_apply(bse_handle h, bse_op op, bse_precision precision, int64_t nvec, const void* x,
                      void* y) {
-  if (!h) return BSE_ERR_INVALID_ARG;
-  if (nvec < 0 || (nvec > 0 && (!x || !y))) return fail(h, BSE_ERR_INVALID_ARG, "bad vectors");
-  if (op != BSE_OP_A && h->kind == BSE_TDA)
-    return fail(h, BSE_ERR_INVALID_ARG, "K1/K2/H need a pseudo-Hermitian handle");
-  if (op < BSE_OP_A || op > BSE_OP_H) return fail(h, BSE_ERR_INVALID_ARG, "bad op");
-  if (precision < BSE_PREC_FP64 || precision > BSE_PREC_HI_FP64)
-    return fail(h, BSE_ERR_INVALID_ARG, "bad precision");
-  if (precision != BSE_PREC_FP64 && h->storage != BSE_STORE_HILO)
-    return fail(h, BSE_ERR_INVALID_ARG, "the hi-only operators need HILO storage");
-  const Arith ar = precision == BSE_PREC_MIXED    ? bse::AR_HI
-                   : precision == BSE_PREC_HI_FP64 ? bse::AR_HI64
-                                                   : fp64_arith(h);
-  bse::MatPtrs mp = mat_ptrs(h);
-  if (ar == bse::AR_HI || ar == bse::AR_HI64) {
-    mp.alo = nullptr;
-    mp.blo = nullptr;
-  }
-  const int64_t n = h->n;
-  const double2* xv = (const double2*)x;
-  double2* yv = (double2*)y;
-  if (op == BSE_OP_H && ar != bse::AR_HI) {
-    // fused: up to four vectors per read of A and B
-    if (bse_status st = ensure_mhpart(h)) return st;
-    for (int64_t c = 0; c < nvec; c += 4) {
-      const int nh = (int)std::min<int64_t>(4, nvec - c);
-      HIP_TRY(h, bse::mh_apply(h->L, ar, mp, nh, xv + (size_t)c * 2 * n, 2 * n, n, h->mhpart,
-                               yv + (size_t)c * 2 * n, -1.0, h->stream));
-    }
-    return BSE_OK;
-  }
-  if (op != BSE_OP_H && nvec > 1) {
-    // up to four vectors per read of the triangles
-    if (bse_status st = ensure_mhpart(h)) return st;
-    const bse::BMode bm = op == BSE_OP_A ? bse::BM_NONE : bse::BM_CONJ;
-    const double sb = op == BSE_OP_K2 ? -1.0 : 1.0;
-    for (int64_t c = 0; c < nvec; c += 4) {
-      const int nv = (int)std::min<int64_t>(4, nvec - c);
-      HIP_TRY(h, bse::mk_apply(h->L, ar, bm, mp, nv, xv + (size_t)c * n, n, sb, h->mhpart, yv + (size_t)c * n, n,
-                               h->stream));
-    }
-    return BSE_OK;
-  }
-  for (int64_t c = 0; c < nvec; ++c) {
-    if (op == BSE_OP_H) {
-      const double2* xt = xv + (size_t)c * 2 * n;
-      const double2* xb = xt + n;
-      double2* yt = yv + (size_t)c * 2 * n;
-      double2* yb = yt + n;
-      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, xt, 0, xb, 0, 1.0, h->part, yt, h->stream));
-      HIP_TRY(h, bse::matvec(h->L, ar, bse::BM_EXPLICIT, mp, xb, 1, xt, 1, 1.0, h->part, yb, h->stream));
-      HIP_TRY(h, bse::conj_copy(yb, yb, n, -1.0, h->stream));
-    } else {
-      const double2* xc = xv + (size_t)c * n;
-      double2* yc = yv + (size_t)c * n;
-      const bse::BMode bm = op == BSE_OP_A ? bse::BM_NONE : bse::BM_CONJ;
-      const double sb = op == BSE_OP_K2 ? -1.0 : 1.0;
-      HIP_TRY(h, bse::matvec(h->L, ar, bm, mp, xc, 0, nullptr, 0, sb, h->part, yc, h->stream));
-    }
-  }
-  return BSE_OK;
+  return bse::apply_into(h, op, precision, nvec, x, y, nullptr, 0);
 }
 
 bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* opts, double* omega,
