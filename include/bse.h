@@ -29,7 +29,8 @@
  *     that return results to the host (bse_solve, bse_backward,
  *     bse_strength) synchronize that stream before returning.
  *   - A handle is not thread-safe; distinct handles are independent.
- *   - The library allocates its own device memory with hipMalloc.
+ *   - The library allocates its own device memory with hipMalloc (bse_apply_noalloc
+ *     excepted: it allocates nothing).
  */
 #ifndef BSE_H
 #define BSE_H
@@ -106,6 +107,15 @@ typedef struct {
                            (zero-diagonal projected matrix, coupled K1- and K2-orthonormal
                            bases, Ritz values omega).  Both take two reads of the triangles per
                            step.  TDA: ignored. */
+  int32_t warm_k;       /* warm start: number of previous eigenvectors in warm_x / warm_y (0: cold
+                           start from the seeded random vector).  The start vector (column q of
+                           the start block) is the sum of previous vectors q, q + b, ... -- PH:
+                           x_c + conj(y_c), which is proportional to the folded vector of pair
+                           c -- plus the random vector at 1e-4 of its norm.  For a matrix close
+                           to the one they solve (finite differences, parameter scans). */
+  int32_t reserved_;
+  const void* warm_x;   /* device, N x warm_k complex128, column-major (bse_solve's x layout) */
+  const void* warm_y;   /* device, N x warm_k complex128 (PH: bse_solve's y); NULL for TDA */
 } bse_solve_opts;
 
 /* Statistics of the last bse_solve (host struct). */
@@ -135,7 +145,7 @@ typedef struct {
   double gemm_flops;        /* their algorithmic flops (real: 2 M N K; complex: 8 M N K) */
   double ms_dense_form;     /* bse_direct: forming the dense matrix (A, or M_r) from the triangles */
   double ms_dense_factor;   /* bse_direct, PH: Cholesky of M_r and the product W = L^T J L */
-  double ms_dense_eig;      /* bse_direct: the Hermitian eigensolver */
+  double ms_dense_eig;      /* bse_direct: eigenpairs (PH: skew reduction, tridiagonal pairs, back-transformation; TDA: the Hermitian eigensolver) */
   /* bse_solve, time per phase (ms): */
   double ms_matvec;   /* passes over the stored triangles in the Lanczos phases: the sampled average
                          block-kernel duration times the number of passes */
@@ -276,22 +286,25 @@ bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse
  * structure-preserving route (Sec. 2.1): M_r of Eq. (5) from the stored
  * A and B (FP64: complex128, or hi + lo), the Cholesky factor M_r = L L^T
  * (it exists iff M is positive definite), the real skew-symmetric
- * W = L^T J L of Eq. (6), the eigenpairs of the Hermitian -i W (whose
- * eigenvalues are the +-omega of H), and the back-transformation
- * v = Q L^{-T} z with Q of Eq. (4), normalized to X^H X - Y^H Y = 1.  TDA:
- * the dense Hermitian eigenproblem of A.  The Cholesky factorization and
- * the Hermitian eigensolver are rocSOLVER calls, W is one rocBLAS product;
- * forming the dense matrices and the back-transformation are kernels of
- * this library.  Device memory: 32 (2N)^2 bytes for PH, 16 N^2 for TDA.
+ * W = L^T J L of Eq. (6), its real Householder reduction to a skew
+ * tridiagonal T (Sec. 2.1.1), the k smallest positive eigenvalues of -i T
+ * (the +-omega of H) with their vectors, and the back-transformation
+ * v = Q L^{-T} Q_T D z with Q of Eq. (4), normalized to X^H X - Y^H Y = 1;
+ * every step is a kernel of this library (FP64 MFMA for the products) or,
+ * for the tridiagonal eigenpairs, host code.  TDA: the dense Hermitian
+ * eigenproblem of A (rocSOLVER).  Device memory: 24 (2N)^2 bytes for PH,
+ * 16 N^2 for TDA.
  * Arguments and outputs as bse_solve (omega ascending; x, y column-major
  * N x k complex128).  stats (nullable): ms_total, ms_fp64_phase (dense
- * matrices and factorizations), ms_final (back-transformation and the
- * FP64 residuals), passes (reads of the triangles for the residuals),
- * max_rel_residual.  The pairs are kept for bse_backward / bse_strength.
+ * matrices, factorizations and eigenpairs), ms_dense_form / _factor / _eig
+ * (M_r; Cholesky and W; reduction, tridiagonal pairs and back-transformation),
+ * ms_final (normalization and the FP64 residuals), passes (reads of the
+ * triangles for the residuals), max_rel_residual.  The pairs are kept for
+ * bse_backward / bse_strength.
  * Errors: INVALID_ARG (k outside [1, N], nulls, y given for TDA, dense
  * order 2N (PH) or N (TDA) above 32767), NOT_POSITIVE_DEFINITE (the
- * Cholesky factorization fails), DEVICE (a library call fails or the
- * eigensolver does not converge), OUT_OF_MEMORY, NONFINITE.
+ * Cholesky factorization fails), DEVICE (a kernel or library call fails or
+ * an eigensolver does not converge), OUT_OF_MEMORY, NONFINITE.
  */
 bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, bse_stats* stats);
 

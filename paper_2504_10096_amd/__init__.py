@@ -40,7 +40,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("ncv", ctypes.c_int32), ("keep", ctypes.c_int32), ("max_restarts", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("switch_tol", ctypes.c_double), ("start_seed", ctypes.c_uint64),
                 ("fp32_arith", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("refine_start", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("refine_start", ctypes.c_int32), ("variant", ctypes.c_int32), ("warm_k", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32), ("warm_x", ctypes.c_void_p), ("warm_y", ctypes.c_void_p)]
 
 
 VARIANT_FOLDED, VARIANT_COUPLED = 0, 1
@@ -224,13 +225,14 @@ class Solver:
         return y
 
     def solve(self, k, tol, precision="fp64", ncv=0, keep=0, max_restarts=0, switch_tol=0.0, seed=1,
-              raise_not_converged=True, fp32_arith=False, block=0, refine_start=0, variant=0):
+              raise_not_converged=True, fp32_arith=False, block=0, refine_start=0, variant=0, warm=None):
         """Lowest k pairs.  Returns (omega[k] f64, X[k, N] c128, Y[k, N] c128 or None, stats dict);
         row c of X/Y is pair c (column c of the column-major N x k ABI layout).  With
         precision="mixed", fp32_arith selects complex FP32 arithmetic for the bulk passes
         (default: FP64 arithmetic on the FP32-stored triangles).  block: vectors per read of the
         triangles in the Lanczos iteration (0: automatic).  variant (PH): 0 the K1-metric
-        iteration on K2 K1, 1 the Lanczos process on H in the M inner product."""
+        iteration on K2 K1, 1 the Lanczos process on H in the M inner product.  warm: (X, Y) of a
+        previous solve of a nearby matrix (rows = pairs, Y None for TDA) to start from."""
         k = int(k)
         dev = self.device
         omega = torch.empty(k, dtype=torch.float64, device=dev)
@@ -239,19 +241,38 @@ class Solver:
         opts = SolveOpts(int(ncv), int(keep), int(max_restarts), PREC_MIXED if precision == "mixed" else PREC_FP64,
                          float(switch_tol), int(seed), 1 if fp32_arith else 0, int(block), int(refine_start),
                          int(variant))
+        if warm is not None:
+            wx, wy = warm
+            wx = wx.to(device=dev, dtype=torch.complex128).reshape(-1, self.n).contiguous()
+            opts.warm_k = wx.shape[0]
+            opts.warm_x = wx.data_ptr()
+            if wy is not None:
+                wy = wy.to(device=dev, dtype=torch.complex128).reshape(-1, self.n).contiguous()
+                if wy.shape != wx.shape:
+                    raise ValueError("warm X and Y must have the same shape")
+                opts.warm_y = wy.data_ptr()
         stats = Stats()
         with torch.cuda.device(dev):
             st = load_library().bse_solve(self._h, k, float(tol), ctypes.byref(opts), _dev_ptr(omega),
                                           _dev_ptr(X), _dev_ptr(Y), ctypes.byref(stats))
         self.last_stats = stats.as_dict()
+        self.solved_k = None
         if st == ERR_NOT_CONVERGED and not raise_not_converged:
             return omega, X, Y, self.last_stats
         self._check(st, "bse_solve")
+        self.solved_k = k
         return omega, X, Y, self.last_stats
+
+    def _weights(self, g):
+        """Eigenvalue weights on the device, one per pair of the last successful solve."""
+        g = g.to(device=self.device, dtype=torch.float64).contiguous()
+        if getattr(self, "solved_k", None) is not None and g.numel() != self.solved_k:
+            raise ValueError(f"g has {g.numel()} weights; the last solve returned {self.solved_k} pairs")
+        return g
 
     def backward(self, g, want_a=True, want_b=True):
         """Packed gradients (dL/dA, dL/dB) of L = sum_c g_c omega_c (LAPACK-'U', off-diagonal x2)."""
-        g = g.to(device=self.device, dtype=torch.float64).contiguous()
+        g = self._weights(g)
         m = self.n * (self.n + 1) // 2
         da = torch.empty(m, dtype=torch.complex128, device=self.device) if want_a else None
         db = (torch.empty(m, dtype=torch.complex128, device=self.device)
@@ -319,7 +340,7 @@ class Solver:
         (target 'A'|'B', form 'packed'|'lowrank'|'diag'|'stored', data tensor or None, scale).
         packed: LAPACK-'U' complex128; lowrank: N x r complex128 factor F (C = s F F^H for A,
         s F F^T for B); diag: N float64 (A only); stored: the stored block itself."""
-        g = g.to(device=self.device, dtype=torch.float64).contiguous()
+        g = self._weights(g)
         forms = {"packed": COMP_PACKED, "lowrank": COMP_LOWRANK, "diag": COMP_DIAG, "stored": COMP_STORED}
         arr = (Component * len(comps))()
         keep = []

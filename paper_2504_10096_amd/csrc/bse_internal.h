@@ -117,6 +117,11 @@ hipError_t colnorms(const double2* V, int ncol, int64_t ld, int64_t n, double* p
 // Random start vector (uniform entries in [-0.5, 0.5) per component).
 hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s);
 
+// Warm start: v = sv v + sum_{c = q, q + b, ... < k} (X[:, c] + conj(Y[:, c]))
+// (Y == nullptr: X only); X, Y column-major with leading dimension ld.
+hipError_t warm_sum(const double2* X, const double2* Y, int64_t ld, int64_t n, int k, int b, int q, double sv,
+                    double2* v, hipStream_t s);
+
 // PH eigenvectors: X = (w u + p) / (2 sqrt(w)), Y = conj(w u - p) / (2 sqrt(w)).
 hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const double* omega, int k,
                       int64_t n, double2* X, double2* Y, int64_t ldo, hipStream_t s);
@@ -230,6 +235,35 @@ hipError_t direct_split(const double2* z, int64_t ldz, int64_t n2, int c0, int k
 hipError_t direct_back(const double* rm, int64_t ldr, int64_t n, int k, double2* x, double2* y, int64_t ldo,
                        hipStream_t s);
 hipError_t scale_cols(double2* x, double2* y, int64_t ld, int64_t n, int k, const double* f, hipStream_t s);
+
+// Dense FP64 pieces of the pseudo-Hermitian direct solve (bse_direct.hip).
+//   dense_gemm: C (M x N) = alpha op(A) op(B) + beta C, column-major, FP64
+//     MFMA; ta / tb = 1 transposes the stored A (K x M) / B (N x K); lower != 0
+//     writes only entries on or below the diagonal.
+//   dense_cholesky: A = L L^T in place (lower triangle of the m x m A; the
+//     strict upper triangle is left as it was); *flag (zeroed by the caller)
+//     is set when a pivot is not positive.
+//   skew_tridiag: Householder reduction Q^T W Q = T of the real skew-symmetric
+//     m x m W (full storage, destroyed): T[j+1, j] = e[j] (j < m - 1); the
+//     reflector H_j = I - tau[j] v v^T of column j, v_0 = 1, is left in
+//     W[j+1:, j].  Workspace: Vp, Zp (ldp >= m, 64 columns each), part
+//     (ceil((m - 1) / 256) * m), dots (128).
+//   skew_back: for ncol real columns of R (m x ncol, leading dimension ldr),
+//     x <- L^{-T} Q x with Q = H_0 H_1 ... H_{m-2} from skew_tridiag and the
+//     lower factor L (leading dimension ldl).
+hipError_t dense_gemm(int ta, int tb, int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                      const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int lower, hipStream_t s);
+hipError_t dense_cholesky(double* A, int64_t ld, int64_t m, int* flag, hipStream_t s);
+hipError_t skew_tridiag(double* W, int64_t ld, int64_t m, double* Vp, double* Zp, int64_t ldp, double* part,
+                        double* dots, double* tau, double* e, hipStream_t s);
+hipError_t skew_back(const double* W, int64_t ld, const double* tau, const double* l, int64_t ldl, int64_t m,
+                     double* R, int64_t ldr, int ncol, hipStream_t s);
+
+// Host: the k smallest positive eigenvalues w (ascending) and orthonormal
+// eigenvectors z (m x k, column-major) of the symmetric tridiagonal matrix
+// with zero diagonal and off-diagonal f (m - 1 entries, f >= 0).  False if
+// fewer than k positive eigenvalues exist or an iteration fails.
+bool tridiag0_lowest_positive(int64_t m, const double* f, int k, double* w, double* z);
 
 // bse_apply's work with its partial sums in a caller-supplied workspace ws
 // (ws_elems complex entries) when ws != nullptr -- nothing is allocated then,

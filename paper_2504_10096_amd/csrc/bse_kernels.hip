@@ -1765,6 +1765,28 @@ __global__ void __launch_bounds__(kThreads)
   v[i] = make_double2((double)(a >> 11) * 0x1.0p-53 - 0.5, (double)(b >> 11) * 0x1.0p-53 - 0.5);
 }
 
+// v[i] = sv v[i] + sum over columns c = q, q + b, q + 2b, ... < k of
+// X[i + c ld] (+ conj(Y[i + c ld]) when Y is given)
+__global__ void __launch_bounds__(kThreads)
+    warm_sum_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, int64_t ld, int64_t n, int k,
+                    int b, int q, double sv, double2* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  double re = 0.0, im = 0.0;
+  for (int c = q; c < k; c += b) {
+    const double2 x = X[i + (size_t)c * ld];
+    re += x.x;
+    im += x.y;
+    if (Y) {
+      const double2 y = Y[i + (size_t)c * ld];
+      re += y.x;
+      im -= y.y;
+    }
+  }
+  const double2 o = v[i];
+  v[i] = make_double2(fma(sv, o.x, re), fma(sv, o.y, im));
+}
+
 __global__ void __launch_bounds__(kThreads)
     ph_vectors_kernel(const double2* __restrict__ U, const double2* __restrict__ P, int64_t ld,
                       const double* __restrict__ omega, int64_t n, double2* __restrict__ X,
@@ -2387,6 +2409,13 @@ hipError_t colnorms(const double2* V, int ncol, int64_t ld, int64_t n, double* p
 hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s) {
   hipLaunchKernelGGL(start_vector_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)),
                      dim3(kThreads), 0, s, v, n, seed);
+  return hipGetLastError();
+}
+
+hipError_t warm_sum(const double2* X, const double2* Y, int64_t ld, int64_t n, int k, int b, int q, double sv,
+                    double2* v, hipStream_t s) {
+  hipLaunchKernelGGL(warm_sum_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, X, Y,
+                     ld, n, k, b, q, sv, v);
   return hipGetLastError();
 }
 

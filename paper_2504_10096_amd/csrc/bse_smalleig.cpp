@@ -28,6 +28,7 @@
 #include <mutex>
 #include <numeric>
 #include <thread>
+#include <limits>
 #include <vector>
 
 #include "bse_internal.h"
@@ -464,6 +465,145 @@ void zlhsolve(int s, const double2* l2, double2* x2, int c) {
       }
     }
   });
+}
+
+
+// ---------------------------------------------------------------------
+// Symmetric tridiagonal matrix with zero diagonal and off-diagonal f
+// (f_i >= 0, m - 1 entries): the k smallest positive eigenvalues by
+// bisection on the Sturm sequence and their eigenvectors by inverse
+// iteration.  This is the real symmetric form of -i T for the skew
+// tridiagonal T of the direct solve (its eigenvalues are +-omega).
+// ---------------------------------------------------------------------
+namespace {
+
+// Eigenvalues of S below x: negative pivots of the LDL^T factorization of
+// S - x I (pivots of tiny magnitude are moved to -pmin).
+int64_t neg_count(int64_t m, const double* f, double x, double pmin) {
+  int64_t c = 0;
+  double q = -x;
+  for (int64_t i = 0;; ++i) {
+    if (fabs(q) < pmin) q = -pmin;
+    if (q < 0.0) ++c;
+    if (i + 1 == m) break;
+    q = -x - f[i] * f[i] / q;
+  }
+  return c;
+}
+
+// LU factorization of S - x I with partial pivoting (row interchanges):
+// u0 / u1 / u2 the diagonals of U, lm the multipliers, sw[i] = 1 when rows
+// i and i + 1 were interchanged.  Zero pivots are replaced by tiny.
+struct TriLU {
+  std::vector<double> u0, u1, u2, lm;
+  std::vector<char> sw;
+};
+
+void tri_lu(int64_t m, const double* f, double x, double tiny, TriLU& F) {
+  F.u0.assign(m, -x);
+  F.u1.assign(m, 0.0);
+  F.u2.assign(m, 0.0);
+  F.lm.assign(m, 0.0);
+  F.sw.assign(m, 0);
+  for (int64_t i = 0; i + 1 < m; ++i) F.u1[i] = f[i];
+  for (int64_t i = 0; i + 1 < m; ++i) {
+    const double sub = f[i];  // entry (i + 1, i)
+    if (fabs(F.u0[i]) >= fabs(sub)) {
+      if (F.u0[i] == 0.0) F.u0[i] = tiny;
+      const double l = sub / F.u0[i];
+      F.lm[i] = l;
+      F.u0[i + 1] -= l * F.u1[i];
+    } else {
+      // row i + 1 becomes the pivot row: (sub, u0[i+1], f[i+1]) over (u0[i], u1[i], 0)
+      const double l = F.u0[i] / sub;
+      F.lm[i] = l;
+      F.sw[i] = 1;
+      const double a1 = F.u1[i], b1 = F.u0[i + 1], c1 = i + 2 < m ? F.u1[i + 1] : 0.0;
+      F.u0[i] = sub;
+      F.u1[i] = b1;
+      F.u2[i] = c1;
+      F.u0[i + 1] = a1 - l * b1;
+      if (i + 2 < m) F.u1[i + 1] = -l * c1;
+    }
+  }
+  if (F.u0[m - 1] == 0.0) F.u0[m - 1] = tiny;
+}
+
+void tri_solve(int64_t m, const TriLU& F, double* b) {
+  for (int64_t i = 0; i + 1 < m; ++i) {
+    if (F.sw[i]) std::swap(b[i], b[i + 1]);
+    b[i + 1] -= F.lm[i] * b[i];
+  }
+  for (int64_t i = m - 1; i >= 0; --i) {
+    double v = b[i];
+    if (i + 1 < m) v -= F.u1[i] * b[i + 1];
+    if (i + 2 < m) v -= F.u2[i] * b[i + 2];
+    b[i] = v / F.u0[i];
+  }
+}
+
+}  // namespace
+
+bool tridiag0_lowest_positive(int64_t m, const double* f, int k, double* w, double* z) {
+  if (m < 2 || k < 1) return false;
+  double fmax = 0.0;
+  for (int64_t i = 0; i + 1 < m; ++i) fmax = std::max(fmax, fabs(f[i]));
+  const double bound = 2.0 * fmax;  // Gershgorin
+  const double eps = std::numeric_limits<double>::epsilon();
+  const double pmin = std::max(std::numeric_limits<double>::min(), eps * eps * fmax * fmax);
+  // the graph of the matrix is a path (bipartite): the spectrum is symmetric about zero, so the
+  // positive eigenvalues start at index m / 2 (odd m: one eigenvalue is zero, at (m - 1) / 2)
+  const int64_t i0 = (m + 1) / 2;
+  if (i0 + k > m) return false;
+  std::vector<double> lam(k);
+  par(k, 1, [&](int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c) {
+      const int64_t idx = i0 + c;  // the idx-th smallest eigenvalue (0-based)
+      double lo = 0.0, hi = bound;
+      for (int it = 0; it < 200 && hi - lo > 2.0 * eps * std::max(fabs(lo), fabs(hi)) + pmin; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (neg_count(m, f, mid, pmin) > idx)
+          hi = mid;
+        else
+          lo = mid;
+      }
+      lam[c] = 0.5 * (lo + hi);
+    }
+  });
+  // inverse iteration; vectors of eigenvalues closer than 1e-3 bound are
+  // kept orthogonal to the earlier ones of their cluster
+  const double tiny = eps * bound;
+  std::vector<double> v(m);
+  int64_t cl0 = 0;
+  for (int c = 0; c < k; ++c) {
+    if (c > 0 && lam[c] - lam[c - 1] > 1e-3 * bound) cl0 = c;
+    double x = lam[c];
+    if (c > cl0 && x <= lam[c - 1]) x = lam[c - 1] + 10.0 * eps * std::max(bound, 1.0);
+    TriLU F;
+    tri_lu(m, f, x, tiny, F);
+    uint64_t st = 0x9E3779B97F4A7C15ull * (uint64_t)(c + 1);
+    for (int64_t i = 0; i < m; ++i) {
+      st = st * 6364136223846793005ull + 1442695040888963407ull;
+      v[i] = (double)(st >> 11) * 0x1.0p-53 - 0.5;
+    }
+    for (int it = 0; it < 4; ++it) {
+      tri_solve(m, F, v.data());
+      for (int64_t q = cl0; q < c; ++q) {
+        const double* zq = z + (size_t)q * m;
+        double d = 0.0;
+        for (int64_t i = 0; i < m; ++i) d += zq[i] * v[i];
+        for (int64_t i = 0; i < m; ++i) v[i] -= d * zq[i];
+      }
+      double nv = 0.0;
+      for (int64_t i = 0; i < m; ++i) nv += v[i] * v[i];
+      nv = sqrt(nv);
+      if (!(nv > 0.0) || !std::isfinite(nv)) return false;
+      for (int64_t i = 0; i < m; ++i) v[i] /= nv;
+    }
+    std::copy(v.begin(), v.end(), z + (size_t)c * m);
+    w[c] = lam[c];
+  }
+  return true;
 }
 
 }  // namespace bse

@@ -437,9 +437,22 @@ bse_status orth_block(Solver& S, int c, int nb, int rec) {
 
 // Start block in columns [0, b): seeded random vectors, orthonormalized
 // (PH: K1-orthonormal, with P = K1 U).
-bse_status init_basis(Solver& S, Arith ar, uint64_t seed) {
+// Warm start (wk > 0): column q is the sum of the previous eigenvectors
+// q, q + b, ... (PH: x + conj(y), proportional to the folded vector u of the
+// pair) plus the random vector scaled to 1e-4 of that sum's norm, so that
+// the Krylov space does not stop at the nearly invariant subspace they span.
+bse_status init_basis(Solver& S, Arith ar, uint64_t seed, int wk = 0, const double2* wx = nullptr,
+                      const double2* wy = nullptr) {
   bse_handle h = S.h;
-  for (int q = 0; q < S.b; ++q) HIP_TRY(h, bse::start_vector(S.U + (size_t)q * S.ld, S.n, seed + q, S.s));
+  for (int q = 0; q < S.b; ++q) {
+    HIP_TRY(h, bse::start_vector(S.U + (size_t)q * S.ld, S.n, seed + q, S.s));
+    const int cols = wk > q ? (wk - q + S.b - 1) / S.b : 0;
+    if (cols > 0) {
+      // random entries have E|z|^2 = 1/6; the previous vectors have norms ~1
+      const double sv = 1e-4 * sqrt((double)cols / (S.n / 6.0));
+      HIP_TRY(h, bse::warm_sum(wx, S.ph ? wy : nullptr, S.n, S.n, wk, S.b, q, sv, S.U + (size_t)q * S.ld, S.s));
+    }
+  }
   if (S.ph) {
     bse_status st = passes_n(S, ar, 1, S.b, S.U, S.P);
     if (st) return st;
@@ -1497,6 +1510,8 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   const int64_t n = h->n;
   if (o.block < 0 || o.block > 4) return fail(h, BSE_ERR_INVALID_ARG, "block must be in [0, 4]");
   if (o.variant < 0 || o.variant > 1) return fail(h, BSE_ERR_INVALID_ARG, "variant must be 0 or 1");
+  if (o.warm_k < 0 || o.warm_k > n || (o.warm_k > 0 && (!o.warm_x || (ph && !o.warm_y))))
+    return fail(h, BSE_ERR_INVALID_ARG, "warm start needs warm_k in [0, N] and its vectors");
   int m = o.ncv > 0 ? o.ncv : (int)round_up(std::max(2 * k, k + 32), 16);
   m = (int)std::min<int64_t>(m, n);
   if (m < k) return fail(h, BSE_ERR_INVALID_ARG, "ncv must be at least k");
@@ -1538,7 +1553,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   Arith ar = mixed ? bulk : fp64_arith(h);
   double tol_int = mixed ? std::max(switch_tol, tol) : tol;
   double t_phase = now_ms(), ms32 = 0.0, ms64 = 0.0;
-  st = init_basis(S, ar, seed);
+  st = init_basis(S, ar, seed, o.warm_k, (const double2*)o.warm_x, (const double2*)o.warm_y);
   if (st) return st;
   int jstart = 0;
   RitzInfo R;
@@ -2087,104 +2102,130 @@ bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, 
   };
   const size_t sq = (size_t)n2 * n2;
   DevBuf bMr, bG, bZ, bEv, bE, bInfo, bRm, bF, bW, bRed, bRes;
-  HIP_TRY(h, hipMalloc(&bZ.p, sizeof(double2) * sq));
-  HIP_TRY(h, hipMalloc(&bEv.p, sizeof(double) * n2));
-  HIP_TRY(h, hipMalloc(&bE.p, sizeof(double) * n2));
-  HIP_TRY(h, hipMalloc(&bInfo.p, sizeof(rocblas_int)));
   HIP_TRY(h, hipMalloc(&bF.p, sizeof(double) * k));
-  double2* Z = (double2*)bZ.p;
-  double* ev = (double*)bEv.p;
-  rocblas_int* info = (rocblas_int*)bInfo.p;
-  rocblas_int inf = 0;
   double ms_form = 0.0, ms_chol = 0.0, ms_eig = 0.0;
-  int c0 = 0;  // first wanted eigenpair of the Hermitian problem
+  double2* X = (double2*)x;
+  double2* Y = (double2*)y;
   if (!ph) {
-    // TDA: the Hermitian eigenproblem of A
+    // TDA: the dense Hermitian eigenproblem of A (rocSOLVER, divide and conquer)
+    HIP_TRY(h, hipMalloc(&bZ.p, sizeof(double2) * sq));
+    HIP_TRY(h, hipMalloc(&bEv.p, sizeof(double) * n2));
+    HIP_TRY(h, hipMalloc(&bE.p, sizeof(double) * n2));
+    HIP_TRY(h, hipMalloc(&bInfo.p, sizeof(rocblas_int)));
+    double2* Z = (double2*)bZ.p;
+    double* ev = (double*)bEv.p;
+    rocblas_int* info = (rocblas_int*)bInfo.p;
+    rocblas_int inf = 0;
     HIP_TRY(h, bse::direct_dense(h->L, hilo, mp, Z, nullptr, n, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     ms_form = now_ms() - t0;
+    const double te = now_ms();
+    if (bse_status e = rb(rocsolver_zheevd(blas.b, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n2,
+                                           reinterpret_cast<rocblas_double_complex*>(Z), (rocblas_int)n2, ev,
+                                           (double*)bE.p, info),
+                          "rocsolver_zheevd"))
+      return e;
+    HIP_TRY(h, hipMemcpyAsync(&inf, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    if (inf != 0) return fail(h, BSE_ERR_DEVICE, "Hermitian eigensolver did not converge");
+    ms_eig = now_ms() - te;
+    HIP_TRY(h, hipMemcpyAsync(omega, ev, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(h, bse::copy_cols(Z, n, X, n, n, k, s));
   } else {
-    // M_r of Eq. (5); M_r = L L^T; W = L^T J L (Eq. (6)); Z = -i W
+    // M_r of Eq. (5); its Cholesky factor M_r = L L^T (blocked, own kernels); W = L^T J L
+    // (Eq. (6)), real skew-symmetric; Householder reduction Q^T W Q = T (real skew
+    // tridiagonal, off-diagonal e); -i T is similar, through a diagonal of powers of -i with
+    // signs, to the real symmetric tridiagonal S with zero diagonal and off-diagonal |e|,
+    // whose eigenvalues are the +-omega; the lowest k positive ones and their vectors z by
+    // bisection and inverse iteration; the eigenvectors of -i W are Q D z, and v = Q4 L^{-T} Q D z
+    // with Q4 the Q of Eq. (4).
     HIP_TRY(h, hipMalloc(&bMr.p, sizeof(double) * sq));
     HIP_TRY(h, hipMalloc(&bG.p, sizeof(double) * sq));
+    HIP_TRY(h, hipMalloc(&bZ.p, sizeof(double) * sq));  // W
+    HIP_TRY(h, hipMalloc(&bInfo.p, sizeof(int)));
     double* Mr = (double*)bMr.p;
     double* G = (double*)bG.p;
+    double* Wm = (double*)bZ.p;
+    int* flag = (int*)bInfo.p;
     HIP_TRY(h, bse::direct_dense(h->L, hilo, mp, nullptr, Mr, n2, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     ms_form = now_ms() - t0;
     const double tc = now_ms();
-    if (bse_status e = rb(rocsolver_dpotrf(blas.b, rocblas_fill_lower, (rocblas_int)n2, Mr, (rocblas_int)n2, info),
-                          "rocsolver_dpotrf"))
-      return e;
-    HIP_TRY(h, hipMemcpyAsync(&inf, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemsetAsync(flag, 0, sizeof(int), s));
+    HIP_TRY(h, bse::dense_cholesky(Mr, n2, n2, flag, s));
+    int fl = 0;
+    HIP_TRY(h, hipMemcpyAsync(&fl, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
-    if (inf != 0)
-      return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "Cholesky of M_r failed: M is not positive definite");
+    if (fl != 0) return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "Cholesky of M_r failed: M is not positive definite");
     HIP_TRY(h, bse::direct_jl(Mr, n2, n, G, s));  // G = J L; the upper triangle of L cleared
-    const double one = 1.0, zero = 0.0;
-    // W = L^T (J L) goes to the first half of Z's memory (L stays for the back-transformation),
-    // then to G, and Z receives -i W
-    double* Wm = reinterpret_cast<double*>(Z);
-    if (bse_status e = rb(rocblas_dgemm(blas.b, rocblas_operation_transpose, rocblas_operation_none,
-                                        (rocblas_int)n2, (rocblas_int)n2, (rocblas_int)n2, &one, Mr,
-                                        (rocblas_int)n2, G, (rocblas_int)n2, &zero, Wm, (rocblas_int)n2),
-                          "rocblas_dgemm"))
-      return e;
-    HIP_TRY(h, hipMemcpyAsync(G, Wm, sizeof(double) * sq, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(h, bse::direct_negi(G, n2, n2, Z, n2, s));
+    HIP_TRY(h, bse::dense_gemm(1, 0, n2, n2, n2, 1.0, Mr, n2, G, n2, 0.0, Wm, n2, 0, s));  // W = L^T G
     HIP_TRY(h, hipStreamSynchronize(s));
     ms_chol = now_ms() - tc;
-    c0 = (int)n;  // eigenvalues of -i W ascend: -omega_max .. -omega_min, omega_min .. omega_max
-  }
-  const double te = now_ms();
-  if (bse_status e = rb(rocsolver_zheevd(blas.b, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n2,
-                                         reinterpret_cast<rocblas_double_complex*>(Z), (rocblas_int)n2, ev,
-                                         (double*)bE.p, info),
-                        "rocsolver_zheevd"))
-    return e;
-  HIP_TRY(h, hipMemcpyAsync(&inf, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
-  HIP_TRY(h, hipStreamSynchronize(s));
-  if (inf != 0) return fail(h, BSE_ERR_DEVICE, "Hermitian eigensolver did not converge");
-  ms_eig = now_ms() - te;
-  std::vector<double> om(k);
-  HIP_TRY(h, hipMemcpyAsync(om.data(), ev + c0, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-  HIP_TRY(h, hipStreamSynchronize(s));
-  if (ph && !(om[0] > 0.0))
-    return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "non-positive omega: M is not positive definite");
-  HIP_TRY(h, hipMemcpyAsync(omega, ev + c0, sizeof(double) * k, hipMemcpyDeviceToDevice, s));
-  double2* X = (double2*)x;
-  double2* Y = (double2*)y;
-  if (!ph) {
-    HIP_TRY(h, bse::copy_cols(Z, n, X, n, n, k, s));
-  } else {
-    // x = L^{-T} z for the k wanted columns (real and imaginary parts), v = Q x
-    HIP_TRY(h, hipMalloc(&bRm.p, sizeof(double) * (size_t)n2 * 2 * k));
+    const double te = now_ms();
+    // reduction workspace: G is free now
+    const int64_t nch = (n2 - 1 + 255) / 256;
+    HIP_TRY(h, hipMalloc(&bE.p, sizeof(double) * (size_t)(2 * n2 * 64 + nch * n2 + 128 + 2 * n2)));
+    double* Vp = (double*)bE.p;
+    double* Zp = Vp + (size_t)n2 * 64;
+    double* part = Zp + (size_t)n2 * 64;
+    double* dots = part + (size_t)nch * n2;
+    double* tau = dots + 128;
+    double* ed = tau + n2;
+    HIP_TRY(h, bse::skew_tridiag(Wm, n2, n2, Vp, Zp, n2, part, dots, tau, ed, s));
+    std::vector<double> e(n2 - 1), f(n2 - 1), w(k), zt((size_t)n2 * k);
+    HIP_TRY(h, hipMemcpyAsync(e.data(), ed, sizeof(double) * (n2 - 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    for (int64_t j = 0; j + 1 < n2; ++j) {
+      if (!std::isfinite(e[j])) return fail(h, BSE_ERR_NONFINITE, "non-finite skew tridiagonal form");
+      f[j] = fabs(e[j]);
+    }
+    if (!bse::tridiag0_lowest_positive(n2, f.data(), k, w.data(), zt.data()))
+      return fail(h, BSE_ERR_DEVICE, "tridiagonal eigensolver failed");
+    if (!(w[0] > 0.0)) return fail(h, BSE_ERR_NOT_POSITIVE_DEFINITE, "non-positive omega: M is not positive definite");
+    // y = D z, D_j = s_j (-i)^j with s_0 = 1, s_{j+1} = s_j sign(e_j): real parts to columns
+    // 0..k-1, imaginary parts to k..2k-1 of R (each entry of y is real or imaginary)
+    std::vector<double> rh((size_t)n2 * 2 * k, 0.0);
+    for (int c = 0; c < k; ++c) {
+      double sg = 1.0;
+      for (int64_t j = 0; j < n2; ++j) {
+        const double v = sg * zt[(size_t)c * n2 + j];
+        switch (j & 3) {
+          case 0: rh[(size_t)c * n2 + j] = v; break;
+          case 1: rh[(size_t)(k + c) * n2 + j] = -v; break;
+          case 2: rh[(size_t)c * n2 + j] = -v; break;
+          default: rh[(size_t)(k + c) * n2 + j] = v; break;
+        }
+        if (j + 1 < n2 && e[j] < 0.0) sg = -sg;
+      }
+    }
+    HIP_TRY(h, hipMalloc(&bRm.p, sizeof(double) * rh.size()));
     double* Rm = (double*)bRm.p;
-    HIP_TRY(h, bse::direct_split(Z, n2, n2, c0, k, Rm, n2, s));
-    const double one = 1.0;
-    if (bse_status e = rb(rocblas_dtrsm(blas.b, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
-                                        rocblas_diagonal_non_unit, (rocblas_int)n2, (rocblas_int)(2 * k), &one,
-                                        (const double*)bMr.p, (rocblas_int)n2, Rm, (rocblas_int)n2),
-                          "rocblas_dtrsm"))
-      return e;
+    HIP_TRY(h, hipMemcpyAsync(Rm, rh.data(), sizeof(double) * rh.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(h, bse::skew_back(Wm, n2, tau, Mr, n2, n2, Rm, n2, 2 * k, s));  // R <- L^{-T} Q R
+    HIP_TRY(h, hipMemcpyAsync(omega, w.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
     HIP_TRY(h, bse::direct_back(Rm, n2, n, k, X, Y, n, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    ms_eig = now_ms() - te;
     // X^H X - Y^H Y = 1 per pair
     HIP_TRY(h, hipMalloc(&bRed.p, sizeof(double) * ((size_t)bse::nchunks(n) * std::max(k, 2) + 64)));
     HIP_TRY(h, hipMalloc(&bRes.p, sizeof(double) * 2 * k));
     double* nr = (double*)bRes.p;
     HIP_TRY(h, bse::colnorms(X, k, n, n, (double*)bRed.p, nr, s));
     HIP_TRY(h, bse::colnorms(Y, k, n, n, (double*)bRed.p, nr + k, s));
-    std::vector<double> nrm(2 * k), f(k);
+    std::vector<double> nrm(2 * k), fs(k);
     HIP_TRY(h, hipMemcpyAsync(nrm.data(), nr, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     for (int c = 0; c < k; ++c) {
       const double d = nrm[c] - nrm[k + c];
       if (!(d > 0.0)) return fail(h, BSE_ERR_NONFINITE, "eigenvector with X^H X - Y^H Y <= 0");
-      f[c] = 1.0 / sqrt(d);
+      fs[c] = 1.0 / sqrt(d);
     }
-    HIP_TRY(h, hipMemcpyAsync(bF.p, f.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync(bF.p, fs.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
     HIP_TRY(h, bse::scale_cols(X, Y, n, n, k, (const double*)bF.p, s));
   }
+  std::vector<double> om(k);
+  HIP_TRY(h, hipMemcpyAsync(om.data(), omega, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  HIP_TRY(h, hipStreamSynchronize(s));
   // FP64 residuals of the k pairs through the stored operator
   HIP_TRY(h, hipMalloc(&bW.p, sizeof(double2) * (size_t)round_up(n, 64)));
   if (!bRed.p) HIP_TRY(h, hipMalloc(&bRed.p, sizeof(double) * ((size_t)bse::nchunks(n) * 2 + 64)));

@@ -281,6 +281,19 @@ hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t) {
   return hipSuccess;
 }
 
+hipError_t warm_sum(const double2* X, const double2* Y, int64_t ld, int64_t n, int k, int b, int q, double sv,
+                    double2* v, hipStream_t) {
+  for (int64_t i = 0; i < n; ++i) {
+    cplx acc = 0.0;
+    for (int c = q; c < k; c += b) {
+      acc += C(X[i + (size_t)c * ld]);
+      if (Y) acc += std::conj(C(Y[i + (size_t)c * ld]));
+    }
+    v[i] = D(sv * C(v[i]) + acc);
+  }
+  return hipSuccess;
+}
+
 hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const double* omega, int k, int64_t n,
                       double2* X, double2* Y, int64_t ldo, hipStream_t) {
   for (int c = 0; c < k; ++c) {
@@ -493,6 +506,19 @@ hipError_t direct_split(const double2*, int64_t, int64_t, int, int, double*, int
   return hipErrorInvalidValue;
 }
 hipError_t direct_back(const double*, int64_t, int64_t, int, double2*, double2*, int64_t, hipStream_t) {
+  return hipErrorInvalidValue;
+}
+hipError_t dense_gemm(int, int, int64_t, int64_t, int64_t, double, const double*, int64_t, const double*, int64_t,
+                      double, double*, int64_t, int, hipStream_t) {
+  return hipErrorInvalidValue;
+}
+hipError_t dense_cholesky(double*, int64_t, int64_t, int*, hipStream_t) { return hipErrorInvalidValue; }
+hipError_t skew_tridiag(double*, int64_t, int64_t, double*, double*, int64_t, double*, double*, double*, double*,
+                        hipStream_t) {
+  return hipErrorInvalidValue;
+}
+hipError_t skew_back(const double*, int64_t, const double*, const double*, int64_t, int64_t, double*, int64_t, int,
+                     hipStream_t) {
   return hipErrorInvalidValue;
 }
 hipError_t scale_cols(double2*, double2*, int64_t, int64_t, int, const double*, hipStream_t) {

@@ -2,7 +2,9 @@
 // reads "kind m" and a column-major matrix (real, or re im pairs) from
 // stdin, prints the eigenvalues and eigenvectors.  Kind "c": a Hermitian
 // positive definite G and a complex C (both m x m); prints the status of
-// zchol, then L^{-1} C (zlsolve) and L^{-H} C (zlhsolve).
+// zchol, then L^{-1} C (zlsolve) and L^{-H} C (zlhsolve).  Kind "t": "t m k"
+// and the m - 1 off-diagonal entries of a zero-diagonal symmetric tridiagonal;
+// prints the status, the k smallest positive eigenvalues and their vectors.
 #include <hip/hip_runtime.h>
 #include <cstdio>
 #include <vector>
@@ -14,7 +16,16 @@ int main() {
   int m;
   while (scanf("%7s %d", kind, &m) == 2) {
     std::vector<double> w(m);
-    if (kind[0] == 'c') {
+    if (kind[0] == 't') {
+      int k = 0;
+      if (scanf("%d", &k) != 1) return 1;
+      std::vector<double> f(m - 1), wk(k), z((size_t)m * k);
+      for (auto& v : f) scanf("%lf", &v);
+      const bool ok = bse::tridiag0_lowest_positive(m, f.data(), k, wk.data(), z.data());
+      printf("%d\n", ok ? 1 : 0);
+      for (double v : wk) printf("%.17g\n", v);
+      for (double v : z) printf("%.17g\n", v);
+    } else if (kind[0] == 'c') {
       std::vector<double2> g((size_t)m * m), c((size_t)m * m);
       for (auto& v : g) scanf("%lf %lf", &v.x, &v.y);
       for (auto& v : c) scanf("%lf %lf", &v.x, &v.y);

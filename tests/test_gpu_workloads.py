@@ -85,15 +85,16 @@ def test_workload_ph_n16384_k32_gradient_fd():
     print(f"workload {w['name']}", flush=True)
     g = synth.loss_weights(w["seed"], k)
     s = generated_solver(mat, "c128")
-    om1, X, Y, st = s.solve(k + 1, 1e-12)
+    # completeness cross-check: another start vector finds the same k + 1 pairs
+    om_s, _, _, st_s = s.solve(k + 1, 1e-10, seed=7921)
+    om1, X, Y, st = s.solve(k + 1, 1e-12)  # the handle keeps this solution for the adjoint
     assert st["max_rel_residual"] <= 1e-12
+    assert np.max(np.abs(host(om_s) - host(om1)) / host(om1)) < 1e-9
     om = om1[:k]
     # the loss's last pair must stay separated from the next one under the +-h perturbations
     gap = float(om1[k] - om1[k - 1])
     assert gap > 1e-4, gap
-    # completeness cross-check: another start vector finds the same k + 1 pairs
-    om_s, _, _, st_s = s.solve(k + 1, 1e-10, seed=7921)
-    assert np.max(np.abs(host(om_s) - host(om1)) / host(om1)) < 1e-9
+    g1 = np.append(g, 0.0)  # weights of the k + 1 stored pairs (the extra pair is not in the loss)
     n = mat.n
     t = mat.tables
     xf = torch.as_tensor(t.x_factor()).cuda()
@@ -101,7 +102,7 @@ def test_workload_ph_n16384_k32_gradient_fd():
     comps = [("A", "lowrank", xf, 1.0 / n), ("B", "lowrank", yf, mat.b0_scale),
              ("A", "diag", torch.as_tensor(t.eps + mat.shift).cuda(), 1.0), ("A", "stored", None, 1.0),
              ("B", "stored", None, 1.0)]
-    kx, b0, dg, sa, sbb = s.strength(torch.as_tensor(g), comps)
+    kx, b0, dg, sa, sbb = s.strength(torch.as_tensor(g1), comps)
     # A = D + alpha Kx - beta W, B = alpha B0: dL/dalpha = <G_A, Kx> + <G_B, B0>,
     # dL/dbeta = -<G_A, W> with W = (D + alpha Kx - A) / beta
     d_alpha = kx + b0
@@ -120,7 +121,8 @@ def test_workload_ph_n16384_k32_gradient_fd():
         for sign in (1, -1):
             v = getattr(mat, name) + sign * h
             s2 = generated_solver(mat, "c128", **{kw: v})
-            om2, _, _, st2 = s2.solve(k, 1e-12)
+            # warm start from the base solution (the FD matrices differ from it by h)
+            om2, _, _, st2 = s2.solve(k, 1e-12, warm=(X[:k], Y[:k]))
             assert st2["max_rel_residual"] <= 1e-12
             vals.append(float(g @ host(om2)))
             s2.close()

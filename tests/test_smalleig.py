@@ -125,3 +125,29 @@ def test_cholesky_and_triangular_solves(driver, m):
     out = subprocess.run([driver], input=f"c {m}\n{body}\n", capture_output=True, text=True,
                          check=True).stdout.split("\n")
     assert out[0] == "0"
+
+
+@pytest.mark.parametrize("m,k,clustered", [(2, 1, False), (10, 3, False), (400, 12, False), (600, 20, True)])
+def test_tridiag0_lowest_positive(driver, m, k, clustered):
+    """Zero-diagonal symmetric tridiagonal (the real form of -i T for the skew tridiagonal T of the
+    direct solve): the k smallest positive eigenvalues and orthonormal vectors against numpy."""
+    rng = np.random.default_rng(m + k)
+    f = rng.uniform(0.05, 3.0, m - 1)
+    if clustered:
+        # two equal halves joined by a tiny coupling: every eigenvalue comes as a nearly equal pair
+        h = m // 2
+        f[h:] = f[:h - 1]
+        f[h - 1] = 1e-10
+    body = " ".join(f"{v:.17g}" for v in f)
+    out = subprocess.run([driver], input=f"t {m} {k}\n{body}\n", capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    assert out[0] == "1"
+    w = np.array([float(x) for x in out[1:1 + k]])
+    z = np.array([float(x) for x in out[1 + k:1 + k + m * k]]).reshape(k, m).T
+    S = np.diag(f, 1) + np.diag(f, -1)
+    ev = np.linalg.eigvalsh(S)
+    ref = np.sort(ev[ev > 0])[:k]
+    scale = np.abs(ev).max()
+    assert np.abs(w - ref).max() <= 1e-13 * scale
+    assert np.abs(z.T @ z - np.eye(k)).max() <= 1e-10
+    assert np.abs(S @ z - z * w).max() <= 1e-11 * scale
