@@ -35,6 +35,13 @@ struct MatPtrs {
   const void* alo = nullptr; // lo (HILO)
   const void* b = nullptr;
   const void* blo = nullptr;
+  // Diagonal correction added to every output of a pass: out_i += dsign *
+  // dc_i * x_i, x the vector multiplied by A (dc == nullptr: none).  With
+  // dc = 2 Re(lo_ii) it turns a pass over the hi triangles into "hi off the
+  // diagonal, FP64 on it" (dsign = 1), and a pass over the lo triangles alone
+  // into its complement (dsign = -1).
+  const double* dc = nullptr;
+  double dsign = 0.0;
 };
 
 // B handling of a pass: none (TDA), xb = sb * conj(xa) (K1: +1, K2: -1), or

@@ -620,7 +620,8 @@ __global__ void __launch_bounds__(kThreads)
 // left too few loads in flight.
 __global__ void __launch_bounds__(kThreads)
     mv_reduce_kernel(const double2* __restrict__ rowpart, const double2* __restrict__ colpart,
-                     int R, int NS, int nb, int64_t n, double2* __restrict__ out) {
+                     int R, int NS, int nb, int64_t n, double2* __restrict__ out, const double* __restrict__ dc,
+                     double dsg, const double2* __restrict__ xa, int conja) {
   __shared__ double2 sh[4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
@@ -653,6 +654,12 @@ __global__ void __launch_bounds__(kThreads)
     for (int w = 1; w < 4; ++w) {
       t.x += sh[w][lane].x;
       t.y += sh[w][lane].y;
+    }
+    if (dc) {  // diagonal correction on the A input
+      const double f = dsg * dc[i];
+      const double2 x = xa[i];
+      t.x = fma(f, x.x, t.x);
+      t.y = fma(f, conja ? -x.y : x.y, t.y);
     }
     out[i] = t;
   }
@@ -1213,7 +1220,8 @@ __global__ void __launch_bounds__(kThreads)
 __global__ void __launch_bounds__(kThreads)
     mh_reduce_kernel(const double2* __restrict__ rowpart, const double2* __restrict__ colpart, int R, int NS,
                      int nb, int64_t nblk, int64_t n, double2* __restrict__ MV, int64_t ldv, int64_t ldh,
-                     double bsign, int pairs) {
+                     double bsign, int pairs, const double* __restrict__ dc, double dsg,
+                     const double2* __restrict__ X, int64_t ldx, int64_t ldhx) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   const int o = blockIdx.y;
   if (i >= n) return;
@@ -1233,6 +1241,24 @@ __global__ void __launch_bounds__(kThreads)
       const double2 v = cp[((size_t)b * NS + sl) * R + r];
       sx += v.x;
       sy += v.y;
+    }
+  }
+  // diagonal correction: output o multiplies A by x_o (mk) or, for the fused
+  // full-H product, by x_q (top) and conj(y_q) (the conjugate of the bottom)
+  if (dc) {
+    const double f = dsg * dc[i];
+    if (!pairs) {
+      const double2 x = X[(size_t)o * ldx + i];
+      sx = fma(f, x.x, sx);
+      sy = fma(f, x.y, sy);
+    } else if (o & 1) {
+      const double2 y = X[(size_t)(o >> 1) * ldx + ldhx + i];
+      sx = fma(f, y.x, sx);
+      sy = fma(-f, y.y, sy);
+    } else {
+      const double2 x = X[(size_t)(o >> 1) * ldx + i];
+      sx = fma(f, x.x, sx);
+      sy = fma(f, x.y, sy);
     }
   }
   if (!pairs) {
@@ -2182,7 +2208,7 @@ hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const d
   const double2* rowpart = part;
   const double2* colpart = part + (size_t)L.nblk * L.R;
   hipLaunchKernelGGL(mv_reduce_kernel, dim3((unsigned)((L.n + 63) / 64)), dim3(kThreads), 0, s, rowpart, colpart,
-                     L.R, mv_slices(L), L.nb, L.n, out);
+                     L.R, mv_slices(L), L.nb, L.n, out, m.dc, m.dsign, va, conja);
   return hipGetLastError();
 }
 
@@ -2240,7 +2266,8 @@ hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const d
   const double2* rowpart = part;
   const double2* colpart = part + (size_t)2 * nh * L.nblk * L.R;
   hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)(2 * nh)),
-                     dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, MV, ldv, ldh, bsign, 1);
+                     dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, MV, ldv, ldh, bsign, 1,
+                     m.dc, m.dsign, V, ldv, ldh);
   return hipGetLastError();
 }
 
@@ -2333,7 +2360,7 @@ hipError_t mk_apply(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, int n
   const double2* colpart = part + (size_t)nv * L.nblk * L.R;
   hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)nv),
                      dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, out, ldo, (int64_t)0, 1.0,
-                     0);
+                     0, m.dc, m.dsign, V, ldv, (int64_t)0);
   return hipGetLastError();
 }
 

@@ -40,6 +40,12 @@ struct bse_handle_s {
   void* blo = nullptr;
   double2* part = nullptr;  // matvec partials
   double2* mhpart = nullptr;  // fused full-H partials (bse_apply, allocated on first use)
+  // HILO: 2 Re(lo_ii), the part of the FP64 diagonal of A that the hi triangle
+  // misses; passes over hi add it (the FP32 rounding of the large diagonal
+  // dominates the hi operator's error otherwise).  Computed from the stored lo
+  // blocks when first needed after the triangles change.
+  double* dcorr = nullptr;
+  bool dcorr_ok = false;
   std::string err;
   // last successful solve
   bool solved = false;
@@ -81,6 +87,23 @@ bse::MatPtrs mat_ptrs(const bse_handle_s* h) {
   m.b = h->b;
   m.blo = h->blo;
   return m;
+}
+
+// Operator of a pass over the hi triangles alone: hi off the diagonal, the
+// FP64 diagonal on it (the correction 2 Re(lo_ii) added in the pass's sum).
+hipError_t hi_ptrs(bse_handle h, bse::MatPtrs* mp) {
+  *mp = mat_ptrs(h);
+  mp->alo = nullptr;
+  mp->blo = nullptr;
+  if (h->storage != BSE_STORE_HILO) return hipSuccess;
+  if (!h->dcorr_ok) {
+    hipError_t e = bse::diag_a(h->L, bse::AR_HI, h->alo, nullptr, h->dcorr, h->stream);
+    if (e != hipSuccess) return e;
+    h->dcorr_ok = true;
+  }
+  mp->dc = h->dcorr;
+  mp->dsign = 1.0;
+  return hipSuccess;
 }
 
 // Workspace of the fused full-H products, kept with the handle.
@@ -359,12 +382,8 @@ bse_status alloc_solver(Solver& S) {
 // One pass: out = K(v) for the operator of the current phase.
 bse_status pass(Solver& S, Arith ar, int op /*0: A, 1: K1, 2: K2*/, const double2* v, double2* out) {
   bse_handle h = S.h;
-  const bse::MatPtrs mp = mat_ptrs(h);
-  bse::MatPtrs mm = mp;
-  if (ar == bse::AR_HI || ar == bse::AR_HI64) {
-    mm.alo = nullptr;
-    mm.blo = nullptr;
-  }
+  bse::MatPtrs mm = mat_ptrs(h);
+  if (ar == bse::AR_HI || ar == bse::AR_HI64) HIP_TRY(h, hi_ptrs(h, &mm));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (S.passes % 8 == 0 && S.ev_free.size() >= 2) {
     e1 = S.ev_free.back();
@@ -392,10 +411,7 @@ bse_status passes_n(Solver& S, Arith ar, int op, int nv, const double2* v, doubl
   bse_handle h = S.h;
   if (bse_status e = ensure_mhpart(h)) return e;
   bse::MatPtrs mm = mat_ptrs(h);
-  if (ar == bse::AR_HI || ar == bse::AR_HI64) {
-    mm.alo = nullptr;
-    mm.blo = nullptr;
-  }
+  if (ar == bse::AR_HI || ar == bse::AR_HI64) HIP_TRY(h, hi_ptrs(h, &mm));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (S.passes % 8 == 0 && S.ev_free.size() >= 2) {
     e1 = S.ev_free.back();
@@ -1124,10 +1140,13 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   }
   bse_status st;
   const bse::MatPtrs exact = mat_ptrs(h);
+  // the lo triangles alone, minus the diagonal correction the hi passes added
   bse::MatPtrs lo_only = exact;
   lo_only.a = exact.alo;
   lo_only.b = exact.blo;
   lo_only.alo = lo_only.blo = nullptr;
+  lo_only.dc = h->dcorr;
+  lo_only.dsign = -1.0;
   // M V of the starting vectors.  PH: from the iteration's own products,
   // M v = s [omega p + kp; conj(omega p - kp)] with p = K1 u, kp = K2 p
   // (variant 1: M v = [K1 u + K2 p; conj(K1 u - K2 p)] / 2, the same call
@@ -1325,10 +1344,7 @@ bse_status apply_into(bse_handle h, bse_op op, bse_precision precision, int64_t 
   double2* part1 = ws ? ws : h->part;      // one-vector passes
   double2* partm = ws ? ws : h->mhpart;    // fused and multi-vector passes
   bse::MatPtrs mp = mat_ptrs(h);
-  if (ar == bse::AR_HI || ar == bse::AR_HI64) {
-    mp.alo = nullptr;
-    mp.blo = nullptr;
-  }
+  if (ar == bse::AR_HI || ar == bse::AR_HI64) HIP_TRY(h, hi_ptrs(h, &mp));
   const int64_t n = h->n;
   const double2* xv = (const double2*)x;
   double2* yv = (double2*)y;
@@ -1450,6 +1466,8 @@ bse_status bse_create(bse_handle* out, bse_kind kind, int64_t n, bse_storage sto
   }
   if (!alloc((void**)&h->part, sizeof(double2) * bse::mv_part_elems(L)))
     return cleanup(BSE_ERR_OUT_OF_MEMORY);
+  if (storage == BSE_STORE_HILO && !alloc((void**)&h->dcorr, sizeof(double) * (size_t)n))
+    return cleanup(BSE_ERR_OUT_OF_MEMORY);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(BSE_ERR_DEVICE);
   *out = h;
   return BSE_OK;
@@ -1458,7 +1476,7 @@ bse_status bse_create(bse_handle* out, bse_kind kind, int64_t n, bse_storage sto
 bse_status bse_destroy(bse_handle h) {
   if (!h) return BSE_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  void* ptrs[] = {h->a, h->alo, h->b, h->blo, h->part, h->mhpart, h->L.blkmap, h->X, h->Y, h->omega};
+  void* ptrs[] = {h->a, h->alo, h->b, h->blo, h->part, h->mhpart, h->L.blkmap, h->X, h->Y, h->omega, h->dcorr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete h;
@@ -1482,6 +1500,7 @@ bse_status bse_set_packed(bse_handle h, bse_block which, int64_t j0, int64_t j1,
   void* dlo = is_a ? h->alo : h->blo;
   HIP_TRY(h, bse::ingest(h->L, is_a, hilo, src, dtype == BSE_C64, j0, j1, dst, dlo, h->stream));
   h->solved = false;
+  h->dcorr_ok = false;
   return BSE_OK;
 }
 

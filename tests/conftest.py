@@ -25,6 +25,19 @@ def synth_matrix(n, seed, ph, **kw):
     return ph_matrix(n, seed, **kw) if ph else synth.Matrix(n, seed, ph=False, **kw)
 
 
+def hi_operator(ap, bp=None):
+    """Packed blocks of the operator that passes over the complex64 hi triangles apply: every
+    entry rounded to complex64 (round to nearest) except the diagonal of A, which those passes
+    take in FP64 (the stored lo part of the diagonal is added back)."""
+    ap = np.asarray(ap, dtype=np.complex128)
+    a32 = ap.astype(np.complex64).astype(np.complex128)
+    n = int(round(((8 * len(ap) + 1) ** 0.5 - 1) / 2))
+    d = np.arange(n) * (np.arange(n) + 1) // 2 + np.arange(n)  # packed offsets of (j, j)
+    a32[d] = ap[d]
+    b32 = None if bp is None else np.asarray(bp, dtype=np.complex128).astype(np.complex64).astype(np.complex128)
+    return a32, b32
+
+
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP C-ABI library)")
     config.addinivalue_line("markers", "slow: long CPU test")

@@ -132,6 +132,8 @@ hipError_t matvec(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, const d
         if (i < n) y[i] += cplx(rf[r]);
       }
   }
+  if (m.dc)  // diagonal correction on the A input
+    for (int64_t i = 0; i < n; ++i) y[i] += m.dsign * m.dc[i] * xa[i];
   for (int64_t i = 0; i < n; ++i) out[i] = D(y[i]);
   return hipSuccess;
 }

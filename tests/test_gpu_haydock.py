@@ -11,7 +11,7 @@ import torch
 import oracle.haydock as hy
 import paper_2504_10096_amd as bse
 import synth
-from conftest import pack_upper, ph_matrix, random_herm, random_sym, synth_matrix
+from conftest import hi_operator, pack_upper, ph_matrix, random_herm, random_sym, synth_matrix
 
 pytestmark = pytest.mark.gpu
 
@@ -103,14 +103,13 @@ def test_converged_spectrum_matches_definition(kind, n):
 def test_reduced_precision_passes(kind):
     n = 700
     ap, bp, d, _ = case(kind, n)
-    ap32 = ap.astype(np.complex64).astype(np.complex128)  # hi = fl32(a), round to nearest
-    bp32 = None if bp is None else bp.astype(np.complex64).astype(np.complex128)
+    ap32, bp32 = hi_operator(ap, bp)  # hi = fl32(a) (round to nearest), FP64 diagonal of A
     s = make_solver(kind, ap, bp, storage="hilo")
     # FP64 operator from hi + lo: the FP64 recurrence
     al, be, nn, _, _ = s.haydock(dev(d), 20, precision="fp64")
     ra, rb, rn = oracle_recurrence(kind, ap, bp, d, 20)
     assert np.max(np.abs(host(al) - ra)) <= 1e-11 * np.max(np.abs(ra))
-    # FP64 arithmetic on hi: the recurrence of the complex64-rounded matrix
+    # FP64 arithmetic on hi: the recurrence of the complex64-rounded matrix (FP64 diagonal of A)
     al, be, nn, _, _ = s.haydock(dev(d), 20, precision="hi64")
     ra, rb, rn = oracle_recurrence(kind, ap32, bp32, d, 20)
     assert np.max(np.abs(host(al) - ra)) <= 1e-11 * np.max(np.abs(ra))

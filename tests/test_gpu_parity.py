@@ -13,7 +13,7 @@ import torch
 import oracle
 import paper_2504_10096_amd as bse
 import synth
-from conftest import pack_upper, ph_matrix, random_herm, random_sym, synth_matrix
+from conftest import hi_operator, pack_upper, ph_matrix, random_herm, random_sym, synth_matrix
 
 pytestmark = pytest.mark.gpu
 
@@ -59,8 +59,9 @@ def test_matvec_parity(block, storage, monkeypatch):
     x = rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))
     xh = rng.standard_normal((2, 2 * n)) + 1j * rng.standard_normal((2, 2 * n))
     precs = ["fp64"] + (["fp32", "hi64"] if storage == "hilo" else [])
-    # hi64 is FP64 arithmetic on the complex64-rounded triangles: the oracle applied to them
-    ap32, bp32 = (v.astype(np.complex64).astype(np.complex128) for v in (ap, bp))
+    # hi64 is FP64 arithmetic on the complex64-rounded triangles with the FP64 diagonal of A: the
+    # oracle applied to that operator
+    ap32, bp32 = hi_operator(ap, bp)
     for prec in precs:
         tol = 2e-6 if prec == "fp32" else 1e-13
         for op in ["A", "K1", "K2", "H"]:
@@ -86,8 +87,9 @@ def test_matvec_multi_vector_counts(nvec, block, monkeypatch):
     s = make_solver("ph", ap, bp, "hilo", block, monkeypatch)
     x = rng.standard_normal((nvec, n)) + 1j * rng.standard_normal((nvec, n))
     xh = rng.standard_normal((nvec, 2 * n)) + 1j * rng.standard_normal((nvec, 2 * n))
-    # hi64: FP64 arithmetic on the complex64-rounded triangles, the oracle applied to them
-    ap32, bp32 = (v.astype(np.complex64).astype(np.complex128) for v in (ap, bp))
+    # hi64: FP64 arithmetic on the complex64-rounded triangles (FP64 diagonal of A), the oracle
+    # applied to that operator
+    ap32, bp32 = hi_operator(ap, bp)
     for prec in ["fp64", "fp32", "hi64"]:
         tol = 2e-6 if prec == "fp32" else 1e-13
         for op in ["A", "K1", "K2", "H"]:
