@@ -212,8 +212,9 @@ def main():
                         "(0: default)")
     p.add_argument("--haydock", choices=["on", "off"], default="on",
                    help="also time a Lanczos-Haydock spectrum of the same matrix")
-    p.add_argument("--variant", type=int, default=0, choices=[0, 1],
-                   help="PH iteration: 0 K1-metric Lanczos on K2 K1, 1 Lanczos on H in the M inner product")
+    p.add_argument("--variant", type=int, default=0, choices=[0, 1, 2],
+                   help="PH iteration: 0 K1-metric Lanczos on K2 K1, 1 Lanczos on H in the M inner product, "
+                        "2 K2-metric Lanczos on K1 K2")
     p.add_argument("--precision", choices=["auto", "fp64"], default="auto",
                    help="auto: the mixed path where the workload uses it; fp64: FP64 passes only")
     p.add_argument("--budget-s", type=float, default=480.0,
@@ -487,7 +488,8 @@ def main():
                    "storage": storage, "precision": precision, "block_edge": None, "start_seed": args.start_seed,
                    "recipe": mat.recipe, "shift_eV": mat.shift, "lambda_min_raw_eV": mat.lambda_min_raw,
                    "lambda_min_A_eV": mat.lambda_min_a if ph else None, "b_norm2": mat.b_norm if ph else None,
-                   "variant": ("lanczos_h_m_metric" if args.variant == 1 else "k1_metric_folded") if ph else None},
+                   "variant": {0: "k1_metric_folded", 1: "lanczos_h_m_metric", 2: "k2_metric_folded"}[args.variant]
+                   if ph else None},
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": gbps / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": (f"mv_stream_kernel ({kernel_dtype})" if st["block"] <= 1 else

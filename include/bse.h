@@ -29,8 +29,8 @@
  *     that return results to the host (bse_solve, bse_backward,
  *     bse_strength) synchronize that stream before returning.
  *   - A handle is not thread-safe; distinct handles are independent.
- *   - The library allocates its own device memory with hipMalloc (bse_apply_noalloc
- *     excepted: it allocates nothing).
+ *   - The library allocates its device memory with hipMalloc, or with the
+ *     allocator given to bse_create_ex (bse_apply_noalloc allocates nothing).
  */
 #ifndef BSE_H
 #define BSE_H
@@ -47,7 +47,7 @@ typedef struct bse_handle_s* bse_handle;
 typedef enum {
   BSE_OK = 0,
   BSE_ERR_INVALID_ARG = 1,           /* bad size, null required pointer, bad enum */
-  BSE_ERR_OUT_OF_MEMORY = 2,         /* hipMalloc failed */
+  BSE_ERR_OUT_OF_MEMORY = 2,         /* hipMalloc or the handle's allocator failed */
   BSE_ERR_DEVICE = 3,                /* a HIP runtime call failed */
   BSE_ERR_NOT_POSITIVE_DEFINITE = 4, /* <w, K1 w> <= 0: M is not positive definite */
   BSE_ERR_NOT_CONVERGED = 5,         /* max_restarts reached; best results returned */
@@ -105,8 +105,10 @@ typedef struct {
                            process on K2 K1, whose Ritz values are omega^2; 1 the Lanczos
                            process on H in the inner product of M, started from [u; conj(u)]
                            (zero-diagonal projected matrix, coupled K1- and K2-orthonormal
-                           bases, Ritz values omega).  Both take two reads of the triangles per
-                           step.  TDA: ignored. */
+                           bases, Ritz values omega); 2 the dual folded process, Lanczos on
+                           K1 K2 in the K2 inner product (a basis of the other half-vectors,
+                           p = K1 u; Ritz values omega^2).  All take two reads of the
+                           triangles per step.  TDA: ignored. */
   int32_t warm_k;       /* warm start: number of previous eigenvectors in warm_x / warm_y (0: cold
                            start from the seeded random vector).  The start vector (column q of
                            the start block) is the sum of previous vectors q, q + b, ... -- PH:
@@ -184,6 +186,30 @@ typedef struct {
  */
 bse_status bse_create(bse_handle* out, bse_kind kind, int64_t n, bse_storage storage,
                       void* hip_stream);
+
+/*
+ * Device-memory allocator of a handle (for instance a framework's caching
+ * allocator).  alloc returns `bytes` of device memory on the handle's
+ * device, usable on `stream`, or NULL when it cannot; free releases a
+ * pointer that alloc returned, on the same stream.  ctx is passed through.
+ */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, void* stream, void* ctx);
+  void* ctx;
+} bse_allocator;
+
+/*
+ * bse_create_ex -- bse_create with the handle's device memory (the stored
+ * triangles and every workspace of the calls on the handle) taken from
+ * `alloc` instead of hipMalloc; NULL is bse_create.  The allocator must stay
+ * valid until bse_destroy.  (rocSOLVER's workspace of the TDA dense solve
+ * in bse_direct is allocated by rocSOLVER itself.)
+ * Errors: as bse_create; INVALID_ARG when alloc is given without both
+ * functions; OUT_OF_MEMORY when alloc returns NULL.
+ */
+bse_status bse_create_ex(bse_handle* out, bse_kind kind, int64_t n, bse_storage storage, void* hip_stream,
+                         const bse_allocator* alloc);
 
 /*
  * bse_set_packed -- copy columns j0 <= j < j1 of the upper triangle of A or

@@ -31,7 +31,7 @@ BLOCK_A, BLOCK_B = 0, 1
 OP_A, OP_K1, OP_K2, OP_H = 0, 1, 2, 3
 COMP_PACKED, COMP_LOWRANK, COMP_DIAG, COMP_STORED = 0, 1, 2, 3
 
-EXPORTS = ["bse_create", "bse_set_packed", "bse_apply", "bse_apply_noalloc", "bse_solve", "bse_backward", "bse_strength",
+EXPORTS = ["bse_create", "bse_create_ex", "bse_set_packed", "bse_apply", "bse_apply_noalloc", "bse_solve", "bse_backward", "bse_strength",
            "bse_direct", "bse_haydock", "bse_haydock_spectrum", "bse_destroy", "bse_status_string",
            "bse_last_error"]
 
@@ -44,7 +44,7 @@ class SolveOpts(ctypes.Structure):
                 ("reserved_", ctypes.c_int32), ("warm_x", ctypes.c_void_p), ("warm_y", ctypes.c_void_p)]
 
 
-VARIANT_FOLDED, VARIANT_COUPLED = 0, 1
+VARIANT_FOLDED, VARIANT_COUPLED, VARIANT_DUAL = 0, 1, 2
 
 
 class Stats(ctypes.Structure):
@@ -64,6 +64,31 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+def torch_allocator(device):
+    """bse_allocator backed by PyTorch's caching allocator on `device` (the library's device
+    memory then shows in torch.cuda.memory_allocated and is reused by torch after close)."""
+    dev = torch.device(device).index if not isinstance(device, int) else device
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=int(stream or 0))
+        except Exception:  # out of memory: the library reports BSE_ERR_OUT_OF_MEMORY
+            return None
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return Allocator(_ALLOC_FN(_alloc), _FREE_FN(_free), None)
 
 
 class Component(ctypes.Structure):
@@ -99,6 +124,7 @@ def load_library():
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
         "bse_create": ([ctypes.POINTER(vp), i32, i64, i32, vp], i32),
+        "bse_create_ex": ([ctypes.POINTER(vp), i32, i64, i32, vp, ctypes.POINTER(Allocator)], i32),
         "bse_set_packed": ([vp, i32, i64, i64, vp, i32], i32),
         "bse_apply": ([vp, i32, i32, i64, vp, vp], i32),
         "bse_apply_noalloc": ([vp, i32, i32, i64, vp, vp], i32),
@@ -140,7 +166,9 @@ def _dev_ptr(t, dtype=None, name="tensor"):
 class Solver:
     """One handle of the C ABI: a resonant block (and a coupling block for 'ph')."""
 
-    def __init__(self, kind, n, storage="c128", device=None):
+    def __init__(self, kind, n, storage="c128", device=None, allocator=None):
+        """allocator: None (the library's hipMalloc) or "torch" (PyTorch's caching allocator,
+        through bse_create_ex)."""
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the BSE solver needs a HIP device")
@@ -149,9 +177,18 @@ class Solver:
         self.storage = {"c128": STORE_C128, "hilo": STORE_HILO}[storage]
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = ctypes.c_void_p()
+        self._alloc = None
+        if allocator not in (None, "torch"):
+            raise ValueError("allocator must be None or 'torch'")
         with torch.cuda.device(self.device):
-            self._check(lib.bse_create(ctypes.byref(self._h), self.kind, self.n, self.storage,
-                                       ctypes.c_void_p(_stream_ptr(self.device))), "bse_create", created=False)
+            stream = ctypes.c_void_p(_stream_ptr(self.device))
+            if allocator == "torch":
+                self._alloc = torch_allocator(self.device.index)  # kept alive until close
+                self._check(lib.bse_create_ex(ctypes.byref(self._h), self.kind, self.n, self.storage, stream,
+                                              ctypes.byref(self._alloc)), "bse_create_ex", created=False)
+            else:
+                self._check(lib.bse_create(ctypes.byref(self._h), self.kind, self.n, self.storage, stream),
+                            "bse_create", created=False)
         self.last_stats = None
 
     # -- helpers ---------------------------------------------------------------
@@ -231,7 +268,8 @@ class Solver:
         precision="mixed", fp32_arith selects complex FP32 arithmetic for the bulk passes
         (default: FP64 arithmetic on the FP32-stored triangles).  block: vectors per read of the
         triangles in the Lanczos iteration (0: automatic).  variant (PH): 0 the K1-metric
-        iteration on K2 K1, 1 the Lanczos process on H in the M inner product.  warm: (X, Y) of a
+        iteration on K2 K1, 1 the Lanczos process on H in the M inner product, 2 the dual
+        K2-metric iteration on K1 K2.  warm: (X, Y) of a
         previous solve of a nearby matrix (rows = pairs, Y None for TDA) to start from."""
         k = int(k)
         dev = self.device

@@ -124,10 +124,13 @@ hipError_t colnorms(const double2* V, int ncol, int64_t ld, int64_t n, double* p
 // Random start vector (uniform entries in [-0.5, 0.5) per component).
 hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s);
 
-// Warm start: v = sv v + sum_{c = q, q + b, ... < k} (X[:, c] + conj(Y[:, c]))
+// Warm start: v = sv v + sum_{c = q, q + b, ... < k} (X[:, c] + ys conj(Y[:, c]))
 // (Y == nullptr: X only); X, Y column-major with leading dimension ld.
-hipError_t warm_sum(const double2* X, const double2* Y, int64_t ld, int64_t n, int k, int b, int q, double sv,
-                    double2* v, hipStream_t s);
+hipError_t warm_sum(const double2* X, const double2* Y, double ys, int64_t ld, int64_t n, int k, int b, int q,
+                    double sv, double2* v, hipStream_t s);
+
+// x[:, c] = -x[:, c] for k columns of n entries (column stride ld).
+hipError_t neg_cols(double2* x, int64_t ld, int64_t n, int k, hipStream_t s);
 
 // PH eigenvectors: X = (w u + p) / (2 sqrt(w)), Y = conj(w u - p) / (2 sqrt(w)).
 hipError_t ph_vectors(const double2* U, const double2* P, int64_t ld, const double* omega, int k,

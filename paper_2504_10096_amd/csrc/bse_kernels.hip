@@ -1792,10 +1792,10 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // v[i] = sv v[i] + sum over columns c = q, q + b, q + 2b, ... < k of
-// X[i + c ld] (+ conj(Y[i + c ld]) when Y is given)
+// X[i + c ld] (+ ys conj(Y[i + c ld]) when Y is given)
 __global__ void __launch_bounds__(kThreads)
-    warm_sum_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, int64_t ld, int64_t n, int k,
-                    int b, int q, double sv, double2* __restrict__ v) {
+    warm_sum_kernel(const double2* __restrict__ X, const double2* __restrict__ Y, double ys, int64_t ld, int64_t n,
+                    int k, int b, int q, double sv, double2* __restrict__ v) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
   double re = 0.0, im = 0.0;
@@ -1805,12 +1805,20 @@ __global__ void __launch_bounds__(kThreads)
     im += x.y;
     if (Y) {
       const double2 y = Y[i + (size_t)c * ld];
-      re += y.x;
-      im -= y.y;
+      re = fma(ys, y.x, re);
+      im = fma(-ys, y.y, im);
     }
   }
   const double2 o = v[i];
   v[i] = make_double2(fma(sv, o.x, re), fma(sv, o.y, im));
+}
+
+// x[:, c] = -x[:, c] (n rows, column stride ld), c = blockIdx.y
+__global__ void __launch_bounds__(kThreads) neg_cols_kernel(double2* __restrict__ x, int64_t ld, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  double2* p = x + (size_t)blockIdx.y * ld + i;
+  *p = make_double2(-p->x, -p->y);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -2439,10 +2447,17 @@ hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t warm_sum(const double2* X, const double2* Y, int64_t ld, int64_t n, int k, int b, int q, double sv,
-                    double2* v, hipStream_t s) {
+hipError_t warm_sum(const double2* X, const double2* Y, double ys, int64_t ld, int64_t n, int k, int b, int q,
+                    double sv, double2* v, hipStream_t s) {
   hipLaunchKernelGGL(warm_sum_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, X, Y,
-                     ld, n, k, b, q, sv, v);
+                     ys, ld, n, k, b, q, sv, v);
+  return hipGetLastError();
+}
+
+hipError_t neg_cols(double2* x, int64_t ld, int64_t n, int k, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(neg_cols_kernel, dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)k), dim3(kThreads),
+                     0, s, x, ld, n);
   return hipGetLastError();
 }
 

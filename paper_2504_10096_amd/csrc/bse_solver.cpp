@@ -53,6 +53,8 @@ struct bse_handle_s {
   double2* X = nullptr;
   double2* Y = nullptr;
   double* omega = nullptr;
+  // device memory of this handle: the caller's allocator (bse_create_ex) or hipMalloc
+  bse_allocator alloc{};
 };
 
 namespace {
@@ -60,12 +62,33 @@ namespace {
 using bse::Arith;
 using cplx = std::complex<double>;
 
+hipError_t dmalloc(bse_handle h, void** p, size_t bytes) {
+  if (h && h->alloc.alloc) {
+    *p = h->alloc.alloc(bytes ? bytes : 1, h->stream, h->alloc.ctx);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+void dfree(bse_handle h, void* p) {
+  if (!p) return;
+  if (h && h->alloc.free)
+    h->alloc.free(p, h->stream, h->alloc.ctx);
+  else
+    (void)hipFree(p);
+}
+
+// Device buffer of one call, freed on scope exit through the handle's allocator.
 struct DevBuf {
   void* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
+  bse_handle h = nullptr;
+  ~DevBuf() { dfree(h, p); }
 };
+
+hipError_t dev_alloc(bse_handle h, DevBuf& b, size_t bytes) {
+  b.h = h;
+  return dmalloc(h, &b.p, bytes);
+}
 
 bse_status fail(bse_handle h, bse_status s, const std::string& msg) {
   if (h) h->err = msg;
@@ -110,7 +133,7 @@ hipError_t hi_ptrs(bse_handle h, bse::MatPtrs* mp) {
 bse_status ensure_mhpart(bse_handle h) {
   if (h->mhpart) return BSE_OK;
   const size_t el = std::max(bse::mh_part_elems(h->L, 4), bse::mk_part_elems(h->L, 4));
-  if (hipMalloc((void**)&h->mhpart, sizeof(double2) * el) != hipSuccess) {
+  if (dmalloc(h, (void**)&h->mhpart, sizeof(double2) * el) != hipSuccess) {
     h->mhpart = nullptr;
     return fail(h, BSE_ERR_OUT_OF_MEMORY, "full-H workspace");
   }
@@ -146,18 +169,17 @@ bse_status keep_solution(bse_handle h, int k, const double* omega, const void* x
   const bool ph = h->kind == BSE_PSEUDO_HERMITIAN;
   const int64_t n = h->n;
   void* ptrs[] = {h->X, h->Y, h->omega};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  for (void* p : ptrs) dfree(h, p);
   h->X = h->Y = nullptr;
   h->omega = nullptr;
   h->solved = false;
-  HIP_TRY(h, hipMalloc((void**)&h->X, sizeof(double2) * (size_t)n * k));
+  HIP_TRY(h, dmalloc(h, (void**)&h->X, sizeof(double2) * (size_t)n * k));
   HIP_TRY(h, hipMemcpyAsync(h->X, x, sizeof(double2) * (size_t)n * k, hipMemcpyDeviceToDevice, h->stream));
   if (ph) {
-    HIP_TRY(h, hipMalloc((void**)&h->Y, sizeof(double2) * (size_t)n * k));
+    HIP_TRY(h, dmalloc(h, (void**)&h->Y, sizeof(double2) * (size_t)n * k));
     HIP_TRY(h, hipMemcpyAsync(h->Y, y, sizeof(double2) * (size_t)n * k, hipMemcpyDeviceToDevice, h->stream));
   }
-  HIP_TRY(h, hipMalloc((void**)&h->omega, sizeof(double) * k));
+  HIP_TRY(h, dmalloc(h, (void**)&h->omega, sizeof(double) * k));
   HIP_TRY(h, hipMemcpyAsync(h->omega, omega, sizeof(double) * k, hipMemcpyDeviceToDevice, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   h->k = k;
@@ -200,6 +222,10 @@ struct Solver {
   // image in Y (rotation partners P2, KP2, Z), and the coefficients of the
   // K2 P products in Tc2.
   int variant = 0;
+  // variant 2 (dual): the folded iteration on K1 K2 in the K2 inner product,
+  // run as variant 0 with the two operators exchanged (K1 <-> K2 is B -> -B);
+  // its pairs are those of H' = diag(I, -I) H diag(I, -I), and v = diag(I, -I) v'.
+  bool dual = false;
   DevBuf bufTc2;
   double2* Tc2 = nullptr;
   int ncolmax = 0;  // columns of one coefficient vector in H1 / H3
@@ -343,7 +369,7 @@ bse_status alloc_solver(Solver& S) {
   };
   for (auto& r : req) {
     if (r.bytes == 0) continue;
-    HIP_TRY(h, hipMalloc(&r.b->p, r.bytes));
+    HIP_TRY(h, dev_alloc(h, *r.b, r.bytes));
   }
   S.U = (double2*)S.bufU.p;
   S.U2 = (double2*)S.bufU2.p;
@@ -396,7 +422,7 @@ bse_status pass(Solver& S, Arith ar, int op /*0: A, 1: K1, 2: K2*/, const double
   if (op == 0)
     e = bse::matvec(h->L, ar, bse::BM_NONE, mm, v, 0, nullptr, 0, 0.0, h->part, out, S.s, e0, e1);
   else
-    e = bse::matvec(h->L, ar, bse::BM_CONJ, mm, v, 0, nullptr, 0, op == 1 ? 1.0 : -1.0, h->part, out,
+    e = bse::matvec(h->L, ar, bse::BM_CONJ, mm, v, 0, nullptr, 0, (op == 1) != S.dual ? 1.0 : -1.0, h->part, out,
                     S.s, e0, e1);
   HIP_TRY(h, e);
   ++S.passes;
@@ -421,7 +447,8 @@ bse_status passes_n(Solver& S, Arith ar, int op, int nv, const double2* v, doubl
     S.ev_pending.push_back({{e0, e1}, ar == bse::AR_HI || ar == bse::AR_HI64});
   }
   const bse::BMode bm = op == 0 ? bse::BM_NONE : bse::BM_CONJ;
-  HIP_TRY(h, bse::mk_apply(h->L, ar, bm, mm, nv, v, S.ld, op == 2 ? -1.0 : 1.0, h->mhpart, out, S.ld, S.s, e0, e1));
+  const double sb = op == 0 ? 1.0 : ((op == 1) != S.dual ? 1.0 : -1.0);
+  HIP_TRY(h, bse::mk_apply(h->L, ar, bm, mm, nv, v, S.ld, sb, h->mhpart, out, S.ld, S.s, e0, e1));
   ++S.passes;
   if (ar == bse::AR_HI || ar == bse::AR_HI64) ++S.passes32;
   return BSE_OK;
@@ -466,7 +493,8 @@ bse_status init_basis(Solver& S, Arith ar, uint64_t seed, int wk = 0, const doub
     if (cols > 0) {
       // random entries have E|z|^2 = 1/6; the previous vectors have norms ~1
       const double sv = 1e-4 * sqrt((double)cols / (S.n / 6.0));
-      HIP_TRY(h, bse::warm_sum(wx, S.ph ? wy : nullptr, S.n, S.n, wk, S.b, q, sv, S.U + (size_t)q * S.ld, S.s));
+      HIP_TRY(h, bse::warm_sum(wx, S.ph ? wy : nullptr, S.dual ? -1.0 : 1.0, S.n, S.n, wk, S.b, q, sv,
+                               S.U + (size_t)q * S.ld, S.s));
     }
   }
   if (S.ph) {
@@ -951,10 +979,12 @@ bse_status finalize(Solver& S, const RitzInfo& R, double* omega, double2* X, dou
   std::vector<double> om(S.k);
   for (int i = 0; i < S.k; ++i) om[i] = S.ph ? sqrt(std::max(R.theta[i], 0.0)) : R.theta[i];
   HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * S.k, hipMemcpyHostToDevice, S.s));
-  if (S.ph)
+  if (S.ph) {
     HIP_TRY(h, bse::ph_vectors(S.U, S.P, S.ld, omega, S.k, S.n, X, Y, S.n, S.s));
-  else
+    if (S.dual) HIP_TRY(h, bse::neg_cols(Y, S.n, S.n, S.k, S.s));
+  } else {
     HIP_TRY(h, bse::copy_cols(S.U, S.ld, X, S.n, S.n, S.k, S.s));
+  }
   const Arith ar = fp64_arith(h);
   const bse::MatPtrs mp = mat_ptrs(h);
   rel.assign(S.k, 0.0);
@@ -1044,7 +1074,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
       {&bNrm, sizeof(double) * 2 * cap},
   };
   for (auto& r : req) {
-    hipError_t e = hipMalloc(&r.b->p, r.bytes);
+    hipError_t e = dev_alloc(h, *r.b, r.bytes);
     if (e != hipSuccess) return fail(h, BSE_ERR_OUT_OF_MEMORY, "refinement workspace");
   }
   double2 *V = (double2*)bV.p, *MV = (double2*)bMV.p, *V2 = (double2*)bV2.p, *MV2 = (double2*)bMV2.p;
@@ -1135,6 +1165,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     for (int c = 0; c < s0; ++c) om0[c] = coupled ? 1.0 : sqrt(std::max(theta0[c], 1e-300));
     HIP_TRY(h, hipMemcpyAsync(Om, om0.data(), sizeof(double) * s0, hipMemcpyHostToDevice, S.s));
     HIP_TRY(h, bse::ph_vectors(S.U, Pv, ld, Om, s0, n, V, V + ld, ld2, S.s));
+    if (S.dual) HIP_TRY(h, bse::neg_cols(V + ld, ld2, n, s0, S.s));  // v = diag(I, -I) v'
   } else {
     HIP_TRY(h, bse::copy_cols(S.U, ld, V, ld2, n, s0, S.s));
   }
@@ -1158,7 +1189,11 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
     if (bulk_ar == bse::AR_HI64) {
       if ((st = mapply(0, s0, bse::AR_HI64, lo_only))) return st;
     }
+    // dual: the iteration's products are M' v' of the exchanged operators, and
+    // M v = diag(I, -I) M' v' (the bottoms are flipped before and after the sum)
+    if (S.dual && bulk_ar == bse::AR_HI64) HIP_TRY(h, bse::neg_cols(MV + ld, ld2, n, s0, S.s));
     HIP_TRY(h, bse::ph_mvectors(S.P, KPv, ld, Om, s0, n, MV, ld2, ld, bulk_ar == bse::AR_HI64 ? 1 : 0, S.s));
+    if (S.dual) HIP_TRY(h, bse::neg_cols(MV + ld, ld2, n, s0, S.s));
   } else {
     if ((st = mapply(0, s0, ar, exact))) return st;
   }
@@ -1272,8 +1307,13 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
       return write_out();
     }
     if (iter + 1 == max_iter) break;
+    // Few pairs left: restart the basis to the lowest k + 32 Ritz vectors, so
+    // that the remaining sweeps (one expansion each for a handful of pairs)
+    // solve a Rayleigh-Ritz problem of that order instead of the full basis.
+    const int nbad = (int)bad.size();
+    if (nbad <= std::max(4, k / 16) && s > k + 64) s = k + 32;
     // room for the expansion: drop the highest Ritz vectors if needed
-    if (s + (int)bad.size() > cap) s = std::max(k, cap - (int)bad.size());
+    if (s + nbad > cap) s = std::max(k, cap - nbad);
     const int s_old = s;
     for (int a : bad) {
       if (s >= cap) break;
@@ -1416,12 +1456,19 @@ const char* bse_last_error(bse_handle h) { return h ? h->err.c_str() : "null han
 
 bse_status bse_create(bse_handle* out, bse_kind kind, int64_t n, bse_storage storage,
                       void* hip_stream) {
+  return bse_create_ex(out, kind, n, storage, hip_stream, nullptr);
+}
+
+bse_status bse_create_ex(bse_handle* out, bse_kind kind, int64_t n, bse_storage storage, void* hip_stream,
+                         const bse_allocator* alloc) {
   if (!out) return BSE_ERR_INVALID_ARG;
   *out = nullptr;
   if (n < 1 || (kind != BSE_TDA && kind != BSE_PSEUDO_HERMITIAN) ||
       (storage != BSE_STORE_C128 && storage != BSE_STORE_HILO) || n > (int64_t)1 << 31)
     return BSE_ERR_INVALID_ARG;
+  if (alloc && (!alloc->alloc || !alloc->free)) return BSE_ERR_INVALID_ARG;
   bse_handle h = new bse_handle_s();
+  if (alloc) h->alloc = *alloc;
   h->kind = kind;
   h->n = n;
   h->storage = storage;
@@ -1445,28 +1492,28 @@ bse_status bse_create(bse_handle* out, bse_kind kind, int64_t n, bse_storage sto
     bse_destroy(h);
     return s;
   };
-  auto alloc = [&](void** p, size_t bytes) -> bool {
-    hipError_t e = hipMalloc(p, bytes);
+  auto zalloc = [&](void** p, size_t bytes) -> bool {
+    hipError_t e = dmalloc(h, p, bytes);
     if (e != hipSuccess) return false;
     return hipMemsetAsync(*p, 0, bytes, h->stream) == hipSuccess;
   };
-  if (!alloc((void**)&L.blkmap, sizeof(int2) * L.nblk)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
+  if (!zalloc((void**)&L.blkmap, sizeof(int2) * L.nblk)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
   if (hipMemcpyAsync(L.blkmap, bm.data(), sizeof(int2) * L.nblk, hipMemcpyHostToDevice, h->stream) !=
       hipSuccess)
     return cleanup(BSE_ERR_DEVICE);
   const size_t el = L.elems();
   const bool ph = kind == BSE_PSEUDO_HERMITIAN;
   if (storage == BSE_STORE_C128) {
-    if (!alloc(&h->a, el * 16)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
-    if (ph && !alloc(&h->b, el * 16)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
+    if (!zalloc(&h->a, el * 16)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
+    if (ph && !zalloc(&h->b, el * 16)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
   } else {
-    if (!alloc(&h->a, el * 8) || !alloc(&h->alo, el * 8)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
-    if (ph && (!alloc(&h->b, el * 8) || !alloc(&h->blo, el * 8)))
+    if (!zalloc(&h->a, el * 8) || !zalloc(&h->alo, el * 8)) return cleanup(BSE_ERR_OUT_OF_MEMORY);
+    if (ph && (!zalloc(&h->b, el * 8) || !zalloc(&h->blo, el * 8)))
       return cleanup(BSE_ERR_OUT_OF_MEMORY);
   }
-  if (!alloc((void**)&h->part, sizeof(double2) * bse::mv_part_elems(L)))
+  if (!zalloc((void**)&h->part, sizeof(double2) * bse::mv_part_elems(L)))
     return cleanup(BSE_ERR_OUT_OF_MEMORY);
-  if (storage == BSE_STORE_HILO && !alloc((void**)&h->dcorr, sizeof(double) * (size_t)n))
+  if (storage == BSE_STORE_HILO && !zalloc((void**)&h->dcorr, sizeof(double) * (size_t)n))
     return cleanup(BSE_ERR_OUT_OF_MEMORY);
   if (hipStreamSynchronize(h->stream) != hipSuccess) return cleanup(BSE_ERR_DEVICE);
   *out = h;
@@ -1477,8 +1524,7 @@ bse_status bse_destroy(bse_handle h) {
   if (!h) return BSE_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   void* ptrs[] = {h->a, h->alo, h->b, h->blo, h->part, h->mhpart, h->L.blkmap, h->X, h->Y, h->omega, h->dcorr};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  for (void* p : ptrs) dfree(h, p);
   delete h;
   return BSE_OK;
 }
@@ -1528,7 +1574,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
     return fail(h, BSE_ERR_INVALID_ARG, "mixed precision needs HILO storage");
   const int64_t n = h->n;
   if (o.block < 0 || o.block > 4) return fail(h, BSE_ERR_INVALID_ARG, "block must be in [0, 4]");
-  if (o.variant < 0 || o.variant > 1) return fail(h, BSE_ERR_INVALID_ARG, "variant must be 0 or 1");
+  if (o.variant < 0 || o.variant > 2) return fail(h, BSE_ERR_INVALID_ARG, "variant must be 0, 1 or 2");
   if (o.warm_k < 0 || o.warm_k > n || (o.warm_k > 0 && (!o.warm_x || (ph && !o.warm_y))))
     return fail(h, BSE_ERR_INVALID_ARG, "warm start needs warm_k in [0, N] and its vectors");
   int m = o.ncv > 0 ? o.ncv : (int)round_up(std::max(2 * k, k + 32), 16);
@@ -1561,7 +1607,8 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   S.m = m;
   S.keep = keep;
   S.b = b;
-  S.variant = ph ? o.variant : 0;
+  S.variant = ph && o.variant != 2 ? o.variant : 0;
+  S.dual = ph && o.variant == 2;
   S.tol = tol;
   S.s = h->stream;
   if (const char* tr = getenv("BSE_TRACE")) S.trace = tr[0] == '1';
@@ -1722,13 +1769,13 @@ bse_status bse_backward(bse_handle h, const double* g, void* d_a, void* d_b) {
   const int k = h->k;
   const int64_t n = h->n;
   DevBuf wgt, red, nx, ny;
-  HIP_TRY(h, hipMalloc(&wgt.p, sizeof(double) * k));
+  HIP_TRY(h, dev_alloc(h, wgt, sizeof(double) * k));
   std::vector<double> gh(k), w(k, 1.0);
   HIP_TRY(h, hipMemcpyAsync(gh.data(), g, sizeof(double) * k, hipMemcpyDeviceToHost, h->stream));
   if (ph) {
-    HIP_TRY(h, hipMalloc(&red.p, sizeof(double) * (size_t)bse::nchunks(n) * k));
-    HIP_TRY(h, hipMalloc(&nx.p, sizeof(double) * k));
-    HIP_TRY(h, hipMalloc(&ny.p, sizeof(double) * k));
+    HIP_TRY(h, dev_alloc(h, red, sizeof(double) * (size_t)bse::nchunks(n) * k));
+    HIP_TRY(h, dev_alloc(h, nx, sizeof(double) * k));
+    HIP_TRY(h, dev_alloc(h, ny, sizeof(double) * k));
     HIP_TRY(h, bse::colnorms(h->X, k, n, n, (double*)red.p, (double*)nx.p, h->stream));
     HIP_TRY(h, bse::colnorms(h->Y, k, n, n, (double*)red.p, (double*)ny.p, h->stream));
     std::vector<double> a(k), b(k);
@@ -1776,13 +1823,13 @@ bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse
   for (int q = 0; q < n_comp; ++q)
     if (comps[q].form == BSE_COMP_LOWRANK) maxrank = std::max<int64_t>(maxrank, comps[q].rank);
   DevBuf wgt, part, tmp, tmp2, zero, hv, cpart;
-  HIP_TRY(h, hipMalloc(&wgt.p, sizeof(double) * k));
-  HIP_TRY(h, hipMalloc(&part.p, sizeof(double) * std::max<int64_t>({n, nch * k, bse::quad_packed_parts(n)})));
-  HIP_TRY(h, hipMalloc(&tmp.p, sizeof(double2) * n));
-  HIP_TRY(h, hipMalloc(&tmp2.p, sizeof(double2) * n));
-  HIP_TRY(h, hipMalloc(&zero.p, sizeof(double2) * n));
-  HIP_TRY(h, hipMalloc(&hv.p, sizeof(double2) * (maxrank + 2)));
-  HIP_TRY(h, hipMalloc(&cpart.p, sizeof(double2) * nch * (maxrank + 2)));
+  HIP_TRY(h, dev_alloc(h, wgt, sizeof(double) * k));
+  HIP_TRY(h, dev_alloc(h, part, sizeof(double) * std::max<int64_t>({n, nch * k, bse::quad_packed_parts(n)})));
+  HIP_TRY(h, dev_alloc(h, tmp, sizeof(double2) * n));
+  HIP_TRY(h, dev_alloc(h, tmp2, sizeof(double2) * n));
+  HIP_TRY(h, dev_alloc(h, zero, sizeof(double2) * n));
+  HIP_TRY(h, dev_alloc(h, hv, sizeof(double2) * (maxrank + 2)));
+  HIP_TRY(h, dev_alloc(h, cpart, sizeof(double2) * nch * (maxrank + 2)));
   HIP_TRY(h, hipMemsetAsync(zero.p, 0, sizeof(double2) * n, st));
   if (ph) {
     std::vector<double> a(k), b(k);
@@ -1858,8 +1905,8 @@ bse_status bse_strength(bse_handle h, const double* g, int32_t n_comp, const bse
       // stored FP64 block, up to four vectors per read of the triangle
       if (bse_status e = ensure_mhpart(h)) return e;
       DevBuf vin, vout;
-      HIP_TRY(h, hipMalloc(&vin.p, sizeof(double2) * 4 * (size_t)n));
-      HIP_TRY(h, hipMalloc(&vout.p, sizeof(double2) * 4 * (size_t)n));
+      HIP_TRY(h, dev_alloc(h, vin, sizeof(double2) * 4 * (size_t)n));
+      HIP_TRY(h, dev_alloc(h, vout, sizeof(double2) * 4 * (size_t)n));
       double2* vi = (double2*)vin.p;
       double2* vo = (double2*)vout.p;
       const int nvec = ph ? 2 * k : k;
@@ -1945,7 +1992,7 @@ bse_status bse_haydock(bse_handle h, int32_t nd, const void* d, int32_t max_iter
   };
   for (auto& r : req) {
     if (r.bytes == 0) continue;
-    HIP_TRY(h, hipMalloc(&r.b->p, r.bytes));
+    HIP_TRY(h, dev_alloc(h, *r.b, r.bytes));
   }
   if (nd > 1)
     if (bse_status e = ensure_mhpart(h)) return e;
@@ -2121,16 +2168,16 @@ bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, 
   };
   const size_t sq = (size_t)n2 * n2;
   DevBuf bMr, bG, bZ, bEv, bE, bInfo, bRm, bF, bW, bRed, bRes;
-  HIP_TRY(h, hipMalloc(&bF.p, sizeof(double) * k));
+  HIP_TRY(h, dev_alloc(h, bF, sizeof(double) * k));
   double ms_form = 0.0, ms_chol = 0.0, ms_eig = 0.0;
   double2* X = (double2*)x;
   double2* Y = (double2*)y;
   if (!ph) {
     // TDA: the dense Hermitian eigenproblem of A (rocSOLVER, divide and conquer)
-    HIP_TRY(h, hipMalloc(&bZ.p, sizeof(double2) * sq));
-    HIP_TRY(h, hipMalloc(&bEv.p, sizeof(double) * n2));
-    HIP_TRY(h, hipMalloc(&bE.p, sizeof(double) * n2));
-    HIP_TRY(h, hipMalloc(&bInfo.p, sizeof(rocblas_int)));
+    HIP_TRY(h, dev_alloc(h, bZ, sizeof(double2) * sq));
+    HIP_TRY(h, dev_alloc(h, bEv, sizeof(double) * n2));
+    HIP_TRY(h, dev_alloc(h, bE, sizeof(double) * n2));
+    HIP_TRY(h, dev_alloc(h, bInfo, sizeof(rocblas_int)));
     double2* Z = (double2*)bZ.p;
     double* ev = (double*)bEv.p;
     rocblas_int* info = (rocblas_int*)bInfo.p;
@@ -2158,10 +2205,10 @@ bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, 
     // whose eigenvalues are the +-omega; the lowest k positive ones and their vectors z by
     // bisection and inverse iteration; the eigenvectors of -i W are Q D z, and v = Q4 L^{-T} Q D z
     // with Q4 the Q of Eq. (4).
-    HIP_TRY(h, hipMalloc(&bMr.p, sizeof(double) * sq));
-    HIP_TRY(h, hipMalloc(&bG.p, sizeof(double) * sq));
-    HIP_TRY(h, hipMalloc(&bZ.p, sizeof(double) * sq));  // W
-    HIP_TRY(h, hipMalloc(&bInfo.p, sizeof(int)));
+    HIP_TRY(h, dev_alloc(h, bMr, sizeof(double) * sq));
+    HIP_TRY(h, dev_alloc(h, bG, sizeof(double) * sq));
+    HIP_TRY(h, dev_alloc(h, bZ, sizeof(double) * sq));  // W
+    HIP_TRY(h, dev_alloc(h, bInfo, sizeof(int)));
     double* Mr = (double*)bMr.p;
     double* G = (double*)bG.p;
     double* Wm = (double*)bZ.p;
@@ -2183,7 +2230,7 @@ bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, 
     const double te = now_ms();
     // reduction workspace: G is free now
     const int64_t nch = (n2 - 1 + 255) / 256;
-    HIP_TRY(h, hipMalloc(&bE.p, sizeof(double) * (size_t)(2 * n2 * 64 + nch * n2 + 128 + 2 * n2)));
+    HIP_TRY(h, dev_alloc(h, bE, sizeof(double) * (size_t)(2 * n2 * 64 + nch * n2 + 128 + 2 * n2)));
     double* Vp = (double*)bE.p;
     double* Zp = Vp + (size_t)n2 * 64;
     double* part = Zp + (size_t)n2 * 64;
@@ -2217,7 +2264,7 @@ bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, 
         if (j + 1 < n2 && e[j] < 0.0) sg = -sg;
       }
     }
-    HIP_TRY(h, hipMalloc(&bRm.p, sizeof(double) * rh.size()));
+    HIP_TRY(h, dev_alloc(h, bRm, sizeof(double) * rh.size()));
     double* Rm = (double*)bRm.p;
     HIP_TRY(h, hipMemcpyAsync(Rm, rh.data(), sizeof(double) * rh.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(h, bse::skew_back(Wm, n2, tau, Mr, n2, n2, Rm, n2, 2 * k, s));  // R <- L^{-T} Q R
@@ -2226,8 +2273,8 @@ bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, 
     HIP_TRY(h, hipStreamSynchronize(s));
     ms_eig = now_ms() - te;
     // X^H X - Y^H Y = 1 per pair
-    HIP_TRY(h, hipMalloc(&bRed.p, sizeof(double) * ((size_t)bse::nchunks(n) * std::max(k, 2) + 64)));
-    HIP_TRY(h, hipMalloc(&bRes.p, sizeof(double) * 2 * k));
+    HIP_TRY(h, dev_alloc(h, bRed, sizeof(double) * ((size_t)bse::nchunks(n) * std::max(k, 2) + 64)));
+    HIP_TRY(h, dev_alloc(h, bRes, sizeof(double) * 2 * k));
     double* nr = (double*)bRes.p;
     HIP_TRY(h, bse::colnorms(X, k, n, n, (double*)bRed.p, nr, s));
     HIP_TRY(h, bse::colnorms(Y, k, n, n, (double*)bRed.p, nr + k, s));
@@ -2246,9 +2293,9 @@ bse_status bse_direct(bse_handle h, int32_t k, double* omega, void* x, void* y, 
   HIP_TRY(h, hipMemcpyAsync(om.data(), omega, sizeof(double) * k, hipMemcpyDeviceToHost, s));
   HIP_TRY(h, hipStreamSynchronize(s));
   // FP64 residuals of the k pairs through the stored operator
-  HIP_TRY(h, hipMalloc(&bW.p, sizeof(double2) * (size_t)round_up(n, 64)));
-  if (!bRed.p) HIP_TRY(h, hipMalloc(&bRed.p, sizeof(double) * ((size_t)bse::nchunks(n) * 2 + 64)));
-  if (!bRes.p) HIP_TRY(h, hipMalloc(&bRes.p, sizeof(double) * 4));
+  HIP_TRY(h, dev_alloc(h, bW, sizeof(double2) * (size_t)round_up(n, 64)));
+  if (!bRed.p) HIP_TRY(h, dev_alloc(h, bRed, sizeof(double) * ((size_t)bse::nchunks(n) * 2 + 64)));
+  if (!bRes.p) HIP_TRY(h, dev_alloc(h, bRes, sizeof(double) * 4));
   double2* Wv = (double2*)bW.p;
   double* red = (double*)bRed.p;
   double* res = (double*)bRes.p;

@@ -283,16 +283,22 @@ hipError_t start_vector(double2* v, int64_t n, uint64_t seed, hipStream_t) {
   return hipSuccess;
 }
 
-hipError_t warm_sum(const double2* X, const double2* Y, int64_t ld, int64_t n, int k, int b, int q, double sv,
-                    double2* v, hipStream_t) {
+hipError_t warm_sum(const double2* X, const double2* Y, double ys, int64_t ld, int64_t n, int k, int b, int q,
+                    double sv, double2* v, hipStream_t) {
   for (int64_t i = 0; i < n; ++i) {
     cplx acc = 0.0;
     for (int c = q; c < k; c += b) {
       acc += C(X[i + (size_t)c * ld]);
-      if (Y) acc += std::conj(C(Y[i + (size_t)c * ld]));
+      if (Y) acc += ys * std::conj(C(Y[i + (size_t)c * ld]));
     }
     v[i] = D(sv * C(v[i]) + acc);
   }
+  return hipSuccess;
+}
+
+hipError_t neg_cols(double2* x, int64_t ld, int64_t n, int k, hipStream_t) {
+  for (int c = 0; c < k; ++c)
+    for (int64_t i = 0; i < n; ++i) x[(size_t)c * ld + i] = make_double2(-x[(size_t)c * ld + i].x, -x[(size_t)c * ld + i].y);
   return hipSuccess;
 }
 

@@ -28,7 +28,8 @@ vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_do
 
 # the ABI structs of include/bse.h, as the binding declares them (kept in one place so that a field
 # added to the header cannot leave a shorter struct here for the library to write past)
-from paper_2504_10096_amd import SolveOpts as Opts, Stats  # noqa: E402
+from paper_2504_10096_amd import Allocator, SolveOpts as Opts, Stats  # noqa: E402
+from paper_2504_10096_amd import _ALLOC_FN, _FREE_FN  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -43,6 +44,7 @@ def lib(tmp_path_factory):
         pytest.skip("host compiler or ROCm libraries unavailable: " + r.stderr[-300:])
     L = ctypes.CDLL(so)
     L.bse_create.argtypes = [ctypes.POINTER(vp), i32, i64, i32, vp]
+    L.bse_create_ex.argtypes = [ctypes.POINTER(vp), i32, i64, i32, vp, ctypes.POINTER(Allocator)]
     L.bse_set_packed.argtypes = [vp, i32, i64, i64, vp, i32]
     L.bse_solve.argtypes = [vp, i32, dbl, ctypes.POINTER(Opts), vp, vp, vp, ctypes.POINTER(Stats)]
     L.bse_haydock.argtypes = [vp, i32, vp, i32, dbl, i32, vp, i32, dbl, vp, vp, ctypes.POINTER(dbl), vp,
@@ -105,7 +107,7 @@ def ph_case(n=120, seed=5):
     return m.pack_host(0), m.pack_host(1)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("storage,precision,fp32,tol", [(0, 0, 0, 1e-10), (1, 1, 0, 1e-8), (1, 1, 1, 1e-8)])
 def test_ph_solve_matches_oracle(lib, variant, storage, precision, fp32, tol):
     ap, bp = ph_case()
@@ -187,7 +189,7 @@ def test_not_positive_definite_is_reported(lib):
     A = np.diag(np.arange(1.0, n + 1)).astype(complex)
     B = np.zeros((n, n), dtype=complex)
     B[0, 0] = 1.6  # ||B|| > lambda_min(A): M indefinite
-    for variant in (0, 1):
+    for variant in (0, 1, 2):
         h = Handle(lib, 1, pack_upper(A), pack_upper(B))
         rc, *_ = h.solve(4, 1e-10, variant=variant)
         assert rc == NOT_PD, (variant, rc, h.error())
@@ -216,6 +218,26 @@ def test_not_converged_returns_best(lib):
     h.close()
 
 
+@pytest.mark.parametrize("variant", [0, 2])
+def test_ph_not_converged_returns_pairs_of_h(lib, variant):
+    """An unreachable tol (1e-17): after the restart budget the best approximations come back as (X, Y) of H
+    itself (the dual iteration's vectors are mapped back from diag(I, -I) H diag(I, -I)),
+    normalized, and the lowest pairs, converged by then, have small residuals with respect to H
+    (a Y of the wrong sign would leave a residual of the size of Y)."""
+    ap, bp = ph_case(150, 4)
+    h = Handle(lib, 1, ap, bp)
+    rc, om, X, Y, st = h.solve(6, 1e-17, max_restarts=20, ncv=24, variant=variant)
+    assert rc == NOT_CONV
+    nrm = np.sum(np.abs(X) ** 2, axis=0) - np.sum(np.abs(Y) ** 2, axis=0)
+    assert np.max(np.abs(nrm - 1)) < 1e-9
+    rel = oracle.residual_ph(ap, bp, om, X, Y)
+    assert rel[0] < 1e-6, rel
+    assert np.min(np.linalg.norm(Y, axis=0)) > 1e-3  # the check above sees the sign of Y
+    ref, _, _ = oracle.ph(ap, bp, 6, vectors=False)
+    assert np.all(om >= ref * (1 - 1e-12))
+    h.close()
+
+
 def test_nonfinite_input_is_reported(lib):
     n = 40
     A = random_herm(np.random.default_rng(2), n)
@@ -233,7 +255,7 @@ def test_invalid_arguments(lib):
     for k, tol in [(0, 1e-8), (31, 1e-8), (3, 0.0), (3, -1.0)]:
         rc, *_ = h.solve(k, tol)
         assert rc == INVALID, (k, tol)
-    rc, *_ = h.solve(3, 1e-8, variant=2)
+    rc, *_ = h.solve(3, 1e-8, variant=3)
     assert rc == INVALID
     rc, *_ = h.solve(3, 1e-8, precision=1)  # mixed needs hi + lo storage
     assert rc == INVALID
@@ -268,3 +290,80 @@ def test_haydock_several_dipoles(lib, kind):
         assert np.max(np.abs(be[q] - rb)) <= 1e-11 * np.max(np.abs(rb))
         assert abs(nn[q] - rn) <= 1e-12 * rn
     h.close()
+
+
+class CountingAllocator:
+    """bse_allocator over libc malloc/free that tracks live blocks; fail_at = n makes the n-th
+    request (1-based) return NULL."""
+
+    def __init__(self, fail_at=0):
+        self.libc = ctypes.CDLL(None)
+        self.libc.malloc.restype, self.libc.malloc.argtypes = vp, [ctypes.c_size_t]
+        self.libc.free.argtypes = [vp]
+        self.live, self.calls, self.fail_at = {}, 0, fail_at
+        self.struct = Allocator(_ALLOC_FN(self._alloc), _FREE_FN(self._free), None)
+
+    def _alloc(self, nbytes, stream, ctx):
+        self.calls += 1
+        if self.calls == self.fail_at:
+            return None
+        p = self.libc.malloc(nbytes)
+        self.libc.memset(ctypes.c_void_p(p), 0, ctypes.c_size_t(nbytes))
+        self.live[p] = nbytes
+        return p
+
+    def _free(self, ptr, stream, ctx):
+        assert ptr in self.live, "free of a pointer the allocator did not return"
+        del self.live[ptr]
+        self.libc.free(ctypes.c_void_p(ptr))
+
+
+def test_allocator_hook_takes_every_buffer(lib):
+    """bse_create_ex: the triangles and every workspace of solve / backward / Haydock come from
+    the caller's allocator, results equal those of bse_create's handle, and destroy returns every
+    block.  A NULL from the allocator at any request of create is OUT_OF_MEMORY with nothing
+    leaked."""
+    ap, bp = ph_case(90, 11)
+    n, k = 90, 4
+    ref = Handle(lib, 1, ap, bp)
+    rc, om0, X0, Y0, _ = ref.solve(k, 1e-12)
+    assert rc == OK
+    al = CountingAllocator()
+    h = vp()
+    assert lib.bse_create_ex(ctypes.byref(h), 1, n, 0, None, ctypes.byref(al.struct)) == OK
+    assert sum(al.live.values()) >= 2 * 16 * n * (n + 1) // 2
+    other = Handle.__new__(Handle)
+    other.L, other.kind, other.n, other.h = lib, 1, n, h
+    other.keep = [np.ascontiguousarray(ap), np.ascontiguousarray(bp)]
+    assert lib.bse_set_packed(h, 0, 0, n, other.keep[0].ctypes.data, 1) == OK
+    assert lib.bse_set_packed(h, 1, 0, n, other.keep[1].ctypes.data, 1) == OK
+    calls = al.calls
+    rc, om1, X1, Y1, _ = other.solve(k, 1e-12)
+    assert rc == OK and al.calls > calls  # the solve's workspaces went through the hook
+    assert np.array_equal(om0, om1) and np.array_equal(X0, X1) and np.array_equal(Y0, Y1)
+    g = synth.loss_weights(3, k)
+    ga, gb = np.zeros(len(ap), complex), np.zeros(len(ap), complex)
+    assert lib.bse_backward(h, g.ctypes.data, ga.ctypes.data, gb.ctypes.data) == OK
+    d = np.random.default_rng(2).standard_normal(n) + 0j
+    assert other.haydock(d, 6)[0] == OK
+    # a NULL from the allocator inside a solve is OUT_OF_MEMORY; the handle stays usable
+    al.fail_at = al.calls + 1
+    rc, *_ = other.solve(k, 1e-12)
+    assert rc == OOM, rc
+    rc, om2, *_ = other.solve(k, 1e-12)
+    assert rc == OK and np.array_equal(om0, om2)
+    other.close()
+    assert not al.live
+    ref.close()
+    # allocator failure at each request of create: OUT_OF_MEMORY and nothing left allocated
+    n_create = CountingAllocator()
+    assert lib.bse_create_ex(ctypes.byref(h), 1, n, 1, None, ctypes.byref(n_create.struct)) == OK
+    lib.bse_destroy(h)
+    for fail_at in range(1, n_create.calls + 1):
+        bad = CountingAllocator(fail_at)
+        h = vp()
+        assert lib.bse_create_ex(ctypes.byref(h), 1, n, 1, None, ctypes.byref(bad.struct)) == OOM
+        assert not bad.live, fail_at
+    # an allocator without both functions is rejected
+    half = Allocator(al.struct.alloc, _FREE_FN(), None)
+    assert lib.bse_create_ex(ctypes.byref(h), 1, n, 0, None, ctypes.byref(half)) == INVALID

@@ -171,7 +171,7 @@ def test_solve_tda_synth(n, k):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("n,k", [(300, 8), (900, 10)])
 def test_solve_ph_synth(n, k, variant):
     print(f"ph synth n={n} k={k} variant={variant}", flush=True)
@@ -182,7 +182,7 @@ def test_solve_ph_synth(n, k, variant):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("n,k", [(200, 6), (640, 10)])
 def test_solve_ph_strong_coupling(n, k, variant):
     """Generic dense blocks with ||B||_2 = 0.6 lambda_min(A): large Y components."""
@@ -221,7 +221,7 @@ def test_tiny_sizes(n):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_all_pairs_k_equals_n(variant):
     n = 24
     rng = np.random.default_rng(9)
@@ -231,7 +231,7 @@ def test_all_pairs_k_equals_n(variant):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_real_blocks_no_duplicate_pairs(variant):
     n, k = 150, 10
     rng = np.random.default_rng(4)
@@ -246,7 +246,7 @@ def test_real_blocks_no_duplicate_pairs(variant):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_b_zero_reduces_to_tda(variant):
     n, k = 200, 8
     m = ph_matrix(n, 77)
@@ -260,7 +260,7 @@ def test_b_zero_reduces_to_tda(variant):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_not_positive_definite(variant):
     n = 60
     A = np.diag(np.arange(1.0, n + 1)).astype(complex)
@@ -285,7 +285,7 @@ def test_invalid_arguments():
     with pytest.raises(bse.BSEError) as e:
         s.solve(4, 1e-8, precision="mixed")
     assert e.value.status == bse.ERR_INVALID_ARG
-    for v in (-1, 2):
+    for v in (-1, 3):
         with pytest.raises(bse.BSEError) as e:
             s.solve(4, 1e-8, variant=v)
         assert e.value.status == bse.ERR_INVALID_ARG
@@ -329,6 +329,45 @@ def test_deterministic_bitwise():
     s.close()
 
 
+def test_torch_allocator_hook():
+    """bse_create_ex with PyTorch's caching allocator: the handle's triangles and the workspaces
+    of solve, apply, direct and backward come from torch's pool (memory_allocated grows by at
+    least the stored triangles and returns to its level after close), and every result is
+    bitwise that of the hipMalloc handle on the same input."""
+    n, k = 600, 6
+    m = ph_matrix(n, 8)
+    ap, bp = m.pack_host(0), m.pack_host(1)
+    ref = make_solver("ph", ap, bp, storage="hilo")
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    s = bse.Solver("ph", n, storage="hilo", allocator="torch")
+    grown = torch.cuda.memory_allocated() - base
+    assert grown >= 4 * 8 * n * (n + 1) // 2  # hi and lo triangles of A and B
+    s.set_packed("A", dev(ap))
+    s.set_packed("B", dev(bp))
+    for prec in ("mixed", "fp64"):
+        a = ref.solve(k, 1e-10, precision=prec)
+        b = s.solve(k, 1e-10, precision=prec)
+        assert all(torch.equal(u, v) for u, v in zip(a[:3], b[:3]))
+    g = torch.linspace(0.5, 1.5, k, dtype=torch.float64)
+    ga, gb = ref.backward(g)
+    ha, hb = s.backward(g)
+    assert torch.equal(ga, ha) and torch.equal(gb, hb)
+    x = dev(np.random.default_rng(3).standard_normal((3, 2 * n)) + 0j)
+    assert torch.equal(ref.apply("H", x), s.apply("H", x))
+    d0, d1 = ref.direct(k), s.direct(k)
+    assert all(torch.equal(u, v) for u, v in zip(d0[:3], d1[:3]))
+    del a, b, ga, gb, ha, hb, x, d0, d1
+    held = torch.cuda.memory_allocated() - base
+    assert held >= grown
+    s.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base
+    ref.close()
+    with pytest.raises(ValueError):
+        bse.Solver("ph", n, allocator="bogus")
+
+
 # ------------------------------------------------------------------ mixed path
 def test_mixed_tda_matches_oracle():
     n, k = 1500, 12
@@ -344,7 +383,7 @@ def test_mixed_tda_matches_oracle():
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_mixed_ph_matches_oracle(variant):
     n, k = 900, 10
     m = ph_matrix(n, 32)
@@ -503,7 +542,7 @@ def _golden(name):
     return mod.load(name)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_workload_ph_n4096_k32_golden(variant):
     """Pseudo-Hermitian workload N = 4096 (operator 8192), lowest 32 pairs at
     tol 1e-10 against the oracle's stored values; residuals checked by the oracle."""

@@ -65,6 +65,44 @@ def test_workload_tda_n32768_k64_mixed_and_fp64():
     s.close()
 
 
+def test_workload_ph_n100000_k100_mixed():
+    """The benchmark workload at full size, in the configuration bench.py times (PH N = 1e5,
+    k = 100, tol 1e-8, mixed path on hi + lo storage from the device generator): the solver's own
+    FP64 residuals, the oracle's streaming FP64 residual of pairs spread over the 100, the
+    normalization X^H X - Y^H Y = 1 and ascending omega above the recipe's lower edge."""
+    w = synth.WORKLOADS[4]
+    mat = synth.workload_matrix(4)
+    k, tol = w["k"], w["tol"]
+    print(f"workload {w['name']}", flush=True)
+    s = generated_solver(mat, "hilo", chunk_entries=1 << 27)
+    om, X, Y, st = s.solve(k, tol, precision="mixed")
+    print("mixed", st["passes"], st["ms_total"], st["max_rel_residual"], flush=True)
+    s.close()
+    assert st["n_converged"] == k and st["max_rel_residual"] <= tol
+    o = host(om)
+    assert np.all(np.diff(o) >= 0) and o[0] > 0.9
+    Xh, Yh = host(X), host(Y)
+    nrm = np.sum(np.abs(Xh) ** 2, axis=1) - np.sum(np.abs(Yh) ** 2, axis=1)
+    assert np.max(np.abs(nrm - 1)) < 1e-9
+    idx = [0, 33, 66, 99]
+    rel = oracle.residual_generated(mat, o[idx], Xh[idx].T, Yh[idx].T)
+    print("oracle residuals", rel, flush=True)
+    assert np.max(rel) <= tol * 1.01
+
+
+def test_recorded_lambda_min_raw_n100000():
+    """lambda_min of the raw block of the N = 1e5 workload, from which the benchmark's shift is
+    taken: the FP64 GPU TDA path at k = 1 (hi + lo storage) against the oracle's recorded value."""
+    w = synth.WORKLOADS[4]
+    raw = synth.Matrix(w["n"], w["seed"], ph=False)
+    ref = synth.recorded_lambda_min_raw(w["n"], w["seed"])
+    s = generated_solver(raw, "hilo", chunk_entries=1 << 27)
+    lam, X, _, st = s.solve(1, 1e-12)
+    print("lambda_min raw", host(lam)[0], ref, st["passes"], flush=True)
+    assert abs(host(lam)[0] - ref) <= 1e-11 * abs(ref)
+    s.close()
+
+
 def test_recorded_lambda_min_raw_n16384():
     """lambda_min of the raw block of the N = 16384 workload (no shift, the matrix the recipe's
     shift is taken from): the FP64 GPU TDA path at k = 1 against the oracle's recorded value."""
