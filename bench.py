@@ -36,12 +36,18 @@ HBM_PEAK_GBPS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
+PMC_FILES = {"mv_stream_kernel<512, 3, 1>": "pmc_mv_stream_kernel_ph_n100000.txt",
+             "mh_stream_kernel<512, 3, 2>": "pmc_mh_stream_kernel_ph_n100000.txt"}
+
+
 def counter_traffic(kernel_name):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary, or
     None when there is none for this kernel or the kernel source changed since the counters were taken."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(here, "profiles", "pmc_mv_stream_kernel_ph_n100000.txt")
+    if kernel_name not in PMC_FILES:
+        return None
+    path = os.path.join(here, "profiles", PMC_FILES[kernel_name])
     src = os.path.join(here, "paper_2504_10096_amd", "csrc", "bse_kernels.hip")
     try:
         fields = {}
@@ -203,7 +209,8 @@ def main():
     p.add_argument("--chunk-gb", type=float, default=2.0)
     p.add_argument("--grad", choices=["on", "off"], default="on",
                    help="PH: dL/dalpha and dL/dbeta of the solve through the adjoint")
-    p.add_argument("--block", type=int, default=0, help="TDA Lanczos block size (0: automatic)")
+    p.add_argument("--block", type=int, default=0,
+                   help="TDA / PH variant 3 Lanczos block size (0: automatic)")
     p.add_argument("--ncv", type=int, default=0, help="Lanczos basis size (0: default)")
     p.add_argument("--keep", type=int, default=0, help="Ritz vectors kept at a restart (0: default)")
     p.add_argument("--refine-start", type=int, default=0, help="Ritz vectors starting the refinement (0: default)")
@@ -212,9 +219,9 @@ def main():
                         "(0: default)")
     p.add_argument("--haydock", choices=["on", "off"], default="on",
                    help="also time a Lanczos-Haydock spectrum of the same matrix")
-    p.add_argument("--variant", type=int, default=0, choices=[0, 1, 2],
+    p.add_argument("--variant", type=int, default=3, choices=[0, 1, 2, 3],
                    help="PH iteration: 0 K1-metric Lanczos on K2 K1, 1 Lanczos on H in the M inner product, "
-                        "2 K2-metric Lanczos on K1 K2")
+                        "2 K2-metric Lanczos on K1 K2, 3 block Lanczos on H in the M inner product")
     p.add_argument("--precision", choices=["auto", "fp64"], default="auto",
                    help="auto: the mixed path where the workload uses it; fp64: FP64 passes only")
     p.add_argument("--budget-s", type=float, default=480.0,
@@ -304,7 +311,7 @@ def main():
             fill_from_generator(solver, mat, int(args.chunk_gb * 2 ** 30 / 16), stream)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, _, _, st = solver.solve(k, tol, precision="mixed")
+            _, _, _, st = solver.solve(k, tol, precision="mixed", variant=args.variant, block=args.block)
             torch.cuda.synchronize()
             t = time.perf_counter() - t0
             rows.append({"n": n, "seconds": t, "passes": st["passes"], "restarts": st["restarts"],
@@ -318,7 +325,8 @@ def main():
         A, B = np.polyfit(ln, lt, 1)
         lp = np.log10([r["passes"] for r in rows])
         Ap, _ = np.polyfit(ln, lp, 1)
-        print(json.dumps({"mode": "nsweep", "k": k, "tol": tol, "precision": "mixed", "runs": rows,
+        print(json.dumps({"mode": "nsweep", "k": k, "tol": tol, "precision": "mixed", "variant": args.variant,
+                          "runs": rows,
                           "fit_log10_t": {"A": A, "B": B}, "fit_log10_passes": {"A": Ap}}), flush=True)
         return
 
@@ -364,7 +372,10 @@ def main():
         multi = [("hi64", op, 4, 8)] if storage == "hilo" else []
         multi += [("fp64", op, 4, 16)]
         if ph:
+            # the fused full-H product: 2 vectors in FP64; 1..3 on hi (the block full-H iteration)
             multi += [("fp64", "H", 2, 16)]
+            if storage == "hilo":
+                multi += [("hi64", "H", nv, 8) for nv in (1, 2, 3)]
         for prec, mop, nv, e in multi:
             xm = torch.randn((nv, 2 * n if mop == "H" else n), dtype=torch.complex128, device="cuda")
             solver.apply(mop, xm, precision=prec)
@@ -464,8 +475,16 @@ def main():
     # measured HBM traffic of the same kernel (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated), as a rate
     # over the same launch duration; null unless this run's dominant kernel is the one counted
     traffic = tb = None
-    if ph and storage == "hilo" and precision == "mixed" and st["block"] <= 1 and ms_launch > 0 and n == 100000:
-        tb = counter_traffic("mv_stream_kernel<512, 3, 1>")
+    hblock = ph and args.variant == 3
+    if hblock:
+        kernel_label = f"mh_stream_kernel ({kernel_dtype}, {st['block']} full-H vectors)"
+        counted = f"mh_stream_kernel<512, 3, {st['block']}>"
+    elif st["block"] <= 1:
+        kernel_label, counted = f"mv_stream_kernel ({kernel_dtype})", "mv_stream_kernel<512, 3, 1>"
+    else:
+        kernel_label, counted = f"mk_block_kernel ({kernel_dtype}, {st['block']} vectors)", None
+    if ph and storage == "hilo" and precision == "mixed" and counted and ms_launch > 0 and n == 100000:
+        tb = counter_traffic(counted)
         traffic = tb / (ms_launch * 1e-3) / 1e9 if tb else None
     result = {
         "metric": METRIC,
@@ -488,12 +507,12 @@ def main():
                    "storage": storage, "precision": precision, "block_edge": None, "start_seed": args.start_seed,
                    "recipe": mat.recipe, "shift_eV": mat.shift, "lambda_min_raw_eV": mat.lambda_min_raw,
                    "lambda_min_A_eV": mat.lambda_min_a if ph else None, "b_norm2": mat.b_norm if ph else None,
-                   "variant": {0: "k1_metric_folded", 1: "lanczos_h_m_metric", 2: "k2_metric_folded"}[args.variant]
+                   "variant": {0: "k1_metric_folded", 1: "lanczos_h_m_metric", 2: "k2_metric_folded",
+                               3: "block_lanczos_h_m_metric"}[args.variant]
                    if ph else None},
         "roofline": {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": gbps / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": (f"mv_stream_kernel ({kernel_dtype})" if st["block"] <= 1 else
-                                f"mk_block_kernel ({kernel_dtype}, {st['block']} vectors)"),
+                     "kernel": kernel_label,
                      "bytes_per_launch": bytes_launch, "traffic_bytes_per_launch": tb,
                      "ms_per_launch": ms_launch},
         "solve": {k_: st[k_] for k_ in st if not k_.endswith("_") and not k_.startswith("ms_dense")},

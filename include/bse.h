@@ -83,37 +83,46 @@ typedef enum {
 
 /* Solver options; a NULL pointer or zero fields select the defaults. */
 typedef struct {
-  int32_t ncv;          /* basis size m (default: max(2k, k + 32) rounded up to 16, at most N) */
-  int32_t keep;         /* Ritz vectors kept at a restart (default: k + (m - k) / 2) */
+  int32_t ncv;          /* basis size m (default: max(2k, k + 32) rounded up to 16, at most N;
+                           PH variant 3: max(4k, 2k + 64) rounded up to 16, at least 2k + 16,
+                           at most 2N) */
+  int32_t keep;         /* Ritz vectors kept at a restart (default: k + (m - k) / 2; variant 3:
+                           k + 2 (m - k) / 3) */
   int32_t max_restarts; /* default 400 */
   int32_t precision;    /* bse_precision; MIXED needs BSE_STORE_HILO (default FP64) */
   double switch_tol;    /* MIXED: FP32-phase estimate that hands over to FP64 (default 1e-6) */
   uint64_t start_seed;  /* seed of the random start vector (default 1) */
   int32_t fp32_arith;   /* MIXED bulk passes over the complex64 triangles: 0 (default) FP64
                            products and sums; 1 complex FP32 products and in-block sums
-                           (FP64 across blocks).  Both read 8 bytes per entry. */
+                           (FP64 across blocks; not with PH variant 3, INVALID_ARG).  Both
+                           read 8 bytes per entry. */
   int32_t block;        /* TDA: block size b of the Lanczos iteration, 1..4 vectors per read of
                            the triangle (0: 2 for N >= 16384, else 1; reduced to 1 when the
                            basis would not leave room for b >= 2); ncv and keep are rounded
-                           up to multiples of b.  PH:
-                           ignored (b = 1: the folded iteration's basis is K1-orthogonal to its
-                           partner space only when grown from one vector). */
+                           up to multiples of b.  PH variants 0 - 2: ignored (b = 1: their
+                           bases are orthogonal to their partner spaces only when grown from
+                           one vector).  PH variant 3: 1..4 full-H vectors per read (0: 2). */
   int32_t refine_start; /* Ritz vectors of the iteration that start the FP64 refinement
                            (0: k after an FP64 iteration, min(keep, k + max(4, k/8)) after the
-                           bulk phase of MIXED; at most keep) */
+                           bulk phase of MIXED; at most keep -- variant 3: at most the number
+                           of positive Ritz values kept) */
   int32_t variant;      /* PH structure-preserving iteration: 0 (default) the K1-metric Lanczos
                            process on K2 K1, whose Ritz values are omega^2; 1 the Lanczos
                            process on H in the inner product of M, started from [u; conj(u)]
                            (zero-diagonal projected matrix, coupled K1- and K2-orthonormal
                            bases, Ritz values omega); 2 the dual folded process, Lanczos on
                            K1 K2 in the K2 inner product (a basis of the other half-vectors,
-                           p = K1 u; Ritz values omega^2).  All take two reads of the
-                           triangles per step.  TDA: ignored. */
+                           p = K1 u; Ritz values omega^2).  These take two reads of the
+                           triangles per step.  3: block Lanczos on H in the inner product of
+                           M over the complex space C^{2N} (complex Hermitian projected
+                           matrix, Ritz values +-omega, both signs kept at a restart), b
+                           full-H vectors per read of the triangles (`block`).  TDA: ignored. */
   int32_t warm_k;       /* warm start: number of previous eigenvectors in warm_x / warm_y (0: cold
                            start from the seeded random vector).  The start vector (column q of
                            the start block) is the sum of previous vectors q, q + b, ... -- PH:
                            x_c + conj(y_c), which is proportional to the folded vector of pair
-                           c -- plus the random vector at 1e-4 of its norm.  For a matrix close
+                           c; variant 3: [x_c; y_c] -- plus the random vector at 1e-4 of its
+                           norm.  For a matrix close
                            to the one they solve (finite differences, parameter scans). */
   int32_t reserved_;
   const void* warm_x;   /* device, N x warm_k complex128, column-major (bse_solve's x layout) */

@@ -44,7 +44,7 @@ class SolveOpts(ctypes.Structure):
                 ("reserved_", ctypes.c_int32), ("warm_x", ctypes.c_void_p), ("warm_y", ctypes.c_void_p)]
 
 
-VARIANT_FOLDED, VARIANT_COUPLED, VARIANT_DUAL = 0, 1, 2
+VARIANT_FOLDED, VARIANT_COUPLED, VARIANT_DUAL, VARIANT_H_BLOCK = 0, 1, 2, 3
 
 
 class Stats(ctypes.Structure):
@@ -269,7 +269,8 @@ class Solver:
         (default: FP64 arithmetic on the FP32-stored triangles).  block: vectors per read of the
         triangles in the Lanczos iteration (0: automatic).  variant (PH): 0 the K1-metric
         iteration on K2 K1, 1 the Lanczos process on H in the M inner product, 2 the dual
-        K2-metric iteration on K1 K2.  warm: (X, Y) of a
+        K2-metric iteration on K1 K2, 3 block Lanczos on H in the M inner product over C^2N
+        (`block` full-H vectors per read, default 2).  warm: (X, Y) of a
         previous solve of a nearby matrix (rows = pairs, Y None for TDA) to start from."""
         k = int(k)
         dev = self.device

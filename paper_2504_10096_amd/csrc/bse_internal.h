@@ -104,6 +104,14 @@ hipError_t cgemv_sub(const double2* V0, int n0, const double2* V1, int n1, const
                      const double2* P1, int64_t ld, const double2* h, int real_h, double2* w,
                      double2* z, int64_t n, hipStream_t s);
 
+// Several vectors against one basis V (ncol columns, leading dimension ld),
+// one read of V for all of them: cdotm h[q ncol + c] = sum_i conj(V[i, c])
+// w_q[i] for the nw (1..4) vectors w_q = W + q ldw (part: nchunks(n) * nw *
+// ncol double2); cgemvm_sub w_q -= V h_q with h_q = h + q ldh.
+hipError_t cdotm(const double2* V, int ncol, int64_t ld, const double2* W, int64_t ldw, int nw, int64_t n,
+                 double2* part, double2* h, hipStream_t s);
+hipError_t cgemvm_sub(const double2* V, int ncol, int64_t ld, const double2* h, int ldh, double2* W, int64_t ldw,
+                      int nw, int64_t n, hipStream_t s);
 // Lanczos normalization of step j: beta^2 = Re(w^H z) (z == w for TDA);
 // writes alpha[j] = Re(h1[jh] + h2[jh]), beta[j] = beta, sets flag (1: beta^2
 // <= 0, 2: non-finite) and scales w, z by 1/beta in place.  part: nchunks(n).

@@ -1582,6 +1582,114 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// Several vectors against one basis, one read of the basis for all of them
+// (the block steps of the full-H iteration).  part[chunk * NW ncol + q ncol +
+// c] = sum over the chunk of conj(V[i, c]) w_q[i], w_q = W + q ldw; the same
+// layout of waves, columns and loads as cdot_part_kernel, with the NW
+// vectors' rows held in registers.
+template <int NW>
+__global__ void __launch_bounds__(kThreads)
+    cdotm_part_kernel(const double2* __restrict__ V, int ncol, int64_t ld, const double2* __restrict__ W,
+                      int64_t ldw, int64_t n, double2* __restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * kChunk;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double wr[NW][4], wi[NW][4];
+  bool rin[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) rin[s] = r0 + lane + 64 * s < n;
+#pragma unroll
+  for (int q = 0; q < NW; ++q)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const double2 v = rin[s] ? W[(size_t)q * ldw + r0 + lane + 64 * s] : make_double2(0.0, 0.0);
+      wr[q][s] = v.x;
+      wi[q][s] = v.y;
+    }
+  const int cbeg = blockIdx.y * 64 + wave * 16;
+  const int cend = min(cbeg + 16, ncol);
+  for (int t0 = cbeg; t0 < cend; t0 += 4) {
+    double2 v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = t0 + u < cend ? t0 + u : t0;  // past the end: a valid column, result unused
+      const double2* col = V + (size_t)c * ld;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[u][s] = rin[s] ? col[r0 + lane + 64 * s] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      double sr[4], si[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sr[u] = 0.0;
+        si[u] = 0.0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          sr[u] += v[u][s].x * wr[q][s] + v[u][s].y * wi[q][s];
+          si[u] += v[u][s].x * wi[q][s] - v[u][s].y * wr[q][s];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        sr[u] = wave_sum(sr[u]);
+        si[u] = wave_sum(si[u]);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (t0 + u < cend)
+            part[(size_t)blockIdx.x * NW * ncol + (size_t)q * ncol + t0 + u] = make_double2(sr[u], si[u]);
+      }
+    }
+  }
+}
+
+// w_q[i] -= sum_c V[i, c] h[q ldh + c] for q < NW: one row per thread, each
+// basis entry loaded once for all NW vectors.
+template <int NW>
+__global__ void __launch_bounds__(kThreads)
+    cgemvm_sub_kernel(const double2* __restrict__ V, int ncol, int64_t ld, const double2* __restrict__ h,
+                      int ldh, double2* __restrict__ W, int64_t ldw, int64_t n) {
+  extern __shared__ double2 hs[];  // NW * ncol coefficients
+  for (int t = threadIdx.x; t < NW * ncol; t += kThreads) hs[t] = h[(size_t)(t / ncol) * ldh + t % ncol];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  double ar[NW], ai[NW];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) ar[q] = ai[q] = 0.0;
+  int c = 0;
+  for (; c + 8 <= ncol; c += 8) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = V[(size_t)(c + u) * ld + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        const double2 hc = hs[q * ncol + c + u];
+        ar[q] += v[u].x * hc.x - v[u].y * hc.y;
+        ai[q] += v[u].x * hc.y + v[u].y * hc.x;
+      }
+  }
+  for (; c < ncol; ++c) {
+    const double2 v = V[(size_t)c * ld + i];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      const double2 hc = hs[q * ncol + c];
+      ar[q] += v.x * hc.x - v.y * hc.y;
+      ai[q] += v.x * hc.y + v.y * hc.x;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NW; ++q) {
+    double2 wv = W[(size_t)q * ldw + i];
+    wv.x -= ar[q];
+    wv.y -= ai[q];
+    W[(size_t)q * ldw + i] = wv;
+  }
+}
+
 // part[chunk] = Re sum conj(w_i) z_i over the chunk.
 __global__ void __launch_bounds__(kThreads)
     rdot_part_kernel(const double2* __restrict__ w, const double2* __restrict__ z, int64_t n,
@@ -2389,6 +2497,63 @@ hipError_t cdot(const double2* V0, int n0, const double2* V1, int n1, int64_t ld
   hipLaunchKernelGGL(cdot_part_kernel, dim3((unsigned)nch, (unsigned)((ncol + 63) / 64)),
                      dim3(kThreads), 0, s, V0, n0, V1, n1, ld, w, n, part);
   hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((ncol + 3) / 4)), dim3(kThreads), 0, s, part, nch, ncol, h);
+  return hipGetLastError();
+}
+
+hipError_t cdotm(const double2* V, int ncol, int64_t ld, const double2* W, int64_t ldw, int nw, int64_t n,
+                 double2* part, double2* h, hipStream_t s) {
+  if (ncol == 0) return hipSuccess;
+  const int64_t nch = nchunks(n);
+  const dim3 grid((unsigned)nch, (unsigned)((ncol + 63) / 64));
+  switch (nw) {
+    case 1:
+      hipLaunchKernelGGL(cdotm_part_kernel<1>, grid, dim3(kThreads), 0, s, V, ncol, ld, W, ldw, n, part);
+      break;
+    case 2:
+      hipLaunchKernelGGL(cdotm_part_kernel<2>, grid, dim3(kThreads), 0, s, V, ncol, ld, W, ldw, n, part);
+      break;
+    case 3:
+      hipLaunchKernelGGL(cdotm_part_kernel<3>, grid, dim3(kThreads), 0, s, V, ncol, ld, W, ldw, n, part);
+      break;
+    case 4:
+      hipLaunchKernelGGL(cdotm_part_kernel<4>, grid, dim3(kThreads), 0, s, V, ncol, ld, W, ldw, n, part);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((nw * ncol + 3) / 4)), dim3(kThreads), 0, s, part, nch,
+                     nw * ncol, h);
+  return hipGetLastError();
+}
+
+hipError_t cgemvm_sub(const double2* V, int ncol, int64_t ld, const double2* h, int ldh, double2* W, int64_t ldw,
+                      int nw, int64_t n, hipStream_t s) {
+  if (ncol == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
+  const size_t lds = (size_t)nw * ncol * sizeof(double2);
+  if (lds > 65536) {  // coefficients beyond the LDS of one group: one vector at a time
+    for (int q = 0; q < nw; ++q) {
+      hipLaunchKernelGGL(cgemvm_sub_kernel<1>, grid, dim3(kThreads), (size_t)ncol * sizeof(double2), s, V, ncol,
+                         ld, h + (size_t)q * ldh, ldh, W + (size_t)q * ldw, ldw, n);
+    }
+    return hipGetLastError();
+  }
+  switch (nw) {
+    case 1:
+      hipLaunchKernelGGL(cgemvm_sub_kernel<1>, grid, dim3(kThreads), lds, s, V, ncol, ld, h, ldh, W, ldw, n);
+      break;
+    case 2:
+      hipLaunchKernelGGL(cgemvm_sub_kernel<2>, grid, dim3(kThreads), lds, s, V, ncol, ld, h, ldh, W, ldw, n);
+      break;
+    case 3:
+      hipLaunchKernelGGL(cgemvm_sub_kernel<3>, grid, dim3(kThreads), lds, s, V, ncol, ld, h, ldh, W, ldw, n);
+      break;
+    case 4:
+      hipLaunchKernelGGL(cgemvm_sub_kernel<4>, grid, dim3(kThreads), lds, s, V, ncol, ld, h, ldh, W, ldw, n);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -226,6 +226,12 @@ struct Solver {
   // run as variant 0 with the two operators exchanged (K1 <-> K2 is B -> -B);
   // its pairs are those of H' = diag(I, -I) H diag(I, -I), and v = diag(I, -I) v'.
   bool dual = false;
+  // variant 3: block Lanczos on the full H (complex-linear) in the M inner
+  // product.  U holds the basis V and P its image M V, both in full-H columns
+  // [top (ld); bottom (ld)] of stride 2 ld; npos: positive Ritz vectors at
+  // the front of the kept set (ascending), the wanted ones first.
+  bool hb = false;
+  int npos = 0;
   DevBuf bufTc2;
   double2* Tc2 = nullptr;
   int ncolmax = 0;  // columns of one coefficient vector in H1 / H3
@@ -337,7 +343,10 @@ std::pair<hipEvent_t, hipEvent_t> gemm_events(Solver& S) {
 
 bse_status alloc_solver(Solver& S) {
   bse_handle h = S.h;
-  const size_t col = (size_t)S.ld * sizeof(double2);
+  // variant 3 keeps full-H columns (2 ld) in U, U2 (basis) and P, P2 (M times it)
+  const size_t col = (size_t)(S.hb ? 2 * S.ld : S.ld) * sizeof(double2);
+  const bool kp = S.ph && !S.hb;  // the half-vector bases of variants 0 - 2
+  const int64_t nred = S.hb ? 2 * S.ld : S.n;  // longest vector of a reduction
   const int nc = S.m + S.b;  // basis columns: m plus the next block
   S.ncolmax = 2 * nc + 4;
   S.ldT = nc;
@@ -349,17 +358,17 @@ bse_status alloc_solver(Solver& S) {
       {&S.bufU2, col * nc},
       {&S.bufP, S.ph ? col * nc : 0},
       {&S.bufP2, S.ph ? col * nc : 0},
-      {&S.bufKP, S.ph ? col * nc : 0},
-      {&S.bufKP2, S.ph ? col * nc : 0},
-      {&S.bufY, S.ph ? col * nc : 0},
-      {&S.bufZ, S.ph ? col * nc : 0},
+      {&S.bufKP, kp ? col * nc : 0},
+      {&S.bufKP2, kp ? col * nc : 0},
+      {&S.bufY, kp ? col * nc : 0},
+      {&S.bufZ, kp ? col * nc : 0},
       {&S.bufH1, sizeof(double2) * (size_t)S.ncolmax * S.b},
       {&S.bufH3, sizeof(double2) * (size_t)S.ncolmax},
       {&S.bufTh, sizeof(double) * (nc + 2)},
       {&S.bufTc, sizeof(double2) * (size_t)nc * nc},
       {&S.bufTc2, S.variant == 1 ? sizeof(double2) * (size_t)nc * nc : 0},
-      {&S.bufPart, sizeof(double2) * (size_t)bse::nchunks(S.n) * S.ncolmax},
-      {&S.bufRed, sizeof(double) * 2 * ((size_t)bse::nchunks(S.n) + 8)},
+      {&S.bufPart, sizeof(double2) * (size_t)bse::nchunks(nred) * std::max(S.ncolmax, S.b * nc)},
+      {&S.bufRed, sizeof(double) * 2 * ((size_t)bse::nchunks(nred) + 8)},
       {&S.bufFlag, sizeof(int) * 4},
       {&S.bufS, sizeof(double2) * (size_t)(nc + 2) * (nc + 2)},
       {&S.bufNrm, sizeof(double) * (2 * (size_t)nc + 8)},
@@ -971,15 +980,317 @@ bse_status restart_g(Solver& S, RitzInfo& R) {
   return BSE_OK;
 }
 
+// ---------------------------------------------------------------------
+// Variant 3: block Lanczos on the full H in the M inner product.  H is
+// self-adjoint in <x, y>_M = x^H M y (Omega H = M), and on the complex space
+// C^{2N} its eigenvalues +-omega are simple, so a block of b start vectors
+// grows a block Krylov space with no duplicate copies to suppress (the
+// doubling that keeps variants 0 - 2 single-vector lives on the real form of
+// the half-vector operators).  One read of the stored A and B applies M to
+// the b vectors of a block (the fused full-H kernel), so the iteration reads
+// the triangles once per block step.  The spectrum is symmetric, so the
+// wanted +omega and their mirror images -omega converge together; the thick
+// restart keeps the `keep` Ritz vectors of smallest |theta| of both signs.
+//
+// Basis V (M-orthonormal) in U and M V in P, full-H columns of stride 2 ld.
+// A step takes block J: H V_J = Omega (M V_J) needs no pass; it is
+// M-orthogonalized against V by CGS2 with the stored M V, one pass gives
+// M R of the remainder R, and R is M-orthonormalized in itself by
+// Gram-Schmidt on (R, M R), which updates both.  The coefficients of the CGS
+// rounds (V^H M H V_J) and the triangular factor of R go to the columns of
+// block J in Tc: T = V^H M H V is complex Hermitian.
+
+// M out for nv (1..4) full-H columns of v, one read of the stored triangles.
+bse_status mpass(Solver& S, Arith ar, int nv, const double2* v, double2* out) {
+  bse_handle h = S.h;
+  if (bse_status e = ensure_mhpart(h)) return e;
+  bse::MatPtrs mm = mat_ptrs(h);
+  if (ar == bse::AR_HI64) HIP_TRY(h, hi_ptrs(h, &mm));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (S.passes % 8 == 0 && S.ev_free.size() >= 2) {
+    e1 = S.ev_free.back();
+    S.ev_free.pop_back();
+    e0 = S.ev_free.back();
+    S.ev_free.pop_back();
+    S.ev_pending.push_back({{e0, e1}, ar == bse::AR_HI64});
+  }
+  HIP_TRY(h, bse::mh_apply(h->L, ar, mm, nv, v, 2 * S.ld, S.ld, h->mhpart, out, 1.0, S.s, e0, e1));
+  ++S.passes;
+  if (ar == bse::AR_HI64) ++S.passes32;
+  return BSE_OK;
+}
+
+// M-orthonormalize columns [c, c + nb) of V among themselves (Gram-Schmidt
+// twice per column on V and M V together); with rec >= 0 the coefficients
+// and norms are the factor of block rec's product (column rec + q of Tc,
+// rows c .. c + q).
+bse_status orth_block_m(Solver& S, int c, int nb, int rec) {
+  bse_handle h = S.h;
+  const int64_t ld2 = 2 * S.ld, n2 = S.ld + S.n;
+  double2* Vc = S.U + (size_t)c * ld2;
+  double2* Mc = S.P + (size_t)c * ld2;
+  for (int q = 0; q < nb; ++q) {
+    double2* w = Vc + (size_t)q * ld2;
+    double2* z = Mc + (size_t)q * ld2;
+    for (int it = 0; it < 2 && q > 0; ++it) {
+      HIP_TRY(h, bse::cdot(Mc, q, nullptr, 0, ld2, w, n2, S.cpart, S.H3, S.s));
+      HIP_TRY(h, bse::cgemv_sub(Vc, q, nullptr, 0, Mc, nullptr, ld2, S.H3, 0, w, z, n2, S.s));
+      if (rec >= 0)
+        HIP_TRY(h, bse::acc_cols(S.Tc + (size_t)(rec + q) * S.ldT + c, S.ldT, S.H3, S.ncolmax, q, 1, 0, S.s));
+    }
+    double* bt = rec >= 0 ? (double*)(S.Tc + (size_t)(rec + q) * S.ldT + c + q) : nullptr;
+    HIP_TRY(h, bse::normalize(w, z, n2, nullptr, nullptr, 0, nullptr, bt, 0, S.flag, S.red, S.s));
+  }
+  return BSE_OK;
+}
+
+// Start block: seeded random top and bottom halves (warm start: plus the
+// previous eigenvectors [x; y], summed as in init_basis), M applied in one
+// pass, M-orthonormalized.
+bse_status init_basis_hb(Solver& S, Arith ar, uint64_t seed, int wk, const double2* wx, const double2* wy) {
+  bse_handle h = S.h;
+  const int64_t ld2 = 2 * S.ld;
+  for (int q = 0; q < S.b; ++q) {
+    double2* v = S.U + (size_t)q * ld2;
+    HIP_TRY(h, bse::start_vector(v, S.n, seed + q, S.s));
+    HIP_TRY(h, bse::start_vector(v + S.ld, S.n, seed + q + 0x5bd1e995ULL, S.s));
+    const int cols = wk > q ? (wk - q + S.b - 1) / S.b : 0;
+    if (cols > 0) {
+      const double sv = 1e-4 * sqrt((double)cols / (2.0 * S.n / 6.0));
+      HIP_TRY(h, bse::warm_sum(wx, nullptr, 1.0, S.n, S.n, wk, S.b, q, sv, v, S.s));
+      HIP_TRY(h, bse::warm_sum(wy, nullptr, 1.0, S.n, S.n, wk, S.b, q, sv, v + S.ld, S.s));
+    }
+  }
+  if (bse_status st = mpass(S, ar, S.b, S.U, S.P)) return st;
+  if (bse_status st = orth_block_m(S, 0, S.b, -1)) return st;
+  S.nka = 0;
+  S.npos = 0;
+  S.theta_keep.clear();
+  return BSE_OK;
+}
+
+// Block step: [c0, c0 + b) -> [c0 + b, c0 + 2b).
+bse_status step_hb(Solver& S, Arith ar, int c0) {
+  bse_handle h = S.h;
+  const int b = S.b, cn = c0 + b;
+  const int64_t ld2 = 2 * S.ld, n2 = S.ld + S.n;
+  double2* R = S.U + (size_t)cn * ld2;
+  OrthTimer ot(S);
+  HIP_TRY(h, ot.begin());
+  // H v = Omega (M v): no pass
+  HIP_TRY(h, bse::copy_cols(S.P + (size_t)c0 * ld2, ld2, R, ld2, n2, b, S.s));
+  HIP_TRY(h, bse::neg_cols(R + S.ld, ld2, S.n, b, S.s));
+  // CGS2 of the whole block: one read of M V and one of V per round
+  for (int it = 0; it < 2; ++it) {
+    HIP_TRY(h, bse::cdotm(S.P, cn, ld2, R, ld2, b, n2, S.cpart, S.H1, S.s));
+    HIP_TRY(h, bse::cgemvm_sub(S.U, cn, ld2, S.H1, cn, R, ld2, b, n2, S.s));
+    HIP_TRY(h, bse::acc_cols(S.Tc + (size_t)c0 * S.ldT, S.ldT, S.H1, cn, cn, b, 0, S.s));
+  }
+  HIP_TRY(h, ot.end());
+  bse_status st = mpass(S, ar, b, R, S.P + (size_t)cn * ld2);
+  if (st) return st;
+  HIP_TRY(h, ot.begin());
+  if ((st = orth_block_m(S, cn, b, c0))) return st;
+  HIP_TRY(h, ot.end());
+  if (ar == bse::AR_HI64)
+    S.steps32 += b;
+  else
+    S.steps64 += b;
+  return BSE_OK;
+}
+
+// Thick restart: T from the recorded coefficients (as for the TDA block
+// iteration), its eigenpairs on the host, the kept set = the k wanted
+// (positive, see rho below) and then the smallest |theta| of both signs up
+// to `keep`; the wanted lead in ascending order.  V and M V are rotated on
+// MFMA, the next block moves behind them, and the residual of wanted pair i,
+// || R F z_i(last block) ||_2 / (theta_i ||V z_i||_2), comes from the
+// Euclidean Gram of the next block.  R.theta: the Ritz values of the kept
+// columns in their order.
+bse_status restart_hb(Solver& S, RitzInfo& R) {
+  bse_handle h = S.h;
+  const int m = S.m, b = S.b, ldT = S.ldT, nka = S.nka, k = S.k;
+  const int64_t ld2 = 2 * S.ld, n2 = S.ld + S.n;
+  if (nka >= m) return fail(h, BSE_ERR_BAD_STATE, "thick restart needs ncv > keep");
+  std::vector<double2> tc((size_t)ldT * ldT);
+  HIP_TRY(h, hipMemcpyAsync(tc.data(), S.Tc, sizeof(double2) * tc.size(), hipMemcpyDeviceToHost, S.s));
+  bse_status st = check_flag(S);
+  if (st) return st;
+  const double t_rs = now_ms();
+  auto c0_of = [&](int c) { return nka + ((c - nka) / b) * b; };
+  auto filled = [&](int i, int c) {
+    if (c < nka) return i < nka;
+    const int c0 = c0_of(c), cn = c0 + b;
+    return i < cn || (i < cn + b && i - cn <= c - c0);
+  };
+  auto val = [&](int i, int c) -> cplx {
+    if (c < nka) return i == c ? cplx(S.theta_keep[i], 0.0) : cplx(0.0);
+    const double2 v = tc[(size_t)c * ldT + i];
+    return cplx(v.x, v.y);
+  };
+  std::vector<cplx> T((size_t)m * m);
+  for (int c = 0; c < m; ++c)
+    for (int i = 0; i < m; ++i) {
+      const bool f1 = filled(i, c), f2 = filled(c, i);
+      cplx v = 0.0;
+      if (f1 && f2)
+        v = 0.5 * (val(i, c) + std::conj(val(c, i)));
+      else if (f1)
+        v = val(i, c);
+      else if (f2)
+        v = std::conj(val(c, i));
+      if (i == c) v = v.real();
+      T[(size_t)c * m + i] = v;
+    }
+  for (cplx v : T)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
+      return fail(h, BSE_ERR_NONFINITE, "non-finite projected matrix");
+  std::vector<double> th(m);
+  std::vector<cplx> Zc((size_t)m * m);
+  const double t_eig = now_ms();
+  if (!bse::herm_eig(m, reinterpret_cast<double2*>(T.data()), th.data(), reinterpret_cast<double2*>(Zc.data())))
+    return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
+  const double ms_eig = now_ms() - t_eig;
+  S.ms_small += ms_eig;
+  // F[p][q]: coefficient of next-block column p in the product of column m - b + q
+  std::vector<cplx> F((size_t)b * b, 0.0);
+  for (int q = 0; q < b; ++q)
+    for (int p = 0; p <= q; ++p) {
+      const double2 v = tc[(size_t)(m - b + q) * ldT + m + p];
+      F[(size_t)q * b + p] = cplx(v.x, v.y);
+    }
+  // c_i = F z_i(last block): the residual H y_i - theta_i y_i is R c_i with R
+  // the M-orthonormal next block, so ||c_i|| is its M-norm (y_i M-normalized)
+  auto coupling = [&](int i, std::vector<cplx>& ci) {
+    const cplx* z = Zc.data() + (size_t)i * m;
+    ci.assign(b, 0.0);
+    for (int p = 0; p < b; ++p)
+      for (int q = p; q < b; ++q) ci[p] += F[(size_t)q * b + p] * z[m - b + q];
+  };
+  // Wanted: the k positive Ritz values with the smallest rho_i = sqrt(theta_i^2
+  // + ||c_i||^2) = ||H y_i||_M, the Rayleigh quotient of H^2, which is never
+  // below the smallest omega^2 (Courant-Fischer).  The wanted omega are
+  // interior to the spectrum of H, and Rayleigh-Ritz can place a spurious
+  // value in the gap between -omega_0 and omega_0 or among the wanted ones;
+  // its residual is large, so rho moves it out of the wanted set, where
+  // ordering by theta would keep it there until it dissolves.
+  std::vector<double> rho(m);
+  {
+    std::vector<cplx> ci;
+    for (int i = 0; i < m; ++i) {
+      coupling(i, ci);
+      double r2 = 0.0;
+      for (const cplx& v : ci) r2 += std::norm(v);
+      rho[i] = sqrt(th[i] * th[i] + r2);
+    }
+  }
+  std::vector<int> pos, order(m);
+  for (int i = 0; i < m; ++i)
+    if (th[i] > 0.0) pos.push_back(i);
+  std::stable_sort(pos.begin(), pos.end(), [&](int a, int c) { return rho[a] < rho[c]; });
+  // (fewer than k positive Ritz values: the missing pairs count as unconverged)
+  const int kp = std::min<int>(k, (int)pos.size());
+  std::sort(pos.begin(), pos.begin() + kp, [&](int a, int c) { return th[a] < th[c]; });
+  for (int i = 0; i < m; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return fabs(th[a]) < fabs(th[c]); });
+  const int keep = S.keep;
+  std::vector<char> in(m, 0);
+  std::vector<int> sel;
+  for (int i = 0; i < kp; ++i) {
+    sel.push_back(pos[i]);
+    in[pos[i]] = 1;
+  }
+  for (int i = 0; i < m && (int)sel.size() < keep; ++i)
+    if (!in[order[i]]) {
+      sel.push_back(order[i]);
+      in[order[i]] = 1;
+    }
+  // order: the wanted (ascending theta), then the other kept positives, then the negatives,
+  // each by rho (the positives right behind the wanted start the refinement)
+  std::stable_sort(sel.begin() + kp, sel.end(), [&](int a, int c) {
+    const bool pa = th[a] > 0.0, pc = th[c] > 0.0;
+    if (pa != pc) return pa;
+    return rho[a] < rho[c];
+  });
+  int npos = 0;
+  for (int i : sel) npos += th[i] > 0.0;
+  std::vector<cplx> Zs((size_t)m * keep);
+  for (int c = 0; c < keep; ++c)
+    for (int i = 0; i < m; ++i) Zs[(size_t)c * m + i] = Zc[(size_t)sel[c] * m + i];
+  HIP_TRY(h, hipMemcpyAsync(S.S, Zs.data(), sizeof(double2) * (size_t)m * keep, hipMemcpyHostToDevice, S.s));
+  const auto ge = gemm_events(S);
+  if (ge.first) HIP_TRY(h, hipEventRecord(ge.first, S.s));
+  HIP_TRY(h, bse::zgemm_mfma(n2, keep, m, S.U, ld2, (const double2*)S.S, m, S.U2, ld2, S.s));
+  HIP_TRY(h, bse::zgemm_mfma(n2, keep, m, S.P, ld2, (const double2*)S.S, m, S.P2, ld2, S.s));
+  if (ge.first) {
+    HIP_TRY(h, hipEventRecord(ge.second, S.s));
+    S.ev_gemm.push_back({ge, 2.0 * 8.0 * (double)n2 * keep * m});
+  }
+  HIP_TRY(h, bse::copy_cols(S.U + (size_t)m * ld2, ld2, S.U2 + (size_t)keep * ld2, ld2, n2, b, S.s));
+  HIP_TRY(h, bse::copy_cols(S.P + (size_t)m * ld2, ld2, S.P2 + (size_t)keep * ld2, ld2, n2, b, S.s));
+  std::swap(S.U, S.U2);
+  std::swap(S.P, S.P2);
+  std::vector<double2> gn((size_t)b * b);
+  for (int q = 0; q < b; ++q)
+    HIP_TRY(h, bse::cdot(S.U + (size_t)keep * ld2, b, nullptr, 0, ld2, S.U + (size_t)(keep + q) * ld2, n2,
+                         S.cpart, S.H1 + (size_t)q * b, S.s));
+  HIP_TRY(h, hipMemcpyAsync(gn.data(), S.H1, sizeof(double2) * b * b, hipMemcpyDeviceToHost, S.s));
+  std::vector<double> nv(k);
+  double* cp = (double*)S.cpart;
+  HIP_TRY(h, bse::colnorms(S.U, k, ld2, n2, cp, S.nrm, S.s));
+  HIP_TRY(h, hipMemcpyAsync(nv.data(), S.nrm, sizeof(double) * k, hipMemcpyDeviceToHost, S.s));
+  HIP_TRY(h, hipMemsetAsync(S.Tc, 0, sizeof(double2) * (size_t)ldT * ldT, S.s));
+  HIP_TRY(h, hipStreamSynchronize(S.s));
+  R.theta.resize(keep);
+  for (int c = 0; c < keep; ++c) R.theta[c] = th[sel[c]];
+  R.est.assign(k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    if (i >= kp) {
+      R.est[i] = INFINITY;
+      continue;
+    }
+    std::vector<cplx> ci;
+    coupling(sel[i], ci);
+    cplx r2 = 0.0;
+    for (int p = 0; p < b; ++p)
+      for (int q = 0; q < b; ++q) r2 += std::conj(ci[p]) * cplx(gn[(size_t)q * b + p].x, gn[(size_t)q * b + p].y) * ci[q];
+    const double den = fabs(th[sel[i]]) * sqrt(std::max(nv[i], 1e-300));
+    R.est[i] = sqrt(std::max(r2.real(), 0.0)) / std::max(den, 1e-300);
+  }
+  S.nka = keep;
+  S.npos = npos;
+  S.theta_keep.resize(keep);
+  for (int c = 0; c < keep; ++c) S.theta_keep[c] = th[sel[c]];
+  ++S.restarts;
+  S.ms_restart += now_ms() - t_rs - ms_eig;
+  return BSE_OK;
+}
+
 // Eigenvalues and vectors of the k wanted pairs from the current basis
 // (columns 0..k-1 after a restart) and their FP64 residuals.
 bse_status finalize(Solver& S, const RitzInfo& R, double* omega, double2* X, double2* Y,
                     std::vector<double>& rel) {
   bse_handle h = S.h;
   std::vector<double> om(S.k);
-  for (int i = 0; i < S.k; ++i) om[i] = S.ph ? sqrt(std::max(R.theta[i], 0.0)) : R.theta[i];
+  for (int i = 0; i < S.k; ++i) om[i] = S.ph && !S.hb ? sqrt(std::max(R.theta[i], 0.0)) : R.theta[i];
   HIP_TRY(h, hipMemcpyAsync(omega, om.data(), sizeof(double) * S.k, hipMemcpyHostToDevice, S.s));
-  if (S.ph) {
+  if (S.hb) {
+    // the positive Ritz vectors lead the kept set, M-normalized: sqrt(omega)
+    // [top; bottom] has X^H X - Y^H Y = 1 at convergence; made exact here
+    HIP_TRY(h, bse::h_out(S.U, omega, S.ld, S.n, S.k, X, Y, S.s));
+    std::vector<double> nx(2 * S.k);
+    double* cp = (double*)S.cpart;
+    HIP_TRY(h, bse::colnorms(X, S.k, S.n, S.n, cp, S.nrm, S.s));
+    HIP_TRY(h, bse::colnorms(Y, S.k, S.n, S.n, cp, S.nrm + S.k, S.s));
+    HIP_TRY(h, hipMemcpyAsync(nx.data(), S.nrm, sizeof(double) * 2 * S.k, hipMemcpyDeviceToHost, S.s));
+    HIP_TRY(h, hipStreamSynchronize(S.s));
+    for (int c = 0; c < S.k; ++c) {
+      const double d = nx[c] - nx[S.k + c];
+      nx[c] = d > 0.0 ? 1.0 / sqrt(d) : 1.0;
+    }
+    HIP_TRY(h, hipMemcpyAsync(S.nrm, nx.data(), sizeof(double) * S.k, hipMemcpyHostToDevice, S.s));
+    HIP_TRY(h, bse::scale_cols(X, Y, S.n, S.n, S.k, S.nrm, S.s));
+  } else if (S.ph) {
     HIP_TRY(h, bse::ph_vectors(S.U, S.P, S.ld, omega, S.k, S.n, X, Y, S.n, S.s));
     if (S.dual) HIP_TRY(h, bse::neg_cols(Y, S.n, S.n, S.k, S.s));
   } else {
@@ -1160,7 +1471,10 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   const bool coupled = ph && S.variant == 1;
   const double2* Pv = coupled ? S.KP : S.P;   // p of v
   const double2* KPv = coupled ? S.Y : S.KP;  // images for M v: K1 u in S.P, and K2 p
-  if (ph) {
+  if (S.hb) {
+    // variant 3: the positive Ritz vectors of the full-H basis, as they are
+    HIP_TRY(h, bse::copy_cols(S.U, ld2, V, ld2, n2, s0, S.s));
+  } else if (ph) {
     std::vector<double> om0(s0);
     for (int c = 0; c < s0; ++c) om0[c] = coupled ? 1.0 : sqrt(std::max(theta0[c], 1e-300));
     HIP_TRY(h, hipMemcpyAsync(Om, om0.data(), sizeof(double) * s0, hipMemcpyHostToDevice, S.s));
@@ -1185,7 +1499,16 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
   // when the iteration ran on the FP64 operator, and completed by one read of
   // the lo triangles (M = M_hi + M_lo) after FP64 arithmetic on hi.  After
   // complex FP32 arithmetic, or for TDA, by FP64 passes.
-  if (ph && bulk_ar != bse::AR_HI) {
+  if (S.hb) {
+    // M V from the iteration's own products: exact after FP64 passes; after
+    // FP64 arithmetic on hi, completed by one read of the lo triangles
+    if (bulk_ar == bse::AR_HI64) {
+      if ((st = mapply(0, s0, bse::AR_HI64, lo_only))) return st;
+      HIP_TRY(h, bse::acc_cols(MV, ld2, S.P, ld2, (int)n2, s0, 0, S.s));
+    } else {
+      HIP_TRY(h, bse::copy_cols(S.P, ld2, MV, ld2, n2, s0, S.s));
+    }
+  } else if (ph && bulk_ar != bse::AR_HI) {
     if (bulk_ar == bse::AR_HI64) {
       if ((st = mapply(0, s0, bse::AR_HI64, lo_only))) return st;
     }
@@ -1574,11 +1897,18 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
     return fail(h, BSE_ERR_INVALID_ARG, "mixed precision needs HILO storage");
   const int64_t n = h->n;
   if (o.block < 0 || o.block > 4) return fail(h, BSE_ERR_INVALID_ARG, "block must be in [0, 4]");
-  if (o.variant < 0 || o.variant > 2) return fail(h, BSE_ERR_INVALID_ARG, "variant must be 0, 1 or 2");
+  if (o.variant < 0 || o.variant > 3) return fail(h, BSE_ERR_INVALID_ARG, "variant must be 0, 1, 2 or 3");
+  const bool hb = ph && o.variant == 3;
+  if (hb && mixed && o.fp32_arith)
+    return fail(h, BSE_ERR_INVALID_ARG, "variant 3 has no complex FP32 arithmetic (fp32_arith must be 0)");
   if (o.warm_k < 0 || o.warm_k > n || (o.warm_k > 0 && (!o.warm_x || (ph && !o.warm_y))))
     return fail(h, BSE_ERR_INVALID_ARG, "warm start needs warm_k in [0, N] and its vectors");
-  int m = o.ncv > 0 ? o.ncv : (int)round_up(std::max(2 * k, k + 32), 16);
-  m = (int)std::min<int64_t>(m, n);
+  // variant 3 works in C^{2N} and keeps both signs of omega: a basis about
+  // twice as large, in a space twice as large
+  const int64_t dim = hb ? 2 * n : n;
+  int m = o.ncv > 0 ? o.ncv : (int)round_up(hb ? std::max(4 * k, 2 * k + 64) : std::max(2 * k, k + 32), 16);
+  if (hb) m = std::max(m, 2 * k + 16);  // room for k positive Ritz values and their mirror images
+  m = (int)std::min<int64_t>(m, dim);
   if (m < k) return fail(h, BSE_ERR_INVALID_ARG, "ncv must be at least k");
   // block size (TDA): several vectors per read of the triangle; the basis
   // and the kept set are whole blocks.  Automatic: b = 2 from N = 16384 on,
@@ -1587,10 +1917,12 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   // orthogonalization dominate and the block's extra products do not pay.
   // The pseudo-Hermitian iteration keeps b = 1: its basis is K1-orthogonal to
   // its own partner space only when it grows from a single vector.
-  int b = ph ? 1 : (o.block > 0 ? o.block : (n >= 16384 ? 2 : 1));
-  if (b > 1 && ((int)round_up(m, b) < k + b || (int64_t)round_up(m, b) + b > n / 2)) b = 1;
+  // Variant 3 grows from a block (default b = 2, one fused full-H read of
+  // the triangles per block step).
+  int b = hb ? (o.block > 0 ? o.block : 2) : ph ? 1 : (o.block > 0 ? o.block : (n >= 16384 ? 2 : 1));
+  if (b > 1 && ((int)round_up(m, b) < k + b || (int64_t)round_up(m, b) + b > dim / 2)) b = 1;
   m = (int)round_up(m, b);
-  int keep = o.keep > 0 ? o.keep : k + (m - k) / 2;
+  int keep = o.keep > 0 ? o.keep : hb ? k + (m - k) * 2 / 3 : k + (m - k) / 2;
   keep = (int)round_up(std::max(keep, k), b);
   if (keep >= m) keep = (m > k) ? m - b : m;
   const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 400;
@@ -1609,6 +1941,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   S.b = b;
   S.variant = ph && o.variant != 2 ? o.variant : 0;
   S.dual = ph && o.variant == 2;
+  S.hb = hb;
   S.tol = tol;
   S.s = h->stream;
   if (const char* tr = getenv("BSE_TRACE")) S.trace = tr[0] == '1';
@@ -1619,7 +1952,8 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   Arith ar = mixed ? bulk : fp64_arith(h);
   double tol_int = mixed ? std::max(switch_tol, tol) : tol;
   double t_phase = now_ms(), ms32 = 0.0, ms64 = 0.0;
-  st = init_basis(S, ar, seed, o.warm_k, (const double2*)o.warm_x, (const double2*)o.warm_y);
+  st = hb ? init_basis_hb(S, ar, seed, o.warm_k, (const double2*)o.warm_x, (const double2*)o.warm_y)
+          : init_basis(S, ar, seed, o.warm_k, (const double2*)o.warm_x, (const double2*)o.warm_y);
   if (st) return st;
   int jstart = 0;
   RitzInfo R;
@@ -1630,10 +1964,10 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   double ms_final = 0.0;
   for (int cyc = 0; cyc < max_restarts; ++cyc) {
     for (int c0 = jstart; c0 < m; c0 += b) {
-      st = S.variant == 1 ? step_g(S, ar, c0) : step(S, ar, c0);
+      st = hb ? step_hb(S, ar, c0) : S.variant == 1 ? step_g(S, ar, c0) : step(S, ar, c0);
       if (st) return st;
     }
-    st = S.variant == 1 ? restart_g(S, R) : restart(S, R);
+    st = hb ? restart_hb(S, R) : S.variant == 1 ? restart_g(S, R) : restart(S, R);
     if (st) return st;
     jstart = S.keep;
     const bool full_space = S.keep >= m;
@@ -1663,8 +1997,10 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
         ms32 += now_ms() - t_phase;
         t_phase = now_ms();
       }
-      int s0 = from32 ? std::min(S.keep, k + std::max(4, k / 8)) : k;
-      if (o.refine_start > 0) s0 = std::max(k, std::min(S.keep, (int)o.refine_start));
+      // variant 3: only the positive Ritz vectors (at the front) start it
+      const int avail = hb ? S.npos : S.keep;
+      int s0 = from32 ? std::min(avail, k + std::max(4, k / 8)) : k;
+      if (o.refine_start > 0) s0 = std::max(k, std::min(avail, (int)o.refine_start));
       RefineOut ro;
       const double tf = now_ms();
       st = refine_h(S, s0, R.theta, tol, 200, ar, omega, (double2*)x, ph ? (double2*)y : nullptr, ro);
@@ -1731,8 +2067,9 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
     stats->ms_fp64_phase = ms64 - ms_final;
     stats->ms_final = ms_final;
     stats->max_rel_residual = max_rel;
-    stats->bytes_per_pass_fp32 = mixed ? bytes_per_pass(h, bse::AR_HI, b) : 0.0;
-    stats->bytes_per_pass_fp64 = bytes_per_pass(h, fp64_arith(h), b);
+    const int nvp = hb ? 2 * b : b;  // half-vectors in and out per read
+    stats->bytes_per_pass_fp32 = mixed ? bytes_per_pass(h, bse::AR_HI, nvp) : 0.0;
+    stats->bytes_per_pass_fp64 = bytes_per_pass(h, fp64_arith(h), nvp);
     stats->block = b;
     stats->samples_fp32 = S.samples32;
     stats->samples_fp64 = S.samples64;

@@ -199,6 +199,28 @@ hipError_t cdot(const double2* V0, int n0, const double2* V1, int n1, int64_t ld
   return hipSuccess;
 }
 
+hipError_t cdotm(const double2* V, int ncol, int64_t ld, const double2* W, int64_t ldw, int nw, int64_t n, double2*,
+                 double2* h, hipStream_t) {
+  for (int q = 0; q < nw; ++q)
+    for (int c = 0; c < ncol; ++c) {
+      cplx acc = 0.0;
+      for (int64_t i = 0; i < n; ++i) acc += std::conj(C(V[(size_t)c * ld + i])) * C(W[(size_t)q * ldw + i]);
+      h[(size_t)q * ncol + c] = D(acc);
+    }
+  return hipSuccess;
+}
+
+hipError_t cgemvm_sub(const double2* V, int ncol, int64_t ld, const double2* h, int ldh, double2* W, int64_t ldw,
+                      int nw, int64_t n, hipStream_t) {
+  for (int q = 0; q < nw; ++q)
+    for (int64_t i = 0; i < n; ++i) {
+      cplx acc = 0.0;
+      for (int c = 0; c < ncol; ++c) acc += C(V[(size_t)c * ld + i]) * C(h[(size_t)q * ldh + c]);
+      W[(size_t)q * ldw + i] = D(C(W[(size_t)q * ldw + i]) - acc);
+    }
+  return hipSuccess;
+}
+
 hipError_t cgemv_sub(const double2* V0, int n0, const double2* V1, int n1, const double2* P0, const double2* P1,
                      int64_t ld, const double2* h, int real_h, double2* w, double2* z, int64_t n, hipStream_t) {
   for (int c = 0; c < n0 + n1; ++c) {
@@ -529,8 +551,17 @@ hipError_t skew_back(const double*, int64_t, const double*, const double*, int64
                      hipStream_t) {
   return hipErrorInvalidValue;
 }
-hipError_t scale_cols(double2*, double2*, int64_t, int64_t, int, const double*, hipStream_t) {
-  return hipErrorInvalidValue;
+hipError_t scale_cols(double2* x, double2* y, int64_t ld, int64_t n, int k, const double* f, hipStream_t) {
+  for (int c = 0; c < k; ++c)
+    for (int64_t i = 0; i < n; ++i) {
+      x[(size_t)c * ld + i].x *= f[c];
+      x[(size_t)c * ld + i].y *= f[c];
+      if (y) {
+        y[(size_t)c * ld + i].x *= f[c];
+        y[(size_t)c * ld + i].y *= f[c];
+      }
+    }
+  return hipSuccess;
 }
 
 }  // namespace bse

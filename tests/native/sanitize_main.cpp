@@ -3,7 +3,7 @@
 // AddressSanitizer and UndefinedBehaviorSanitizer by tests/test_sanitize.py.
 // Every "device" buffer is a host allocation of its exact size here, so an
 // index past a buffer in the driver or a launcher is reported.  The program
-// exercises the calls of include/bse.h on small seeded matrices (TDA, both
+// exercises the calls of include/bse.h on small seeded matrices (TDA, the four
 // pseudo-Hermitian variants, the mixed path, blocks, warm starts, the
 // adjoint, the strength scalars, Haydock, the error paths) and checks each
 // solve's own residuals; it exits 0 only if every check passes.
@@ -158,6 +158,9 @@ int main() {
   solve_case(m, true, BSE_STORE_C128, BSE_PREC_FP64, 0, 1, 1e-10, "ph folded");
   solve_case(m, true, BSE_STORE_C128, BSE_PREC_FP64, 1, 1, 1e-10, "ph coupled");
   solve_case(m, true, BSE_STORE_HILO, BSE_PREC_MIXED, 0, 1, 1e-8, "ph mixed");
+  solve_case(m, true, BSE_STORE_C128, BSE_PREC_FP64, 2, 1, 1e-10, "ph dual");
+  solve_case(m, true, BSE_STORE_C128, BSE_PREC_FP64, 3, 2, 1e-10, "ph block full-H fp64");
+  solve_case(m, true, BSE_STORE_HILO, BSE_PREC_MIXED, 3, 3, 1e-8, "ph block full-H mixed b=3");
 
   // Haydock coefficients, two dipoles in lockstep
   {

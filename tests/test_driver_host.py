@@ -107,12 +107,16 @@ def ph_case(n=120, seed=5):
     return m.pack_host(0), m.pack_host(1)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("storage,precision,fp32,tol", [(0, 0, 0, 1e-10), (1, 1, 0, 1e-8), (1, 1, 1, 1e-8)])
 def test_ph_solve_matches_oracle(lib, variant, storage, precision, fp32, tol):
     ap, bp = ph_case()
     h = Handle(lib, 1, ap, bp, storage)
     rc, om, X, Y, st = h.solve(5, tol, variant=variant, precision=precision, fp32_arith=fp32, ncv=32)
+    if variant == 3 and fp32:  # the fused full-H passes have no complex FP32 form
+        assert rc == INVALID
+        h.close()
+        return
     assert rc == OK, h.error()
     ref, _, _ = oracle.ph(ap, bp, 5, vectors=False)
     assert np.max(np.abs(om - ref) / ref) < tol
@@ -137,24 +141,46 @@ def test_tda_solve_matches_oracle(lib, block):
     h.close()
 
 
-@pytest.mark.parametrize("kind", ["tda", "ph"])
+@pytest.mark.parametrize("block", [1, 2, 3, 4])
+def test_ph_block_full_h_matches_oracle(lib, block):
+    """Variant 3 (block Lanczos on H in the M inner product) with 1..4 full-H vectors per read:
+    the oracle's pairs, residuals within tol, normalized vectors, one read per block step."""
+    ap, bp = ph_case(200, 9)
+    k = 10
+    h = Handle(lib, 1, ap, bp, 1)
+    rc, om, X, Y, st = h.solve(k, 1e-8, variant=3, block=block, precision=1)
+    assert rc == OK, h.error()
+    assert st.block == block
+    ref, _, _ = oracle.ph(ap, bp, k, vectors=False)
+    assert np.max(np.abs(om - ref) / ref) < 1e-8
+    assert oracle.residual_ph(ap, bp, om, X, Y).max() <= 1e-8 * 1.01
+    nrm = np.sum(np.abs(X) ** 2, axis=0) - np.sum(np.abs(Y) ** 2, axis=0)
+    assert np.max(np.abs(nrm - 1)) < 1e-9
+    assert st.steps_fp32 > 0 and st.steps_fp32 % block == 0
+    h.close()
+
+
+@pytest.mark.parametrize("kind", ["tda", "ph", "ph3"])
 def test_warm_start_from_nearby_matrix(lib, kind):
     """A solve started from the eigenvectors of a nearby matrix (alpha + 1e-6, as in a finite
-    difference) finds the same pairs as a cold solve of that matrix, in fewer passes."""
+    difference) finds the same pairs as a cold solve of that matrix, in fewer passes (ph3: the
+    block full-H iteration, variant 3)."""
+    variant = 3 if kind == "ph3" else 0
+    kind = "ph" if kind == "ph3" else kind
     n, k, tol = 160, 8, 1e-12
     base = synth_matrix(n, 12, kind == "ph")
     near = synth.Matrix(n, 12, ph=kind == "ph", alpha=1.0 + 1e-6, tables=base.tables, shift=base.shift,
                         b_norm=base.b_norm if kind == "ph" else None)
     blocks = lambda m: (m.pack_host(0), m.pack_host(1) if kind == "ph" else None)
     h0 = Handle(lib, int(kind == "ph"), *blocks(base))
-    rc, om0, X0, Y0, _ = h0.solve(k, tol, ncv=32)
+    rc, om0, X0, Y0, _ = h0.solve(k, tol, ncv=32, variant=variant)
     assert rc == OK, h0.error()
     h0.close()
     ap, bp = blocks(near)
     h1 = Handle(lib, int(kind == "ph"), ap, bp)
-    rc, om_c, _, _, st_c = h1.solve(k, tol, ncv=32)
+    rc, om_c, _, _, st_c = h1.solve(k, tol, ncv=32, variant=variant)
     assert rc == OK, h1.error()
-    rc, om_w, Xw, Yw, st_w = h1.solve(k, tol, ncv=32, warm=(X0, Y0))
+    rc, om_w, Xw, Yw, st_w = h1.solve(k, tol, ncv=32, warm=(X0, Y0), variant=variant)
     assert rc == OK, h1.error()
     assert np.max(np.abs(om_w - om_c) / np.abs(om_c)) < 1e-11
     rel = oracle.residual_ph(ap, bp, om_w, Xw, Yw) if kind == "ph" else oracle.residual_tda(ap, om_w, Xw)
@@ -189,7 +215,7 @@ def test_not_positive_definite_is_reported(lib):
     A = np.diag(np.arange(1.0, n + 1)).astype(complex)
     B = np.zeros((n, n), dtype=complex)
     B[0, 0] = 1.6  # ||B|| > lambda_min(A): M indefinite
-    for variant in (0, 1, 2):
+    for variant in (0, 1, 2, 3):
         h = Handle(lib, 1, pack_upper(A), pack_upper(B))
         rc, *_ = h.solve(4, 1e-10, variant=variant)
         assert rc == NOT_PD, (variant, rc, h.error())
@@ -218,7 +244,7 @@ def test_not_converged_returns_best(lib):
     h.close()
 
 
-@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("variant", [0, 2, 3])
 def test_ph_not_converged_returns_pairs_of_h(lib, variant):
     """An unreachable tol (1e-17): after the restart budget the best approximations come back as (X, Y) of H
     itself (the dual iteration's vectors are mapped back from diag(I, -I) H diag(I, -I)),
@@ -226,7 +252,8 @@ def test_ph_not_converged_returns_pairs_of_h(lib, variant):
     (a Y of the wrong sign would leave a residual of the size of Y)."""
     ap, bp = ph_case(150, 4)
     h = Handle(lib, 1, ap, bp)
-    rc, om, X, Y, st = h.solve(6, 1e-17, max_restarts=20, ncv=24, variant=variant)
+    # variant 3 keeps both signs of omega: a basis twice as large for the same progress
+    rc, om, X, Y, st = h.solve(6, 1e-17, max_restarts=20, ncv=48 if variant == 3 else 24, variant=variant)
     assert rc == NOT_CONV
     nrm = np.sum(np.abs(X) ** 2, axis=0) - np.sum(np.abs(Y) ** 2, axis=0)
     assert np.max(np.abs(nrm - 1)) < 1e-9
@@ -234,7 +261,9 @@ def test_ph_not_converged_returns_pairs_of_h(lib, variant):
     assert rel[0] < 1e-6, rel
     assert np.min(np.linalg.norm(Y, axis=0)) > 1e-3  # the check above sees the sign of Y
     ref, _, _ = oracle.ph(ap, bp, 6, vectors=False)
-    assert np.all(om >= ref * (1 - 1e-12))
+    # the folded iterations approach omega^2 from above (extreme eigenvalues of K2 K1); on H the
+    # wanted omega are interior, and a Ritz value may sit below by O(residual^2 / gap)
+    assert np.all(om >= ref * (1 - (1e-6 if variant == 3 else 1e-12)))
     h.close()
 
 
@@ -255,7 +284,7 @@ def test_invalid_arguments(lib):
     for k, tol in [(0, 1e-8), (31, 1e-8), (3, 0.0), (3, -1.0)]:
         rc, *_ = h.solve(k, tol)
         assert rc == INVALID, (k, tol)
-    rc, *_ = h.solve(3, 1e-8, variant=3)
+    rc, *_ = h.solve(3, 1e-8, variant=4)
     assert rc == INVALID
     rc, *_ = h.solve(3, 1e-8, precision=1)  # mixed needs hi + lo storage
     assert rc == INVALID

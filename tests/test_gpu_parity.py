@@ -171,7 +171,7 @@ def test_solve_tda_synth(n, k):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("n,k", [(300, 8), (900, 10)])
 def test_solve_ph_synth(n, k, variant):
     print(f"ph synth n={n} k={k} variant={variant}", flush=True)
@@ -182,7 +182,7 @@ def test_solve_ph_synth(n, k, variant):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("n,k", [(200, 6), (640, 10)])
 def test_solve_ph_strong_coupling(n, k, variant):
     """Generic dense blocks with ||B||_2 = 0.6 lambda_min(A): large Y components."""
@@ -218,10 +218,11 @@ def test_tiny_sizes(n):
     s = make_solver("ph", ap, bp)
     check_ph(s, ap, bp, k, 1e-10, 1e-10)
     check_ph(s, ap, bp, k, 1e-10, 1e-10, variant=1)
+    check_ph(s, ap, bp, k, 1e-10, 1e-10, variant=3)
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_all_pairs_k_equals_n(variant):
     n = 24
     rng = np.random.default_rng(9)
@@ -231,7 +232,7 @@ def test_all_pairs_k_equals_n(variant):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_real_blocks_no_duplicate_pairs(variant):
     n, k = 150, 10
     rng = np.random.default_rng(4)
@@ -246,7 +247,7 @@ def test_real_blocks_no_duplicate_pairs(variant):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_b_zero_reduces_to_tda(variant):
     n, k = 200, 8
     m = ph_matrix(n, 77)
@@ -260,7 +261,7 @@ def test_b_zero_reduces_to_tda(variant):
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_not_positive_definite(variant):
     n = 60
     A = np.diag(np.arange(1.0, n + 1)).astype(complex)
@@ -285,7 +286,7 @@ def test_invalid_arguments():
     with pytest.raises(bse.BSEError) as e:
         s.solve(4, 1e-8, precision="mixed")
     assert e.value.status == bse.ERR_INVALID_ARG
-    for v in (-1, 3):
+    for v in (-1, 4):
         with pytest.raises(bse.BSEError) as e:
             s.solve(4, 1e-8, variant=v)
         assert e.value.status == bse.ERR_INVALID_ARG
@@ -383,7 +384,7 @@ def test_mixed_tda_matches_oracle():
     s.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_mixed_ph_matches_oracle(variant):
     n, k = 900, 10
     m = ph_matrix(n, 32)
@@ -542,7 +543,32 @@ def _golden(name):
     return mod.load(name)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("block", [1, 2, 3, 4])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_block_full_h_ph_matches_oracle(block, precision):
+    """Variant 3 (block Lanczos on H in the M inner product) with 1..4 full-H vectors per fused
+    read, FP64 (hi + lo) and mixed: the oracle's pairs and residuals, X^H X - Y^H Y = 1, and one
+    read of the triangles per block step of the bulk phase."""
+    n, k = 1100, 12
+    m = ph_matrix(n, 35)
+    ap, bp = m.pack_host(0), m.pack_host(1)
+    s = make_solver("ph", ap, bp, storage="hilo")
+    tol = 1e-10 if precision == "fp64" else 1e-8
+    om, X, Y, st = s.solve(k, tol, precision=precision, variant=3, block=block)
+    ref, _, _ = oracle.ph(ap, bp, k, vectors=False)
+    assert st["block"] == block
+    assert np.max(np.abs(host(om) - ref) / ref) < tol
+    Xh, Yh = host(X).T, host(Y).T
+    assert oracle.residual_ph(ap, bp, host(om), Xh, Yh).max() <= tol * 1.01
+    nrm = np.sum(np.abs(Xh) ** 2, axis=0) - np.sum(np.abs(Yh) ** 2, axis=0)
+    assert np.max(np.abs(nrm - 1)) < 1e-9
+    steps = st["steps_fp32"] + st["steps_fp64"]
+    assert steps % block == 0
+    print("block", block, precision, "passes", st["passes"], "steps", steps, flush=True)
+    s.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_workload_ph_n4096_k32_golden(variant):
     """Pseudo-Hermitian workload N = 4096 (operator 8192), lowest 32 pairs at
     tol 1e-10 against the oracle's stored values; residuals checked by the oracle."""
