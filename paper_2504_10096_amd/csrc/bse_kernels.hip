@@ -1006,11 +1006,19 @@ __global__ void __launch_bounds__(kThreads)
 // per read for two vectors at N = 1e5)
 __host__ __device__ constexpr int mh_rows(int nh) { return nh >= 3 ? 128 : 256; }
 
-// Full-H products in the streaming form (R >= 128): the products of
-// mh_block_kernel (outputs 2q: A x_q + B y_q; 2q+1: A conj(y_q) + B conj(x_q),
-// rows and columns), with the layout of mk_block_kernel: 16-byte loads of
-// column segments, the next column's loads issued before the current one is
-// consumed, DPP column sums kept one per lane and stored per 64 columns.
+// Full-H products in the streaming form (R >= 128), with the layout of
+// mk_block_kernel: 16-byte loads of column segments, the next column's loads
+// issued before the current one is consumed, column sums kept one per lane
+// and stored per 64 columns.  The outputs are taken in the sum / difference
+// basis: with u = x + conj(y) and w = x - conj(y),
+//   top T = A x + B y and conjugated bottom C = A conj(y) + B conj(x) satisfy
+//   T + C = K1 u = A u + B conj(u),  T - C = K2 w = A w - B conj(w),
+// and each of K1, K2 acts on (Re, Im) of a vector entry as the real 2 x 2
+// block [[ar + br, bi - ai], [ai + bi, ar - br]] (K2: B negated) of the
+// stored pair (a, b), the column (transposed) use as its transpose with the
+// conjugate of A.  The four sums are formed once per entry pair, so a vector
+// costs 16 FMAs per pair instead of the 32 of the four complex products.
+// Outputs 2q: K1 u_q, 2q+1: K2 w_q (mh_reduce_kernel, sd = 1, forms T and C).
 // Row partials: rowpart[o][blk][R]; column partials: colpart[o][blk][slice][R]
 // with R / mh_rows(NH) slices.
 template <int R, int AR, int NH>
@@ -1047,7 +1055,8 @@ __global__ void __launch_bounds__(kThreads)
   double* stage = reinterpret_cast<double*>(lds) + wave * CSW;
   double* colsum = stage + NVAL * stage_ld(NVAL);
 
-  double xr[NH][RPL], xi[NH][RPL], yr[NH][RPL], yi[NH][RPL], rr[NO][RPL], ri[NO][RPL];
+  // row entries of u = x + conj(y) and w = x - conj(y)
+  double ur[NH][RPL], ui[NH][RPL], wr[NH][RPL], wi[NH][RPL], rr[NO][RPL], ri[NO][RPL];
 #pragma unroll
   for (int q = 0; q < NH; ++q)
 #pragma unroll
@@ -1059,10 +1068,10 @@ __global__ void __launch_bounds__(kThreads)
         const bool in = i < n;
         const double2 x = V[(size_t)q * ldv + (in ? i : 0)];
         const double2 y = V[(size_t)q * ldv + ldh + (in ? i : 0)];
-        xr[q][t] = in ? x.x : 0.0;
-        xi[q][t] = in ? x.y : 0.0;
-        yr[q][t] = in ? y.x : 0.0;
-        yi[q][t] = in ? y.y : 0.0;
+        ur[q][t] = in ? x.x + y.x : 0.0;
+        ui[q][t] = in ? x.y - y.y : 0.0;
+        wr[q][t] = in ? x.x - y.x : 0.0;
+        wi[q][t] = in ? x.y + y.y : 0.0;
       }
 #pragma unroll
   for (int o = 0; o < NO; ++o)
@@ -1103,15 +1112,15 @@ __global__ void __launch_bounds__(kThreads)
       const int64_t j = col0 + c;
       const bool in = j < n;
       const int64_t jj = in ? j : 0;
-      double cxr[NH], cxi[NH], cyr[NH], cyi[NH], sr[NO], si[NO];
+      double cur[NH], cui[NH], cwr[NH], cwi[NH], sr[NO], si[NO];
 #pragma unroll
       for (int q = 0; q < NH; ++q) {
         const double2 x = V[(size_t)q * ldv + jj];
         const double2 y = V[(size_t)q * ldv + ldh + jj];
-        cxr[q] = in ? x.x : 0.0;
-        cxi[q] = in ? x.y : 0.0;
-        cyr[q] = in ? y.x : 0.0;
-        cyi[q] = in ? y.y : 0.0;
+        cur[q] = in ? x.x + y.x : 0.0;
+        cui[q] = in ? x.y - y.y : 0.0;
+        cwr[q] = in ? x.x - y.x : 0.0;
+        cwi[q] = in ? x.y + y.y : 0.0;
       }
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
@@ -1126,48 +1135,28 @@ __global__ void __launch_bounds__(kThreads)
           double ar, ai, br, bi;
           raw_get<AR, double>(ca_[g], e, ar, ai);
           raw_get<AR, double>(cbm[g], e, br, bi);
+          const double sp = ar + br, sq = ar - br, ss = ai + bi, st = bi - ai;
 #pragma unroll
           for (int q = 0; q < NH; ++q) {
-            double* r0r = &rr[2 * q][t];
-            double* r0i = &ri[2 * q][t];
-            double* r1r = &rr[2 * q + 1][t];
-            double* r1i = &ri[2 * q + 1][t];
-            // top, row r: A x_c + B y_c
-            mac(*r0r, ar, cxr[q]);
-            mac(*r0r, -ai, cxi[q]);
-            mac(*r0r, br, cyr[q]);
-            mac(*r0r, -bi, cyi[q]);
-            mac(*r0i, ar, cxi[q]);
-            mac(*r0i, ai, cxr[q]);
-            mac(*r0i, br, cyi[q]);
-            mac(*r0i, bi, cyr[q]);
-            // bottom (conjugated), row r: A conj(y_c) + B conj(x_c)
-            mac(*r1r, ar, cyr[q]);
-            mac(*r1r, ai, cyi[q]);
-            mac(*r1r, br, cxr[q]);
-            mac(*r1r, bi, cxi[q]);
-            mac(*r1i, ai, cyr[q]);
-            mac(*r1i, -ar, cyi[q]);
-            mac(*r1i, bi, cxr[q]);
-            mac(*r1i, -br, cxi[q]);
-            // top, column c: conj(A) x_r + B y_r
-            mac(sr[2 * q], ar, xr[q][t]);
-            mac(sr[2 * q], ai, xi[q][t]);
-            mac(sr[2 * q], br, yr[q][t]);
-            mac(sr[2 * q], -bi, yi[q][t]);
-            mac(si[2 * q], ar, xi[q][t]);
-            mac(si[2 * q], -ai, xr[q][t]);
-            mac(si[2 * q], br, yi[q][t]);
-            mac(si[2 * q], bi, yr[q][t]);
-            // bottom (conjugated), column c: conj(A) conj(y_r) + B conj(x_r)
-            mac(sr[2 * q + 1], ar, yr[q][t]);
-            mac(sr[2 * q + 1], -ai, yi[q][t]);
-            mac(sr[2 * q + 1], br, xr[q][t]);
-            mac(sr[2 * q + 1], bi, xi[q][t]);
-            mac(si[2 * q + 1], -ar, yi[q][t]);
-            mac(si[2 * q + 1], -ai, yr[q][t]);
-            mac(si[2 * q + 1], bi, xr[q][t]);
-            mac(si[2 * q + 1], -br, xi[q][t]);
+            // rows: K1 u_c = (sp ur + st ui, ss ur + sq ui); K2 w_c = (sq wr - ss wi, -st wr + sp wi)
+            mac(rr[2 * q][t], sp, cur[q]);
+            mac(rr[2 * q][t], st, cui[q]);
+            mac(ri[2 * q][t], ss, cur[q]);
+            mac(ri[2 * q][t], sq, cui[q]);
+            mac(rr[2 * q + 1][t], sq, cwr[q]);
+            mac(rr[2 * q + 1][t], -ss, cwi[q]);
+            mac(ri[2 * q + 1][t], -st, cwr[q]);
+            mac(ri[2 * q + 1][t], sp, cwi[q]);
+            // columns (conj(A) transposed, B): K1 u_r = (sp ur + ss ui, st ur + sq ui);
+            // K2 w_r = (sq wr - st wi, -ss wr + sp wi)
+            mac(sr[2 * q], sp, ur[q][t]);
+            mac(sr[2 * q], ss, ui[q][t]);
+            mac(si[2 * q], st, ur[q][t]);
+            mac(si[2 * q], sq, ui[q][t]);
+            mac(sr[2 * q + 1], sq, wr[q][t]);
+            mac(sr[2 * q + 1], -st, wi[q][t]);
+            mac(si[2 * q + 1], -ss, wr[q][t]);
+            mac(si[2 * q + 1], sp, wi[q][t]);
           }
         }
       double vals[NVAL];
@@ -1216,33 +1205,63 @@ __global__ void __launch_bounds__(kThreads)
 // Sum of the partials of mh_block_kernel (pairs != 0: output 2q goes to the
 // top of column q of MV, output 2q+1 conjugated and times bsign to its
 // bottom; bsign = 1: M v, -1: H v) or of mk_block_kernel (pairs == 0:
-// output q to column q).  Grid (ceil(n / 256), outputs).
+// output q to column q).  Grid (ceil(n / 256), outputs).  sd != 0 (the
+// streaming full-H kernel): outputs 2q, 2q+1 are K1 u_q and K2 w_q; the
+// thread of vector q (grid (ceil(n / 256), vectors)) sums both and writes
+// the top (K1 u + K2 w) / 2 and the conjugated bottom (K1 u - K2 w) / 2.
 __global__ void __launch_bounds__(kThreads)
     mh_reduce_kernel(const double2* __restrict__ rowpart, const double2* __restrict__ colpart, int R, int NS,
                      int nb, int64_t nblk, int64_t n, double2* __restrict__ MV, int64_t ldv, int64_t ldh,
                      double bsign, int pairs, const double* __restrict__ dc, double dsg,
-                     const double2* __restrict__ X, int64_t ldx, int64_t ldhx) {
+                     const double2* __restrict__ X, int64_t ldx, int64_t ldhx, int sd) {
   const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int o = blockIdx.y;
   if (i >= n) return;
   const int P = (int)(i / R), r = (int)(i % R);
-  const double2* rp = rowpart + (size_t)o * nblk * R;
-  const double2* cp = colpart + (size_t)o * nblk * NS * R;
-  double sx = 0.0, sy = 0.0;
   const int64_t pstart = (int64_t)P * nb - (int64_t)P * (P - 1) / 2;
-  for (int Q = P; Q < nb; ++Q) {
-    const double2 v = rp[(size_t)(pstart + (Q - P)) * R + r];
-    sx += v.x;
-    sy += v.y;
-  }
-  for (int Q = 0; Q <= P; ++Q) {
-    const int64_t b = (int64_t)Q * nb - (int64_t)Q * (Q - 1) / 2 + (P - Q);
-    for (int sl = 0; sl < NS; ++sl) {
-      const double2 v = cp[((size_t)b * NS + sl) * R + r];
+  // the row's sum of output o over its blocks: rows of blocks (P, Q >= P),
+  // columns of blocks (Q <= P, P), in a fixed order
+  auto osum = [&](int o, double& sx, double& sy) {
+    const double2* rp = rowpart + (size_t)o * nblk * R;
+    const double2* cp = colpart + (size_t)o * nblk * NS * R;
+    sx = 0.0;
+    sy = 0.0;
+    for (int Q = P; Q < nb; ++Q) {
+      const double2 v = rp[(size_t)(pstart + (Q - P)) * R + r];
       sx += v.x;
       sy += v.y;
     }
+    for (int Q = 0; Q <= P; ++Q) {
+      const int64_t b = (int64_t)Q * nb - (int64_t)Q * (Q - 1) / 2 + (P - Q);
+      for (int sl = 0; sl < NS; ++sl) {
+        const double2 v = cp[((size_t)b * NS + sl) * R + r];
+        sx += v.x;
+        sy += v.y;
+      }
+    }
+  };
+  if (sd) {
+    const int q = blockIdx.y;
+    double s1x, s1y, s2x, s2y;
+    osum(2 * q, s1x, s1y);
+    osum(2 * q + 1, s2x, s2y);
+    double tx = 0.5 * (s1x + s2x), ty = 0.5 * (s1y + s2y);  // top
+    double cx = 0.5 * (s1x - s2x), cy = 0.5 * (s1y - s2y);  // conjugated bottom
+    if (dc) {
+      const double f = dsg * dc[i];
+      const double2 x = X[(size_t)q * ldx + i];
+      const double2 y = X[(size_t)q * ldx + ldhx + i];
+      tx = fma(f, x.x, tx);
+      ty = fma(f, x.y, ty);
+      cx = fma(f, y.x, cx);
+      cy = fma(-f, y.y, cy);
+    }
+    MV[(size_t)q * ldv + i] = make_double2(tx, ty);
+    MV[(size_t)q * ldv + ldh + i] = make_double2(bsign * cx, -bsign * cy);
+    return;
   }
+  const int o = blockIdx.y;
+  double sx, sy;
+  osum(o, sx, sy);
   // diagonal correction: output o multiplies A by x_o (mk) or, for the fused
   // full-H product, by x_q (top) and conj(y_q) (the conjugate of the bottom)
   if (dc) {
@@ -2381,9 +2400,10 @@ hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const d
   const int ns = mh_slices(L.R, nh);
   const double2* rowpart = part;
   const double2* colpart = part + (size_t)2 * nh * L.nblk * L.R;
-  hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)(2 * nh)),
+  const int sd = L.R >= 128;  // the streaming kernel's sum / difference outputs
+  hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)(sd ? nh : 2 * nh)),
                      dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, MV, ldv, ldh, bsign, 1,
-                     m.dc, m.dsign, V, ldv, ldh);
+                     m.dc, m.dsign, V, ldv, ldh, sd);
   return hipGetLastError();
 }
 
@@ -2476,7 +2496,7 @@ hipError_t mk_apply(const Layout& L, Arith ar, BMode bm, const MatPtrs& m, int n
   const double2* colpart = part + (size_t)nv * L.nblk * L.R;
   hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((L.n + kThreads - 1) / kThreads), (unsigned)nv),
                      dim3(kThreads), 0, s, rowpart, colpart, L.R, ns, L.nb, L.nblk, L.n, out, ldo, (int64_t)0, 1.0,
-                     0, m.dc, m.dsign, V, ldv, (int64_t)0);
+                     0, m.dc, m.dsign, V, ldv, (int64_t)0, 0);
   return hipGetLastError();
 }
 
