@@ -84,10 +84,10 @@ typedef enum {
 /* Solver options; a NULL pointer or zero fields select the defaults. */
 typedef struct {
   int32_t ncv;          /* basis size m (default: max(2k, k + 32) rounded up to 16, at most N;
-                           PH variant 3: max(4k, 2k + 64) rounded up to 16, at least 2k + 16,
+                           PH variant 3: max(5.6k, 2k + 64) rounded up to 16, at least 2k + 16,
                            at most 2N) */
   int32_t keep;         /* Ritz vectors kept at a restart (default: k + (m - k) / 2; variant 3:
-                           k + 2 (m - k) / 3) */
+                           k + 3 (m - k) / 5) */
   int32_t max_restarts; /* default 400 */
   int32_t precision;    /* bse_precision; MIXED needs BSE_STORE_HILO (default FP64) */
   double switch_tol;    /* MIXED: FP32-phase estimate that hands over to FP64 (default 1e-6) */
@@ -104,8 +104,8 @@ typedef struct {
                            one vector).  PH variant 3: 1..4 full-H vectors per read (0: 2). */
   int32_t refine_start; /* Ritz vectors of the iteration that start the FP64 refinement
                            (0: k after an FP64 iteration, min(keep, k + max(4, k/8)) after the
-                           bulk phase of MIXED; at most keep -- variant 3: at most the number
-                           of positive Ritz values kept) */
+                           bulk phase of MIXED -- variant 3: k + max(4, k/2); at most keep, and
+                           for variant 3 at most the number of positive Ritz values kept) */
   int32_t variant;      /* PH structure-preserving iteration: 0 (default) the K1-metric Lanczos
                            process on K2 K1, whose Ritz values are omega^2; 1 the Lanczos
                            process on H in the inner product of M, started from [u; conj(u)]

@@ -1906,7 +1906,11 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   // variant 3 works in C^{2N} and keeps both signs of omega: a basis about
   // twice as large, in a space twice as large
   const int64_t dim = hb ? 2 * n : n;
-  int m = o.ncv > 0 ? o.ncv : (int)round_up(hb ? std::max(4 * k, 2 * k + 64) : std::max(2 * k, k + 32), 16);
+  // (variant 3: 5.6 k measured best at PH N = 1e5, k = 100 -- fewer reads than
+  // 4 k, and beyond it the reads stop falling while the orthogonalization and
+  // the projected eigensolves grow)
+  int m = o.ncv > 0 ? o.ncv
+                    : (int)round_up(hb ? std::max((28 * k + 4) / 5, 2 * k + 64) : std::max(2 * k, k + 32), 16);
   if (hb) m = std::max(m, 2 * k + 16);  // room for k positive Ritz values and their mirror images
   m = (int)std::min<int64_t>(m, dim);
   if (m < k) return fail(h, BSE_ERR_INVALID_ARG, "ncv must be at least k");
@@ -1922,7 +1926,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   int b = hb ? (o.block > 0 ? o.block : 2) : ph ? 1 : (o.block > 0 ? o.block : (n >= 16384 ? 2 : 1));
   if (b > 1 && ((int)round_up(m, b) < k + b || (int64_t)round_up(m, b) + b > dim / 2)) b = 1;
   m = (int)round_up(m, b);
-  int keep = o.keep > 0 ? o.keep : hb ? k + (m - k) * 2 / 3 : k + (m - k) / 2;
+  int keep = o.keep > 0 ? o.keep : hb ? k + (m - k) * 3 / 5 : k + (m - k) / 2;
   keep = (int)round_up(std::max(keep, k), b);
   if (keep >= m) keep = (m > k) ? m - b : m;
   const int max_restarts = o.max_restarts > 0 ? o.max_restarts : 400;
@@ -1999,7 +2003,7 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
       }
       // variant 3: only the positive Ritz vectors (at the front) start it
       const int avail = hb ? S.npos : S.keep;
-      int s0 = from32 ? std::min(avail, k + std::max(4, k / 8)) : k;
+      int s0 = from32 ? std::min(avail, k + std::max(4, hb ? k / 2 : k / 8)) : k;
       if (o.refine_start > 0) s0 = std::max(k, std::min(avail, (int)o.refine_start));
       RefineOut ro;
       const double tf = now_ms();
