@@ -1919,10 +1919,10 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   // where reading the triangle dominates a step and two vectors per read
   // cost little more than one; b = 1 below, where launches and
   // orthogonalization dominate and the block's extra products do not pay.
-  // The pseudo-Hermitian iteration keeps b = 1: its basis is K1-orthogonal to
-  // its own partner space only when it grows from a single vector.
-  // Variant 3 grows from a block (default b = 2, one fused full-H read of
-  // the triangles per block step).
+  // The folded pseudo-Hermitian iterations (variants 0 - 2) keep b = 1: their
+  // bases are orthogonal to their own partner spaces only when grown from a
+  // single vector.  Variant 3 grows from a block (default b = 2, one fused
+  // full-H read of the triangles per block step).
   int b = hb ? (o.block > 0 ? o.block : 2) : ph ? 1 : (o.block > 0 ? o.block : (n >= 16384 ? 2 : 1));
   if (b > 1 && ((int)round_up(m, b) < k + b || (int64_t)round_up(m, b) + b > dim / 2)) b = 1;
   m = (int)round_up(m, b);
