@@ -994,6 +994,25 @@ __global__ void __launch_bounds__(kThreads)
   }
 }
 
+// The sum / difference inputs of mh_stream_kernel: UW[2q][i] = x_q[i] + conj(y_q[i]),
+// UW[2q + 1][i] = x_q[i] - conj(y_q[i]) for i < pl (zero past n), column q of V
+// being [x_q (ldh); y_q].  Grid (ceil(pl / 256), nh).
+__global__ void __launch_bounds__(kThreads)
+    hsd_stage_kernel(const double2* __restrict__ V, int64_t ldv, int64_t ldh, int64_t n, int64_t pl,
+                     double2* __restrict__ UW) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int q = blockIdx.y;
+  if (i >= pl) return;
+  double2 u = make_double2(0.0, 0.0), w = u;
+  if (i < n) {
+    const double2 x = V[(size_t)q * ldv + i], y = V[(size_t)q * ldv + ldh + i];
+    u = make_double2(x.x + y.x, x.y - y.y);
+    w = make_double2(x.x - y.x, x.y + y.y);
+  }
+  UW[(size_t)(2 * q) * pl + i] = u;
+  UW[(size_t)(2 * q + 1) * pl + i] = w;
+}
+
 // rows per workgroup slice of the streaming full-H kernel: 256 rows spread
 // each column's wavefront reductions (four per vector) over four rows per
 // lane; 128 rows left the kernel bound by those reductions (37 ms vs 30 ms
@@ -1020,7 +1039,7 @@ __global__ void __launch_bounds__(kThreads)
     mh_stream_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
                      const void* __restrict__ b0, const void* __restrict__ b1,
                      const int2* __restrict__ blkmap, int64_t nblk, int64_t n,
-                     const double2* __restrict__ V, int64_t ldv, int64_t ldh,
+                     const double2* __restrict__ UW, int64_t pl,
                      double2* __restrict__ rowpart, double2* __restrict__ colpart) {
   constexpr int RS = R < mh_rows(NH) ? R : mh_rows(NH);
   constexpr int NS = R / RS;
@@ -1049,7 +1068,8 @@ __global__ void __launch_bounds__(kThreads)
   double* stage = reinterpret_cast<double*>(lds) + wave * CSW;
   double* colsum = stage + NVAL * stage_ld(NVAL);
 
-  // row entries of u = x + conj(y) and w = x - conj(y)
+  // row entries of u = x + conj(y) and w = x - conj(y) (staged by hsd_stage_kernel over the
+  // padded length pl, zero past n: no bounds selects here)
   double ur[NH][RPL], ui[NH][RPL], wr[NH][RPL], wi[NH][RPL], rr[NO][RPL], ri[NO][RPL];
 #pragma unroll
   for (int q = 0; q < NH; ++q)
@@ -1059,13 +1079,12 @@ __global__ void __launch_bounds__(kThreads)
       for (int e = 0; e < VW; ++e) {
         const int t = g * VW + e;
         const int64_t i = row0 + g * 64 * VW + lane * VW + e;
-        const bool in = i < n;
-        const double2 x = V[(size_t)q * ldv + (in ? i : 0)];
-        const double2 y = V[(size_t)q * ldv + ldh + (in ? i : 0)];
-        ur[q][t] = in ? x.x + y.x : 0.0;
-        ui[q][t] = in ? x.y - y.y : 0.0;
-        wr[q][t] = in ? x.x - y.x : 0.0;
-        wi[q][t] = in ? x.y + y.y : 0.0;
+        const double2 u = UW[(size_t)(2 * q) * pl + i];
+        const double2 w = UW[(size_t)(2 * q + 1) * pl + i];
+        ur[q][t] = u.x;
+        ui[q][t] = u.y;
+        wr[q][t] = w.x;
+        wi[q][t] = w.y;
       }
 #pragma unroll
   for (int o = 0; o < NO; ++o)
@@ -1104,17 +1123,15 @@ __global__ void __launch_bounds__(kThreads)
       __builtin_amdgcn_sched_barrier(0);
       const int c = IL ? cc * 4 + wave : wave * CPW + cc;
       const int64_t j = col0 + c;
-      const bool in = j < n;
-      const int64_t jj = in ? j : 0;
       double cur[NH], cui[NH], cwr[NH], cwi[NH], sr[NO], si[NO];
 #pragma unroll
       for (int q = 0; q < NH; ++q) {
-        const double2 x = V[(size_t)q * ldv + jj];
-        const double2 y = V[(size_t)q * ldv + ldh + jj];
-        cur[q] = in ? x.x + y.x : 0.0;
-        cui[q] = in ? x.y - y.y : 0.0;
-        cwr[q] = in ? x.x - y.x : 0.0;
-        cwi[q] = in ? x.y + y.y : 0.0;
+        const double2 u = UW[(size_t)(2 * q) * pl + j];
+        const double2 w = UW[(size_t)(2 * q + 1) * pl + j];
+        cur[q] = u.x;
+        cui[q] = u.y;
+        cwr[q] = w.x;
+        cwi[q] = w.y;
       }
 #pragma unroll
       for (int o = 0; o < NO; ++o) {
@@ -1297,19 +1314,25 @@ hipError_t launch_mh(int nh, const Layout& L, const MatPtrs& m, const double2* V
   double2* rowpart = part;
   double2* colpart = part + (size_t)2 * nh * L.nblk * R;
   if constexpr (R >= 128) {
-    const dim3 grid((unsigned)L.nblk, (unsigned)mh_slices(R, nh));
+    // u, w of every vector over the padded length, after the partials (mh_part_elems)
+    const int ns = mh_slices(R, nh);
+    const int64_t pl = (int64_t)L.nb * R;
+    double2* uw = colpart + (size_t)2 * nh * L.nblk * ns * R;
+    hipLaunchKernelGGL(hsd_stage_kernel, dim3((unsigned)((pl + kThreads - 1) / kThreads), (unsigned)nh),
+                       dim3(kThreads), 0, s, V, ldv, ldh, L.n, pl, uw);
+    const dim3 grid((unsigned)L.nblk, (unsigned)ns);
     if (nh == 1)
       hipLaunchKernelGGL((mh_stream_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
-                         L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+                         L.blkmap, L.nblk, L.n, uw, pl, rowpart, colpart);
     else if (nh == 2)
       hipLaunchKernelGGL((mh_stream_kernel<R, AR, 2>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
-                         L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+                         L.blkmap, L.nblk, L.n, uw, pl, rowpart, colpart);
     else if (nh == 3)
       hipLaunchKernelGGL((mh_stream_kernel<R, AR, 3>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
-                         L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+                         L.blkmap, L.nblk, L.n, uw, pl, rowpart, colpart);
     else
       hipLaunchKernelGGL((mh_stream_kernel<R, AR, 4>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
-                         L.blkmap, L.nblk, L.n, V, ldv, ldh, rowpart, colpart);
+                         L.blkmap, L.nblk, L.n, uw, pl, rowpart, colpart);
     return hipGetLastError();
   }
   constexpr int NS = 1;  // R = 64: one slice per block
@@ -2348,7 +2371,8 @@ size_t mv_part_elems(const Layout& L) { return (size_t)L.nblk * L.R * (1 + mv_sl
 size_t mh_part_elems(const Layout& L, int nh) {
   size_t mx = 0;
   for (int v = 1; v <= nh; ++v)
-    mx = std::max(mx, (size_t)2 * v * L.nblk * L.R * (1 + mh_slices(L.R, v)));
+    mx = std::max(mx, (size_t)2 * v * L.nblk * L.R * (1 + mh_slices(L.R, v)) +
+                          (L.R >= 128 ? (size_t)2 * v * L.nb * L.R : 0));  // + staged u, w
   return mx;
 }
 
