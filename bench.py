@@ -34,10 +34,13 @@ sys.path.insert(0, ROOT)
 METRIC = "time to lowest-k BSE pairs at N=1e5, mixed vs FP64 at 1e-8 residual; matvec GB/s"
 HBM_PEAK_GBPS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
+FP64_VALU_PEAK_TFLOPS = 78.6
 
 
 PMC_FILES = {"mv_stream_kernel<512, 3, 1>": "pmc_mv_stream_kernel_ph_n100000.txt",
-             "mh_stream_kernel<512, 3, 2>": "pmc_mh_stream_kernel_ph_n100000.txt"}
+             "mh_stream_kernel<512, 3, 2>": "pmc_mh_stream_kernel_x2_ph_n100000.txt",
+             "mh_stream_kernel<512, 3, 3>": "pmc_mh_stream_kernel_x3_ph_n100000.txt",
+             "mh_stream_kernel<512, 3, 4>": "pmc_mh_stream_kernel_x4_ph_n100000.txt"}
 
 
 def counter_traffic(kernel_name):
@@ -375,7 +378,7 @@ def main():
             # the fused full-H product: 2 vectors in FP64; 1..3 on hi (the block full-H iteration)
             multi += [("fp64", "H", 2, 16)]
             if storage == "hilo":
-                multi += [("hi64", "H", nv, 8) for nv in (1, 2, 3)]
+                multi += [("hi64", "H", nv, 8) for nv in (1, 2, 3, 4)]
         for prec, mop, nv, e in multi:
             xm = torch.randn((nv, 2 * n if mop == "H" else n), dtype=torch.complex128, device="cuda")
             solver.apply(mop, xm, precision=prec)
@@ -518,6 +521,14 @@ def main():
         "solve": {k_: st[k_] for k_ in st if not k_.endswith("_") and not k_.startswith("ms_dense")},
         "setup_s": t_setup,
     }
+    if hblock and ms_launch > 0:
+        # the same launch seen from its FP64 arithmetic: 16 FMAs per stored entry pair and full-H
+        # vector (sum / difference form) plus 4 adds per pair, against the FP64 vector peak
+        pairs = n * (n + 1) / 2
+        fl = (32.0 * st["block"] + 4.0) * pairs
+        tf = fl / (ms_launch * 1e-3) / 1e12
+        result["roofline"].update({"fp64_flops_per_launch": fl, "fp64_tflops": tf,
+                                   "fp64_frac": tf / FP64_VALU_PEAK_TFLOPS})
     if st["ms_gemm"] > 0:
         tf = st["gemm_flops"] / (st["ms_gemm"] * 1e-3) / 1e12
         result["mfma"] = {"kernel": "dgemm_mfma_kernel / zgemm_mfma_kernel (basis rotations)",

@@ -68,7 +68,7 @@ def test_workload_tda_n32768_k64_mixed_and_fp64():
 def test_workload_ph_n100000_k100_mixed():
     """The benchmark workload at full size, in the configuration bench.py times (PH N = 1e5,
     k = 100, tol 1e-8, mixed path on hi + lo storage from the device generator, block Lanczos on
-    the full H with two vectors per read): the solver's own FP64 residuals, the oracle's
+    the full H with four vectors per read): the solver's own FP64 residuals, the oracle's
     streaming FP64 residual of pairs spread over the 100, the normalization X^H X - Y^H Y = 1 and
     ascending omega above the recipe's lower edge."""
     w = synth.WORKLOADS[4]
