@@ -101,7 +101,8 @@ typedef struct {
                            basis would not leave room for b >= 2); ncv and keep are rounded
                            up to multiples of b.  PH variants 0 - 2: ignored (b = 1: their
                            bases are orthogonal to their partner spaces only when grown from
-                           one vector).  PH variant 3: 1..4 full-H vectors per read (0: 4). */
+                           one vector).  PH variant 3: 1..4 full-H vectors per read (0: 4 for
+                           N >= 16384, else 2). */
   int32_t refine_start; /* Ritz vectors of the iteration that start the FP64 refinement
                            (0: k after an FP64 iteration, min(keep, k + max(4, k/8)) after the
                            bulk phase of MIXED -- variant 3: k + max(4, k/2); at most keep, and

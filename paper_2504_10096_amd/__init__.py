@@ -270,7 +270,7 @@ class Solver:
         triangles in the Lanczos iteration (0: automatic).  variant (PH): 0 the K1-metric
         iteration on K2 K1, 1 the Lanczos process on H in the M inner product, 2 the dual
         K2-metric iteration on K1 K2, 3 block Lanczos on H in the M inner product over C^2N
-        (`block` full-H vectors per read, default 4).  warm: (X, Y) of a
+        (`block` full-H vectors per read; default 4 from N = 16384 on, else 2).  warm: (X, Y) of a
         previous solve of a nearby matrix (rows = pairs, Y None for TDA) to start from."""
         k = int(k)
         dev = self.device

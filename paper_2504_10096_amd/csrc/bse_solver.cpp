@@ -1921,11 +1921,13 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   // orthogonalization dominate and the block's extra products do not pay.
   // The folded pseudo-Hermitian iterations (variants 0 - 2) keep b = 1: their
   // bases are orthogonal to their own partner spaces only when grown from a
-  // single vector.  Variant 3 grows from a block (default b = 4, one fused
-  // full-H read of the triangles per block step: at PH N = 1e5 four vectors
-  // per read took 74.6-77.1 s against 78.7 s for two, with 16 % more vector
-  // steps but 40 % fewer reads).
-  int b = hb ? (o.block > 0 ? o.block : 4) : ph ? 1 : (o.block > 0 ? o.block : (n >= 16384 ? 2 : 1));
+  // single vector.  Variant 3 grows from a block, one fused full-H read of
+  // the triangles per block step: b = 4 from N = 16384 on (at PH N = 1e5 four
+  // vectors per read took 74.6-77.1 s against 78.7 s for two, with 16 % more
+  // vector steps but 40 % fewer reads), b = 2 below, where reads are cheap
+  // and a small basis leaves few block steps per restart.
+  int b = hb ? (o.block > 0 ? o.block : (n >= 16384 ? 4 : 2))
+             : ph ? 1 : (o.block > 0 ? o.block : (n >= 16384 ? 2 : 1));
   if (b > 1 && ((int)round_up(m, b) < k + b || (int64_t)round_up(m, b) + b > dim / 2)) b = 1;
   m = (int)round_up(m, b);
   int keep = o.keep > 0 ? o.keep : hb ? k + (m - k) * 3 / 5 : k + (m - k) / 2;
