@@ -411,6 +411,13 @@ bse_status alloc_solver(Solver& S) {
   HIP_TRY(h, hipMemsetAsync(S.Tc, 0, sizeof(double2) * (size_t)nc * nc, S.s));
   if (S.Tc2) HIP_TRY(h, hipMemsetAsync(S.Tc2, 0, sizeof(double2) * (size_t)nc * nc, S.s));
   if (S.ph) HIP_TRY(h, hipMemsetAsync(S.P, 0, col * nc, S.s));
+  if (S.hb) {
+    // full-H columns are used over ld + n rows, the top half's padding rows
+    // [n, ld) included, and the passes write rows below n only: every buffer
+    // that becomes the basis or its M image starts with zero padding
+    HIP_TRY(h, hipMemsetAsync(S.U2, 0, col * nc, S.s));
+    HIP_TRY(h, hipMemsetAsync(S.P2, 0, col * nc, S.s));
+  }
   return BSE_OK;
 }
 
