@@ -375,8 +375,8 @@ def main():
         multi = [("hi64", op, 4, 8)] if storage == "hilo" else []
         multi += [("fp64", op, 4, 16)]
         if ph:
-            # the fused full-H product: 2 vectors in FP64; 1..3 on hi (the block full-H iteration)
-            multi += [("fp64", "H", 2, 16)]
+            # the fused full-H product: 2 and 4 vectors in FP64; 1..4 on hi (the block full-H iteration)
+            multi += [("fp64", "H", nv, 16) for nv in (2, 4)]
             if storage == "hilo":
                 multi += [("hi64", "H", nv, 8) for nv in (1, 2, 3, 4)]
         for prec, mop, nv, e in multi:

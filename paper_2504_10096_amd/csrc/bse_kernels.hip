@@ -6,6 +6,7 @@
 // goal is to stream every stored block exactly once with fully coalesced
 // loads and keep everything else small next to it.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <math.h>
 
 #include <algorithm>
@@ -382,16 +383,22 @@ __device__ __forceinline__ void lds_colsum(const double (&v)[NV], double* stage,
   wave_lds_sync();
   const int j = lane / LPV, p = lane % LPV;
   const int jj = j < NV ? j : 0;
-  double t = 0.0;
+  double t[NP];
 #pragma unroll
-  for (int m = 0; m < NP; ++m) t += stage[jj * LD + p + LPV * m];
-  t += dpp_f64<0xB1>(t);                     // quad_perm [1,0,3,2]: lane xor 1
-  t += dpp_f64<0x4E>(t);                     // quad_perm [2,3,0,1]: lane xor 2
-  if (LPV >= 8) t += dpp_f64<0x141>(t);      // row_half_mirror: 8-lane groups
-  if (LPV == 16) t += dpp_f64<0x140>(t);     // row_mirror: 16-lane rows
+  for (int m = 0; m < NP; ++m) t[m] = stage[jj * LD + p + LPV * m];
+  // pairwise: depth log2 NP instead of a chain of NP - 1 dependent adds
+#pragma unroll
+  for (int h = NP / 2; h >= 1; h /= 2)
+#pragma unroll
+    for (int m = 0; m < h; ++m) t[m] += t[m + h];
+  double s = t[0];
+  s += dpp_f64<0xB1>(s);                     // quad_perm [1,0,3,2]: lane xor 1
+  s += dpp_f64<0x4E>(s);                     // quad_perm [2,3,0,1]: lane xor 2
+  if (LPV >= 8) s += dpp_f64<0x141>(s);      // row_half_mirror: 8-lane groups
+  if (LPV == 16) s += dpp_f64<0x140>(s);     // row_mirror: 16-lane rows
   // every lane of a group stores the same sum (no branch); the padding
   // groups of NV < NP store to row NV, which is never read
-  colsum[(j < NV ? j : NV) * 64 + c] = t;
+  colsum[(j < NV ? j : NV) * 64 + c] = s;
   wave_lds_sync();
 }
 
@@ -1032,8 +1039,8 @@ __host__ __device__ constexpr int mh_rows(int nh) { return nh >= 3 ? 128 : 256; 
 // conjugate of A.  The four sums are formed once per entry pair, so a vector
 // costs 16 FMAs per pair instead of the 32 of the four complex products.
 // Outputs 2q: K1 u_q, 2q+1: K2 w_q (mh_reduce_kernel, sd = 1, forms T and C).
-// Row partials: rowpart[o][blk][R]; column partials: colpart[o][blk][slice][R]
-// with R / mh_rows(NH) slices.
+// One workgroup per block takes its R / mh_rows(NH) row slices in turn.
+// Row partials: rowpart[o][blk][R]; column partials: colpart[o][blk][R].
 template <int R, int AR, int NH>
 __global__ void __launch_bounds__(kThreads)
     mh_stream_kernel(const void* __restrict__ a0, const void* __restrict__ a1,
@@ -1059,157 +1066,185 @@ __global__ void __launch_bounds__(kThreads)
   double2(*sh)[RS] = reinterpret_cast<double2(*)[RS]>(lds);
 
   const int blk = blockIdx.x;
-  const int slice = blockIdx.y;
   const int2 pq = blkmap[blk];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t row0 = (int64_t)pq.x * R + slice * RS, col0 = (int64_t)pq.y * R;
-  const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
+  const int64_t col0 = (int64_t)pq.y * R;
   double* stage = reinterpret_cast<double*>(lds) + wave * CSW;
   double* colsum = stage + NVAL * stage_ld(NVAL);
 
-  // row entries of u = x + conj(y) and w = x - conj(y) (staged by hsd_stage_kernel over the
-  // padded length pl, zero past n: no bounds selects here)
-  double ur[NH][RPL], ui[NH][RPL], wr[NH][RPL], wi[NH][RPL], rr[NO][RPL], ri[NO][RPL];
-#pragma unroll
-  for (int q = 0; q < NH; ++q)
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-      for (int e = 0; e < VW; ++e) {
-        const int t = g * VW + e;
-        const int64_t i = row0 + g * 64 * VW + lane * VW + e;
-        const double2 u = UW[(size_t)(2 * q) * pl + i];
-        const double2 w = UW[(size_t)(2 * q + 1) * pl + i];
-        ur[q][t] = u.x;
-        ui[q][t] = u.y;
-        wr[q][t] = w.x;
-        wi[q][t] = w.y;
-      }
-#pragma unroll
-  for (int o = 0; o < NO; ++o)
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-      rr[o][t] = 0.0;
-      ri[o][t] = 0.0;
-    }
+  // the row slices of the block in sequence: each adds its column sums to
+  // those of the slices before (the same lane wrote them), so one set of
+  // column partials per block leaves the kernel instead of one per slice
+  for (int slice = 0; slice < NS; ++slice) {
+    const int64_t row0 = (int64_t)pq.x * R + slice * RS;
+    const size_t base = (size_t)blk * R * R + (size_t)slice * RS;
 
-  // hi + lo: the four waves interleave columns (wave w takes columns
-  // 4 cc + w; measured 27.4 vs 28.3 ms per read); the lo-only products keep
-  // contiguous column ranges per wave (16.5 vs 17.5 ms)
-  constexpr bool IL = AR == AR_HILO;
-  constexpr int CST = IL ? 4 : 1;  // column stride of a wave
-  const size_t lbase = base + (size_t)wave * (IL ? 1 : CPW) * R + lane * VW;
-  RawCol<AR> ca_[G], cbm[G], na_[G], nbm[G];
+    // row entries of u = x + conj(y) and w = x - conj(y) (staged by hsd_stage_kernel over the
+    // padded length pl, zero past n: no bounds selects here)
+    double ur[NH][RPL], ui[NH][RPL], wr[NH][RPL], wi[NH][RPL], rr[NO][RPL], ri[NO][RPL];
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    raw_load<AR>(a0, a1, lbase + g * 64 * VW, ca_[g]);
-    raw_load<AR>(b0, b1, lbase + g * 64 * VW, cbm[g]);
-  }
-  for (int cb = 0; cb < CPW; cb += CH) {
-    // unrolled by two so the prefetched registers are renamed, not copied (a
-    // copy would wait for the loads just issued)
-#pragma unroll 2
-    for (int c2 = 0; c2 < CH; ++c2) {
-      const int cc = cb + c2;
-      const int cn = cc + 1 < CPW ? cc + 1 : cc;
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        raw_load<AR>(a0, a1, lbase + (size_t)cn * CST * R + g * 64 * VW, na_[g]);
-        raw_load<AR>(b0, b1, lbase + (size_t)cn * CST * R + g * 64 * VW, nbm[g]);
-      }
-      // keep the loads here: under register pressure the scheduler would sink
-      // them next to their use in the following column
-      __builtin_amdgcn_sched_barrier(0);
-      const int c = IL ? cc * 4 + wave : wave * CPW + cc;
-      const int64_t j = col0 + c;
-      double cur[NH], cui[NH], cwr[NH], cwi[NH], sr[NO], si[NO];
-#pragma unroll
-      for (int q = 0; q < NH; ++q) {
-        const double2 u = UW[(size_t)(2 * q) * pl + j];
-        const double2 w = UW[(size_t)(2 * q + 1) * pl + j];
-        cur[q] = u.x;
-        cui[q] = u.y;
-        cwr[q] = w.x;
-        cwi[q] = w.y;
-      }
-#pragma unroll
-      for (int o = 0; o < NO; ++o) {
-        sr[o] = 0.0;
-        si[o] = 0.0;
-      }
+    for (int q = 0; q < NH; ++q)
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
           const int t = g * VW + e;
-          double ar, ai, br, bi;
-          raw_get<AR, double>(ca_[g], e, ar, ai);
-          raw_get<AR, double>(cbm[g], e, br, bi);
-          const double sp = ar + br, sq = ar - br, ss = ai + bi, st = bi - ai;
-#pragma unroll
-          for (int q = 0; q < NH; ++q) {
-            // rows: K1 u_c = (sp ur + st ui, ss ur + sq ui); K2 w_c = (sq wr - ss wi, -st wr + sp wi)
-            mac(rr[2 * q][t], sp, cur[q]);
-            mac(rr[2 * q][t], st, cui[q]);
-            mac(ri[2 * q][t], ss, cur[q]);
-            mac(ri[2 * q][t], sq, cui[q]);
-            mac(rr[2 * q + 1][t], sq, cwr[q]);
-            mac(rr[2 * q + 1][t], -ss, cwi[q]);
-            mac(ri[2 * q + 1][t], -st, cwr[q]);
-            mac(ri[2 * q + 1][t], sp, cwi[q]);
-            // columns (conj(A) transposed, B): K1 u_r = (sp ur + ss ui, st ur + sq ui);
-            // K2 w_r = (sq wr - st wi, -ss wr + sp wi)
-            mac(sr[2 * q], sp, ur[q][t]);
-            mac(sr[2 * q], ss, ui[q][t]);
-            mac(si[2 * q], st, ur[q][t]);
-            mac(si[2 * q], sq, ui[q][t]);
-            mac(sr[2 * q + 1], sq, wr[q][t]);
-            mac(sr[2 * q + 1], -st, wi[q][t]);
-            mac(si[2 * q + 1], -ss, wr[q][t]);
-            mac(si[2 * q + 1], sp, wi[q][t]);
-          }
+          const int64_t i = row0 + g * 64 * VW + lane * VW + e;
+          const double2 u = UW[(size_t)(2 * q) * pl + i];
+          const double2 w = UW[(size_t)(2 * q + 1) * pl + i];
+          ur[q][t] = u.x;
+          ui[q][t] = u.y;
+          wr[q][t] = w.x;
+          wi[q][t] = w.y;
         }
-      double vals[NVAL];
 #pragma unroll
-      for (int o = 0; o < NO; ++o) {
-        vals[2 * o] = sr[o];
-        vals[2 * o + 1] = si[o];
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+      for (int t = 0; t < RPL; ++t) {
+        rr[o][t] = 0.0;
+        ri[o][t] = 0.0;
       }
-      lds_colsum<NVAL>(vals, stage, colsum, c2, lane);
+
+    // hi + lo: the four waves interleave columns (wave w takes columns
+    // 4 cc + w; measured 27.4 vs 28.3 ms per read); the lo-only products keep
+    // contiguous column ranges per wave (16.5 vs 17.5 ms)
+    constexpr bool IL = AR == AR_HILO;
+    constexpr int CST = IL ? 4 : 1;  // column stride of a wave
+    const size_t lbase = base + (size_t)wave * (IL ? 1 : CPW) * R + lane * VW;
+    // column buffers: a wave's loads run NBUF - 1 columns ahead of its
+    // arithmetic (three for the complex64 hi triangles, whose columns are 8
+    // VGPRs; one for the wider hi + lo and complex128 columns); column cc sits
+    // in slot cc % NBUF, and the loop is unrolled by NBUF so the slots are
+    // renamed, not copied (a copy would wait for the loads just issued)
+    constexpr int NBUF = AR == AR_HI64 && G == 1 ? 4 : 2;
+    static_assert(CH % NBUF == 0, "column chunk of whole buffer rounds");
+    RawCol<AR> ra[NBUF][G], rb[NBUF][G];
+#pragma unroll
+    for (int k = 0; k < NBUF - 1; ++k) {
+      const int cn = k < CPW ? k : CPW - 1;
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        ca_[g] = na_[g];
-        cbm[g] = nbm[g];
+        raw_load<AR>(a0, a1, lbase + (size_t)cn * CST * R + g * 64 * VW, ra[k][g]);
+        raw_load<AR>(b0, b1, lbase + (size_t)cn * CST * R + g * 64 * VW, rb[k][g]);
       }
     }
-    if (lane < CH) {
+    for (int cb = 0; cb < CPW; cb += CH) {
+      for (int c4 = 0; c4 < CH; c4 += NBUF) {
+        auto step = [&](auto slot) {
+          constexpr int S = decltype(slot)::value;
+          constexpr int SN = (S + NBUF - 1) % NBUF;  // the slot of column cc + NBUF - 1
+          const int c2 = c4 + S;
+          const int cc = cb + c2;
+          const int cn = cc + NBUF - 1 < CPW ? cc + NBUF - 1 : CPW - 1;
 #pragma unroll
-      for (int o = 0; o < NO; ++o)
-        colpart[(((size_t)o * nblk + blk) * NS + slice) * R + (IL ? (cb + lane) * 4 + wave : wave * CPW + cb + lane)] =
-            make_double2(colsum[(2 * o) * 64 + lane], colsum[(2 * o + 1) * 64 + lane]);
+          for (int g = 0; g < G; ++g) {
+            raw_load<AR>(a0, a1, lbase + (size_t)cn * CST * R + g * 64 * VW, ra[SN][g]);
+            raw_load<AR>(b0, b1, lbase + (size_t)cn * CST * R + g * 64 * VW, rb[SN][g]);
+          }
+          // keep the loads here: under register pressure the scheduler would sink
+          // them next to their use in the following column
+          __builtin_amdgcn_sched_barrier(0);
+          const int c = IL ? cc * 4 + wave : wave * CPW + cc;
+          const int64_t j = col0 + c;
+          double cur[NH], cui[NH], cwr[NH], cwi[NH], sr[NO], si[NO];
+#pragma unroll
+          for (int q = 0; q < NH; ++q) {
+            const double2 u = UW[(size_t)(2 * q) * pl + j];
+            const double2 w = UW[(size_t)(2 * q + 1) * pl + j];
+            cur[q] = u.x;
+            cui[q] = u.y;
+            cwr[q] = w.x;
+            cwi[q] = w.y;
+          }
+#pragma unroll
+          for (int o = 0; o < NO; ++o) {
+            sr[o] = 0.0;
+            si[o] = 0.0;
+          }
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+              const int t = g * VW + e;
+              double ar, ai, br, bi;
+              raw_get<AR, double>(ra[S][g], e, ar, ai);
+              raw_get<AR, double>(rb[S][g], e, br, bi);
+              const double sp = ar + br, sq = ar - br, ss = ai + bi, st = bi - ai;
+#pragma unroll
+              for (int q = 0; q < NH; ++q) {
+                // rows: K1 u_c = (sp ur + st ui, ss ur + sq ui); K2 w_c = (sq wr - ss wi, -st wr + sp wi)
+                mac(rr[2 * q][t], sp, cur[q]);
+                mac(rr[2 * q][t], st, cui[q]);
+                mac(ri[2 * q][t], ss, cur[q]);
+                mac(ri[2 * q][t], sq, cui[q]);
+                mac(rr[2 * q + 1][t], sq, cwr[q]);
+                mac(rr[2 * q + 1][t], -ss, cwi[q]);
+                mac(ri[2 * q + 1][t], -st, cwr[q]);
+                mac(ri[2 * q + 1][t], sp, cwi[q]);
+                // columns (conj(A) transposed, B): K1 u_r = (sp ur + ss ui, st ur + sq ui);
+                // K2 w_r = (sq wr - st wi, -ss wr + sp wi)
+                mac(sr[2 * q], sp, ur[q][t]);
+                mac(sr[2 * q], ss, ui[q][t]);
+                mac(si[2 * q], st, ur[q][t]);
+                mac(si[2 * q], sq, ui[q][t]);
+                mac(sr[2 * q + 1], sq, wr[q][t]);
+                mac(sr[2 * q + 1], -st, wi[q][t]);
+                mac(si[2 * q + 1], -ss, wr[q][t]);
+                mac(si[2 * q + 1], sp, wi[q][t]);
+              }
+            }
+          double vals[NVAL];
+#pragma unroll
+          for (int o = 0; o < NO; ++o) {
+            vals[2 * o] = sr[o];
+            vals[2 * o + 1] = si[o];
+          }
+          lds_colsum<NVAL>(vals, stage, colsum, c2, lane);
+        };
+        step(std::integral_constant<int, 0>());
+        step(std::integral_constant<int, 1>());
+        if constexpr (NBUF == 4) {
+          step(std::integral_constant<int, 2>());
+          step(std::integral_constant<int, 3>());
+        }
+      }
+      if (lane < CH) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o) {
+          double2* cp = colpart + ((size_t)o * nblk + blk) * R + (IL ? (cb + lane) * 4 + wave : wave * CPW + cb + lane);
+          double2 t = make_double2(colsum[(2 * o) * 64 + lane], colsum[(2 * o + 1) * 64 + lane]);
+          if (slice) {
+            const double2 p = *cp;
+            t.x += p.x;
+            t.y += p.y;
+          }
+          *cp = t;
+        }
+      }
+      wave_lds_sync();  // the flush reads colsum before the next chunk's columns store to it
     }
-  }
-  __syncthreads();  // the row-sum combine below reuses the column-sum LDS of every wave
+    __syncthreads();  // the row-sum combine below reuses the column-sum LDS of every wave
 
 #pragma unroll
-  for (int o = 0; o < NO; ++o) {
+    for (int o = 0; o < NO; ++o) {
 #pragma unroll
-    for (int g = 0; g < G; ++g)
+      for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int e = 0; e < VW; ++e)
-        sh[wave][g * 64 * VW + lane * VW + e] = make_double2(rr[o][g * VW + e], ri[o][g * VW + e]);
-    __syncthreads();
-    for (int r = threadIdx.x; r < RS; r += kThreads) {
-      double2 t = sh[0][r];
+        for (int e = 0; e < VW; ++e)
+          sh[wave][g * 64 * VW + lane * VW + e] = make_double2(rr[o][g * VW + e], ri[o][g * VW + e]);
+      __syncthreads();
+      for (int r = threadIdx.x; r < RS; r += kThreads) {
+        double2 t = sh[0][r];
 #pragma unroll
-      for (int w = 1; w < 4; ++w) {
-        t.x += sh[w][r].x;
-        t.y += sh[w][r].y;
+        for (int w = 1; w < 4; ++w) {
+          t.x += sh[w][r].x;
+          t.y += sh[w][r].y;
+        }
+        rowpart[((size_t)o * nblk + blk) * R + slice * RS + r] = t;
       }
-      rowpart[((size_t)o * nblk + blk) * R + slice * RS + r] = t;
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -1302,12 +1337,6 @@ __global__ void __launch_bounds__(kThreads)
     MV[(size_t)q * ldv + i] = make_double2(sx, sy);
 }
 
-// Row slices per block of the full-H products with nh vectors.
-int mh_slices(int R, int nh) {
-  if (R < 128) return 1;
-  return R < mh_rows(nh) ? 1 : R / mh_rows(nh);
-}
-
 template <int R, int AR>
 hipError_t launch_mh(int nh, const Layout& L, const MatPtrs& m, const double2* V, int64_t ldv, int64_t ldh,
                      double2* part, hipStream_t s) {
@@ -1315,12 +1344,11 @@ hipError_t launch_mh(int nh, const Layout& L, const MatPtrs& m, const double2* V
   double2* colpart = part + (size_t)2 * nh * L.nblk * R;
   if constexpr (R >= 128) {
     // u, w of every vector over the padded length, after the partials (mh_part_elems)
-    const int ns = mh_slices(R, nh);
     const int64_t pl = (int64_t)L.nb * R;
-    double2* uw = colpart + (size_t)2 * nh * L.nblk * ns * R;
+    double2* uw = colpart + (size_t)2 * nh * L.nblk * R;
     hipLaunchKernelGGL(hsd_stage_kernel, dim3((unsigned)((pl + kThreads - 1) / kThreads), (unsigned)nh),
                        dim3(kThreads), 0, s, V, ldv, ldh, L.n, pl, uw);
-    const dim3 grid((unsigned)L.nblk, (unsigned)ns);
+    const dim3 grid((unsigned)L.nblk);
     if (nh == 1)
       hipLaunchKernelGGL((mh_stream_kernel<R, AR, 1>), grid, dim3(kThreads), 0, s, m.a, m.alo, m.b, m.blo,
                          L.blkmap, L.nblk, L.n, uw, pl, rowpart, colpart);
@@ -2371,7 +2399,7 @@ size_t mv_part_elems(const Layout& L) { return (size_t)L.nblk * L.R * (1 + mv_sl
 size_t mh_part_elems(const Layout& L, int nh) {
   size_t mx = 0;
   for (int v = 1; v <= nh; ++v)
-    mx = std::max(mx, (size_t)2 * v * L.nblk * L.R * (1 + mh_slices(L.R, v)) +
+    mx = std::max(mx, (size_t)2 * v * L.nblk * L.R * 2 +  // row and column partials
                           (L.R >= 128 ? (size_t)2 * v * L.nb * L.R : 0));  // + staged u, w
   return mx;
 }
@@ -2415,7 +2443,7 @@ hipError_t mh_apply(const Layout& L, Arith ar, const MatPtrs& m, int nh, const d
     e = hipEventRecord(ev1, s);
     if (e != hipSuccess) return e;
   }
-  const int ns = mh_slices(L.R, nh);
+  const int ns = 1;  // one set of column partials per block (both kernels)
   const double2* rowpart = part;
   const double2* colpart = part + (size_t)2 * nh * L.nblk * L.R;
   const int sd = L.R >= 128;  // the streaming kernel's sum / difference outputs
