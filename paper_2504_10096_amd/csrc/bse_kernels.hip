@@ -357,8 +357,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 // 64 / NP and NP = NV rounded up to 4, 8 or 16, adds value j of lanes p,
 // p + LPV, ..., p + (NP - 1) LPV; a DPP butterfly over the LPV lanes of
 // value j (lane xor 1, xor 2, then mirror within 8 and within 16 as LPV
-// requires) completes the sum, which goes to colsum[j * 64 + c].  Fixed
-// order: deterministic.  colsum holds (NV + 1) rows of 64 when NV < NP.
+// requires) completes the sum (lds_group_sum returns it in every lane of
+// group j; the caller syncs before the stage is written again), which
+// lds_colsum stores to colsum[j * 64 + c].  Fixed order: deterministic.
+// colsum holds (NV + 1) rows of 64 when NV < NP.
 // The stride puts the lanes of each 16-lane read phase on distinct banks
 // (72 for two value groups per phase, 68 for four).
 __host__ __device__ constexpr int colsum_np(int nv) { return nv <= 4 ? 4 : (nv <= 8 ? 8 : 16); }
@@ -372,8 +374,7 @@ __device__ __forceinline__ double dpp_f64(double x) {
   return __hiloint2double(hi, lo);
 }
 template <int NV>
-__device__ __forceinline__ void lds_colsum(const double (&v)[NV], double* stage, double* colsum, int c,
-                                           int lane) {
+__device__ __forceinline__ double lds_group_sum(const double (&v)[NV], double* stage, int lane) {
   static_assert(NV >= 4 && NV <= 16, "lds_colsum: 4..16 values");
   constexpr int NP = colsum_np(NV);
   constexpr int LPV = 64 / NP;
@@ -396,8 +397,16 @@ __device__ __forceinline__ void lds_colsum(const double (&v)[NV], double* stage,
   s += dpp_f64<0x4E>(s);                     // quad_perm [2,3,0,1]: lane xor 2
   if (LPV >= 8) s += dpp_f64<0x141>(s);      // row_half_mirror: 8-lane groups
   if (LPV == 16) s += dpp_f64<0x140>(s);     // row_mirror: 16-lane rows
+  return s;
+}
+template <int NV>
+__device__ __forceinline__ void lds_colsum(const double (&v)[NV], double* stage, double* colsum, int c,
+                                           int lane) {
+  constexpr int LPV = 64 / colsum_np(NV);
+  const double s = lds_group_sum<NV>(v, stage, lane);
   // every lane of a group stores the same sum (no branch); the padding
   // groups of NV < NP store to row NV, which is never read
+  const int j = lane / LPV;
   colsum[(j < NV ? j : NV) * 64 + c] = s;
   wave_lds_sync();
 }
@@ -1499,12 +1508,14 @@ __global__ void __launch_bounds__(kThreads)
 // part[chunk * ncol + c] = sum over the 256-row chunk of conj(V[i, c]) w[i].
 // Grid (chunks, ceil(ncol / 64)); wave w of the group handles 16 columns,
 // four at a time: the 16 loads of four columns are issued together, then the
-// eight wavefront sums (independent chains) follow; lane l holds rows
+// eight sums over the wavefront go through LDS (lds_group_sum: eight values
+// per lane in, one sum per eight-lane group out); lane l holds rows
 // l + 64 s (s < 4) of w in registers.
 __global__ void __launch_bounds__(kThreads)
     cdot_part_kernel(const double2* __restrict__ V0, int n0, const double2* __restrict__ V1,
                      int n1, int64_t ld, const double2* __restrict__ w, int64_t n,
                      double2* __restrict__ part) {
+  __shared__ double stg[4][8 * stage_ld(8)];  // per wave: the column-sum stage
   const int ncol = n0 + n1;
   const int64_t r0 = (int64_t)blockIdx.x * kChunk;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1540,16 +1551,17 @@ __global__ void __launch_bounds__(kThreads)
         si[u] += v[u][s].x * wi[s] - v[u][s].y * wr[s];
       }
     }
+    double vals[8];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      sr[u] = wave_sum(sr[u]);
-      si[u] = wave_sum(si[u]);
+      vals[2 * u] = sr[u];
+      vals[2 * u + 1] = si[u];
     }
-    if (lane == 0) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (t0 + u < cend) part[(size_t)blockIdx.x * ncol + t0 + u] = make_double2(sr[u], si[u]);
-    }
+    const double sum = lds_group_sum<8>(vals, stg[wave], lane);
+    wave_lds_sync();
+    const int j = lane >> 3, u = j >> 1;
+    if ((lane & 7) == 0 && t0 + u < cend)
+      reinterpret_cast<double*>(part)[2 * ((size_t)blockIdx.x * ncol + t0 + u) + (j & 1)] = sum;
   }
 }
 
@@ -1655,6 +1667,7 @@ template <int NW>
 __global__ void __launch_bounds__(kThreads)
     cdotm_part_kernel(const double2* __restrict__ V, int ncol, int64_t ld, const double2* __restrict__ W,
                       int64_t ldw, int64_t n, double2* __restrict__ part) {
+  __shared__ double stg[4][8 * stage_ld(8)];  // per wave: the column-sum stage
   const int64_t r0 = (int64_t)blockIdx.x * kChunk;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   double wr[NW][4], wi[NW][4];
@@ -1693,17 +1706,20 @@ __global__ void __launch_bounds__(kThreads)
           si[u] += v[u][s].x * wi[q][s] - v[u][s].y * wr[q][s];
         }
       }
+      // the eight sums over the wavefront through LDS: lane group j = lane / 8
+      // holds value j (column u = j / 2, real part for even j)
+      double vals[8];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        sr[u] = wave_sum(sr[u]);
-        si[u] = wave_sum(si[u]);
+        vals[2 * u] = sr[u];
+        vals[2 * u + 1] = si[u];
       }
-      if (lane == 0) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (t0 + u < cend)
-            part[(size_t)blockIdx.x * NW * ncol + (size_t)q * ncol + t0 + u] = make_double2(sr[u], si[u]);
-      }
+      const double sum = lds_group_sum<8>(vals, stg[wave], lane);
+      wave_lds_sync();
+      const int j = lane >> 3, u = j >> 1;
+      if ((lane & 7) == 0 && t0 + u < cend)
+        reinterpret_cast<double*>(part)[2 * ((size_t)blockIdx.x * NW * ncol + (size_t)q * ncol + t0 + u) + (j & 1)] =
+            sum;
     }
   }
 }
