@@ -213,8 +213,9 @@ typedef struct {
  * bse_create_ex -- bse_create with the handle's device memory (the stored
  * triangles and every workspace of the calls on the handle) taken from
  * `alloc` instead of hipMalloc; NULL is bse_create.  The allocator must stay
- * valid until bse_destroy.  (rocSOLVER's workspace of the TDA dense solve
- * in bse_direct is allocated by rocSOLVER itself.)
+ * valid until bse_destroy.  (rocSOLVER's workspace of the projected
+ * eigenproblems of bse_solve comes from `alloc` too; that of the TDA dense
+ * solve in bse_direct is allocated by rocSOLVER itself.)
  * Errors: as bse_create; INVALID_ARG when alloc is given without both
  * functions; OUT_OF_MEMORY when alloc returns NULL.
  */

@@ -55,6 +55,13 @@ struct bse_handle_s {
   double* omega = nullptr;
   // device memory of this handle: the caller's allocator (bse_create_ex) or hipMalloc
   bse_allocator alloc{};
+  // projected complex Hermitian eigenproblems of the solves on the device
+  // (rocSOLVER, set up on first use with a workspace from this handle's
+  // memory; eig_state -1: not available here, the host QR runs instead)
+  rocblas_handle eigh = nullptr;
+  int eig_state = 0;
+  int eig_cap = 0;  // largest order the buffers below hold
+  void *eig_a = nullptr, *eig_w = nullptr, *eig_e = nullptr, *eig_info = nullptr, *eig_work = nullptr;
 };
 
 namespace {
@@ -102,6 +109,73 @@ bse_status fail(bse_handle h, bse_status s, const std::string& msg) {
       return fail((h), e_ == hipErrorOutOfMemory ? BSE_ERR_OUT_OF_MEMORY : BSE_ERR_DEVICE, \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                  \
   } while (0)
+
+// Complex Hermitian eigenproblem of order m (column-major a, overwritten;
+// ascending w, orthonormal vectors z), the projected problems of the
+// restarts and of the refinement.  On the device with rocSOLVER's divide and
+// conquer when it can be set up: at order 560 it takes 16 ms against 53 ms
+// for the host QR of bse_smalleig.cpp; atomics are off in its rocBLAS calls,
+// so repeated solves stay bitwise identical.  The buffers grow with the
+// largest order seen and stay with the handle.  Where rocBLAS cannot create
+// a handle (no device), or the call reports an error or no convergence, the
+// host QR solves the same problem.  Returns false only if that fails too.
+bool herm_eig_proj(bse_handle h, int m, double2* a, double* w, double2* z) {
+  auto device = [&]() -> bool {
+    if (h->eig_state == 0) {
+      h->eig_state = -1;
+      if (rocblas_create_handle(&h->eigh) != rocblas_status_success) {
+        h->eigh = nullptr;
+        return false;
+      }
+      if (rocblas_set_stream(h->eigh, h->stream) != rocblas_status_success ||
+          rocblas_set_atomics_mode(h->eigh, rocblas_atomics_not_allowed) != rocblas_status_success)
+        return false;
+      h->eig_state = 1;
+    }
+    if (h->eig_state != 1) return false;
+    if (m > h->eig_cap) {
+      for (void** p : {&h->eig_a, &h->eig_w, &h->eig_e, &h->eig_info, &h->eig_work}) {
+        dfree(h, *p);
+        *p = nullptr;
+      }
+      h->eig_cap = 0;
+      if (dmalloc(h, &h->eig_a, sizeof(double2) * (size_t)m * m) != hipSuccess ||
+          dmalloc(h, &h->eig_w, sizeof(double) * m) != hipSuccess ||
+          dmalloc(h, &h->eig_e, sizeof(double) * m) != hipSuccess ||
+          dmalloc(h, &h->eig_info, sizeof(rocblas_int)) != hipSuccess)
+        return false;
+      // rocSOLVER's workspace for this order, from the handle's memory
+      size_t ws = 0;
+      if (rocblas_start_device_memory_size_query(h->eigh) != rocblas_status_success) return false;
+      (void)rocsolver_zheevd(h->eigh, rocblas_evect_original, rocblas_fill_upper, m,
+                             static_cast<rocblas_double_complex*>(h->eig_a), m, static_cast<double*>(h->eig_w),
+                             static_cast<double*>(h->eig_e), static_cast<rocblas_int*>(h->eig_info));
+      if (rocblas_stop_device_memory_size_query(h->eigh, &ws) != rocblas_status_success) return false;
+      if (dmalloc(h, &h->eig_work, ws ? ws : 1) != hipSuccess) return false;
+      if (rocblas_set_workspace(h->eigh, h->eig_work, ws) != rocblas_status_success) return false;
+      h->eig_cap = m;
+    }
+    if (hipMemcpyAsync(h->eig_a, a, sizeof(double2) * (size_t)m * m, hipMemcpyHostToDevice, h->stream) !=
+        hipSuccess)
+      return false;
+    if (rocsolver_zheevd(h->eigh, rocblas_evect_original, rocblas_fill_upper, m,
+                         static_cast<rocblas_double_complex*>(h->eig_a), m, static_cast<double*>(h->eig_w),
+                         static_cast<double*>(h->eig_e),
+                         static_cast<rocblas_int*>(h->eig_info)) != rocblas_status_success)
+      return false;
+    rocblas_int info = -1;
+    if (hipMemcpyAsync(&info, h->eig_info, sizeof(info), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipMemcpyAsync(w, h->eig_w, sizeof(double) * m, hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipMemcpyAsync(z, h->eig_a, sizeof(double2) * (size_t)m * m, hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return false;
+    return info == 0;
+  };
+  if (m < 1) return true;
+  if (device()) return true;
+  return bse::herm_eig(m, a, w, z);
+}
 
 bse::MatPtrs mat_ptrs(const bse_handle_s* h) {
   bse::MatPtrs m;
@@ -702,7 +776,7 @@ bse_status restart(Solver& S, RitzInfo& R) {
       return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
     for (size_t t = 0; t < Zr.size(); ++t) Zc[t] = Zr[t];
   } else {
-    if (!bse::herm_eig(m, reinterpret_cast<double2*>(T.data()), th.data(), reinterpret_cast<double2*>(Zc.data())))
+    if (!herm_eig_proj(h, m, reinterpret_cast<double2*>(T.data()), th.data(), reinterpret_cast<double2*>(Zc.data())))
       return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
   }
   const double ms_eig = now_ms() - t_eig;
@@ -1155,7 +1229,7 @@ bse_status restart_hb(Solver& S, RitzInfo& R) {
   std::vector<double> th(m);
   std::vector<cplx> Zc((size_t)m * m);
   const double t_eig = now_ms();
-  if (!bse::herm_eig(m, reinterpret_cast<double2*>(T.data()), th.data(), reinterpret_cast<double2*>(Zc.data())))
+  if (!herm_eig_proj(h, m, reinterpret_cast<double2*>(T.data()), th.data(), reinterpret_cast<double2*>(Zc.data())))
     return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
   const double ms_eig = now_ms() - t_eig;
   S.ms_small += ms_eig;
@@ -1571,7 +1645,7 @@ bse_status refine_h(Solver& S, int s0, const std::vector<double>& theta0, double
       if (!std::isfinite(v.real()) || !std::isfinite(v.imag()))
         return fail(h, BSE_ERR_NONFINITE, "non-finite projected pencil in the refinement");
     std::vector<double> mu(s);
-    if (!bse::herm_eig(s, reinterpret_cast<double2*>(C.data()), mu.data(), reinterpret_cast<double2*>(Z.data())))
+    if (!herm_eig_proj(h, s, reinterpret_cast<double2*>(C.data()), mu.data(), reinterpret_cast<double2*>(Z.data())))
       return fail(h, BSE_ERR_DEVICE, "projected eigensolver did not converge");
     // PH: descending mu = ascending positive omega, the negative branch is
     // dropped; TDA: ascending lambda
@@ -1853,8 +1927,11 @@ bse_status bse_create_ex(bse_handle* out, bse_kind kind, int64_t n, bse_storage 
 bse_status bse_destroy(bse_handle h) {
   if (!h) return BSE_OK;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  void* ptrs[] = {h->a, h->alo, h->b, h->blo, h->part, h->mhpart, h->L.blkmap, h->X, h->Y, h->omega, h->dcorr};
+  void* ptrs[] = {h->a,         h->alo,   h->b,     h->blo,    h->part,     h->mhpart,
+                  h->L.blkmap, h->X,     h->Y,     h->omega,  h->dcorr,    h->eig_a,
+                  h->eig_w,    h->eig_e, h->eig_info, h->eig_work};
   for (void* p : ptrs) dfree(h, p);
+  if (h->eigh) (void)rocblas_destroy_handle(h->eigh);
   delete h;
   return BSE_OK;
 }
