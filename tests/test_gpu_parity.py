@@ -543,16 +543,19 @@ def _golden(name):
     return mod.load(name)
 
 
+@pytest.mark.parametrize("edge", [None, 512])
 @pytest.mark.parametrize("block", [1, 2, 3, 4])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_block_full_h_ph_matches_oracle(block, precision):
+def test_block_full_h_ph_matches_oracle(block, precision, edge, monkeypatch):
     """Variant 3 (block Lanczos on H in the M inner product) with 1..4 full-H vectors per fused
     read, FP64 (hi + lo) and mixed: the oracle's pairs and residuals, X^H X - Y^H Y = 1, and one
-    read of the triangles per block step of the bulk phase."""
+    read of the triangles per block step of the bulk phase.  Block edge 512 runs the streaming
+    full-H kernel as at the benchmark size (one workgroup per block taking its 128- or 256-row
+    slices in turn), here over three ragged block rows."""
     n, k = 1100, 12
     m = ph_matrix(n, 35)
     ap, bp = m.pack_host(0), m.pack_host(1)
-    s = make_solver("ph", ap, bp, storage="hilo")
+    s = make_solver("ph", ap, bp, storage="hilo", block=edge, monkeypatch=monkeypatch)
     tol = 1e-10 if precision == "fp64" else 1e-8
     om, X, Y, st = s.solve(k, tol, precision=precision, variant=3, block=block)
     ref, _, _ = oracle.ph(ap, bp, k, vectors=False)
@@ -564,7 +567,7 @@ def test_block_full_h_ph_matches_oracle(block, precision):
     assert np.max(np.abs(nrm - 1)) < 1e-9
     steps = st["steps_fp32"] + st["steps_fp64"]
     assert steps % block == 0
-    print("block", block, precision, "passes", st["passes"], "steps", steps, flush=True)
+    print("block", block, precision, "edge", edge, "passes", st["passes"], "steps", steps, flush=True)
     s.close()
 
 
