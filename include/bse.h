@@ -84,7 +84,7 @@ typedef enum {
 /* Solver options; a NULL pointer or zero fields select the defaults. */
 typedef struct {
   int32_t ncv;          /* basis size m (default: max(2k, k + 32) rounded up to 16, at most N;
-                           PH variant 3: max(5.6k, 2k + 64) rounded up to 16, at least 2k + 16,
+                           PH variant 3: max(6k, 2k + 64) rounded up to 16, at least 2k + 16,
                            at most 2N) */
   int32_t keep;         /* Ritz vectors kept at a restart (default: k + (m - k) / 2; variant 3:
                            k + 3 (m - k) / 5) */

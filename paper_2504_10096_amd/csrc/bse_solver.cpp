@@ -1990,11 +1990,12 @@ bse_status bse_solve(bse_handle h, int32_t k, double tol, const bse_solve_opts* 
   // variant 3 works in C^{2N} and keeps both signs of omega: a basis about
   // twice as large, in a space twice as large
   const int64_t dim = hb ? 2 * n : n;
-  // (variant 3: 5.6 k measured best at PH N = 1e5, k = 100 -- fewer reads than
-  // 4 k, and beyond it the reads stop falling while the orthogonalization and
-  // the projected eigensolves grow)
+  // (variant 3: 6 k measured best at PH N = 1e5, k = 100 with four vectors per
+  // read -- 608 took 2586-2600 reads from two start seeds against 2690-2729
+  // for 560 and 2693-2780 for 592 and 624; much beyond it the reads stop
+  // falling while the orthogonalization and the projected eigensolves grow)
   int m = o.ncv > 0 ? o.ncv
-                    : (int)round_up(hb ? std::max((28 * k + 4) / 5, 2 * k + 64) : std::max(2 * k, k + 32), 16);
+                    : (int)round_up(hb ? std::max(6 * k, 2 * k + 64) : std::max(2 * k, k + 32), 16);
   if (hb) m = std::max(m, 2 * k + 16);  // room for k positive Ritz values and their mirror images
   m = (int)std::min<int64_t>(m, dim);
   if (m < k) return fail(h, BSE_ERR_INVALID_ARG, "ncv must be at least k");
