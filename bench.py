@@ -5,9 +5,10 @@ Default workload: pseudo-Hermitian BSE-shaped matrix, N = 100000 (operator
 2N = 200000), lowest k = 100 positive pairs to relative residual 1e-8, A and
 B generated on the device from the seeded recipe in ``synth`` and stored as
 complex64 hi + lo triangles (80 GB + 80 GB).  One step is one full
-``bse_solve`` with the mixed path (FP32 matvec, FP64 orthogonalization,
-projected eigensolve and refinement); the FP64 path on the same stored
-matrix is timed once beside it.  Generation and ingestion are setup, outside
+``bse_solve`` with the mixed path (the block Lanczos on the full H reading
+the complex64 hi triangles, four vectors per read, with FP64 arithmetic;
+FP64 orthogonalization, projected eigensolves and refinement on hi + lo);
+the FP64 path on the same stored matrix is timed once beside it.  Generation and ingestion are setup, outside
 the timed region.
 
 The run keeps to a wall-clock budget (``--budget-s``, counted from process
